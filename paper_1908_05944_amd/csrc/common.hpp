@@ -1,0 +1,105 @@
+// Shared device utilities: wave-level prefix sums and appends, a device-wide
+// exclusive scan, and an order-preserving int64 encoding of float64 for
+// atomicMin. Wavefronts are 64 lanes wide on gfx950.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace acx {
+
+constexpr int WAVE = 64;
+
+// float64 -> int64 whose signed order matches the float order (no NaNs).
+__device__ __forceinline__ long long ordered_from_double(double x) {
+    long long b = __double_as_longlong(x);
+    return b >= 0 ? b : (b ^ 0x7fffffffffffffffLL);
+}
+__device__ __forceinline__ double double_from_ordered(long long k) {
+    long long b = k >= 0 ? k : (k ^ 0x7fffffffffffffffLL);
+    return __longlong_as_double(b);
+}
+constexpr long long ORDERED_POS_INF = 0x7ff0000000000000LL;  // +inf encoded
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ int wave_inclusive_scan(int v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) {
+        int t = __shfl_up(v, off, WAVE);
+        if (lane >= off) v += t;
+    }
+    return v;
+}
+
+// Append one item per lane where pred holds; returns the slot (or -1). Must be
+// reached by every active lane of the wave together.
+__device__ __forceinline__ int wave_append(int *counter, bool pred) {
+    const unsigned long long mask = __ballot(pred);
+    if (mask == 0) return -1;
+    const int lane = lane_id();
+    const int leader = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, __popcll(mask));
+    base = __shfl(base, leader, WAVE);
+    const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+    return pred ? base + rank : -1;
+}
+
+// ---------------------------------------------------------------------------
+// Device-wide exclusive scan of int32: out[i] = sum(in[0..i)), out[n] = total.
+// Tiles of SCAN_TILE items per 256-thread block; tile totals are scanned
+// recursively and added back.
+constexpr int SCAN_BLOCK = 256;
+constexpr int SCAN_IPT = 8;
+constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_IPT;
+
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_tiles(const int *__restrict__ in, int *__restrict__ out,
+                                                            int *__restrict__ tile_sums, long long n) {
+    __shared__ int wsum[SCAN_BLOCK / WAVE];
+    const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_IPT;
+    int v[SCAN_IPT];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_IPT; k++) {
+        const long long i = base + k;
+        v[k] = i < n ? in[i] : 0;
+        s += v[k];
+    }
+    const int incl = wave_inclusive_scan(s);
+    const int w = threadIdx.x / WAVE, lane = lane_id();
+    if (lane == WAVE - 1) wsum[w] = incl;
+    __syncthreads();
+    int woff = 0;
+    for (int k = 0; k < w; k++) woff += wsum[k];
+    int run = woff + incl - s;
+#pragma unroll
+    for (int k = 0; k < SCAN_IPT; k++) {
+        const long long i = base + k;
+        if (i < n) out[i] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == SCAN_BLOCK - 1) {
+        int tot = 0;
+        for (int k = 0; k < SCAN_BLOCK / WAVE; k++) tot += wsum[k];
+        tile_sums[blockIdx.x] = tot;
+    }
+}
+
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_add(int *__restrict__ out, const int *__restrict__ tile_off,
+                                                          long long n) {
+    const long long base = (long long)blockIdx.x * SCAN_TILE;
+    const int add = tile_off[blockIdx.x];
+    for (int k = threadIdx.x; k < SCAN_TILE; k += SCAN_BLOCK) {
+        const long long i = base + k;
+        if (i < n) out[i] += add;
+    }
+}
+
+__global__ void k_scan_total(int *__restrict__ out, const int *__restrict__ in, long long n) {
+    // single thread: total = out[n-1] + in[n-1]
+    if (threadIdx.x == 0 && blockIdx.x == 0) out[n] = n > 0 ? out[n - 1] + in[n - 1] : 0;
+}
+
+}  // namespace acx

@@ -1,0 +1,131 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Simplex sets must be identical and Sizes within 1e-9 A^2 + 1e-12 relative
+(every membership decision is exact on both sides; Sizes are float64 on the
+GPU and exact rationals in the oracle).
+"""
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import assert_same_complex
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def acx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1908_05944_amd as m
+    return m
+
+
+def _dev(arr):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(arr, dtype=np.float64)).to("cuda:0")
+
+
+def _run(acx, xyz, rad, alpha, **opt):
+    print(f"[case] n={len(rad)} alpha={alpha} opt={opt}", flush=True)
+    return acx.ac_alpha_complex_device(_dev(xyz), _dev(rad), alpha, options=opt or None)
+
+
+def test_tiny_inputs(acx):
+    cases = [
+        ([[0, 0, 0]], [1.5]),
+        ([[0, 0, 0], [2.5, 0, 0]], [1.5, 1.7]),
+        ([[0, 0, 0], [2.5, 0, 0], [0.7, 2.2, 0]], [1.5, 1.7, 1.6]),
+        ([[0, 0, 0], [2.5, 0, 0], [5.1, 0, 0]], [1.6, 1.6, 1.6]),
+        ([[0, 0, 0], [2.5, 0, 0], [0.7, 2.2, 0], [2.9, 2.4, 0], [1.4, -2.0, 0]], [1.6] * 5),
+        ([[0, 0, 0], [2.4, 0, 0], [0, 2.4, 0], [0, 0, 2.4], [2.0, 2.0, 2.0]], [1.7, 1.5, 1.6, 1.8, 1.5]),
+    ]
+    for xyz, rad in cases:
+        xyz, rad = np.array(xyz, dtype=float), np.array(rad, dtype=float)
+        for alpha in (0.0, 1.0, 6.0):
+            assert_same_complex(_run(acx, xyz, rad, alpha), oracle.alpha_complex(xyz, rad, alpha), f"n={len(rad)}")
+
+
+def test_random_small(acx):
+    rng = random.Random(42)
+    for trial in range(40):
+        n = rng.choice([4, 6, 10, 20, 40])
+        box = rng.choice([3.0, 5.0, 8.0])
+        xyz = np.array([[rng.randint(-int(box * 1000), int(box * 1000)) / 1000 for _ in range(3)] for _ in range(n)])
+        xyz = np.unique(xyz, axis=0)
+        rad = np.array([rng.choice([1.2, 1.5, 1.7, 2.0, 0.5]) for _ in range(len(xyz))])
+        alpha = rng.choice([0.0, 1.0, -0.5, 4.0, 20.0])
+        assert_same_complex(_run(acx, xyz, rad, alpha), oracle.alpha_complex(xyz, rad, alpha), f"trial {trial}")
+
+
+@pytest.mark.parametrize("rad", [1.0, 1.5])
+def test_cubic_lattice_ties(acx, rad):
+    """4x4x4 cubic lattice, equal radii: every cube has eight co-spherical
+    centres; simulation of simplicity decides, and alpha = 2.0 / 0.75 hits the
+    cube-corner tetrahedra's OrthoSize exactly."""
+    pts = np.array([[2.0 * i, 2.0 * j, 2.0 * k] for i in range(4) for j in range(4) for k in range(4)])
+    for perm_seed in (None, 3):
+        p = pts if perm_seed is None else pts[np.random.RandomState(perm_seed).permutation(len(pts))]
+        r = np.full(len(p), rad)
+        for alpha in (0.0, 0.75, 1.0, 2.0, 3.0):
+            assert_same_complex(_run(acx, p, r, alpha), oracle.alpha_complex(p, r, alpha), f"lattice a={alpha}")
+
+
+def test_integer_grid_ties(acx):
+    rng = random.Random(8)
+    for trial in range(10):
+        pts = np.unique(np.array([[rng.randint(-4, 4) for _ in range(3)] for _ in range(60)], dtype=float), axis=0)
+        pts = pts[np.random.RandomState(trial).permutation(len(pts))]
+        rad = np.array([rng.choice([1.0, 1.5]) for _ in range(len(pts))])
+        alpha = rng.choice([0.0, 0.5, 2.0, 8.0])
+        assert_same_complex(_run(acx, pts, rad, alpha), oracle.alpha_complex(pts, rad, alpha), f"grid {trial}")
+
+
+def test_small_molecule_alphas(acx):
+    m = synth.config_small()
+    for alpha in (0.0, 0.5, 1.0, 2.0):
+        assert_same_complex(_run(acx, m.xyz, m.radii, alpha), oracle.alpha_complex(m.xyz, m.radii, alpha),
+                            f"1k a={alpha}")
+
+
+def test_options_do_not_change_result(acx):
+    m = synth.molecule(2000, 11)
+    want = oracle.alpha_complex(m.xyz, m.radii, 1.0)
+    for opt in ({"force_exact": 1}, {"cell_mA": 900}, {"cell_mA": 4000}, {"cell_mA": 2500, "force_exact": 1}):
+        assert_same_complex(_run(acx, m.xyz, m.radii, 1.0, **opt), want, str(opt))
+
+
+def test_host_path_matches(acx):
+    m = synth.molecule(1500, 12)
+    got = acx.ac_alpha_complex(m.xyz, m.radii, 0.0)
+    assert_same_complex(got, oracle.alpha_complex(m.xyz, m.radii, 0.0), "host path")
+
+
+def test_errors(acx):
+    with pytest.raises(acx.AlphaCxError) as e:
+        _run(acx, np.zeros((2, 3)), np.ones(2), 0.0)
+    assert e.value.status == 2
+    with pytest.raises(acx.AlphaCxError) as e:
+        _run(acx, np.array([[0, 0, 0], [1, np.nan, 0.0]]), np.ones(2), 0.0)
+    assert e.value.status == 1
+    with pytest.raises(acx.AlphaCxError) as e:
+        _run(acx, np.array([[0, 0, 0], [600, 0, 0.0]]), np.ones(2), 0.0)
+    assert e.value.status == 3
+    with pytest.raises(acx.AlphaCxError) as e:
+        _run(acx, np.array([[0, 0, 0], [3, 0, 0.0]]), np.array([1.0, 0.0]), 0.0)
+    assert e.value.status == 1
+    # alpha so negative that no ball is left: an empty complex, not an error
+    c = _run(acx, np.array([[0, 0, 0], [3, 0, 0.0]]), np.ones(2), -5.0)
+    assert c.counts() == [0, 0, 0, 0]
+
+
+@pytest.mark.parametrize("sas", [False, True])
+def test_100k_full_parity(acx, sas):
+    m = synth.config_100k(sas=sas)
+    got = _run(acx, m.xyz, m.radii, 0.0)
+    assert_same_complex(got, oracle.alpha_complex(m.xyz, m.radii, 0.0), f"100k sas={sas}")
