@@ -199,27 +199,62 @@ static long long isqrt_ceil(long long v) {
     return r;
 }
 
-// Emit one dimension: remap to input ids, sort, write result-owned arrays.
+// Candidate arrays of one call, used by the emit stage.
+struct Cands {
+    const int *up, *edge_i, *tri_k, *tri_e, *tet_t, *tet_l, *perm;
+};
+
+// Stable LSD radix sort of (key, payload) on the low `bits` bits of key;
+// the result ends in key/pay.
+template <class P>
+static void radix_sort(unsigned *key, P *pay, int n, int bits, hipStream_t s, Scope &sc) {
+    if (n <= 1 || bits <= 0) return;
+    const int tiles = (n + RS_TILE - 1) / RS_TILE;
+    unsigned *k2 = sc.get<unsigned>(n);
+    P *p2 = sc.get<P>(n);
+    int *hist = sc.get<int>((size_t)RS_BINS * tiles);
+    int *offs = sc.get<int>((size_t)RS_BINS * tiles + 1);
+    unsigned *kin = key, *kout = k2;
+    P *pin = pay, *pout = p2;
+    for (int shift = 0; shift < bits; shift += RS_BITS) {
+        k_rs_hist<<<tiles, RS_BLOCK, 0, s>>>(kin, n, shift, hist, tiles);
+        LAUNCH_CHECK();
+        scan_i32(hist, offs, (long long)RS_BINS * tiles, s, sc);
+        k_rs_scatter<P><<<tiles, RS_BLOCK, 0, s>>>(kin, pin, kout, pout, n, shift, offs, tiles);
+        LAUNCH_CHECK();
+        std::swap(kin, kout);
+        std::swap(pin, pout);
+    }
+    if (kin != key) {
+        HIP_TRY(hipMemcpyAsync(key, kin, sizeof(unsigned) * n, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(pay, pin, sizeof(P) * n, hipMemcpyDeviceToDevice, s));
+    }
+}
+
+static int bits_for(long long n) {
+    int b = 1;
+    while ((1LL << b) < n) b++;
+    return b;
+}
+
+// Emit dimension d (K = d + 1 >= 2): kept candidates (flags `in`, compacted
+// positions `fpos`), remapped to input ids, radix-sorted by their least id,
+// then ranked inside each bucket by the remaining ids.
 template <int K>
-static void emit_dim(const int *rows, const double *sizes, int m, const int *perm, int n, hipStream_t s, Scope &sc,
-                     ac_complex *res, int d) {
-    res->count[d] = m;
-    res->d_simp[d] = static_cast<int32_t *>(dev_alloc((size_t)(m > 0 ? m : 1) * K * sizeof(int32_t)));
-    res->d_size[d] = static_cast<double *>(dev_alloc((size_t)(m > 0 ? m : 1) * sizeof(double)));
-    if (m == 0) return;
-    int4 *tmp = sc.get<int4>(m);
-    int4 *rows2 = sc.get<int4>(m);
-    double *size2 = sc.get<double>(m);
-    int *bcnt = sc.get<int>(n);
-    int *bstart = sc.get<int>(n + 1);
-    fill<int>(bcnt, 0, n, s);
-    k_emit_remap<K><<<grid_for(m), BLOCK, 0, s>>>(rows, perm, m, tmp, bcnt);
+static void emit_dim(const unsigned char *in, const int *fpos, const double *sizes, int M, const Cands &cd, int n,
+                     hipStream_t s, Scope &sc, ac_complex *res, int d, int m_out) {
+    typedef typename EmitPay<K>::type P;
+    res->count[d] = m_out;
+    res->d_simp[d] = static_cast<int32_t *>(dev_alloc((size_t)(m_out > 0 ? m_out : 1) * K * sizeof(int32_t)));
+    res->d_size[d] = static_cast<double *>(dev_alloc((size_t)(m_out > 0 ? m_out : 1) * sizeof(double)));
+    if (m_out == 0) return;
+    unsigned *key = sc.get<unsigned>(m_out);
+    P *pay = sc.get<P>(m_out);
+    k_emit_keys<K><<<grid_for(M), BLOCK, 0, s>>>(in, fpos, M, cd.up, cd.edge_i, cd.tri_k, cd.tri_e, cd.tet_t,
+                                                 cd.tet_l, cd.perm, key, pay);
     LAUNCH_CHECK();
-    scan_i32(bcnt, bstart, n, s, sc);
-    HIP_TRY(hipMemcpyAsync(bcnt, bstart, sizeof(int) * n, hipMemcpyDeviceToDevice, s));
-    k_emit_scatter<<<grid_for(m), BLOCK, 0, s>>>(tmp, sizes, m, bcnt, rows2, size2);
-    LAUNCH_CHECK();
-    k_emit_sort<K><<<grid_for(n), BLOCK, 0, s>>>(rows2, size2, bstart, n, res->d_simp[d], res->d_size[d]);
+    radix_sort<P>(key, pay, m_out, bits_for(n), s, sc);
+    k_emit_rank<K><<<grid_for(m_out), BLOCK, 0, s>>>(key, pay, m_out, sizes, res->d_simp[d], res->d_size[d]);
     LAUNCH_CHECK();
 }
 
@@ -233,11 +268,13 @@ struct Options {
 // Stages timed by HIP events when profiling (one event before each).
 enum Stage {
     ST_QUANTISE, ST_BIN, ST_NBR_COUNT, ST_NBR_SCAN, ST_NBR_FILL, ST_TRI_COUNT, ST_TRI_SCAN, ST_TRI_FILL,
-    ST_TETRA, ST_TRI_FINAL, ST_EDGE_FINAL, ST_VERT_FINAL, ST_EMIT, ST_COUNT
+    ST_TRI_GABRIEL, ST_TET_COUNT, ST_TET_FILL, ST_TETRA, ST_TRI_FINAL, ST_EDGE_FINAL, ST_VERT_FINAL, ST_EMIT,
+    ST_COUNT
 };
 static const char *kStageNames[ST_COUNT] = {
     "quantise", "binning", "neighbours_count", "neighbours_scan", "neighbours_fill", "triangles_count",
-    "triangles_scan", "triangles_fill", "tetrahedra_ac2", "triangles_final", "edges_final", "vertices_final", "emit"};
+    "triangles_scan", "triangles_fill", "triangles_ac2", "tetrahedra_count", "tetrahedra_fill", "tetrahedra_ac2",
+    "triangles_final", "edges_final", "vertices_final", "emit"};
 
 struct StageTimer {
     bool on = false;
@@ -271,6 +308,24 @@ struct StageTimer {
     }
 };
 
+__global__ void __launch_bounds__(BLOCK) k_flags_to_int(const unsigned char *__restrict__ f, long long M,
+                                                         int *__restrict__ out) {
+    const long long i = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (i < M) out[i] = f[i];
+}
+
+// Exclusive scan of 0/1 flags into pos[0..M]; pos[M] is the number set.
+static void scan_flags(const unsigned char *flags, long long M, int *pos, hipStream_t s, Scope &sc) {
+    if (M <= 0) {
+        fill<int>(pos, 0, 1, s);
+        return;
+    }
+    int *work = sc.get<int>(M);
+    k_flags_to_int<<<grid_for(M), BLOCK, 0, s>>>(flags, M, work);
+    LAUNCH_CHECK();
+    scan_i32(work, pos, M, s, sc);
+}
+
 // The whole pipeline from device arrays. Returns AC_OK and *out on success.
 static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n64, double alpha, const Options &o,
                               hipStream_t s, ac_complex **out) {
@@ -295,12 +350,13 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         Stats *st = sc.get<Stats>(1);
         Counters *cnt = sc.get<Counters>(1);
         HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(Counters), s));
-        k_stats_init<<<1, 1, 0, s>>>(st);
-        LAUNCH_CHECK();
         {
             long long b = grid_for(n);
-            if (b > 4096) b = 4096;
-            k_quantise<<<(unsigned)b, BLOCK, 0, s>>>(d_xyz, d_r, n, q, st);
+            if (b > 2048) b = 2048;
+            Stats *part = sc.get<Stats>(b);
+            k_quantise<<<(unsigned)b, BLOCK, 0, s>>>(d_xyz, d_r, n, q, part);
+            LAUNCH_CHECK();
+            k_stats_reduce<<<1, BLOCK, 0, s>>>(part, (int)b, st);
             LAUNCH_CHECK();
         }
         const Stats hs = read_one(st, s);
@@ -352,9 +408,10 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         // ---- neighbours and candidate edges ----
         int *deg_n = sc.get<int>(n), *deg_up = sc.get<int>(n);
         int *nbr_start = sc.get<int>(n + 1), *up_start = sc.get<int>(n + 1);
+        unsigned char *vgab = sc.get<unsigned char>(n);
         tm.mark(ST_NBR_COUNT);
-        k_neighbours<false><<<grid_for(n), BLOCK, 0, s>>>(atom, n, g, cell_start, pp, deg_n, deg_up, nullptr, nullptr,
-                                                         nullptr, nullptr, nullptr, cnt);
+        k_neighbours<false><<<grid_for(n), BLOCK, 0, s>>>(atom, perm, n, g, cell_start, pp, deg_n, deg_up, nullptr,
+                                                         nullptr, nullptr, nullptr, nullptr, nullptr);
         LAUNCH_CHECK();
         tm.mark(ST_NBR_SCAN);
         scan_i32(deg_n, nbr_start, n, s, sc);
@@ -367,17 +424,18 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         int *up = sc.get<int>(E > 0 ? E : 1);
         int *edge_i = sc.get<int>(E > 0 ? E : 1);
         tm.mark(ST_NBR_FILL);
-        k_neighbours<true><<<grid_for(n), BLOCK, 0, s>>>(atom, n, g, cell_start, pp, nullptr, nullptr, nbr_start,
-                                                        up_start, nbr, up, edge_i, cnt);
+        k_neighbours<true><<<grid_for(n), BLOCK, 0, s>>>(atom, perm, n, g, cell_start, pp, nullptr, nullptr, nbr_start,
+                                                        up_start, nbr, up, edge_i, vgab);
         LAUNCH_CHECK();
 
-        // ---- candidate triangles ----
+        // ---- candidate triangles (with AC2 of the edges) ----
         int *tri_cnt = sc.get<int>(E > 0 ? E : 1);
         int *tri_start = sc.get<int>(E + 1);
+        unsigned char *egab = sc.get<unsigned char>(E > 0 ? E : 1);
         tm.mark(ST_TRI_COUNT);
         if (E > 0) {
-            k_triangles<false><<<grid_for(E), BLOCK, 0, s>>>(atom, up_start, up, edge_i, E, pp, tri_cnt, nullptr,
-                                                            nullptr, nullptr, cnt);
+            k_triangles<false><<<grid_for(E), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr, up_start, up, edge_i, E, pp,
+                                                            tri_cnt, egab, nullptr, nullptr, nullptr, cnt);
             LAUNCH_CHECK();
         }
         tm.mark(ST_TRI_SCAN);
@@ -385,73 +443,111 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         const int T = read_one(tri_start + E, s);
         int *tri_k = sc.get<int>(T > 0 ? T : 1);
         int *tri_e = sc.get<int>(T > 0 ? T : 1);
+        unsigned char *tgab = sc.get<unsigned char>(T > 0 ? T : 1);
+        double *tsize = sc.get<double>(T > 0 ? T : 1);
+        int *tet_cnt = sc.get<int>(T > 0 ? T : 1);
+        int *tet_start = sc.get<int>(T + 1);
         tm.mark(ST_TRI_FILL);
         if (T > 0) {
-            k_triangles<true><<<grid_for(E), BLOCK, 0, s>>>(atom, up_start, up, edge_i, E, pp, nullptr, tri_start, tri_k,
-                                                           tri_e, cnt);
+            k_triangles<true><<<grid_for(E), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr, up_start, up, edge_i, E, pp,
+                                                           nullptr, nullptr, tri_start, tri_k, tri_e, cnt);
+            LAUNCH_CHECK();
+        }
+        // ---- AC2 of triangles; candidate tetrahedra ----
+        tm.mark(ST_TRI_GABRIEL);
+        if (T > 0) {
+            k_tri_gabriel<<<grid_for(T), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr, up, edge_i, tri_k, tri_e, T, pp,
+                                                       tgab, tsize, cnt);
+            LAUNCH_CHECK();
+        }
+        tm.mark(ST_TET_COUNT);
+        if (T > 0) {
+            k_tet_candidates<false><<<grid_for(T), BLOCK, 0, s>>>(atom, up_start, up, edge_i, tri_k, tri_e, T, pp,
+                                                                 tet_cnt, nullptr, nullptr, nullptr, cnt);
+            LAUNCH_CHECK();
+        }
+        scan_i32(tet_cnt, tet_start, T, s, sc);
+        const int Q = read_one(tet_start + T, s);
+        int *tet_t = sc.get<int>(Q > 0 ? Q : 1);
+        int *tet_l = sc.get<int>(Q > 0 ? Q : 1);
+        unsigned char *qin = sc.get<unsigned char>(Q > 0 ? Q : 1);
+        double *qsize = sc.get<double>(Q > 0 ? Q : 1);
+        tm.mark(ST_TET_FILL);
+        if (Q > 0) {
+            k_tet_candidates<true><<<grid_for(T), BLOCK, 0, s>>>(atom, up_start, up, edge_i, tri_k, tri_e, T, pp,
+                                                                nullptr, tet_start, tet_t, tet_l, cnt);
             LAUNCH_CHECK();
         }
 
-        // ---- pruning: tetrahedra, triangles, edges, vertices ----
+        // ---- pruning: tetrahedra, then triangles, edges, vertices ----
         int *tri_att = sc.get<int>(T > 0 ? T : 1);
         long long *tri_min = sc.get<long long>(T > 0 ? T : 1);
         int *edge_att = sc.get<int>(E > 0 ? E : 1);
         long long *edge_min = sc.get<long long>(E > 0 ? E : 1);
         int *vert_att = sc.get<int>(n);
         long long *vert_min = sc.get<long long>(n);
+        unsigned char *tin = sc.get<unsigned char>(T > 0 ? T : 1);
+        unsigned char *ein = sc.get<unsigned char>(E > 0 ? E : 1);
+        double *esize = sc.get<double>(E > 0 ? E : 1);
+        int *vin_in = sc.get<int>(n);
+        double *vsize_in = sc.get<double>(n);
         fill<int>(tri_att, 0, T, s);
         fill<long long>(tri_min, ORDERED_POS_INF, T, s);
         fill<int>(edge_att, 0, E, s);
         fill<long long>(edge_min, ORDERED_POS_INF, E, s);
         fill<int>(vert_att, 0, n, s);
         fill<long long>(vert_min, ORDERED_POS_INF, n, s);
-        // a triangle has at most two tetrahedra in K, each tetrahedron four facets
-        const int cap3 = T / 2 + 1;
-        int4 *k3 = sc.get<int4>(cap3);
-        double *k3_size = sc.get<double>(cap3);
-        int4 *k2 = sc.get<int4>(T > 0 ? T : 1);
-        double *k2_size = sc.get<double>(T > 0 ? T : 1);
-        int2 *k1 = sc.get<int2>(E > 0 ? E : 1);
-        double *k1_size = sc.get<double>(E > 0 ? E : 1);
-        int *k0 = sc.get<int>(n);
-        double *k0_size = sc.get<double>(n);
         tm.mark(ST_TETRA);
-        if (T > 0) {
-            k_tetrahedra<<<grid_for(T), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr, up_start, up, edge_i, tri_start,
-                                                      tri_k, tri_e, T, pp, tri_att, tri_min, k3, k3_size, cap3, cnt);
+        if (Q > 0) {
+            k_tet_ac2<<<grid_for(Q), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr, up_start, up, edge_i, tri_start, tri_k,
+                                                   tri_e, tet_t, tet_l, Q, pp, tgab, tri_att, tri_min, qin, qsize, cnt);
             LAUNCH_CHECK();
         }
         tm.mark(ST_TRI_FINAL);
         if (T > 0) {
-            k_tri_final<<<grid_for(T), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr, up_start, up, edge_i, tri_k, tri_e, T,
-                                                     pp, tri_att, tri_min, edge_att, edge_min, k2, k2_size, cnt);
+            k_tri_final<<<grid_for(T), BLOCK, 0, s>>>(up_start, up, edge_i, tri_k, tri_e, T, tgab, tsize, tri_att,
+                                                     tri_min, tin, egab, edge_att, edge_min, cnt);
             LAUNCH_CHECK();
         }
         tm.mark(ST_EDGE_FINAL);
         if (E > 0) {
-            k_edge_final<<<grid_for(E), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr, up, edge_i, E, edge_att, edge_min,
-                                                      vert_att, vert_min, k1, k1_size, cnt);
+            k_edge_final<<<grid_for(E), BLOCK, 0, s>>>(atom, up, edge_i, E, egab, edge_att, edge_min, ein, esize, vgab,
+                                                      vert_att, vert_min);
             LAUNCH_CHECK();
         }
         tm.mark(ST_VERT_FINAL);
-        k_vert_final<<<grid_for(n), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr, n, pp, o.vertex_shortcut, vert_att,
-                                                  vert_min, k0, k0_size, cnt);
+        k_vert_final<<<grid_for(n), BLOCK, 0, s>>>(atom, perm, n, pp, o.vertex_shortcut, vgab, vert_att, vert_min,
+                                                  vin_in, vsize_in);
         LAUNCH_CHECK();
-        tm.mark(ST_EMIT);
-        const Counters cf = read_one(cnt, s);
-        if (cf.lookup) throw HipError{AC_E_DEVICE, "internal error: a facet of a kept simplex is not a candidate"};
-        if (cf.k3 > cap3) throw HipError{AC_E_CAPACITY, "tetrahedron list overflow"};
-        res->cand[0] = n;  // refined below to active balls
-        res->cand[1] = E;
-        res->cand[2] = T;
-        res->cand[3] = cf.k3;  // candidates that reached AC2 are not counted separately
-        res->fallbacks = (int64_t)cf.exact_fallbacks;
 
         // ---- emit ----
-        emit_dim<1>(k0, k0_size, cf.k0, perm, n, s, sc, res, 0);
-        emit_dim<2>(reinterpret_cast<const int *>(k1), k1_size, cf.k1, perm, n, s, sc, res, 1);
-        emit_dim<3>(reinterpret_cast<const int *>(k2), k2_size, cf.k2, perm, n, s, sc, res, 2);
-        emit_dim<4>(reinterpret_cast<const int *>(k3), k3_size, cf.k3, perm, n, s, sc, res, 3);
+        tm.mark(ST_EMIT);
+        int *vpos = sc.get<int>(n + 1);
+        scan_i32(vin_in, vpos, n, s, sc);
+        int *epos = sc.get<int>(E + 1), *tpos = sc.get<int>(T + 1), *qpos = sc.get<int>(Q + 1);
+        scan_flags(ein, E, epos, s, sc);
+        scan_flags(tin, T, tpos, s, sc);
+        scan_flags(qin, Q, qpos, s, sc);
+        const int m1 = read_one(epos + E, s);
+        const int m2 = read_one(tpos + T, s);
+        const int m3 = read_one(qpos + Q, s);
+        const int m0 = read_one(vpos + n, s);
+        const Counters cf = read_one(cnt, s);
+        if (cf.lookup) throw HipError{AC_E_DEVICE, "internal error: a facet of a kept simplex is not a candidate"};
+        res->cand[0] = n;
+        res->cand[1] = E;
+        res->cand[2] = T;
+        res->cand[3] = Q;
+        res->fallbacks = (int64_t)cf.exact_fallbacks;
+        res->count[0] = m0;
+        res->d_simp[0] = static_cast<int32_t *>(dev_alloc((size_t)(m0 > 0 ? m0 : 1) * sizeof(int32_t)));
+        res->d_size[0] = static_cast<double *>(dev_alloc((size_t)(m0 > 0 ? m0 : 1) * sizeof(double)));
+        k_vert_emit<<<grid_for(n), BLOCK, 0, s>>>(vin_in, vpos, vsize_in, n, res->d_simp[0], res->d_size[0]);
+        LAUNCH_CHECK();
+        const Cands cd{up, edge_i, tri_k, tri_e, tet_t, tet_l, perm};
+        emit_dim<2>(ein, epos, esize, E, cd, n, s, sc, res, 1, m1);
+        emit_dim<3>(tin, tpos, tsize, T, cd, n, s, sc, res, 2, m2);
+        emit_dim<4>(qin, qpos, qsize, Q, cd, n, s, sc, res, 3, m3);
         tm.mark(ST_COUNT);
         HIP_TRY(hipStreamSynchronize(s));
         tm.collect(res->stage_ms);

@@ -20,6 +20,7 @@
 #pragma once
 #include "common.hpp"
 #include "predicates.hpp"
+#include "radix.hpp"
 
 namespace acx {
 
@@ -38,9 +39,10 @@ struct Grid {
 constexpr int BLOCK = 256;
 
 // ---------------------------------------------------------------------------
-// Quantise: x -> rint(1000 x) (round half to even), W = R^2.
+// Quantise: x -> rint(1000 x) (round half to even), W = R^2. Each block writes
+// its partial bounding box and flags; k_stats_reduce folds the partials.
 __global__ void __launch_bounds__(BLOCK) k_quantise(const double *__restrict__ xyz, const double *__restrict__ r,
-                                                     int n, int4 *__restrict__ q, Stats *st) {
+                                                     int n, int4 *__restrict__ q, Stats *__restrict__ part) {
     int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN}, wmax = 0, flags = 0;
     for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
         int c[3];
@@ -73,7 +75,6 @@ __global__ void __launch_bounds__(BLOCK) k_quantise(const double *__restrict__ x
         wmax = max(wmax, W);
         q[i] = make_int4(c[0], c[1], c[2], W);
     }
-    // wave reduction, then one atomic per wave
 #pragma unroll
     for (int off = WAVE / 2; off > 0; off >>= 1) {
 #pragma unroll
@@ -84,19 +85,43 @@ __global__ void __launch_bounds__(BLOCK) k_quantise(const double *__restrict__ x
         wmax = max(wmax, __shfl_xor(wmax, off, WAVE));
         flags |= __shfl_xor(flags, off, WAVE);
     }
-    if (lane_id() == 0) {
-        atomicMin(&st->minx, mn[0]); atomicMin(&st->miny, mn[1]); atomicMin(&st->minz, mn[2]);
-        atomicMax(&st->maxx, mx[0]); atomicMax(&st->maxy, mx[1]); atomicMax(&st->maxz, mx[2]);
-        atomicMax(&st->wmax, wmax);
-        atomicOr(&st->flags, flags);
+    __shared__ Stats ws[BLOCK / WAVE];
+    const int w = threadIdx.x / WAVE;
+    if (lane_id() == 0) ws[w] = Stats{mn[0], mn[1], mn[2], mx[0], mx[1], mx[2], wmax, flags};
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Stats b = ws[0];
+        for (int k = 1; k < BLOCK / WAVE; k++) {
+            const Stats &o = ws[k];
+            b.minx = min(b.minx, o.minx); b.miny = min(b.miny, o.miny); b.minz = min(b.minz, o.minz);
+            b.maxx = max(b.maxx, o.maxx); b.maxy = max(b.maxy, o.maxy); b.maxz = max(b.maxz, o.maxz);
+            b.wmax = max(b.wmax, o.wmax); b.flags |= o.flags;
+        }
+        part[blockIdx.x] = b;
     }
 }
 
-__global__ void k_stats_init(Stats *st) {
-    st->minx = st->miny = st->minz = INT_MAX;
-    st->maxx = st->maxy = st->maxz = INT_MIN;
-    st->wmax = 0;
-    st->flags = 0;
+// One block folds the per-block partials into st.
+__global__ void __launch_bounds__(BLOCK) k_stats_reduce(const Stats *__restrict__ part, int nparts, Stats *st) {
+    Stats b{INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN, 0, 0};
+    for (int k = threadIdx.x; k < nparts; k += BLOCK) {
+        const Stats &o = part[k];
+        b.minx = min(b.minx, o.minx); b.miny = min(b.miny, o.miny); b.minz = min(b.minz, o.minz);
+        b.maxx = max(b.maxx, o.maxx); b.maxy = max(b.maxy, o.maxy); b.maxz = max(b.maxz, o.maxz);
+        b.wmax = max(b.wmax, o.wmax); b.flags |= o.flags;
+    }
+    __shared__ Stats ws[BLOCK];
+    ws[threadIdx.x] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < BLOCK; k++) {
+            const Stats &o = ws[k];
+            b.minx = min(b.minx, o.minx); b.miny = min(b.miny, o.miny); b.minz = min(b.minz, o.minz);
+            b.maxx = max(b.maxx, o.maxx); b.maxy = max(b.maxy, o.maxy); b.maxz = max(b.maxz, o.maxz);
+            b.wmax = max(b.wmax, o.wmax); b.flags |= o.flags;
+        }
+        *st = b;
+    }
 }
 
 template <class T>
@@ -159,19 +184,22 @@ __global__ void __launch_bounds__(BLOCK) k_cell_order(const int4 *__restrict__ t
 // ---------------------------------------------------------------------------
 // Neighbour lists and candidate edges (Sec. 4.3, first step). A thread per
 // ball scans the cells within `reach`; cells of one grid row are contiguous
-// in the sorted order, so each (dz, dy) row is one contiguous range.
+// in the sorted order, so each (dz, dy) row is one contiguous range. The fill
+// pass also decides AC2 for the ball as a vertex (Step 5): every ball that
+// could be strictly closer in power to its centre is in its neighbour list.
 template <bool FILL>
-__global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ atom, int n, Grid g,
-                                                       const int *__restrict__ cell_start, PredParams pp,
+__global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ atom, const int *__restrict__ perm, int n,
+                                                       Grid g, const int *__restrict__ cell_start, PredParams pp,
                                                        int *__restrict__ deg_n, int *__restrict__ deg_up,
                                                        const int *__restrict__ nbr_start, const int *__restrict__ up_start,
                                                        int *__restrict__ nbr, int *__restrict__ up,
-                                                       int *__restrict__ edge_i, Counters *cnt) {
+                                                       int *__restrict__ edge_i, unsigned char *__restrict__ vgab) {
     const int i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
     const int4 a = atom[i];
     const i64 ra = (i64)a.w + pp.aq;
     int cn = 0, cu = 0;
+    bool gab = true;
     if (ra >= 0) {
         const int pn = FILL ? nbr_start[i] : 0, pu = FILL ? up_start[i] : 0;
         const int cx = (a.x - g.ox) / g.s, cy = (a.y - g.oy) / g.s, cz = (a.z - g.oz) / g.s;
@@ -188,14 +216,16 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
                     const int4 b = atom[j];
                     const i64 dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
                     const i64 d2 = dx * dx + dy * dy + dz * dz;
-                    if (d2 > lim) continue;
-                    if (d2 == 0) continue; /* duplicates are reported by k_cell_order */
+                    if (d2 > lim || d2 == 0) continue; /* equal centres are reported by k_cell_order */
                     const i64 rb2 = (i64)b.w + pp.aq;
                     if (rb2 < 0) continue;
                     // grown balls meet: d <= rho_a + rho_b
                     const i64 L = d2 - ra - rb2;
                     if (L > 0 && L * L > 4 * ra * rb2) continue;
-                    if (FILL) nbr[pn + cn] = j;
+                    if (FILL) {
+                        nbr[pn + cn] = j;
+                        if (gab && vertex_violation_sign(a, i, b, j, perm) < 0) gab = false;
+                    }
                     cn++;
                     if (j > i) {
                         const Edge ed = edge_setup(a, b);
@@ -208,6 +238,7 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
             }
     }
     if (!FILL) { deg_n[i] = cn; deg_up[i] = cu; }
+    else vgab[i] = (unsigned char)(ra >= 0 && gab);
 }
 
 // Position of b in the (sorted) upper-edge list of a, i.e. the edge id; -1 if absent.
@@ -240,21 +271,36 @@ __device__ __forceinline__ int find_tri(const int *__restrict__ up_start, const 
 
 // ---------------------------------------------------------------------------
 // Candidate triangles (Sec. 4.3): for an edge (i, j), every k > j adjacent to
-// both by a candidate edge, not collinear, with OrthoSize <= alpha.
+// both by a candidate edge, not collinear, with OrthoSize <= alpha. The count
+// pass also decides AC2 for the edge at its own ortho-centre (violators of any
+// candidate lie in the neighbour list of each of its vertices).
 template <bool FILL>
-__global__ void __launch_bounds__(BLOCK) k_triangles(const int4 *__restrict__ atom, const int *__restrict__ up_start,
-                                                      const int *__restrict__ up, const int *__restrict__ edge_i, int E,
-                                                      PredParams pp, int *__restrict__ tri_cnt,
+__global__ void __launch_bounds__(BLOCK) k_triangles(const int4 *__restrict__ atom, const int *__restrict__ perm,
+                                                      const int *__restrict__ nbr_start, const int *__restrict__ nbr,
+                                                      const int *__restrict__ up_start, const int *__restrict__ up,
+                                                      const int *__restrict__ edge_i, int E, PredParams pp,
+                                                      int *__restrict__ tri_cnt, unsigned char *__restrict__ egab,
                                                       const int *__restrict__ tri_start, int *__restrict__ tri_k,
                                                       int *__restrict__ tri_e, Counters *cnt) {
     const int e = blockIdx.x * BLOCK + threadIdx.x;
     if (e >= E) return;
     const int i = edge_i[e], j = up[e];
+    const int4 vi = atom[i], vj = atom[j];
+    const int ns = nbr_start[i], ne = nbr_start[i + 1];
+    if (!FILL) {
+        const Edge ed = edge_setup(vi, vj);
+        bool gab = true;
+        for (int p = ns; p < ne; p++) {
+            const int q = nbr[p];
+            if (q == j) continue;
+            if (edge_violation_sign(ed, i, j, atom[q], q, perm) < 0) { gab = false; break; }
+        }
+        egab[e] = (unsigned char)gab;
+    }
     int pa = e + 1;
     const int ea = up_start[i + 1];
     int pb = up_start[j];
     const int eb = up_start[j + 1];
-    const int4 vi = atom[i], vj = atom[j];
     int c = 0;
     const int out = FILL ? tri_start[e] : 0;
     while (pa < ea && pb < eb) {
@@ -264,32 +310,51 @@ __global__ void __launch_bounds__(BLOCK) k_triangles(const int4 *__restrict__ at
         pa++; pb++;
         const Tri t = tri_setup(vi, vj, atom[ka], pp);
         if (tri_degenerate(t) || !tri_ac3(t, pp, cnt)) continue;
-        if (FILL) { tri_k[out + c] = ka; tri_e[out + c] = e; }
+        if (FILL) {
+            tri_k[out + c] = ka;
+            tri_e[out + c] = e;
+        }
         c++;
     }
     if (!FILL) tri_cnt[e] = c;
 }
 
-// ---------------------------------------------------------------------------
-// Candidate tetrahedra with AC2 (Steps 1-2): for a triangle (i, j, k), every
-// l > k adjacent to all three by candidate edges (all six edges in
-// Sigma_ortho^1 suffice since OrthoSize grows from face to coface), not flat,
-// with OrthoSize <= alpha; kept iff no ball is strictly closer in power to its
-// ortho-centre. Kept tetrahedra mark their four facets.
-__device__ __forceinline__ void mark_face(int *att, long long *mins, int f, long long key, Counters *cnt) {
-    if (f < 0) { atomicOr(&cnt->lookup, 1); return; }
-    atomicOr(&att[f], 1);
-    atomicMin(&mins[f], key);
+// Triangles: AC2 at their own ortho-centre and OrthoSize (one thread each).
+__global__ void __launch_bounds__(BLOCK) k_tri_gabriel(const int4 *__restrict__ atom, const int *__restrict__ perm,
+                                                        const int *__restrict__ nbr_start, const int *__restrict__ nbr,
+                                                        const int *__restrict__ up, const int *__restrict__ edge_i,
+                                                        const int *__restrict__ tri_k, const int *__restrict__ tri_e,
+                                                        int T, PredParams pp, unsigned char *__restrict__ tgab,
+                                                        double *__restrict__ tsize, Counters *cnt) {
+    const int t = blockIdx.x * BLOCK + threadIdx.x;
+    if (t >= T) return;
+    const int e = tri_e[t];
+    const int i = edge_i[e], j = up[e], k = tri_k[t];
+    const Tri tr = tri_setup(atom[i], atom[j], atom[k], pp);
+    bool gab = true;
+    const int ns = nbr_start[i], ne = nbr_start[i + 1];
+    for (int p = ns; p < ne; p++) {
+        const int q = nbr[p];
+        if (q == j || q == k) continue;
+        if (tri_violation_sign(tr, i, j, k, atom[q], q, perm, pp, cnt) < 0) { gab = false; break; }
+    }
+    tgab[t] = (unsigned char)gab;
+    tsize[t] = tri_orthosize(tr);
 }
 
-__global__ void __launch_bounds__(BLOCK) k_tetrahedra(const int4 *__restrict__ atom, const int *__restrict__ perm,
-                                                       const int *__restrict__ nbr_start, const int *__restrict__ nbr,
-                                                       const int *__restrict__ up_start, const int *__restrict__ up,
-                                                       const int *__restrict__ edge_i, const int *__restrict__ tri_start,
-                                                       const int *__restrict__ tri_k, const int *__restrict__ tri_e,
-                                                       int T, PredParams pp, int *__restrict__ tri_att,
-                                                       long long *__restrict__ tri_min, int4 *__restrict__ k3,
-                                                       double *__restrict__ k3_size, int cap3, Counters *cnt) {
+// ---------------------------------------------------------------------------
+// Candidate tetrahedra (Step 1, d = 3): for a triangle (i, j, k), every l > k
+// adjacent to all three by candidate edges (all six edges in Sigma_ortho^1
+// suffice, since OrthoSize grows from face to coface, Sec. 4.3), not flat,
+// with OrthoSize <= alpha. Count pass, then fill pass into (triangle, l) pairs.
+template <bool FILL>
+__global__ void __launch_bounds__(BLOCK) k_tet_candidates(const int4 *__restrict__ atom,
+                                                           const int *__restrict__ up_start, const int *__restrict__ up,
+                                                           const int *__restrict__ edge_i, const int *__restrict__ tri_k,
+                                                           const int *__restrict__ tri_e, int T, PredParams pp,
+                                                           int *__restrict__ tet_cnt, const int *__restrict__ tet_start,
+                                                           int *__restrict__ tet_t, int *__restrict__ tet_l,
+                                                           Counters *cnt) {
     const int t = blockIdx.x * BLOCK + threadIdx.x;
     if (t >= T) return;
     const int e = tri_e[t];
@@ -300,8 +365,10 @@ __global__ void __launch_bounds__(BLOCK) k_tetrahedra(const int4 *__restrict__ a
     const int eb = up_start[j + 1];
     int pc = up_start[k];
     const int ec = up_start[k + 1];
-    const int4 vi = atom[i], vj = atom[j], vk = atom[k];
-    const int ns = nbr_start[i], ne = nbr_start[i + 1];
+    int c = 0;
+    const int out = FILL ? tet_start[t] : 0;
+    int4 vi = make_int4(0, 0, 0, 0), vj = vi, vk = vi;
+    bool loaded = false;
     while (pa < ea && pb < eb && pc < ec) {
         const int la = up[pa], lb = up[pb], lc = up[pc];
         const int m = max(la, max(lb, lc));
@@ -309,218 +376,245 @@ __global__ void __launch_bounds__(BLOCK) k_tetrahedra(const int4 *__restrict__ a
         if (lb < m) { pb++; continue; }
         if (lc < m) { pc++; continue; }
         pa++; pb++; pc++;
-        const int l = m;
-        const Tet te = tet_setup(vi, vj, vk, atom[l], pp);
+        if (!loaded) { vi = atom[i]; vj = atom[j]; vk = atom[k]; loaded = true; }
+        const Tet te = tet_setup(vi, vj, vk, atom[m], pp);
         if (te.D == 0 || !tet_ac3(te, pp, cnt)) continue;
-        bool keep = true;
-        for (int p = ns; p < ne; p++) {
-            const int q = nbr[p];
-            if (q == j || q == k || q == l) continue;
-            if (tet_violation_sign(te, i, j, k, l, atom[q], q, perm, pp, cnt) < 0) { keep = false; break; }
-        }
-        if (!keep) continue;
-        const double sz = tet_orthosize(te);
-        const int slot = atomicAdd(&cnt->k3, 1);
-        if (slot < cap3) { k3[slot] = make_int4(i, j, k, l); k3_size[slot] = sz; }
-        const long long key = ordered_from_double(sz);
-        mark_face(tri_att, tri_min, t, key, cnt);
-        mark_face(tri_att, tri_min, find_tri(up_start, up, tri_start, tri_k, i, j, l), key, cnt);
-        mark_face(tri_att, tri_min, find_tri(up_start, up, tri_start, tri_k, i, k, l), key, cnt);
-        mark_face(tri_att, tri_min, find_tri(up_start, up, tri_start, tri_k, j, k, l), key, cnt);
+        if (FILL) { tet_t[out + c] = t; tet_l[out + c] = m; }
+        c++;
     }
+    if (!FILL) tet_cnt[t] = c;
+}
+
+// A face that passes AC2 itself is in K with Size = OrthoSize whatever its
+// cofaces do, so only faces failing AC2 record the kept coface.
+__device__ __forceinline__ void mark_face(const unsigned char *gab, int *att, long long *mins, int f, long long key,
+                                          Counters *cnt) {
+    if (f < 0) { atomicOr(&cnt->lookup, 1); return; }
+    if (gab[f]) return;
+    atomicOr(&att[f], 1);
+    atomicMin(&mins[f], key);
+}
+
+// Tetrahedra (Step 2): kept iff no ball is strictly closer in power to the
+// ortho-centre; a kept tetrahedron records itself on its facets (Step 3).
+__global__ void __launch_bounds__(BLOCK) k_tet_ac2(const int4 *__restrict__ atom, const int *__restrict__ perm,
+                                                    const int *__restrict__ nbr_start, const int *__restrict__ nbr,
+                                                    const int *__restrict__ up_start, const int *__restrict__ up,
+                                                    const int *__restrict__ edge_i, const int *__restrict__ tri_start,
+                                                    const int *__restrict__ tri_k, const int *__restrict__ tri_e,
+                                                    const int *__restrict__ tet_t, const int *__restrict__ tet_l, int Q,
+                                                    PredParams pp, const unsigned char *__restrict__ tgab,
+                                                    int *__restrict__ tri_att, long long *__restrict__ tri_min,
+                                                    unsigned char *__restrict__ qin, double *__restrict__ qsize,
+                                                    Counters *cnt) {
+    const int c = blockIdx.x * BLOCK + threadIdx.x;
+    if (c >= Q) return;
+    const int t = tet_t[c], l = tet_l[c];
+    const int e = tri_e[t];
+    const int i = edge_i[e], j = up[e], k = tri_k[t];
+    const Tet te = tet_setup(atom[i], atom[j], atom[k], atom[l], pp);
+    bool keep = true;
+    const int ns = nbr_start[i], ne = nbr_start[i + 1];
+    for (int p = ns; p < ne; p++) {
+        const int q = nbr[p];
+        if (q == j || q == k || q == l) continue;
+        if (tet_violation_sign(te, i, j, k, l, atom[q], q, perm, pp, cnt) < 0) { keep = false; break; }
+    }
+    qin[c] = (unsigned char)keep;
+    if (!keep) return;
+    const double sz = tet_orthosize(te);
+    qsize[c] = sz;
+    const long long key = ordered_from_double(sz);
+    mark_face(tgab, tri_att, tri_min, t, key, cnt);
+    mark_face(tgab, tri_att, tri_min, find_tri(up_start, up, tri_start, tri_k, i, j, l), key, cnt);
+    mark_face(tgab, tri_att, tri_min, find_tri(up_start, up, tri_start, tri_k, i, k, l), key, cnt);
+    mark_face(tgab, tri_att, tri_min, find_tri(up_start, up, tri_start, tri_k, j, k, l), key, cnt);
 }
 
 // Triangles (Step 3): kept iff AC2 holds at the ortho-centre or a kept
-// tetrahedron has it as a facet.
-__global__ void __launch_bounds__(BLOCK) k_tri_final(const int4 *__restrict__ atom, const int *__restrict__ perm,
-                                                      const int *__restrict__ nbr_start, const int *__restrict__ nbr,
-                                                      const int *__restrict__ up_start, const int *__restrict__ up,
+// tetrahedron has it as a facet; Size is then the OrthoSize or the least Size
+// of a kept tetrahedron. Kept triangles record themselves on their edges.
+__global__ void __launch_bounds__(BLOCK) k_tri_final(const int *__restrict__ up_start, const int *__restrict__ up,
                                                       const int *__restrict__ edge_i, const int *__restrict__ tri_k,
-                                                      const int *__restrict__ tri_e, int T, PredParams pp,
-                                                      const int *__restrict__ tri_att,
-                                                      const long long *__restrict__ tri_min, int *__restrict__ edge_att,
-                                                      long long *__restrict__ edge_min, int4 *__restrict__ k2,
-                                                      double *__restrict__ k2_size, Counters *cnt) {
+                                                      const int *__restrict__ tri_e, int T,
+                                                      const unsigned char *__restrict__ tgab,
+                                                      double *__restrict__ tsize, const int *__restrict__ tri_att,
+                                                      const long long *__restrict__ tri_min,
+                                                      unsigned char *__restrict__ tin,
+                                                      const unsigned char *__restrict__ egab, int *__restrict__ edge_att,
+                                                      long long *__restrict__ edge_min, Counters *cnt) {
     const int t = blockIdx.x * BLOCK + threadIdx.x;
-    const bool valid = t < T;
-    bool in = false;
-    int i = 0, j = 0, k = 0, e = 0;
-    double sz = 0.0;
-    if (valid) {
-        e = tri_e[t];
-        i = edge_i[e]; j = up[e]; k = tri_k[t];
-        const Tri tr = tri_setup(atom[i], atom[j], atom[k], pp);
-        bool gab = true;
-        const int ns = nbr_start[i], ne = nbr_start[i + 1];
-        for (int p = ns; p < ne; p++) {
-            const int q = nbr[p];
-            if (q == j || q == k) continue;
-            if (tri_violation_sign(tr, i, j, k, atom[q], q, perm, pp, cnt) < 0) { gab = false; break; }
-        }
-        in = gab || tri_att[t];
-        sz = gab ? tri_orthosize(tr) : double_from_ordered(tri_min[t]);
+    if (t >= T) return;
+    const bool gab = tgab[t];
+    const bool in = gab || tri_att[t];
+    tin[t] = (unsigned char)in;
+    if (!in) return;
+    double sz = tsize[t];
+    if (!gab) {
+        sz = double_from_ordered(tri_min[t]);
+        tsize[t] = sz;
     }
-    const int slot = wave_append(&cnt->k2, in);
-    if (in) {
-        k2[slot] = make_int4(i, j, k, 0);
-        k2_size[slot] = sz;
-        const long long key = ordered_from_double(sz);
-        mark_face(edge_att, edge_min, e, key, cnt);
-        mark_face(edge_att, edge_min, find_edge(up_start, up, i, k), key, cnt);
-        mark_face(edge_att, edge_min, find_edge(up_start, up, j, k), key, cnt);
-    }
+    const int e = tri_e[t];
+    const int i = edge_i[e], j = up[e], k = tri_k[t];
+    const long long key = ordered_from_double(sz);
+    mark_face(egab, edge_att, edge_min, e, key, cnt);
+    mark_face(egab, edge_att, edge_min, find_edge(up_start, up, i, k), key, cnt);
+    mark_face(egab, edge_att, edge_min, find_edge(up_start, up, j, k), key, cnt);
 }
 
 // Edges (Step 4).
-__global__ void __launch_bounds__(BLOCK) k_edge_final(const int4 *__restrict__ atom, const int *__restrict__ perm,
-                                                       const int *__restrict__ nbr_start, const int *__restrict__ nbr,
-                                                       const int *__restrict__ up, const int *__restrict__ edge_i, int E,
+__global__ void __launch_bounds__(BLOCK) k_edge_final(const int4 *__restrict__ atom, const int *__restrict__ up,
+                                                       const int *__restrict__ edge_i, int E,
+                                                       const unsigned char *__restrict__ egab,
                                                        const int *__restrict__ edge_att,
                                                        const long long *__restrict__ edge_min,
-                                                       int *__restrict__ vert_att, long long *__restrict__ vert_min,
-                                                       int2 *__restrict__ k1, double *__restrict__ k1_size,
-                                                       Counters *cnt) {
+                                                       unsigned char *__restrict__ ein, double *__restrict__ esize,
+                                                       const unsigned char *__restrict__ vgab,
+                                                       int *__restrict__ vert_att, long long *__restrict__ vert_min) {
     const int e = blockIdx.x * BLOCK + threadIdx.x;
-    const bool valid = e < E;
-    bool in = false;
-    int i = 0, j = 0;
-    double sz = 0.0;
-    if (valid) {
-        i = edge_i[e]; j = up[e];
-        const Edge ed = edge_setup(atom[i], atom[j]);
-        bool gab = true;
-        const int ns = nbr_start[i], ne = nbr_start[i + 1];
-        for (int p = ns; p < ne; p++) {
-            const int q = nbr[p];
-            if (q == j) continue;
-            if (edge_violation_sign(ed, i, j, atom[q], q, perm) < 0) { gab = false; break; }
-        }
-        in = gab || edge_att[e];
-        sz = gab ? edge_orthosize(ed) : double_from_ordered(edge_min[e]);
-    }
-    const int slot = wave_append(&cnt->k1, in);
-    if (in) {
-        k1[slot] = make_int2(i, j);
-        k1_size[slot] = sz;
-        const long long key = ordered_from_double(sz);
-        atomicOr(&vert_att[i], 1); atomicMin(&vert_min[i], key);
-        atomicOr(&vert_att[j], 1); atomicMin(&vert_min[j], key);
-    }
+    if (e >= E) return;
+    const bool gab = egab[e];
+    const bool in = gab || edge_att[e];
+    ein[e] = (unsigned char)in;
+    if (!in) return;
+    const int i = edge_i[e], j = up[e];
+    const double sz = gab ? edge_orthosize(edge_setup(atom[i], atom[j])) : double_from_ordered(edge_min[e]);
+    esize[e] = sz;
+    const long long key = ordered_from_double(sz);
+    if (!vgab[i]) { atomicOr(&vert_att[i], 1); atomicMin(&vert_min[i], key); }
+    if (!vgab[j]) { atomicOr(&vert_att[j], 1); atomicMin(&vert_min[j], key); }
 }
 
 // Vertices (Step 5): a ball with -W <= alpha is kept iff no ball is strictly
-// closer in power to its own centre, or it ends a kept edge.
-__global__ void __launch_bounds__(BLOCK) k_vert_final(const int4 *__restrict__ atom, const int *__restrict__ perm,
-                                                       const int *__restrict__ nbr_start, const int *__restrict__ nbr,
-                                                       int n, PredParams pp, int shortcut,
+// closer in power to its own centre (decided in k_neighbours), or it ends a
+// kept edge. With `shortcut`, every such ball is kept with Size -W (the
+// paper's implementation shortcut). Results are scattered to input order.
+__global__ void __launch_bounds__(BLOCK) k_vert_final(const int4 *__restrict__ atom, const int *__restrict__ perm, int n,
+                                                       PredParams pp, int shortcut,
+                                                       const unsigned char *__restrict__ vgab,
                                                        const int *__restrict__ vert_att,
-                                                       const long long *__restrict__ vert_min, int *__restrict__ k0,
-                                                       double *__restrict__ k0_size, Counters *cnt) {
+                                                       const long long *__restrict__ vert_min,
+                                                       int *__restrict__ vin_in, double *__restrict__ vsize_in) {
     const int v = blockIdx.x * BLOCK + threadIdx.x;
+    if (v >= n) return;
+    const int w = atom[v].w;
     bool in = false;
     double sz = 0.0;
-    if (v < n) {
-        const int4 a = atom[v];
-        if ((i64)a.w + pp.aq >= 0) {
-            bool gab = true;
-            if (!shortcut) {
-                const int ns = nbr_start[v], ne = nbr_start[v + 1];
-                for (int p = ns; p < ne; p++) {
-                    const int q = nbr[p];
-                    if (vertex_violation_sign(a, v, atom[q], q, perm) < 0) { gab = false; break; }
-                }
-            }
-            in = gab || vert_att[v];
-            sz = gab ? -(double)a.w : double_from_ordered(vert_min[v]);
-        }
+    if ((i64)w + pp.aq >= 0) {
+        const bool gab = shortcut || vgab[v];
+        in = gab || vert_att[v];
+        sz = gab ? -(double)w : double_from_ordered(vert_min[v]);
     }
-    const int slot = wave_append(&cnt->k0, in);
-    if (in) { k0[slot] = v; k0_size[slot] = sz; }
+    const int u = perm[v];
+    vin_in[u] = in ? 1 : 0;
+    vsize_in[u] = sz;
+}
+
+__global__ void __launch_bounds__(BLOCK) k_vert_emit(const int *__restrict__ vin_in, const int *__restrict__ vpos,
+                                                      const double *__restrict__ vsize_in, int n, int *__restrict__ out,
+                                                      double *__restrict__ out_size) {
+    const int u = blockIdx.x * BLOCK + threadIdx.x;
+    if (u >= n || !vin_in[u]) return;
+    const int p = vpos[u];
+    out[p] = u;
+    out_size[p] = vsize_in[u] / 1.0e6;  // mA^2 -> A^2
 }
 
 // ---------------------------------------------------------------------------
 // Emit: rows of sorted-order indices -> rows of input ids sorted ascending,
 // rows in lexicographic order. Bucket by the first id (counting sort), then
 // insertion-sort each (short) bucket.
+// Row of candidate c (sorted-order indices) for d = 1, 2, 3.
 template <int K>
-__device__ __forceinline__ void load_row(const int *rows, int r, int (&v)[4]) {
-    if (K == 1) { v[0] = rows[r]; v[1] = v[2] = v[3] = 0; }
-    else if (K == 2) { const int2 t = reinterpret_cast<const int2 *>(rows)[r]; v[0] = t.x; v[1] = t.y; v[2] = v[3] = 0; }
-    else { const int4 t = reinterpret_cast<const int4 *>(rows)[r]; v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = K == 4 ? t.w : 0; }
+__device__ __forceinline__ void candidate_row(int c, const int *__restrict__ up, const int *__restrict__ edge_i,
+                                              const int *__restrict__ tri_k, const int *__restrict__ tri_e,
+                                              const int *__restrict__ tet_t, const int *__restrict__ tet_l,
+                                              int (&v)[4]) {
+    v[3] = 0;
+    if (K == 2) {
+        v[0] = edge_i[c]; v[1] = up[c]; v[2] = 0;
+    } else if (K == 3) {
+        const int e = tri_e[c];
+        v[0] = edge_i[e]; v[1] = up[e]; v[2] = tri_k[c];
+    } else {
+        const int t = tet_t[c];
+        const int e = tri_e[t];
+        v[0] = edge_i[e]; v[1] = up[e]; v[2] = tri_k[t]; v[3] = tet_l[c];
+    }
 }
 
+template <int K> struct EmitPay;
+template <> struct EmitPay<2> { typedef uint2 type; };
+template <> struct EmitPay<3> { typedef uint3 type; };
+template <> struct EmitPay<4> { typedef uint4 type; };
+
+// Kept candidates -> (least input id, rest of the row + candidate index),
+// compacted by the flag scan `fpos`.
 template <int K>
-__global__ void __launch_bounds__(BLOCK) k_emit_remap(const int *__restrict__ rows, const int *__restrict__ perm, int m,
-                                                       int4 *__restrict__ tmp, int *__restrict__ bucket_cnt) {
-    const int r = blockIdx.x * BLOCK + threadIdx.x;
-    if (r >= m) return;
+__global__ void __launch_bounds__(BLOCK) k_emit_keys(const unsigned char *__restrict__ in,
+                                                      const int *__restrict__ fpos, int M,
+                                                      const int *__restrict__ up, const int *__restrict__ edge_i,
+                                                      const int *__restrict__ tri_k, const int *__restrict__ tri_e,
+                                                      const int *__restrict__ tet_t, const int *__restrict__ tet_l,
+                                                      const int *__restrict__ perm, unsigned *__restrict__ key,
+                                                      typename EmitPay<K>::type *__restrict__ pay) {
+    const int c = blockIdx.x * BLOCK + threadIdx.x;
+    if (c >= M || !in[c]) return;
     int v[4];
-    load_row<K>(rows, r, v);
+    candidate_row<K>(c, up, edge_i, tri_k, tri_e, tet_t, tet_l, v);
 #pragma unroll
     for (int u = 0; u < K; u++) v[u] = perm[v[u]];
 #pragma unroll
     for (int a = 1; a < K; a++)
 #pragma unroll
         for (int b = a; b > 0; b--)
-            if (v[b - 1] > v[b]) { const int s = v[b]; v[b] = v[b - 1]; v[b - 1] = s; }
-    tmp[r] = make_int4(v[0], v[1], v[2], v[3]);
-    atomicAdd(&bucket_cnt[v[0]], 1);
-}
-
-__global__ void __launch_bounds__(BLOCK) k_emit_scatter(const int4 *__restrict__ tmp, const double *__restrict__ size_in,
-                                                         int m, int *__restrict__ cursor, int4 *__restrict__ rows2,
-                                                         double *__restrict__ size2) {
-    const int r = blockIdx.x * BLOCK + threadIdx.x;
-    if (r >= m) return;
-    const int4 v = tmp[r];
-    const int pos = atomicAdd(&cursor[v.x], 1);
-    rows2[pos] = v;
-    size2[pos] = size_in[r];
-}
-
-__device__ __forceinline__ bool row_less(const int4 &a, const int4 &b) {
-    if (a.y != b.y) return a.y < b.y;
-    if (a.z != b.z) return a.z < b.z;
-    return a.w < b.w;
+            if (v[b - 1] > v[b]) { const int t = v[b]; v[b] = v[b - 1]; v[b - 1] = t; }
+    const int p = fpos[c];
+    key[p] = (unsigned)v[0];
+    typename EmitPay<K>::type q;
+    if constexpr (K == 2) q = make_uint2((unsigned)v[1], (unsigned)c);
+    else if constexpr (K == 3) q = make_uint3((unsigned)v[1], (unsigned)v[2], (unsigned)c);
+    else q = make_uint4((unsigned)v[1], (unsigned)v[2], (unsigned)v[3], (unsigned)c);
+    pay[p] = q;
 }
 
 template <int K>
-__global__ void __launch_bounds__(BLOCK) k_emit_sort(const int4 *__restrict__ rows2, const double *__restrict__ size2,
-                                                      const int *__restrict__ bstart, int nb, int *__restrict__ out,
+__device__ __forceinline__ void pay_row(const typename EmitPay<K>::type &q, unsigned (&r)[3], unsigned &c) {
+    if constexpr (K == 2) { r[0] = q.x; r[1] = 0; r[2] = 0; c = q.y; }
+    else if constexpr (K == 3) { r[0] = q.x; r[1] = q.y; r[2] = 0; c = q.z; }
+    else { r[0] = q.x; r[1] = q.y; r[2] = q.z; c = q.w; }
+}
+
+// After the sort by least id, each row finds its bucket (equal keys are
+// adjacent; buckets are short) and its rank in the bucket by the remaining
+// ids, and writes itself to the final place.
+template <int K>
+__global__ void __launch_bounds__(BLOCK) k_emit_rank(const unsigned *__restrict__ key,
+                                                      const typename EmitPay<K>::type *__restrict__ pay, int m,
+                                                      const double *__restrict__ size_in, int *__restrict__ out,
                                                       double *__restrict__ out_size) {
-    const int b = blockIdx.x * BLOCK + threadIdx.x;
-    if (b >= nb) return;
-    const int s = bstart[b], e = bstart[b + 1];
-    constexpr int LOCAL = 32;
-    if (e - s <= LOCAL) {
-        int4 r[LOCAL];
-        double z[LOCAL];
-        const int m = e - s;
-        for (int u = 0; u < m; u++) {
-            int4 x = rows2[s + u];
-            double y = size2[s + u];
-            int w = u;
-            while (w > 0 && row_less(x, r[w - 1])) { r[w] = r[w - 1]; z[w] = z[w - 1]; w--; }
-            r[w] = x; z[w] = y;
-        }
-        for (int u = 0; u < m; u++) {
-            const int v[4] = {r[u].x, r[u].y, r[u].z, r[u].w};
-#pragma unroll
-            for (int c = 0; c < K; c++) out[(long long)(s + u) * K + c] = v[c];
-            out_size[s + u] = z[u] / 1.0e6;  // mA^2 -> A^2
-        }
-    } else {
-        // long bucket (only on very dense inputs): selection by rank, O(m^2)
-        for (int u = s; u < e; u++) {
-            const int4 x = rows2[u];
-            int rank = 0;
-            for (int w = s; w < e; w++) rank += row_less(rows2[w], x);
-            const int v[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-            for (int c = 0; c < K; c++) out[(long long)(s + rank) * K + c] = v[c];
-            out_size[s + rank] = size2[u] / 1.0e6;
-        }
+    const int p = blockIdx.x * BLOCK + threadIdx.x;
+    if (p >= m) return;
+    const unsigned u0 = key[p];
+    unsigned r[3], c;
+    pay_row<K>(pay[p], r, c);
+    int s = p;
+    while (s > 0 && key[s - 1] == u0) s--;
+    int e = p + 1;
+    while (e < m && key[e] == u0) e++;
+    int rank = 0;
+    for (int w = s; w < e; w++) {
+        if (w == p) continue;
+        unsigned o[3], oc;
+        pay_row<K>(pay[w], o, oc);
+        const bool less = o[0] != r[0] ? o[0] < r[0] : (o[1] != r[1] ? o[1] < r[1] : o[2] < r[2]);
+        rank += less;
     }
+    const long long q = (long long)(s + rank) * K;
+    out[q] = (int)u0;
+#pragma unroll
+    for (int u = 1; u < K; u++) out[q + u] = (int)r[u - 1];
+    out_size[s + rank] = size_in[c] / 1.0e6;  // mA^2 -> A^2
 }
 
 }  // namespace acx
