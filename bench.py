@@ -33,6 +33,8 @@ def main():
     ap.add_argument("--alpha", type=float, default=0.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=600_000, help="atoms of the oracle's sample")
+    ap.add_argument("--cache-dir", default=os.environ.get("ALPHACX_INPUT_CACHE", ""),
+                    help="keep the generated input here between runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU design is described "
@@ -46,7 +48,7 @@ def main():
     import paper_1908_05944_amd as acx
 
     t0 = time.time()
-    mol = synth.config_shell_3m()
+    mol = synth.config_shell_3m(args.cache_dir or None)
     log(f"[bench] generated {mol.n} atoms in {time.time() - t0:.1f} s")
     dev = torch.device("cuda:0")
     xyz = torch.from_numpy(mol.xyz).to(dev)

@@ -163,23 +163,25 @@ static void fill(T *p, T v, long long n, hipStream_t s) {
     LAUNCH_CHECK();
 }
 
-// out[0..n] = exclusive scan of in[0..n), out[n] = total.
+// out[0..n] = exclusive scan of in[0..n), out[n] = total. One launch up to
+// SCAN_SMALL items, three above (tile scan, scan of tile sums, add).
 static void scan_i32(const int *in, int *out, long long n, hipStream_t s, Scope &sc) {
     if (n <= 0) {
         fill<int>(out, 0, 1, s);
         return;
     }
+    if (n <= SCAN_SMALL) {
+        k_scan_small<<<1, SCAN_BLOCK, 0, s>>>(in, out, (int)n);
+        LAUNCH_CHECK();
+        return;
+    }
     const long long tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
     int *sums = sc.get<int>(tiles);
+    int *offs = sc.get<int>(tiles + 1);
     k_scan_tiles<<<(unsigned)tiles, SCAN_BLOCK, 0, s>>>(in, out, sums, n);
     LAUNCH_CHECK();
-    if (tiles > 1) {
-        int *offs = sc.get<int>(tiles + 1);
-        scan_i32(sums, offs, tiles, s, sc);
-        k_scan_add<<<(unsigned)tiles, SCAN_BLOCK, 0, s>>>(out, offs, n);
-        LAUNCH_CHECK();
-    }
-    k_scan_total<<<1, 1, 0, s>>>(out, in, n);
+    scan_i32(sums, offs, tiles, s, sc);
+    k_scan_add_total<<<(unsigned)tiles, SCAN_BLOCK, 0, s>>>(out, offs, n, (int)tiles);
     LAUNCH_CHECK();
 }
 
@@ -368,6 +370,7 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         pp.aq = aq;
         pp.sg2 = sg2 < 0 ? 0 : sg2;
         const long long sgc = isqrt_ceil(pp.sg2);
+        pp.sgc = sgc;
         pp.bmax = 2.0 * (double)sgc;
         pp.gmax = 4.0 * (double)pp.sg2 + (double)hs.wmax;
         pp.force_exact = o.force_exact;
@@ -388,45 +391,47 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
 
         // ---- binning ----
         tm.mark(ST_BIN);
-        long long *key = sc.get<long long>(n);
+        unsigned *ckey = sc.get<unsigned>(n);
+        unsigned *cidx = sc.get<unsigned>(n);
         int *cell_count = sc.get<int>(ncell + 1);
         int *cell_start = sc.get<int>(ncell + 1);
-        fill<int>(cell_count, 0, ncell + 1, s);
-        k_cell_hist<<<grid_for(n), BLOCK, 0, s>>>(q, n, g, key, cell_count);
+        k_cell_key<<<grid_for(n), BLOCK, 0, s>>>(q, n, g, ckey, cidx);
+        LAUNCH_CHECK();
+        radix_sort<unsigned>(ckey, cidx, n, bits_for(ncell), s, sc);
+        fill<int>(cell_count, 0, ncell, s);
+        k_cell_runs<<<grid_for(n), BLOCK, 0, s>>>(ckey, n, cell_count);
         LAUNCH_CHECK();
         scan_i32(cell_count, cell_start, ncell, s, sc);
-        HIP_TRY(hipMemcpyAsync(cell_count, cell_start, sizeof(int) * ncell, hipMemcpyDeviceToDevice, s));
-        int4 *tmp_atom = sc.get<int4>(n);
-        int *tmp_perm = sc.get<int>(n);
-        k_scatter<<<grid_for(n), BLOCK, 0, s>>>(q, key, n, cell_count, tmp_atom, tmp_perm);
-        LAUNCH_CHECK();
         int4 *atom = sc.get<int4>(n);
         int *perm = sc.get<int>(n);
-        k_cell_order<<<grid_for(n), BLOCK, 0, s>>>(tmp_atom, tmp_perm, n, g, cell_start, atom, perm, cnt);
+        k_gather_atoms<<<grid_for(n), BLOCK, 0, s>>>(q, ckey, cidx, n, atom, perm, cnt);
         LAUNCH_CHECK();
 
-        // ---- neighbours and candidate edges ----
+        // ---- neighbours and candidate edges: count, scan, fill ----
         int *deg_n = sc.get<int>(n), *deg_up = sc.get<int>(n);
         int *nbr_start = sc.get<int>(n + 1), *up_start = sc.get<int>(n + 1);
         unsigned char *vgab = sc.get<unsigned char>(n);
         tm.mark(ST_NBR_COUNT);
-        k_neighbours<false><<<grid_for(n), BLOCK, 0, s>>>(atom, perm, n, g, cell_start, pp, deg_n, deg_up, nullptr,
-                                                         nullptr, nullptr, nullptr, nullptr, nullptr);
+        k_neighbours<NB_COUNT><<<grid_for(n), BLOCK, 0, s>>>(atom, perm, n, g, cell_start, pp, deg_n, deg_up, nullptr,
+                                                            nullptr, nullptr, nullptr, nullptr, nullptr);
         LAUNCH_CHECK();
         tm.mark(ST_NBR_SCAN);
         scan_i32(deg_n, nbr_start, n, s, sc);
         scan_i32(deg_up, up_start, n, s, sc);
+        k_copy_int<<<1, 1, 0, s>>>(&cnt->Nn, nbr_start + n);
+        k_copy_int<<<1, 1, 0, s>>>(&cnt->E, up_start + n);
+        LAUNCH_CHECK();
         const Counters c0 = read_one(cnt, s);
         if (c0.dup) throw HipError{AC_E_DUPLICATE, "two balls have equal quantised centres"};
-        const int Nn = read_one(nbr_start + n, s);
-        const int E = read_one(up_start + n, s);
+        const int E = c0.E, Nn = c0.Nn;
         int *nbr = sc.get<int>(Nn > 0 ? Nn : 1);
         int *up = sc.get<int>(E > 0 ? E : 1);
         int *edge_i = sc.get<int>(E > 0 ? E : 1);
         tm.mark(ST_NBR_FILL);
-        k_neighbours<true><<<grid_for(n), BLOCK, 0, s>>>(atom, perm, n, g, cell_start, pp, nullptr, nullptr, nbr_start,
-                                                        up_start, nbr, up, edge_i, vgab);
+        k_neighbours<NB_FILL><<<grid_for(n), BLOCK, 0, s>>>(atom, perm, n, g, cell_start, pp, nullptr, nullptr,
+                                                           nbr_start, up_start, nbr, up, edge_i, vgab);
         LAUNCH_CHECK();
+        const int *nbr_cnt = deg_n;
 
         // ---- candidate triangles (with AC2 of the edges) ----
         int *tri_cnt = sc.get<int>(E > 0 ? E : 1);
@@ -434,13 +439,15 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         unsigned char *egab = sc.get<unsigned char>(E > 0 ? E : 1);
         tm.mark(ST_TRI_COUNT);
         if (E > 0) {
-            k_triangles<false><<<grid_for(E), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr, up_start, up, edge_i, E, pp,
+            k_triangles<false><<<grid_for(E), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i, E, pp,
                                                             tri_cnt, egab, nullptr, nullptr, nullptr, cnt);
             LAUNCH_CHECK();
         }
         tm.mark(ST_TRI_SCAN);
         scan_i32(tri_cnt, tri_start, E, s, sc);
-        const int T = read_one(tri_start + E, s);
+        k_copy_int<<<1, 1, 0, s>>>(&cnt->T, tri_start + E);
+        LAUNCH_CHECK();
+        const int T = read_one(cnt, s).T;
         int *tri_k = sc.get<int>(T > 0 ? T : 1);
         int *tri_e = sc.get<int>(T > 0 ? T : 1);
         unsigned char *tgab = sc.get<unsigned char>(T > 0 ? T : 1);
@@ -449,14 +456,14 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         int *tet_start = sc.get<int>(T + 1);
         tm.mark(ST_TRI_FILL);
         if (T > 0) {
-            k_triangles<true><<<grid_for(E), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr, up_start, up, edge_i, E, pp,
+            k_triangles<true><<<grid_for(E), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i, E, pp,
                                                            nullptr, nullptr, tri_start, tri_k, tri_e, cnt);
             LAUNCH_CHECK();
         }
         // ---- AC2 of triangles; candidate tetrahedra ----
         tm.mark(ST_TRI_GABRIEL);
         if (T > 0) {
-            k_tri_gabriel<<<grid_for(T), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr, up, edge_i, tri_k, tri_e, T, pp,
+            k_tri_gabriel<<<grid_for(T), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up, edge_i, tri_k, tri_e, T, pp,
                                                        tgab, tsize, cnt);
             LAUNCH_CHECK();
         }
@@ -467,7 +474,9 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             LAUNCH_CHECK();
         }
         scan_i32(tet_cnt, tet_start, T, s, sc);
-        const int Q = read_one(tet_start + T, s);
+        k_copy_int<<<1, 1, 0, s>>>(&cnt->Q, tet_start + T);
+        LAUNCH_CHECK();
+        const int Q = read_one(cnt, s).Q;
         int *tet_t = sc.get<int>(Q > 0 ? Q : 1);
         int *tet_l = sc.get<int>(Q > 0 ? Q : 1);
         unsigned char *qin = sc.get<unsigned char>(Q > 0 ? Q : 1);
@@ -499,7 +508,7 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         fill<long long>(vert_min, ORDERED_POS_INF, n, s);
         tm.mark(ST_TETRA);
         if (Q > 0) {
-            k_tet_ac2<<<grid_for(Q), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr, up_start, up, edge_i, tri_start, tri_k,
+            k_tet_ac2<<<grid_for(Q), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i, tri_start, tri_k,
                                                    tri_e, tet_t, tet_l, Q, pp, tgab, tri_att, tri_min, qin, qsize, cnt);
             LAUNCH_CHECK();
         }
@@ -528,11 +537,13 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         scan_flags(ein, E, epos, s, sc);
         scan_flags(tin, T, tpos, s, sc);
         scan_flags(qin, Q, qpos, s, sc);
-        const int m1 = read_one(epos + E, s);
-        const int m2 = read_one(tpos + T, s);
-        const int m3 = read_one(qpos + Q, s);
-        const int m0 = read_one(vpos + n, s);
+        k_copy_int<<<1, 1, 0, s>>>(&cnt->m1, epos + E);
+        k_copy_int<<<1, 1, 0, s>>>(&cnt->m2, tpos + T);
+        k_copy_int<<<1, 1, 0, s>>>(&cnt->m3, qpos + Q);
+        k_copy_int<<<1, 1, 0, s>>>(&cnt->m0, vpos + n);
+        LAUNCH_CHECK();
         const Counters cf = read_one(cnt, s);
+        const int m0 = cf.m0, m1 = cf.m1, m2 = cf.m2, m3 = cf.m3;
         if (cf.lookup) throw HipError{AC_E_DEVICE, "internal error: a facet of a kept simplex is not a candidate"};
         res->cand[0] = n;
         res->cand[1] = E;

@@ -22,6 +22,18 @@ constexpr long long ORDERED_POS_INF = 0x7ff0000000000000LL;  // +inf encoded
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
+// MI355X dispatches consecutive workgroups round-robin over its 8 XCDs, each
+// with its own L2. Renumbering the blocks so that every XCD runs one
+// contiguous range of the grid keeps spatially neighbouring work (and the
+// data it shares) in one L2. A bijection on [0, gridDim.x).
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int xcd_block() {
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int q = nb / NUM_XCD, r = nb % NUM_XCD;
+    const int x = b % NUM_XCD, k = b / NUM_XCD;
+    return x * q + min(x, r) + k;
+}
+
 // Inclusive prefix sum over the 64 lanes of a wave.
 __device__ __forceinline__ int wave_inclusive_scan(int v) {
     const int lane = lane_id();
@@ -87,19 +99,45 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_tiles(const int *__restrict
     }
 }
 
-__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_add(int *__restrict__ out, const int *__restrict__ tile_off,
-                                                          long long n) {
+// Single-block exclusive scan for n <= SCAN_SMALL: out[0..n], out[n] = total.
+constexpr int SCAN_SMALL_IPT = 64;
+constexpr int SCAN_SMALL = SCAN_BLOCK * SCAN_SMALL_IPT;
+
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_small(const int *__restrict__ in, int *__restrict__ out, int n) {
+    __shared__ int wsum[SCAN_BLOCK / WAVE];
+    const int base = threadIdx.x * SCAN_SMALL_IPT;
+    int s = 0;
+    for (int k = 0; k < SCAN_SMALL_IPT; k++) {
+        const int i = base + k;
+        s += i < n ? in[i] : 0;
+    }
+    const int incl = wave_inclusive_scan(s);
+    const int w = threadIdx.x / WAVE;
+    if (lane_id() == WAVE - 1) wsum[w] = incl;
+    __syncthreads();
+    int run = incl - s;
+    for (int k = 0; k < w; k++) run += wsum[k];
+    for (int k = 0; k < SCAN_SMALL_IPT; k++) {
+        const int i = base + k;
+        if (i < n) {
+            const int v = in[i];
+            out[i] = run;
+            run += v;
+        }
+    }
+    if (threadIdx.x == SCAN_BLOCK - 1) out[n] = run;
+}
+
+// Adds tile offsets; block 0 also writes out[n] = total.
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_add_total(int *__restrict__ out, const int *__restrict__ tile_off,
+                                                                long long n, int tiles) {
     const long long base = (long long)blockIdx.x * SCAN_TILE;
     const int add = tile_off[blockIdx.x];
     for (int k = threadIdx.x; k < SCAN_TILE; k += SCAN_BLOCK) {
         const long long i = base + k;
         if (i < n) out[i] += add;
     }
-}
-
-__global__ void k_scan_total(int *__restrict__ out, const int *__restrict__ in, long long n) {
-    // single thread: total = out[n-1] + in[n-1]
-    if (threadIdx.x == 0 && blockIdx.x == 0) out[n] = n > 0 ? out[n - 1] + in[n - 1] : 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = tile_off[tiles];
 }
 
 }  // namespace acx

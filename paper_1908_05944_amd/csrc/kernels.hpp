@@ -29,6 +29,8 @@ struct Stats {
     int wmax, flags;  // flags: 1 invalid value, 2 out of range
 };
 
+// Uniform grid (Sec. 4.2), cells numbered in row-major order (x fastest), so
+// the cells of one grid row are contiguous in the sorted order.
 struct Grid {
     int ox, oy, oz;   // low corner (mA)
     int s;            // cell side (mA)
@@ -130,55 +132,57 @@ __global__ void __launch_bounds__(BLOCK) k_fill(T *__restrict__ p, T v, long lon
 }
 
 // ---------------------------------------------------------------------------
-// Binning (Sec. 4.2): cell key, histogram, scatter, then a deterministic order
-// inside each cell (by input index).
-__device__ __forceinline__ long long cell_of(const Grid &g, int x, int y, int z) {
-    const int cx = (x - g.ox) / g.s, cy = (y - g.oy) / g.s, cz = (z - g.oz) / g.s;
+// Binning (Sec. 4.2): cell key per ball, a stable radix sort by key (inside a
+// cell the balls keep input order), then the dense cell table.
+__device__ __forceinline__ long long cell_id(const Grid &g, int cx, int cy, int cz) {
     return ((long long)cz * g.ny + cy) * g.nx + cx;
 }
 
-__global__ void __launch_bounds__(BLOCK) k_cell_hist(const int4 *__restrict__ q, int n, Grid g,
-                                                      long long *__restrict__ key, int *__restrict__ cell_count) {
+__device__ __forceinline__ long long cell_of(const Grid &g, int x, int y, int z) {
+    return cell_id(g, (x - g.ox) / g.s, (y - g.oy) / g.s, (z - g.oz) / g.s);
+}
+
+__global__ void __launch_bounds__(BLOCK) k_cell_key(const int4 *__restrict__ q, int n, Grid g,
+                                                     unsigned *__restrict__ key, unsigned *__restrict__ idx) {
     const int i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
     const int4 a = q[i];
-    const long long c = cell_of(g, a.x, a.y, a.z);
-    key[i] = c;
-    atomicAdd(&cell_count[c], 1);
+    key[i] = (unsigned)cell_of(g, a.x, a.y, a.z);
+    idx[i] = (unsigned)i;
 }
 
-__global__ void __launch_bounds__(BLOCK) k_scatter(const int4 *__restrict__ q, const long long *__restrict__ key, int n,
-                                                    int *__restrict__ cursor, int4 *__restrict__ tmp_atom,
-                                                    int *__restrict__ tmp_perm) {
-    const int i = blockIdx.x * BLOCK + threadIdx.x;
-    if (i >= n) return;
-    const int pos = atomicAdd(&cursor[key[i]], 1);
-    tmp_atom[pos] = q[i];
-    tmp_perm[pos] = i;
-}
-
-// Also flags duplicate centres (equal centres share a cell).
-__global__ void __launch_bounds__(BLOCK) k_cell_order(const int4 *__restrict__ tmp_atom, const int *__restrict__ tmp_perm,
-                                                       int n, Grid g, const int *__restrict__ cell_start,
-                                                       int4 *__restrict__ atom, int *__restrict__ perm, Counters *cnt) {
+// After the stable sort by cell: the first ball of each cell writes the
+// cell's population (cells are short runs of equal keys).
+__global__ void __launch_bounds__(BLOCK) k_cell_runs(const unsigned *__restrict__ key, int n,
+                                                      int *__restrict__ cell_count) {
     const int p = blockIdx.x * BLOCK + threadIdx.x;
     if (p >= n) return;
-    const int4 a = tmp_atom[p];
-    const int me = tmp_perm[p];
-    const long long c = cell_of(g, a.x, a.y, a.z);
-    const int s = cell_start[c], e = cell_start[c + 1];
-    int rank = 0;
+    const unsigned c = key[p];
+    if (p > 0 && key[p - 1] == c) return;
+    int e = p + 1;
+    while (e < n && key[e] == c) e++;
+    cell_count[c] = e - p;
+}
+
+// Sorted balls and their input indices; equal centres (which share a cell)
+// are reported.
+__global__ void __launch_bounds__(BLOCK) k_gather_atoms(const int4 *__restrict__ q, const unsigned *__restrict__ key,
+                                                         const unsigned *__restrict__ idx, int n,
+                                                         int4 *__restrict__ atom, int *__restrict__ perm,
+                                                         Counters *cnt) {
+    const int p = blockIdx.x * BLOCK + threadIdx.x;
+    if (p >= n) return;
+    const int me = (int)idx[p];
+    const int4 a = q[me];
+    atom[p] = a;
+    perm[p] = me;
+    const unsigned c = key[p];
     bool dup = false;
-    for (int k = s; k < e; k++) {
-        rank += tmp_perm[k] < me;
-        if (k != p) {
-            const int4 b = tmp_atom[k];
-            dup |= b.x == a.x && b.y == a.y && b.z == a.z;
-        }
+    for (int k = p + 1; k < n && key[k] == c; k++) {
+        const int4 b = q[idx[k]];
+        dup |= b.x == a.x && b.y == a.y && b.z == a.z;
     }
     if (dup) atomicOr(&cnt->dup, 1);
-    atom[s + rank] = a;
-    perm[s + rank] = me;
 }
 
 // ---------------------------------------------------------------------------
@@ -187,41 +191,58 @@ __global__ void __launch_bounds__(BLOCK) k_cell_order(const int4 *__restrict__ t
 // in the sorted order, so each (dz, dy) row is one contiguous range. The fill
 // pass also decides AC2 for the ball as a vertex (Step 5): every ball that
 // could be strictly closer in power to its centre is in its neighbour list.
-template <bool FILL>
+// MODE: NB_COUNT counts the rows; NB_FILL writes them into the CSR rows the
+// counts sized (each thread's row contiguous, consecutive rows adjacent).
+enum { NB_COUNT = 0, NB_FILL = 1 };
+
+template <int MODE>
 __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ atom, const int *__restrict__ perm, int n,
                                                        Grid g, const int *__restrict__ cell_start, PredParams pp,
                                                        int *__restrict__ deg_n, int *__restrict__ deg_up,
                                                        const int *__restrict__ nbr_start, const int *__restrict__ up_start,
                                                        int *__restrict__ nbr, int *__restrict__ up,
                                                        int *__restrict__ edge_i, unsigned char *__restrict__ vgab) {
-    const int i = blockIdx.x * BLOCK + threadIdx.x;
+    constexpr bool FILL = MODE == NB_FILL;
+    const int i = xcd_block() * BLOCK + threadIdx.x;
     if (i >= n) return;
     const int4 a = atom[i];
-    const i64 ra = (i64)a.w + pp.aq;
+    const int ra = a.w + (int)pp.aq;  // |aq| < 2^26 and W < 2^26
     int cn = 0, cu = 0;
     bool gab = true;
     if (ra >= 0) {
-        const int pn = FILL ? nbr_start[i] : 0, pu = FILL ? up_start[i] : 0;
+        const int pn = FILL ? nbr_start[i] : 0;
+        const int pu = FILL ? up_start[i] : 0;
         const int cx = (a.x - g.ox) / g.s, cy = (a.y - g.oy) / g.s, cz = (a.z - g.oz) / g.s;
         const int x0 = max(cx - g.reach, 0), x1 = min(cx + g.reach, g.nx - 1);
         const int y0 = max(cy - g.reach, 0), y1 = min(cy + g.reach, g.ny - 1);
         const int z0 = max(cz - g.reach, 0), z1 = min(cz + g.reach, g.nz - 1);
-        const i64 lim = 4 * pp.sg2;
-        for (int z = z0; z <= z1; z++)
+        const int lim = 4 * (int)pp.sg2;     // (2 s_g)^2 < 2^28
+        const int reach1 = 2 * (int)pp.sgc;  // 2 ceil(s_g) <= 2^14
+        for (int z = z0; z <= z1; z++) {
+            // rows whose cells all lie farther than 2 s_g are skipped
+            const int zlo = g.oz + z * g.s, zhi = zlo + g.s - 1;
+            const int dzm = a.z < zlo ? zlo - a.z : (a.z > zhi ? a.z - zhi : 0);
+            if (dzm > reach1) continue;
+            const int rz = lim - dzm * dzm;
+            if (rz < 0) continue;
             for (int y = y0; y <= y1; y++) {
+                const int ylo = g.oy + y * g.s, yhi = ylo + g.s - 1;
+                const int dym = a.y < ylo ? ylo - a.y : (a.y > yhi ? a.y - yhi : 0);
+                if (dym > reach1 || rz - dym * dym < 0) continue;
                 const long long rb = ((long long)z * g.ny + y) * g.nx;
                 const int s = cell_start[rb + x0], e = cell_start[rb + x1 + 1];
                 for (int j = s; j < e; j++) {
                     if (j == i) continue;
                     const int4 b = atom[j];
-                    const i64 dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
-                    const i64 d2 = dx * dx + dy * dy + dz * dz;
-                    if (d2 > lim || d2 == 0) continue; /* equal centres are reported by k_cell_order */
-                    const i64 rb2 = (i64)b.w + pp.aq;
+                    const int dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
+                    if (abs(dx) > reach1 || abs(dy) > reach1 || abs(dz) > reach1) continue;
+                    const int d2 = dx * dx + dy * dy + dz * dz;
+                    if (d2 > lim || d2 == 0) continue; /* equal centres are reported by k_gather_atoms */
+                    const int rb2 = b.w + (int)pp.aq;
                     if (rb2 < 0) continue;
                     // grown balls meet: d <= rho_a + rho_b
-                    const i64 L = d2 - ra - rb2;
-                    if (L > 0 && L * L > 4 * ra * rb2) continue;
+                    const int L = d2 - ra - rb2;
+                    if (L > 0 && (i64)L * L > 4 * (i64)ra * rb2) continue;
                     if (FILL) {
                         nbr[pn + cn] = j;
                         if (gab && vertex_violation_sign(a, i, b, j, perm) < 0) gab = false;
@@ -236,10 +257,13 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
                     }
                 }
             }
+        }
     }
     if (!FILL) { deg_n[i] = cn; deg_up[i] = cu; }
     else vgab[i] = (unsigned char)(ra >= 0 && gab);
 }
+
+__global__ void k_copy_int(int *__restrict__ dst, const int *__restrict__ src) { *dst = *src; }
 
 // Position of b in the (sorted) upper-edge list of a, i.e. the edge id; -1 if absent.
 __device__ __forceinline__ int find_edge(const int *__restrict__ up_start, const int *__restrict__ up, int a, int b) {
@@ -276,24 +300,25 @@ __device__ __forceinline__ int find_tri(const int *__restrict__ up_start, const 
 // candidate lie in the neighbour list of each of its vertices).
 template <bool FILL>
 __global__ void __launch_bounds__(BLOCK) k_triangles(const int4 *__restrict__ atom, const int *__restrict__ perm,
-                                                      const int *__restrict__ nbr_start, const int *__restrict__ nbr,
+                                                      const int *__restrict__ nbr_start, const int *__restrict__ nbr_cnt,
+                                                      const int *__restrict__ nbr,
                                                       const int *__restrict__ up_start, const int *__restrict__ up,
                                                       const int *__restrict__ edge_i, int E, PredParams pp,
                                                       int *__restrict__ tri_cnt, unsigned char *__restrict__ egab,
                                                       const int *__restrict__ tri_start, int *__restrict__ tri_k,
                                                       int *__restrict__ tri_e, Counters *cnt) {
-    const int e = blockIdx.x * BLOCK + threadIdx.x;
+    const int e = xcd_block() * BLOCK + threadIdx.x;
     if (e >= E) return;
     const int i = edge_i[e], j = up[e];
     const int4 vi = atom[i], vj = atom[j];
-    const int ns = nbr_start[i], ne = nbr_start[i + 1];
+    const int ns = nbr_start[i], ne = ns + nbr_cnt[i];
     if (!FILL) {
         const Edge ed = edge_setup(vi, vj);
         bool gab = true;
         for (int p = ns; p < ne; p++) {
             const int q = nbr[p];
             if (q == j) continue;
-            if (edge_violation_sign(ed, i, j, atom[q], q, perm) < 0) { gab = false; break; }
+            if (edge_violation_sign(ed, i, j, atom[q], q, perm, pp.force_exact) < 0) { gab = false; break; }
         }
         egab[e] = (unsigned char)gab;
     }
@@ -321,18 +346,19 @@ __global__ void __launch_bounds__(BLOCK) k_triangles(const int4 *__restrict__ at
 
 // Triangles: AC2 at their own ortho-centre and OrthoSize (one thread each).
 __global__ void __launch_bounds__(BLOCK) k_tri_gabriel(const int4 *__restrict__ atom, const int *__restrict__ perm,
-                                                        const int *__restrict__ nbr_start, const int *__restrict__ nbr,
+                                                        const int *__restrict__ nbr_start, const int *__restrict__ nbr_cnt,
+                                                      const int *__restrict__ nbr,
                                                         const int *__restrict__ up, const int *__restrict__ edge_i,
                                                         const int *__restrict__ tri_k, const int *__restrict__ tri_e,
                                                         int T, PredParams pp, unsigned char *__restrict__ tgab,
                                                         double *__restrict__ tsize, Counters *cnt) {
-    const int t = blockIdx.x * BLOCK + threadIdx.x;
+    const int t = xcd_block() * BLOCK + threadIdx.x;
     if (t >= T) return;
     const int e = tri_e[t];
     const int i = edge_i[e], j = up[e], k = tri_k[t];
     const Tri tr = tri_setup(atom[i], atom[j], atom[k], pp);
     bool gab = true;
-    const int ns = nbr_start[i], ne = nbr_start[i + 1];
+    const int ns = nbr_start[i], ne = ns + nbr_cnt[i];
     for (int p = ns; p < ne; p++) {
         const int q = nbr[p];
         if (q == j || q == k) continue;
@@ -355,7 +381,7 @@ __global__ void __launch_bounds__(BLOCK) k_tet_candidates(const int4 *__restrict
                                                            int *__restrict__ tet_cnt, const int *__restrict__ tet_start,
                                                            int *__restrict__ tet_t, int *__restrict__ tet_l,
                                                            Counters *cnt) {
-    const int t = blockIdx.x * BLOCK + threadIdx.x;
+    const int t = xcd_block() * BLOCK + threadIdx.x;
     if (t >= T) return;
     const int e = tri_e[t];
     const int i = edge_i[e], j = up[e], k = tri_k[t];
@@ -398,7 +424,8 @@ __device__ __forceinline__ void mark_face(const unsigned char *gab, int *att, lo
 // Tetrahedra (Step 2): kept iff no ball is strictly closer in power to the
 // ortho-centre; a kept tetrahedron records itself on its facets (Step 3).
 __global__ void __launch_bounds__(BLOCK) k_tet_ac2(const int4 *__restrict__ atom, const int *__restrict__ perm,
-                                                    const int *__restrict__ nbr_start, const int *__restrict__ nbr,
+                                                    const int *__restrict__ nbr_start, const int *__restrict__ nbr_cnt,
+                                                      const int *__restrict__ nbr,
                                                     const int *__restrict__ up_start, const int *__restrict__ up,
                                                     const int *__restrict__ edge_i, const int *__restrict__ tri_start,
                                                     const int *__restrict__ tri_k, const int *__restrict__ tri_e,
@@ -407,14 +434,14 @@ __global__ void __launch_bounds__(BLOCK) k_tet_ac2(const int4 *__restrict__ atom
                                                     int *__restrict__ tri_att, long long *__restrict__ tri_min,
                                                     unsigned char *__restrict__ qin, double *__restrict__ qsize,
                                                     Counters *cnt) {
-    const int c = blockIdx.x * BLOCK + threadIdx.x;
+    const int c = xcd_block() * BLOCK + threadIdx.x;
     if (c >= Q) return;
     const int t = tet_t[c], l = tet_l[c];
     const int e = tri_e[t];
     const int i = edge_i[e], j = up[e], k = tri_k[t];
     const Tet te = tet_setup(atom[i], atom[j], atom[k], atom[l], pp);
     bool keep = true;
-    const int ns = nbr_start[i], ne = nbr_start[i + 1];
+    const int ns = nbr_start[i], ne = ns + nbr_cnt[i];
     for (int p = ns; p < ne; p++) {
         const int q = nbr[p];
         if (q == j || q == k || q == l) continue;
@@ -443,7 +470,7 @@ __global__ void __launch_bounds__(BLOCK) k_tri_final(const int *__restrict__ up_
                                                       unsigned char *__restrict__ tin,
                                                       const unsigned char *__restrict__ egab, int *__restrict__ edge_att,
                                                       long long *__restrict__ edge_min, Counters *cnt) {
-    const int t = blockIdx.x * BLOCK + threadIdx.x;
+    const int t = xcd_block() * BLOCK + threadIdx.x;
     if (t >= T) return;
     const bool gab = tgab[t];
     const bool in = gab || tri_att[t];
@@ -471,7 +498,7 @@ __global__ void __launch_bounds__(BLOCK) k_edge_final(const int4 *__restrict__ a
                                                        unsigned char *__restrict__ ein, double *__restrict__ esize,
                                                        const unsigned char *__restrict__ vgab,
                                                        int *__restrict__ vert_att, long long *__restrict__ vert_min) {
-    const int e = blockIdx.x * BLOCK + threadIdx.x;
+    const int e = xcd_block() * BLOCK + threadIdx.x;
     if (e >= E) return;
     const bool gab = egab[e];
     const bool in = gab || edge_att[e];
@@ -495,7 +522,7 @@ __global__ void __launch_bounds__(BLOCK) k_vert_final(const int4 *__restrict__ a
                                                        const int *__restrict__ vert_att,
                                                        const long long *__restrict__ vert_min,
                                                        int *__restrict__ vin_in, double *__restrict__ vsize_in) {
-    const int v = blockIdx.x * BLOCK + threadIdx.x;
+    const int v = xcd_block() * BLOCK + threadIdx.x;
     if (v >= n) return;
     const int w = atom[v].w;
     bool in = false;
@@ -558,7 +585,7 @@ __global__ void __launch_bounds__(BLOCK) k_emit_keys(const unsigned char *__rest
                                                       const int *__restrict__ tet_t, const int *__restrict__ tet_l,
                                                       const int *__restrict__ perm, unsigned *__restrict__ key,
                                                       typename EmitPay<K>::type *__restrict__ pay) {
-    const int c = blockIdx.x * BLOCK + threadIdx.x;
+    const int c = xcd_block() * BLOCK + threadIdx.x;
     if (c >= M || !in[c]) return;
     int v[4];
     candidate_row<K>(c, up, edge_i, tri_k, tri_e, tet_t, tet_l, v);

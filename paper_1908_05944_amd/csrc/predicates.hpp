@@ -42,6 +42,7 @@ struct PredParams {
     i64 sg2;       // W_max + aq: squared grown radius bound
     double bmax;   // bound on |b_i| for AC2 queries: 2 sqrt(sg2)
     double gmax;   // bound on |gamma|: 4 sg2 + W_max
+    i64 sgc;       // ceil(sqrt(sg2))
     int force_exact;
 };
 
@@ -49,8 +50,8 @@ struct Counters {
     unsigned long long exact_fallbacks;
     int dup;       // duplicate centres seen
     int lookup;    // a facet lookup failed (must not happen)
-    int k3, k2, k1, k0;
-    int pad[2];
+    int Nn, E, T, Q;  // neighbour entries and candidate counts, copied from scan totals
+    int m0, m1, m2, m3;
 };
 
 __device__ __forceinline__ int sgn128(i128 v) { return (v > 0) - (v < 0); }
@@ -75,20 +76,22 @@ __device__ __forceinline__ void note_fallback(Counters *cnt) { atomicAdd(&cnt->e
 // ---------------------------------------------------------------------------
 // Vertex (d = 0): AC2 at the ball's own centre. P = |b|^2 - W_q + W_v.
 // Sorted-order indices are passed with the input-order map `perm`; input ids
-// are read only when simulation of simplicity has to decide.
+// are read only when simulation of simplicity has to decide. Queries come
+// from neighbour lists, so |b| <= 2 sqrt(sg2) < 2^14 and P fits in int32.
 __device__ __forceinline__ int vertex_violation_sign(int4 v, int sv, int4 q, int sq, const int *perm) {
-    i64 bx = q.x - v.x, by = q.y - v.y, bz = q.z - v.z;
-    i64 P = bx * bx + by * by + bz * bz - q.w + v.w;
-    if (P) return sgn64(P);
+    const int bx = q.x - v.x, by = q.y - v.y, bz = q.z - v.z;
+    const int P = bx * bx + by * by + bz * bz - q.w + v.w;
+    if (P) return P > 0 ? 1 : -1;
     // partials: W_q -> -1, W_v -> +1
     return perm[sq] < perm[sv] ? -1 : 1;
 }
 
 // ---------------------------------------------------------------------------
-// Edge (d = 1), exact int64.
+// Edge (d = 1). |a| < 2^14, so |a|^2 and beta fit in int32; products are
+// filtered in float64 and decided exactly in int64 when the filter cannot.
 struct Edge {
     int4 v0;
-    i64 ax, ay, az, den, beta;
+    int ax, ay, az, den, beta;
 };
 
 __device__ __forceinline__ Edge edge_setup(int4 v0, int4 v1) {
@@ -103,24 +106,32 @@ __device__ __forceinline__ Edge edge_setup(int4 v0, int4 v1) {
 // AC3 for an edge: beta^2 <= 4 |a|^2 (W0 + alpha). Equivalent to the grown
 // spheres (radius^2 W + alpha) crossing. Needs |a|^2 <= 4 sg2 (checked by caller).
 __device__ __forceinline__ bool edge_ac3(const Edge &e, i64 aq) {
-    i64 rhs = 4 * e.den * (e.v0.w + aq);
-    return e.beta * e.beta <= rhs;
+    const i64 rhs = 4 * (i64)e.den * ((i64)e.v0.w + aq);
+    return (i64)e.beta * e.beta <= rhs;
 }
 
 __device__ __forceinline__ double edge_orthosize(const Edge &e) {
-    double b = (double)e.beta;
+    const double b = (double)e.beta;
     return b * b / (4.0 * (double)e.den) - (double)e.v0.w;
 }
 
 // P = |a|^2 gamma - beta (a.b)
-__device__ __forceinline__ int edge_violation_sign(const Edge &e, int s0, int s1, int4 q, int sq, const int *perm) {
-    i64 bx = q.x - e.v0.x, by = q.y - e.v0.y, bz = q.z - e.v0.z;
-    i64 gam = bx * bx + by * by + bz * bz - q.w + e.v0.w;
-    i64 t = e.ax * bx + e.ay * by + e.az * bz;
-    i64 P = e.den * gam - e.beta * t;
-    if (P) return sgn64(P);
+__device__ __forceinline__ int edge_violation_sign(const Edge &e, int s0, int s1, int4 q, int sq, const int *perm,
+                                                   int force_exact) {
+    const int bx = q.x - e.v0.x, by = q.y - e.v0.y, bz = q.z - e.v0.z;
+    const int gam = bx * bx + by * by + bz * bz - q.w + e.v0.w;
+    const int t = e.ax * bx + e.ay * by + e.az * bz;
+    if (!force_exact) {
+        const double p1 = (double)e.den * (double)gam, p2 = (double)e.beta * (double)t;
+        const double P = p1 - p2;
+        const double eb = 4.0 * ACX_U * (fabs(p1) + fabs(p2));
+        if (P > eb) return 1;
+        if (P < -eb) return -1;
+    }
+    const i64 P = (i64)e.den * gam - (i64)e.beta * t;
+    if (P) return P > 0 ? 1 : -1;
     int ids[3] = {perm[sq], perm[s1], perm[s0]};
-    i128 coef[3] = {-(i128)e.den, (i128)t, (i128)(e.den - t)};
+    i128 coef[3] = {-(i128)e.den, (i128)t, (i128)e.den - t};
     return sos_first<3>(ids, coef);
 }
 

@@ -162,6 +162,17 @@ def config_100k(sas: bool = False) -> Molecule:
     return molecule(100_000, 2, sas=sas)
 
 
-def config_shell_3m() -> Molecule:
-    """3,000,000 atoms in a shell (inner radius 0.7 R_out)."""
-    return molecule(3_000_000, 3, shell=True)
+def config_shell_3m(cache_dir: str | None = None) -> Molecule:
+    """3,000,000 atoms in a shell (inner radius 0.7 R_out). With cache_dir, the
+    lattice arrays are kept there as .npy files (generation takes ~30-70 s)."""
+    if cache_dir:
+        fx = os.path.join(cache_dir, "shell3m_s3_X.npy")
+        fr = os.path.join(cache_dir, "shell3m_s3_R.npy")
+        if os.path.exists(fx) and os.path.exists(fr):
+            return Molecule(np.load(fx), np.load(fr), "shell3000000_s3")
+    m = molecule(3_000_000, 3, shell=True)
+    if cache_dir:
+        os.makedirs(cache_dir, exist_ok=True)
+        np.save(fx, m.X_mA)
+        np.save(fr, m.R_mA)
+    return m

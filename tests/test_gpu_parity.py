@@ -51,6 +51,15 @@ def test_tiny_inputs(acx):
             assert_same_complex(_run(acx, xyz, rad, alpha), oracle.alpha_complex(xyz, rad, alpha), f"n={len(rad)}")
 
 
+def test_dense_neighbourhoods(acx):
+    """Balls with many neighbours (long neighbour rows, many candidates per
+    ball), built twice in a row on reused device memory."""
+    m = synth.molecule(4000, 21).with_sas(2200)  # radii ~3.9 A: ~60 neighbours per ball
+    want = oracle.alpha_complex(m.xyz, m.radii, 0.0)
+    for _ in range(2):
+        assert_same_complex(_run(acx, m.xyz, m.radii, 0.0), want, "dense")
+
+
 def test_random_small(acx):
     rng = random.Random(42)
     for trial in range(40):
@@ -129,3 +138,4 @@ def test_100k_full_parity(acx, sas):
     m = synth.config_100k(sas=sas)
     got = _run(acx, m.xyz, m.radii, 0.0)
     assert_same_complex(got, oracle.alpha_complex(m.xyz, m.radii, 0.0), f"100k sas={sas}")
+
