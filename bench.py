@@ -4,7 +4,13 @@ One step = one full alpha-complex build through the C ABI from device-resident
 inputs (quantise, grid binning, candidate edges / triangles / tetrahedra,
 pruning, Size propagation, sorted output on the device). Prints one JSON line.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+The same line carries two secondary workloads (skip them with --no-extras):
+  "batch": 512 molecules of 500-50,000 atoms in one batched call (cell sides
+           from the autotuner), against 512 sequential single-molecule calls;
+  "union_measure": 64 jittered frames of the 100k-atom molecule, union volume
+           and area forward + backward, per frame and as one batch.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extras]
 """
 import argparse
 import json
@@ -20,9 +26,175 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 
+KERNEL_OF_STAGE = {
+    "neighbours_count": "k_neighbours<0>",
+    "neighbours_fill": "k_neighbours<1>",
+    "triangles_count": "k_triangles<false>",
+    "triangles_fill": "k_triangles<true>",
+    "triangles_ac2": "k_tri_gabriel",
+    "tetrahedra_ac2": "k_tet_ac2",
+    "triangles_final": "k_tri_final",
+    "edges_final": "k_edge_final",
+    "vertices_final": "k_vert_final",
+}
+KERNEL_SOURCES = ["paper_1908_05944_amd/csrc/kernels.hpp", "paper_1908_05944_amd/csrc/predicates.hpp",
+                  "paper_1908_05944_amd/csrc/common.hpp", "paper_1908_05944_amd/csrc/radix.hpp",
+                  "paper_1908_05944_amd/csrc/alphacx.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_3Mshell.json")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(stage):
+    """HBM bytes per launch of the stage's kernel from the committed rocprofv3
+    counter summary, or None if it was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(KERNEL_OF_STAGE.get(stage, stage))
+    return None if k is None else k.get("traffic_bytes")
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def _timed(torch, fn, reps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def bench_batch(acx, synth, torch, log, reps=5):
+    """512 molecules, sizes log-uniform in [500, 50000] atoms (seed 999), one
+    batched call against 512 sequential single-molecule calls."""
+    import numpy as np
+    t0 = time.time()
+    sizes = synth.batch_sizes()
+    mols = [synth.molecule(int(k), 1000 + i) for i, k in enumerate(sizes)]
+    xyz = np.concatenate([m.xyz for m in mols])
+    rad = np.concatenate([m.radii for m in mols])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    log(f"[bench] batch: {len(mols)} molecules, {len(rad)} atoms generated in {time.time() - t0:.1f} s")
+    X = torch.from_numpy(xyz).cuda()
+    R = torch.from_numpy(rad).cuda()
+    t0 = time.perf_counter()
+    cells, buckets = acx.ac_tune_cells(X, R, off, 0.0)
+    tune_s = time.perf_counter() - t0
+    per_bucket = {int(b): int(cells[np.nonzero(buckets == b)[0][0]]) for b in np.unique(buckets)}
+    log(f"[bench] batch: tuner {tune_s:.2f} s, cell side (mA) per size bucket {per_bucket}")
+
+    def batched(cell=None):
+        acx.ac_alpha_complex_batch(X, R, off, 0.0, cell_mA=cell).close()
+
+    def sequential():
+        for m in range(len(mols)):
+            a, b = int(off[m]), int(off[m + 1])
+            acx.ac_alpha_complex_device(X[a:b], R[a:b], 0.0).close()
+
+    batched(cells)
+    sequential()
+    t_tuned = _timed(torch, lambda: batched(cells), reps)
+    t_default = _timed(torch, lambda: batched(None), reps)
+    t_seq = _timed(torch, sequential, 1)
+    c = acx.ac_alpha_complex_batch(X, R, off, 0.0, cell_mA=cells)
+    counts = c.counts()
+    c.close()
+    n_mol = len(mols)
+    log(f"[bench] batch: {t_tuned * 1e3:.2f} ms tuned, {t_default * 1e3:.2f} ms default cells, "
+        f"{t_seq * 1e3:.1f} ms as {n_mol} sequential calls")
+    return {
+        "metric": "batched molecules/s",
+        "value": n_mol / t_tuned,
+        "unit": "molecules/s",
+        "ms_per_batch": t_tuned * 1e3,
+        "ms_per_batch_default_cells": t_default * 1e3,
+        "sequential_ms": t_seq * 1e3,
+        "sequential_molecules_per_s": n_mol / t_seq,
+        "speedup_vs_sequential": t_seq / t_tuned,
+        "atoms": int(off[-1]),
+        "counts": counts,
+        "tuned_cell_mA_per_bucket": per_bucket,
+        "tuner_s": tune_s,
+        "config": {"workload": "512 molecules, sizes log-uniform in [500, 50000] atoms (seed 999), spheres at "
+                               "0.05 atoms/A^3, vdW radii, alpha=0", "molecules": n_mol},
+    }
+
+
+def bench_union(acx, synth, torch, log, frames=64, reps=3):
+    """Union volume and area, forward + backward, on 64 jittered frames of the
+    100k-atom molecule (sigma 0.1 A, seeds 2000 + f): complexes built first,
+    then V, A and their gradients timed per frame, and for all frames as one
+    batch (one complex over the 64 frames, one forward, one backward)."""
+    import numpy as np
+    base = synth.config_100k()
+    fr = [synth.jittered(base, 0.1, 2000 + f) for f in range(frames)]
+    Xs = [torch.from_numpy(m.xyz).cuda() for m in fr]
+    R = torch.from_numpy(base.radii).cuda()
+    g = torch.ones(2, dtype=torch.float64, device="cuda")
+    cs = [acx.ac_alpha_complex_device(x, R, 0.0) for x in Xs]
+
+    def build():
+        for x in Xs:
+            acx.ac_alpha_complex_device(x, R, 0.0).close()
+
+    def fwd_bwd():
+        for c, x in zip(cs, Xs):
+            acx.ac_union_measure_device(c, x, R)
+            acx.ac_union_measure_backward(c, x, R, g)
+
+    fwd_bwd()  # first backward on a complex sorts its incidences (kept)
+    t_build = _timed(torch, build, reps) / frames
+    t_fb = _timed(torch, fwd_bwd, reps) / frames
+    V, A = acx.ac_union_measure(cs[0], Xs[0], R)
+    for c in cs:
+        c.close()
+    # all frames in one batch
+    XB = torch.cat(Xs)
+    RB = R.repeat(frames)
+    off = np.arange(frames + 1, dtype=np.int64) * base.n
+    cb = acx.ac_alpha_complex_batch(XB, RB, off, 0.0)
+    acx.ac_union_measure_device(cb, XB, RB)
+    acx.ac_union_measure_backward(cb, XB, RB, g)
+
+    def fwd_bwd_batch():
+        acx.ac_union_measure_device(cb, XB, RB)
+        acx.ac_union_measure_backward(cb, XB, RB, g)
+
+    def build_batch():
+        acx.ac_alpha_complex_batch(XB, RB, off, 0.0).close()
+
+    t_fb_batch = _timed(torch, fwd_bwd_batch, reps) / frames
+    t_build_batch = _timed(torch, build_batch, reps) / frames
+    cb.close()
+    log(f"[bench] union: per frame build {t_build * 1e3:.3f} ms, V+A fwd+bwd {t_fb * 1e3:.3f} ms; "
+        f"batched over {frames} frames: build {t_build_batch * 1e3:.3f} ms, fwd+bwd {t_fb_batch * 1e3:.3f} ms per frame")
+    return {
+        "metric": "V+A fwd+bwd ms",
+        "value": t_fb * 1e3,
+        "unit": "ms per frame",
+        "higher_is_better": False,
+        "build_ms_per_frame": t_build * 1e3,
+        "batched_fwd_bwd_ms_per_frame": t_fb_batch * 1e3,
+        "batched_build_ms_per_frame": t_build_batch * 1e3,
+        "frame0": {"V_A3": V, "A_A2": A},
+        "config": {"workload": "64 frames of the 100k-atom molecule (sphere R 78.2 A), Gaussian jitter 0.1 A, vdW "
+                               "radii, alpha=0", "frames": frames, "atoms": base.n},
+    }
 
 
 def main():
@@ -35,6 +207,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=600_000, help="atoms of the oracle's sample")
     ap.add_argument("--cache-dir", default=os.environ.get("ALPHACX_INPUT_CACHE", ""),
                     help="keep the generated input here between runs")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batch and union-measure workloads")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain device copy of 1 GiB (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU design is described "
@@ -46,6 +221,15 @@ def main():
 
     import synth
     import paper_1908_05944_amd as acx
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 copies of {src.numel() * 4} bytes")
+        del src, dst
 
     t0 = time.time()
     mol = synth.config_shell_3m(args.cache_dir or None)
@@ -83,36 +267,41 @@ def main():
     counts = c.counts()
     cand = [c.candidate_count(d) for d in range(4)]
     fallbacks = c.exact_fallbacks()
+    work = [c.work_count(0), c.work_count(1)]
     c.close()
 
-    # Dominant kernel and its roofline. The tetrahedron/AC2 and finalise kernels
-    # are bound by float64 and integer vector arithmetic on data held in L2;
-    # the neighbour scan by gathers of 16-byte atoms.
-    dom = max(stage_avg, key=lambda k: stage_avg[k])
+    # Dominant kernel and its roofline: among the stages that hold exactly one
+    # kernel launch, the one with the largest event time. Algorithmic bytes are
+    # what that kernel must move from HBM at least.
     n = mol.n
-    E, T = cand[1], cand[2]
-    # algorithmic bytes per launch, by kernel ("Roofline accounting")
+    E, T, Q = cand[1], cand[2], cand[3]
+    Nn = work[1]
     alg_bytes = {
-        "neighbours_fill": 16 * n + 4 * (n + 1) * 2 + 4 * 0 + 8 * E,
         "neighbours_count": 16 * n + 8 * n,
-        "triangles_count": 12 * E + 4 * E,
-        "triangles_fill": 12 * E + 8 * T,
-        "tetrahedra_ac2": 8 * T + 24 * counts[3],
-        "triangles_final": 8 * T + 28 * counts[2],
-        "edges_final": 8 * E + 16 * counts[1],
-        "vertices_final": 16 * n + 12 * counts[0],
+        "neighbours_fill": 16 * n + 8 * (n + 1) + 4 * Nn + 8 * E + n,
+        "triangles_count": 16 * n + 8 * E + 4 * Nn + 4 * E + E,
+        "triangles_fill": 16 * n + 8 * E + 4 * (E + 1) + 8 * T,
+        "triangles_ac2": 16 * n + 8 * T + 4 * Nn + 9 * T,
+        "tetrahedra_ac2": 8 * Q + 8 * T + 16 * n + 9 * Q,
+        "triangles_final": 30 * T,
+        "edges_final": 30 * E,
+        "vertices_final": 30 * n,
     }
-    bytes_dom = alg_bytes.get(dom)
-    dom_ms = stage_avg[dom]
+    single = {k: v for k, v in stage_avg.items() if k in alg_bytes and v > 0}
+    dom = max(single, key=lambda k: single[k])
+    dom_ms = single[dom]
+    achieved = alg_bytes[dom] / (dom_ms * 1e-3) / 1e9
+    traffic = measured_traffic(dom)
     roofline = {
-        "kernel": dom,
+        "kernel": KERNEL_OF_STAGE.get(dom, dom),
         "bound": "hbm",
-        "achieved": (bytes_dom / (dom_ms * 1e-3) / 1e9) if bytes_dom else None,
+        "achieved": achieved,
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
-        "frac": ((bytes_dom / (dom_ms * 1e-3) / 1e9) / HBM_PEAK_GBS) if bytes_dom else None,
-        "traffic": None,
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": traffic,
         "ms_per_launch": dom_ms,
+        "algorithmic_bytes": alg_bytes[dom],
     }
 
     cpu = None
@@ -129,6 +318,13 @@ def main():
         cpu = {"value": len(sel) / dt, "unit": "atoms/s", "cores": 1, "kind": "oracle",
                "sample": f"{len(sel)} atoms of the 3M shell (slab x <= {x0 / 1000:.1f} A), {dt:.1f} s single-threaded"}
         log(f"[bench] oracle sample: {len(sel)} atoms in {dt:.2f} s, counts {oc.counts()}")
+
+    extras = {}
+    if not args.no_extras:
+        del xyz, rad
+        torch.cuda.empty_cache()
+        extras["batch"] = bench_batch(acx, synth, torch, log)
+        extras["union_measure"] = bench_union(acx, synth, torch, log)
 
     out = {
         "metric": "alpha-complex atoms/s at 3M atoms",
@@ -152,6 +348,7 @@ def main():
         "stage_ms": stage_avg,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        **extras,
     }
     print(json.dumps(out), flush=True)
 

@@ -86,6 +86,48 @@ ac_status ac_alpha_complex(const double *xyz, const double *radii, int64_t n, do
 ac_status ac_alpha_complex_device(const double *d_xyz, const double *d_radii, int64_t n, double alpha,
                                   const ac_options *opt, void *stream, ac_complex **out);
 
+/* ---- Batches of molecules ----
+ *
+ * Many independent molecules in one call: molecule m is the balls
+ * [offsets[m], offsets[m+1]) of the concatenated arrays d_xyz / d_radii
+ * (device, as in ac_alpha_complex_device). offsets is a host array of
+ * n_mol + 1 int64 with offsets[0] = 0, strictly increasing (no empty
+ * molecule), offsets[n_mol] < 2^26; 1 <= n_mol <= 2^20. Each molecule gets a
+ * uniform grid of its own (Sec. 4.2) whose cells are numbered after those of
+ * the molecules before it, so balls of different molecules never interact
+ * (their coordinates may overlap). Every stage runs once over the whole
+ * batch. The result is the union of the molecules' complexes, with ids into
+ * the concatenated arrays: rows are sorted by least id, so molecule m's
+ * d-simplices are rows [ac_molecule_rows(c, d)[m], ac_molecule_rows(c, d)[m+1]),
+ * and subtracting offsets[m] from their ids gives exactly what
+ * ac_alpha_complex_device returns for that molecule alone (simulation of
+ * simplicity ranks by id, and the order of ids within a molecule is kept).
+ * cell_mA: NULL, or a host array of n_mol positive cell sides in mA (e.g.
+ * from ac_tune_cells); opt->cell_mA applies to every molecule otherwise.
+ * Errors as ac_alpha_complex_device, plus AC_E_INVALID for bad offsets. */
+ac_status ac_alpha_complex_batch(const double *d_xyz, const double *d_radii, const int64_t *offsets, int64_t n_mol,
+                                 double alpha, const ac_options *opt, const int32_t *cell_mA, void *stream,
+                                 ac_complex **out);
+
+/* Molecules of the call that made c (1 for the single-molecule calls). */
+int64_t ac_molecule_count(const ac_complex *c);
+
+/* Host array of n_mol + 1 row indices into the d-simplex array: molecule m
+ * owns rows [rows[m], rows[m+1]). Valid until ac_free; NULL for a bad dim. */
+const int64_t *ac_molecule_rows(const ac_complex *c, int dim);
+
+/* Cell-size autotuner for a batch (same arguments as ac_alpha_complex_batch).
+ * The molecules are put in size buckets ([0, 2k), [2k, 8k), [8k, 32k) and
+ * [32k, inf) balls); for each bucket its molecules are copied into one
+ * sub-batch and built with cell sides of 0.5, 0.7, 1, 1.4 and 2 times the
+ * grown radius s_g (default 1 s_g), each timed twice by HIP events after a
+ * warm-up run, and the fastest side is written to cell_mA_out[m] for every
+ * molecule m of the bucket (and the bucket index to bucket_out[m] if not
+ * NULL). Both are host arrays of n_mol. The cell side never changes the
+ * result, only the time. Synchronises `stream`. */
+ac_status ac_tune_cells(const double *d_xyz, const double *d_radii, const int64_t *offsets, int64_t n_mol, double alpha,
+                        const ac_options *opt, void *stream, int32_t *cell_mA_out, int32_t *bucket_out);
+
 /* Number of d-simplices in K_alpha (d = 0..3); -1 for a NULL result or bad d. */
 int64_t ac_count(const ac_complex *c, int dim);
 
@@ -104,6 +146,11 @@ const double *ac_sizes_device(const ac_complex *c, int dim);
 int64_t ac_candidate_count(const ac_complex *c, int dim);
 int64_t ac_exact_fallbacks(const ac_complex *c);
 
+/* Sizes of internal structures of the call, for traffic accounting:
+ * which = 0: cells of the uniform grid; 1: entries of the neighbour rows
+ * (each ball's list of balls whose grown ball meets its own). -1 otherwise. */
+int64_t ac_work_count(const ac_complex *c, int which);
+
 /* Per-stage device time of a call made with opt->profile = 1, from HIP events
  * recorded on the call's stream between stages (milliseconds; -1 if not
  * profiled or i out of range). Stage i is named by ac_stage_name(i), for
@@ -111,6 +158,44 @@ int64_t ac_exact_fallbacks(const ac_complex *c);
 int ac_stage_count(void);
 const char *ac_stage_name(int i);
 double ac_stage_ms(const ac_complex *c, int i);
+
+/* ---- Union of balls: volume and boundary area, and their gradients ----
+ *
+ * The alpha complex of a molecule is what its volume and surface area are
+ * computed from (Sec. 1 of the paper). With c the complex at alpha = 0 of the
+ * same n balls, V and A of the union of the balls are the alternating sums,
+ * over the simplices of c, of the volume of the intersection of their balls
+ * and of the area of each sphere's part inside the other balls (short
+ * inclusion-exclusion over the dual complex, Edelsbrunner 1995). A complex
+ * for another alpha gives the measure of the union of the balls grown to
+ * sqrt(r^2 + alpha) when passed those grown radii.
+ *
+ * d_xyz (n x 3 row-major float64, angstrom) and d_radii (n float64) are device
+ * arrays on the complex's device, read on `stream`; they are used as given
+ * (not quantised), so finite differences over them see a smooth function of
+ * the coordinates while the complex stays fixed. n must equal the number of
+ * balls the complex was built on, else AC_E_INVALID.
+ *
+ * The work buffers are kept with the complex: after the first call on a
+ * complex these calls allocate nothing and do not synchronise the host
+ * (except ac_union_measure, which returns host values). Calls on one complex
+ * must not overlap (same stream, or ordered by the caller). */
+
+/* V (A^3) and A (A^2) into host doubles; synchronises `stream`. */
+ac_status ac_union_measure(ac_complex *c, const double *d_xyz, const double *d_radii, int64_t n, double *V,
+                           double *A, void *stream);
+
+/* Same, written as d_out[0] = V, d_out[1] = A into device memory on `stream`. */
+ac_status ac_union_measure_device(ac_complex *c, const double *d_xyz, const double *d_radii, int64_t n,
+                                  double *d_out, void *stream);
+
+/* Gradient of gV * V + gA * A with (gV, gA) = (d_grad[0], d_grad[1]) read from
+ * device memory: d_dxyz (n x 3) and d_dradii (n) are overwritten on the device
+ * (balls in no simplex get 0). The complex is held fixed. Deterministic: each
+ * ball sums its simplices' terms in a fixed order. The first call on a complex
+ * sorts its simplex corners by ball (kept until ac_free). */
+ac_status ac_union_measure_backward(ac_complex *c, const double *d_xyz, const double *d_radii, int64_t n,
+                                    const double *d_grad, double *d_dxyz, double *d_dradii, void *stream);
 
 /* Releases a result (NULL is allowed). */
 void ac_free(ac_complex *c);

@@ -9,6 +9,14 @@ Names follow the C ABI in include/alphacx.h:
     ac_alpha_complex_device(xyz, radii, alpha, options=None,   torch device tensors in,
                             stream=None)                        results kept on the device
 Both return an `AlphaComplex` owning the library's result handle.
+
+    ac_alpha_complex_batch(xyz, radii, offsets, alpha,        many molecules in one call (device
+                           options=None, cell_mA=None)          tensors, host offsets)
+    ac_tune_cells(xyz, radii, offsets, alpha)                   per-molecule cell sides (autotuner)
+    ac_union_measure(c, xyz, radii)                   V, A of the union of the balls (host floats)
+    ac_union_measure_device(c, xyz, radii)            the same as a device tensor [V, A]
+    ac_union_measure_backward(c, xyz, radii, grad)    d(gV V + gA A)/d(xyz, radii), device tensors
+    UnionMeasure.apply(xyz, radii, c)                 torch.autograd.Function over the two
 """
 from __future__ import annotations
 
@@ -92,6 +100,8 @@ def _load():
     lib.ac_candidate_count.restype = i64
     lib.ac_exact_fallbacks.argtypes = [c_p]
     lib.ac_exact_fallbacks.restype = i64
+    lib.ac_work_count.argtypes = [c_p, ctypes.c_int]
+    lib.ac_work_count.restype = i64
     lib.ac_stage_count.argtypes = []
     lib.ac_stage_count.restype = ctypes.c_int
     lib.ac_stage_name.argtypes = [ctypes.c_int]
@@ -106,6 +116,21 @@ def _load():
     lib.ac_status_str.restype = ctypes.c_char_p
     lib.ac_last_error.argtypes = []
     lib.ac_last_error.restype = ctypes.c_char_p
+    lib.ac_alpha_complex_batch.argtypes = [c_p, c_p, c_p, i64, dbl, ctypes.POINTER(Options), c_p, c_p,
+                                           ctypes.POINTER(c_p)]
+    lib.ac_alpha_complex_batch.restype = ctypes.c_int
+    lib.ac_molecule_count.argtypes = [c_p]
+    lib.ac_molecule_count.restype = i64
+    lib.ac_molecule_rows.argtypes = [c_p, ctypes.c_int]
+    lib.ac_molecule_rows.restype = ctypes.POINTER(i64)
+    lib.ac_tune_cells.argtypes = [c_p, c_p, c_p, i64, dbl, ctypes.POINTER(Options), c_p, c_p, c_p]
+    lib.ac_tune_cells.restype = ctypes.c_int
+    lib.ac_union_measure.argtypes = [c_p, c_p, c_p, i64, ctypes.POINTER(dbl), ctypes.POINTER(dbl), c_p]
+    lib.ac_union_measure.restype = ctypes.c_int
+    lib.ac_union_measure_device.argtypes = [c_p, c_p, c_p, i64, c_p, c_p]
+    lib.ac_union_measure_device.restype = ctypes.c_int
+    lib.ac_union_measure_backward.argtypes = [c_p, c_p, c_p, i64, c_p, c_p, c_p, c_p]
+    lib.ac_union_measure_backward.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -178,6 +203,20 @@ class AlphaComplex:
     def exact_fallbacks(self) -> int:
         return int(_load().ac_exact_fallbacks(self._h))
 
+    def work_count(self, which: int) -> int:
+        return int(_load().ac_work_count(self._h, which))
+
+    def molecule_count(self) -> int:
+        return int(_load().ac_molecule_count(self._h))
+
+    def molecule_rows(self, dim: int) -> np.ndarray:
+        """Rows [r[m], r[m+1]) of the dim-simplex array belong to molecule m."""
+        lib = _load()
+        p = lib.ac_molecule_rows(self._h, dim)
+        if not p:
+            _check(1)
+        return np.ctypeslib.as_array(p, shape=(self.molecule_count() + 1,)).copy()
+
 
 def _opts(options):
     if options is None:
@@ -226,5 +265,133 @@ def ac_alpha_complex_device(xyz, radii, alpha: float, options=None, stream=None)
     return AlphaComplex(h)
 
 
+def _batch_args(xyz, radii, offsets):
+    import torch
+    if not (xyz.is_cuda and radii.is_cuda):
+        raise ValueError("device tensors expected")
+    if xyz.dtype != torch.float64 or radii.dtype != torch.float64:
+        raise ValueError("float64 tensors expected")
+    xyz = xyz.contiguous()
+    radii = radii.contiguous()
+    off = np.ascontiguousarray(offsets, dtype=np.int64).reshape(-1)
+    if xyz.dim() != 2 or xyz.shape[1] != 3 or radii.shape[0] != xyz.shape[0]:
+        raise ValueError("xyz must be n x 3 and radii n")
+    if len(off) < 2 or off[-1] != xyz.shape[0]:
+        raise ValueError("offsets must end at the number of balls")
+    return xyz, radii, off
+
+
+def ac_alpha_complex_batch(xyz, radii, offsets, alpha: float, options=None, cell_mA=None, stream=None) -> AlphaComplex:
+    """Molecules [offsets[m], offsets[m+1]) of the concatenated device tensors
+    in one call; ids of the result index the concatenated arrays."""
+    xyz, radii, off = _batch_args(xyz, radii, offsets)
+    cells = None
+    if cell_mA is not None:
+        cells = np.ascontiguousarray(cell_mA, dtype=np.int32).reshape(-1)
+        if len(cells) != len(off) - 1:
+            raise ValueError("cell_mA needs one side per molecule")
+    h = ctypes.c_void_p()
+    st = _load().ac_alpha_complex_batch(xyz.data_ptr(), radii.data_ptr(), off.ctypes.data, len(off) - 1, float(alpha),
+                                        _opts(options), None if cells is None else cells.ctypes.data,
+                                        _stream(xyz.device, stream), ctypes.byref(h))
+    _check(st)
+    return AlphaComplex(h)
+
+
+def ac_tune_cells(xyz, radii, offsets, alpha: float, options=None, stream=None):
+    """Autotuned cell side (mA) per molecule, and each molecule's size bucket."""
+    xyz, radii, off = _batch_args(xyz, radii, offsets)
+    n_mol = len(off) - 1
+    cells = np.zeros(n_mol, dtype=np.int32)
+    buckets = np.zeros(n_mol, dtype=np.int32)
+    _check(_load().ac_tune_cells(xyz.data_ptr(), radii.data_ptr(), off.ctypes.data, n_mol, float(alpha),
+                                 _opts(options), _stream(xyz.device, stream), cells.ctypes.data, buckets.ctypes.data))
+    return cells, buckets
+
+
 def ac_release_workspace():
     _check(_load().ac_release_workspace())
+
+
+def _balls(xyz, radii):
+    import torch
+    if not (xyz.is_cuda and radii.is_cuda):
+        raise ValueError("device tensors expected")
+    if xyz.dtype != torch.float64 or radii.dtype != torch.float64:
+        raise ValueError("float64 tensors expected")
+    xyz = xyz.detach().contiguous()
+    radii = radii.detach().contiguous()
+    if xyz.dim() != 2 or xyz.shape[1] != 3 or radii.dim() != 1 or radii.shape[0] != xyz.shape[0]:
+        raise ValueError("xyz must be n x 3 and radii n")
+    return xyz, radii
+
+
+def _stream(dev, stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def ac_union_measure(c: AlphaComplex, xyz, radii, stream=None):
+    """(V, A) of the union of the balls from the complex at alpha = 0 (host floats)."""
+    xyz, radii = _balls(xyz, radii)
+    V, A = ctypes.c_double(), ctypes.c_double()
+    _check(_load().ac_union_measure(c._h, xyz.data_ptr(), radii.data_ptr(), xyz.shape[0], ctypes.byref(V),
+                                    ctypes.byref(A), _stream(xyz.device, stream)))
+    return V.value, A.value
+
+
+def ac_union_measure_device(c: AlphaComplex, xyz, radii, stream=None):
+    """Device float64 tensor [V, A]; no host synchronisation."""
+    import torch
+    xyz, radii = _balls(xyz, radii)
+    out = torch.empty(2, dtype=torch.float64, device=xyz.device)
+    _check(_load().ac_union_measure_device(c._h, xyz.data_ptr(), radii.data_ptr(), xyz.shape[0], out.data_ptr(),
+                                           _stream(xyz.device, stream)))
+    return out
+
+
+def ac_union_measure_backward(c: AlphaComplex, xyz, radii, grad, stream=None):
+    """Gradient of grad[0] * V + grad[1] * A (grad: device float64 tensor of 2)
+    with respect to xyz (n x 3) and radii (n), the complex held fixed."""
+    import torch
+    xyz, radii = _balls(xyz, radii)
+    grad = grad.detach().to(device=xyz.device, dtype=torch.float64).contiguous()
+    if grad.numel() != 2:
+        raise ValueError("grad must hold (gV, gA)")
+    dx = torch.empty_like(xyz)
+    dr = torch.empty_like(radii)
+    _check(_load().ac_union_measure_backward(c._h, xyz.data_ptr(), radii.data_ptr(), xyz.shape[0], grad.data_ptr(),
+                                             dx.data_ptr(), dr.data_ptr(), _stream(xyz.device, stream)))
+    return dx, dr
+
+
+def _autograd_function():
+    import torch
+
+    class UnionMeasure(torch.autograd.Function):
+        """[V, A] = UnionMeasure.apply(xyz, radii, complex): volume and boundary
+        area of the union of the balls, differentiable in xyz and radii with
+        the complex (built at alpha = 0) held fixed."""
+
+        @staticmethod
+        def forward(ctx, xyz, radii, c):
+            ctx.save_for_backward(xyz, radii)
+            ctx.complex = c
+            return ac_union_measure_device(c, xyz, radii)
+
+        @staticmethod
+        def backward(ctx, g):
+            xyz, radii = ctx.saved_tensors
+            dx, dr = ac_union_measure_backward(ctx.complex, xyz, radii, g)
+            return dx, dr, None
+
+    return UnionMeasure
+
+
+def __getattr__(name):
+    if name == "UnionMeasure":
+        fn = _autograd_function()
+        globals()["UnionMeasure"] = fn
+        return fn
+    raise AttributeError(name)

@@ -17,6 +17,7 @@
 
 #include "alphacx.h"
 #include "kernels.hpp"
+#include "measure.hpp"
 
 using namespace acx;
 
@@ -129,6 +130,10 @@ struct ac_complex {
     int64_t count[4] = {0, 0, 0, 0};
     int64_t cand[4] = {0, 0, 0, 0};
     int64_t fallbacks = 0;
+    int64_t work[2] = {0, 0};
+    int64_t n = 0;  // balls in the input
+    int64_t n_mol = 1;
+    std::vector<int64_t> mol_rows[4];  // per dimension: first row of each molecule, n_mol + 1 entries
     int32_t *d_simp[4] = {nullptr, nullptr, nullptr, nullptr};
     double *d_size[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<int32_t> h_simp[4];
@@ -137,6 +142,15 @@ struct ac_complex {
     bool device_result = false;
     int device = 0;
     double stage_ms[32];
+    // vertex -> incidence slots of the simplices, built on first use by the
+    // union-measure backward (slot of corner k of simplex s of dimension d:
+    // sum_{e<d} count[e] (e+1) + s (d+1) + k)
+    int32_t *inc_slot = nullptr;
+    int32_t *inc_start = nullptr;
+    // work buffers of the union-measure calls, kept with the complex so that
+    // those calls need no allocation or host synchronisation after the first
+    double *meas_part = nullptr;    // block partial sums of V and A, then V, A
+    double4 *meas_contrib = nullptr;  // per incidence slot gradient terms
 };
 
 static void free_complex(ac_complex *c) {
@@ -145,6 +159,10 @@ static void free_complex(ac_complex *c) {
         dev_free(c->d_simp[d]);
         dev_free(c->d_size[d]);
     }
+    dev_free(c->inc_slot);
+    dev_free(c->inc_start);
+    dev_free(c->meas_part);
+    dev_free(c->meas_contrib);
     delete c;
 }
 
@@ -206,31 +224,38 @@ struct Cands {
     const int *up, *edge_i, *tri_k, *tri_e, *tet_t, *tet_l, *perm;
 };
 
-// Stable LSD radix sort of (key, payload) on the low `bits` bits of key;
-// the result ends in key/pay.
-template <class P>
-static void radix_sort(unsigned *key, P *pay, int n, int bits, hipStream_t s, Scope &sc) {
-    if (n <= 1 || bits <= 0) return;
+// Stable LSD radix sort of (key, payload) on the low `bits` bits of key.
+// key / pay are set to the buffers that hold the result (the inputs' or
+// scratch of the scope). Digits of 11 bits above 16 key bits (2 passes up
+// to 22 bits), else of 8.
+template <class P, int BITS>
+static void radix_passes(unsigned *&key, P *&pay, int n, int bits, hipStream_t s, Scope &sc) {
+    constexpr int BINS = 1 << BITS;
     const int tiles = (n + RS_TILE - 1) / RS_TILE;
     unsigned *k2 = sc.get<unsigned>(n);
     P *p2 = sc.get<P>(n);
-    int *hist = sc.get<int>((size_t)RS_BINS * tiles);
-    int *offs = sc.get<int>((size_t)RS_BINS * tiles + 1);
+    int *hist = sc.get<int>((size_t)BINS * tiles);
+    int *offs = sc.get<int>((size_t)BINS * tiles + 1);
     unsigned *kin = key, *kout = k2;
     P *pin = pay, *pout = p2;
-    for (int shift = 0; shift < bits; shift += RS_BITS) {
-        k_rs_hist<<<tiles, RS_BLOCK, 0, s>>>(kin, n, shift, hist, tiles);
+    for (int shift = 0; shift < bits; shift += BITS) {
+        k_rs_hist<BITS><<<tiles, RS_BLOCK, 0, s>>>(kin, n, shift, hist, tiles);
         LAUNCH_CHECK();
-        scan_i32(hist, offs, (long long)RS_BINS * tiles, s, sc);
-        k_rs_scatter<P><<<tiles, RS_BLOCK, 0, s>>>(kin, pin, kout, pout, n, shift, offs, tiles);
+        scan_i32(hist, offs, (long long)BINS * tiles, s, sc);
+        k_rs_scatter<P, BITS><<<tiles, RS_BLOCK, 0, s>>>(kin, pin, kout, pout, n, shift, offs, tiles);
         LAUNCH_CHECK();
         std::swap(kin, kout);
         std::swap(pin, pout);
     }
-    if (kin != key) {
-        HIP_TRY(hipMemcpyAsync(key, kin, sizeof(unsigned) * n, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(pay, pin, sizeof(P) * n, hipMemcpyDeviceToDevice, s));
-    }
+    key = kin;
+    pay = pin;
+}
+
+template <class P>
+static void radix_sort(unsigned *&key, P *&pay, int n, int bits, hipStream_t s, Scope &sc) {
+    if (n <= 1 || bits <= 0) return;
+    if (bits > 16) radix_passes<P, 11>(key, pay, n, bits, s, sc);
+    else radix_passes<P, 8>(key, pay, n, bits, s, sc);
 }
 
 static int bits_for(long long n) {
@@ -239,24 +264,28 @@ static int bits_for(long long n) {
     return b;
 }
 
-// Emit dimension d (K = d + 1 >= 2): kept candidates (flags `in`, compacted
-// positions `fpos`), remapped to input ids, radix-sorted by their least id,
-// then ranked inside each bucket by the remaining ids.
+// Emit dimension d (K = d + 1 >= 2): every candidate keyed by its least
+// input id (not kept: after all ids), radix-sorted, then ranked inside each
+// bucket by the remaining ids. The output arrays have room for all M
+// candidates; the kept count goes to *m_out on the device.
 template <int K>
-static void emit_dim(const unsigned char *in, const int *fpos, const double *sizes, int M, const Cands &cd, int n,
-                     hipStream_t s, Scope &sc, ac_complex *res, int d, int m_out) {
+static void emit_dim(const unsigned char *in, const double *sizes, int M, const Cands &cd, int n, hipStream_t s,
+                     Scope &sc, ac_complex *res, int d, int *m_out) {
     typedef typename EmitPay<K>::type P;
-    res->count[d] = m_out;
-    res->d_simp[d] = static_cast<int32_t *>(dev_alloc((size_t)(m_out > 0 ? m_out : 1) * K * sizeof(int32_t)));
-    res->d_size[d] = static_cast<double *>(dev_alloc((size_t)(m_out > 0 ? m_out : 1) * sizeof(double)));
-    if (m_out == 0) return;
-    unsigned *key = sc.get<unsigned>(m_out);
-    P *pay = sc.get<P>(m_out);
-    k_emit_keys<K><<<grid_for(M), BLOCK, 0, s>>>(in, fpos, M, cd.up, cd.edge_i, cd.tri_k, cd.tri_e, cd.tet_t,
-                                                 cd.tet_l, cd.perm, key, pay);
+    res->d_simp[d] = static_cast<int32_t *>(dev_alloc((size_t)(M > 0 ? M : 1) * K * sizeof(int32_t)));
+    res->d_size[d] = static_cast<double *>(dev_alloc((size_t)(M > 0 ? M : 1) * sizeof(double)));
+    if (M == 0) {
+        fill<int>(m_out, 0, 1, s);
+        return;
+    }
+    unsigned *key = sc.get<unsigned>(M);
+    P *pay = sc.get<P>(M);
+    k_emit_keys<K><<<grid_for(M), BLOCK, 0, s>>>(in, M, cd.up, cd.edge_i, cd.tri_k, cd.tri_e, cd.tet_t, cd.tet_l,
+                                                 cd.perm, n, key, pay);
     LAUNCH_CHECK();
-    radix_sort<P>(key, pay, m_out, bits_for(n), s, sc);
-    k_emit_rank<K><<<grid_for(m_out), BLOCK, 0, s>>>(key, pay, m_out, sizes, res->d_simp[d], res->d_size[d]);
+    radix_sort<P>(key, pay, M, bits_for((long long)n + 1), s, sc);
+    k_emit_rank<K><<<grid_for(M), BLOCK, 0, s>>>(key, pay, M, n, sizes, res->d_simp[d], res->d_size[d]);
+    k_count_kept<<<1, 1, 0, s>>>(key, M, n, m_out);
     LAUNCH_CHECK();
 }
 
@@ -310,27 +339,18 @@ struct StageTimer {
     }
 };
 
-__global__ void __launch_bounds__(BLOCK) k_flags_to_int(const unsigned char *__restrict__ f, long long M,
-                                                         int *__restrict__ out) {
-    const long long i = (long long)blockIdx.x * BLOCK + threadIdx.x;
-    if (i < M) out[i] = f[i];
-}
+// Molecules of one call: balls [off[m], off[m+1]) form molecule m, each with
+// its own grid (cell side cell_mA[m] if given).
+struct Batch {
+    std::vector<int64_t> off;
+    std::vector<int32_t> cell_mA;
+};
 
-// Exclusive scan of 0/1 flags into pos[0..M]; pos[M] is the number set.
-static void scan_flags(const unsigned char *flags, long long M, int *pos, hipStream_t s, Scope &sc) {
-    if (M <= 0) {
-        fill<int>(pos, 0, 1, s);
-        return;
-    }
-    int *work = sc.get<int>(M);
-    k_flags_to_int<<<grid_for(M), BLOCK, 0, s>>>(flags, M, work);
-    LAUNCH_CHECK();
-    scan_i32(work, pos, M, s, sc);
-}
+constexpr int QTILE = 4096;  // balls per block of the quantise kernel
 
 // The whole pipeline from device arrays. Returns AC_OK and *out on success.
-static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n64, double alpha, const Options &o,
-                              hipStream_t s, ac_complex **out) {
+static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n64, const Batch &bt, double alpha,
+                              const Options &o, hipStream_t s, ac_complex **out) {
     *out = nullptr;
     if (n64 < 1 || n64 >= (1 << 26)) return set_error(AC_E_INVALID, "n must be in [1, 2^26)");
     if (!std::isfinite(alpha)) return set_error(AC_E_INVALID, "alpha is not finite");
@@ -346,25 +366,43 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
     res->device_result = true;
     try {
         tm.start(o.profile != 0, s);
-        // ---- quantise + stats ----
+        // ---- quantise + stats (per molecule) ----
         tm.mark(ST_QUANTISE);
+        const int n_mol = (int)bt.off.size() - 1;
         int4 *q = sc.get<int4>(n);
-        Stats *st = sc.get<Stats>(1);
         Counters *cnt = sc.get<Counters>(1);
         HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(Counters), s));
-        {
-            long long b = grid_for(n);
-            if (b > 2048) b = 2048;
-            Stats *part = sc.get<Stats>(b);
-            k_quantise<<<(unsigned)b, BLOCK, 0, s>>>(d_xyz, d_r, n, q, part);
-            LAUNCH_CHECK();
-            k_stats_reduce<<<1, BLOCK, 0, s>>>(part, (int)b, st);
-            LAUNCH_CHECK();
+        std::vector<int2> tiles;
+        std::vector<int> tile_first(n_mol + 1);
+        for (int m = 0; m < n_mol; m++) {
+            tile_first[m] = (int)tiles.size();
+            for (int64_t a = bt.off[m]; a < bt.off[m + 1]; a += QTILE)
+                tiles.push_back(make_int2((int)a, (int)std::min<int64_t>(a + QTILE, bt.off[m + 1])));
         }
-        const Stats hs = read_one(st, s);
-        if (hs.flags & 1) throw HipError{AC_E_INVALID, "non-finite coordinate, or radius not positive"};
-        if (hs.flags & 2) throw HipError{AC_E_RANGE, "coordinate or radius outside the exact bit budget"};
-        const long long sg2 = (long long)hs.wmax + aq;
+        tile_first[n_mol] = (int)tiles.size();
+        std::vector<Stats> hs(n_mol);
+        {
+            int2 *d_tiles = sc.get<int2>(tiles.size());
+            int *d_tile_first = sc.get<int>(n_mol + 1);
+            Stats *part = sc.get<Stats>(tiles.size());
+            Stats *st = sc.get<Stats>(n_mol);
+            HIP_TRY(hipMemcpyAsync(d_tiles, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync(d_tile_first, tile_first.data(), (n_mol + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+            k_quantise<<<(unsigned)tiles.size(), BLOCK, 0, s>>>(d_xyz, d_r, d_tiles, q, part);
+            LAUNCH_CHECK();
+            k_stats_reduce<<<(unsigned)n_mol, BLOCK, 0, s>>>(part, d_tile_first, st);
+            LAUNCH_CHECK();
+            HIP_TRY(hipMemcpyAsync(hs.data(), st, n_mol * sizeof(Stats), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        int flags = 0, wmax = 0;
+        for (const Stats &x : hs) {
+            flags |= x.flags;
+            wmax = std::max(wmax, x.wmax);
+        }
+        if (flags & 1) throw HipError{AC_E_INVALID, "non-finite coordinate, or radius not positive"};
+        if (flags & 2) throw HipError{AC_E_RANGE, "coordinate or radius outside the exact bit budget"};
+        const long long sg2 = (long long)wmax + aq;
         if (sg2 >= (1LL << 26)) throw HipError{AC_E_RANGE, "r_max^2 + alpha too large for the exact bit budget"};
         PredParams pp;
         pp.aq = aq;
@@ -372,22 +410,37 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         const long long sgc = isqrt_ceil(pp.sg2);
         pp.sgc = sgc;
         pp.bmax = 2.0 * (double)sgc;
-        pp.gmax = 4.0 * (double)pp.sg2 + (double)hs.wmax;
+        pp.gmax = 4.0 * (double)pp.sg2 + (double)wmax;
         pp.force_exact = o.force_exact;
 
-        // ---- grid ----
-        Grid g;
-        g.ox = hs.minx; g.oy = hs.miny; g.oz = hs.minz;
-        const long long ex = (long long)hs.maxx - hs.minx + 1, ey = (long long)hs.maxy - hs.miny + 1,
-                        ez = (long long)hs.maxz - hs.minz + 1;
-        long long side = o.cell_mA > 0 ? o.cell_mA : (sgc > 0 ? sgc : 1);
-        const long long cell_limit = std::max<long long>(8LL * n, 1LL << 22);
-        auto ncell_of = [&](long long sd) { return ((ex + sd - 1) / sd) * ((ey + sd - 1) / sd) * ((ez + sd - 1) / sd); };
-        while (ncell_of(side) > cell_limit) side = side + side / 4 + 1;
-        g.s = (int)side;
-        g.nx = (int)((ex + side - 1) / side); g.ny = (int)((ey + side - 1) / side); g.nz = (int)((ez + side - 1) / side);
-        g.reach = (int)((2 * sgc + side - 1) / side);
-        const long long ncell = (long long)g.nx * g.ny * g.nz;
+        // ---- grids: one per molecule, cells numbered consecutively ----
+        std::vector<Grid> grids(n_mol);
+        long long ncell = 0;
+        for (int m = 0; m < n_mol; m++) {
+            const Stats &h = hs[m];
+            const long long nm = bt.off[m + 1] - bt.off[m];
+            Grid &g = grids[m];
+            g.ox = h.minx; g.oy = h.miny; g.oz = h.minz;
+            const long long ex = (long long)h.maxx - h.minx + 1, ey = (long long)h.maxy - h.miny + 1,
+                            ez = (long long)h.maxz - h.minz + 1;
+            long long side = !bt.cell_mA.empty() ? bt.cell_mA[m] : (o.cell_mA > 0 ? o.cell_mA : (sgc > 0 ? sgc : 1));
+            const long long cell_limit = n_mol == 1 ? std::max<long long>(8LL * nm, 1LL << 22)
+                                                    : std::max<long long>(8LL * nm, 1LL << 15);
+            auto ncell_of = [&](long long sd) {
+                return ((ex + sd - 1) / sd) * ((ey + sd - 1) / sd) * ((ez + sd - 1) / sd);
+            };
+            while (ncell_of(side) > cell_limit) side = side + side / 4 + 1;
+            g.s = (int)side;
+            g.nx = (int)((ex + side - 1) / side); g.ny = (int)((ey + side - 1) / side); g.nz = (int)((ez + side - 1) / side);
+            g.reach = (int)((2 * sgc + side - 1) / side);
+            g.base = ncell;
+            g.a0 = (int)bt.off[m];
+            g.a1 = (int)bt.off[m + 1];
+            ncell += (long long)g.nx * g.ny * g.nz;
+        }
+        if (ncell >= (long long)INT_MAX) throw HipError{AC_E_CAPACITY, "too many grid cells"};
+        Grid *d_grids = sc.get<Grid>(n_mol);
+        HIP_TRY(hipMemcpyAsync(d_grids, grids.data(), n_mol * sizeof(Grid), hipMemcpyHostToDevice, s));
 
         // ---- binning ----
         tm.mark(ST_BIN);
@@ -395,7 +448,7 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         unsigned *cidx = sc.get<unsigned>(n);
         int *cell_count = sc.get<int>(ncell + 1);
         int *cell_start = sc.get<int>(ncell + 1);
-        k_cell_key<<<grid_for(n), BLOCK, 0, s>>>(q, n, g, ckey, cidx);
+        k_cell_key<<<grid_for(n), BLOCK, 0, s>>>(q, n, d_grids, n_mol, ckey, cidx);
         LAUNCH_CHECK();
         radix_sort<unsigned>(ckey, cidx, n, bits_for(ncell), s, sc);
         fill<int>(cell_count, 0, ncell, s);
@@ -412,7 +465,7 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         int *nbr_start = sc.get<int>(n + 1), *up_start = sc.get<int>(n + 1);
         unsigned char *vgab = sc.get<unsigned char>(n);
         tm.mark(ST_NBR_COUNT);
-        k_neighbours<NB_COUNT><<<grid_for(n), BLOCK, 0, s>>>(atom, perm, n, g, cell_start, pp, deg_n, deg_up, nullptr,
+        k_neighbours<NB_COUNT><<<grid_for(n), BLOCK, 0, s>>>(atom, perm, n, d_grids, n_mol, cell_start, pp, deg_n, deg_up, nullptr,
                                                             nullptr, nullptr, nullptr, nullptr, nullptr);
         LAUNCH_CHECK();
         tm.mark(ST_NBR_SCAN);
@@ -428,7 +481,7 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         int *up = sc.get<int>(E > 0 ? E : 1);
         int *edge_i = sc.get<int>(E > 0 ? E : 1);
         tm.mark(ST_NBR_FILL);
-        k_neighbours<NB_FILL><<<grid_for(n), BLOCK, 0, s>>>(atom, perm, n, g, cell_start, pp, nullptr, nullptr,
+        k_neighbours<NB_FILL><<<grid_for(n), BLOCK, 0, s>>>(atom, perm, n, d_grids, n_mol, cell_start, pp, nullptr, nullptr,
                                                            nbr_start, up_start, nbr, up, edge_i, vgab);
         LAUNCH_CHECK();
         const int *nbr_cnt = deg_n;
@@ -520,7 +573,7 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         }
         tm.mark(ST_EDGE_FINAL);
         if (E > 0) {
-            k_edge_final<<<grid_for(E), BLOCK, 0, s>>>(atom, up, edge_i, E, egab, edge_att, edge_min, ein, esize, vgab,
+            k_edge_final<<<grid_for(E), BLOCK, 0, s>>>(atom, perm, up, edge_i, E, egab, edge_att, edge_min, ein, esize, vgab,
                                                       vert_att, vert_min);
             LAUNCH_CHECK();
         }
@@ -533,35 +586,52 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         tm.mark(ST_EMIT);
         int *vpos = sc.get<int>(n + 1);
         scan_i32(vin_in, vpos, n, s, sc);
-        int *epos = sc.get<int>(E + 1), *tpos = sc.get<int>(T + 1), *qpos = sc.get<int>(Q + 1);
-        scan_flags(ein, E, epos, s, sc);
-        scan_flags(tin, T, tpos, s, sc);
-        scan_flags(qin, Q, qpos, s, sc);
-        k_copy_int<<<1, 1, 0, s>>>(&cnt->m1, epos + E);
-        k_copy_int<<<1, 1, 0, s>>>(&cnt->m2, tpos + T);
-        k_copy_int<<<1, 1, 0, s>>>(&cnt->m3, qpos + Q);
         k_copy_int<<<1, 1, 0, s>>>(&cnt->m0, vpos + n);
         LAUNCH_CHECK();
-        const Counters cf = read_one(cnt, s);
-        const int m0 = cf.m0, m1 = cf.m1, m2 = cf.m2, m3 = cf.m3;
+        res->d_simp[0] = static_cast<int32_t *>(dev_alloc((size_t)n * sizeof(int32_t)));
+        res->d_size[0] = static_cast<double *>(dev_alloc((size_t)n * sizeof(double)));
+        k_vert_emit<<<grid_for(n), BLOCK, 0, s>>>(vin_in, vpos, vsize_in, n, res->d_simp[0], res->d_size[0]);
+        LAUNCH_CHECK();
+        const Cands cd{up, edge_i, tri_k, tri_e, tet_t, tet_l, perm};
+        emit_dim<2>(ein, esize, E, cd, n, s, sc, res, 1, &cnt->m1);
+        emit_dim<3>(tin, tsize, T, cd, n, s, sc, res, 2, &cnt->m2);
+        emit_dim<4>(qin, qsize, Q, cd, n, s, sc, res, 3, &cnt->m3);
+        tm.mark(ST_COUNT);
+        // rows of each molecule in the sorted outputs
+        res->n_mol = n_mol;
+        long long *d_rows = sc.get<long long>(4 * (n_mol + 1));
+        {
+            long long *d_bound = sc.get<long long>(n_mol + 1);
+            HIP_TRY(hipMemcpyAsync(d_bound, bt.off.data(), (n_mol + 1) * sizeof(long long), hipMemcpyHostToDevice, s));
+            const unsigned nb = (unsigned)((n_mol + 1 + BLOCK - 1) / BLOCK);
+            k_row_lower_bound<1><<<nb, BLOCK, 0, s>>>(res->d_simp[0], &cnt->m0, d_bound, n_mol + 1, d_rows);
+            k_row_lower_bound<2><<<nb, BLOCK, 0, s>>>(res->d_simp[1], &cnt->m1, d_bound, n_mol + 1, d_rows + (n_mol + 1));
+            k_row_lower_bound<3><<<nb, BLOCK, 0, s>>>(res->d_simp[2], &cnt->m2, d_bound, n_mol + 1, d_rows + 2 * (n_mol + 1));
+            k_row_lower_bound<4><<<nb, BLOCK, 0, s>>>(res->d_simp[3], &cnt->m3, d_bound, n_mol + 1, d_rows + 3 * (n_mol + 1));
+            LAUNCH_CHECK();
+        }
+        for (int d = 0; d < 4; d++) {
+            res->mol_rows[d].resize(n_mol + 1);
+            HIP_TRY(hipMemcpyAsync(res->mol_rows[d].data(), d_rows + d * (n_mol + 1), (n_mol + 1) * sizeof(long long),
+                                   hipMemcpyDeviceToHost, s));
+        }
+        Counters cf;
+        HIP_TRY(hipMemcpyAsync(&cf, cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        tm.collect(res->stage_ms);
         if (cf.lookup) throw HipError{AC_E_DEVICE, "internal error: a facet of a kept simplex is not a candidate"};
         res->cand[0] = n;
         res->cand[1] = E;
         res->cand[2] = T;
         res->cand[3] = Q;
         res->fallbacks = (int64_t)cf.exact_fallbacks;
-        res->count[0] = m0;
-        res->d_simp[0] = static_cast<int32_t *>(dev_alloc((size_t)(m0 > 0 ? m0 : 1) * sizeof(int32_t)));
-        res->d_size[0] = static_cast<double *>(dev_alloc((size_t)(m0 > 0 ? m0 : 1) * sizeof(double)));
-        k_vert_emit<<<grid_for(n), BLOCK, 0, s>>>(vin_in, vpos, vsize_in, n, res->d_simp[0], res->d_size[0]);
-        LAUNCH_CHECK();
-        const Cands cd{up, edge_i, tri_k, tri_e, tet_t, tet_l, perm};
-        emit_dim<2>(ein, epos, esize, E, cd, n, s, sc, res, 1, m1);
-        emit_dim<3>(tin, tpos, tsize, T, cd, n, s, sc, res, 2, m2);
-        emit_dim<4>(qin, qpos, qsize, Q, cd, n, s, sc, res, 3, m3);
-        tm.mark(ST_COUNT);
-        HIP_TRY(hipStreamSynchronize(s));
-        tm.collect(res->stage_ms);
+        res->work[0] = ncell;
+        res->work[1] = Nn;
+        res->n = n;
+        res->count[0] = cf.m0;
+        res->count[1] = cf.m1;
+        res->count[2] = cf.m2;
+        res->count[3] = cf.m3;
     } catch (const HipError &e) {
         (void)hipStreamSynchronize(s);
         free_complex(res);
@@ -569,6 +639,136 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
     }
     *out = res;
     g_last_error.clear();
+    return AC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Union volume / area (measure.hpp)
+
+static long long incidence_count(const ac_complex *c) {
+    long long M = 0;
+    for (int d = 0; d < 4; d++) M += c->count[d] * (d + 1);
+    return M;
+}
+
+static void check_measure_args(const ac_complex *c, const double *d_xyz, const double *d_radii, int64_t n) {
+    if (!c) throw HipError{AC_E_INVALID, "complex is NULL"};
+    if (!d_xyz || !d_radii) throw HipError{AC_E_INVALID, "NULL input pointer"};
+    if (n != c->n) throw HipError{AC_E_INVALID, "n differs from the number of balls the complex was built on"};
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != c->device) throw HipError{AC_E_INVALID, "the complex lives on another device"};
+    if (incidence_count(c) >= INT_MAX) throw HipError{AC_E_CAPACITY, "too many simplex corners"};
+}
+
+// Sorts the corners of all simplices by ball id once per complex.
+static void ensure_incidence(ac_complex *c, hipStream_t s) {
+    if (c->inc_slot) return;
+    const long long M = incidence_count(c);
+    const int n = (int)c->n;
+    int32_t *slot = static_cast<int32_t *>(dev_alloc((size_t)(M > 0 ? M : 1) * sizeof(int32_t)));
+    int32_t *start = nullptr;
+    try {
+        start = static_cast<int32_t *>(dev_alloc((size_t)(n + 1) * sizeof(int32_t)));
+        Scope sc;
+        unsigned *key = sc.get<unsigned>(M > 0 ? M : 1);
+        long long off = 0;
+        for (int d = 0; d < 4; d++) {
+            const long long m = c->count[d] * (d + 1);
+            if (m) HIP_TRY(hipMemcpyAsync(key + off, c->d_simp[d], m * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+            off += m;
+        }
+        if (M > 0) {
+            k_iota<<<(unsigned)((M + MEASURE_BLOCK - 1) / MEASURE_BLOCK), MEASURE_BLOCK, 0, s>>>(slot, M);
+            LAUNCH_CHECK();
+            int32_t *sorted = slot;
+            radix_sort<int>(key, sorted, (int)M, bits_for(n), s, sc);
+            if (sorted != slot)
+                HIP_TRY(hipMemcpyAsync(slot, sorted, (size_t)M * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        }
+        k_incidence_start<<<(unsigned)((n + 1 + MEASURE_BLOCK - 1) / MEASURE_BLOCK), MEASURE_BLOCK, 0, s>>>(key, M, n,
+                                                                                                          start);
+        LAUNCH_CHECK();
+        HIP_TRY(hipStreamSynchronize(s));  // before the scope's blocks go back to the pool
+    } catch (...) {
+        dev_free(slot);
+        dev_free(start);
+        throw;
+    }
+    c->inc_slot = slot;
+    c->inc_start = start;
+}
+
+template <int K>
+static void measure_fwd_dim(const ac_complex *c, const double *x, const double *r, double *part, int &nb,
+                            hipStream_t s) {
+    const long long m = c->count[K - 1];
+    if (m == 0) return;
+    const unsigned b = (unsigned)((m + MEASURE_BLOCK - 1) / MEASURE_BLOCK);
+    k_measure_fwd<K><<<b, MEASURE_BLOCK, 0, s>>>(c->d_simp[K - 1], m, x, r, part + 2LL * nb);
+    LAUNCH_CHECK();
+    nb += (int)b;
+}
+
+// Writes V, A to d_out (device), or to the complex's own buffer if d_out is
+// NULL; returns where they are.
+static double *measure_forward(ac_complex *c, const double *x, const double *r, double *d_out, hipStream_t s) {
+    long long nb_total = 0;
+    for (int d = 0; d < 4; d++) nb_total += (c->count[d] + MEASURE_BLOCK - 1) / MEASURE_BLOCK;
+    if (!c->meas_part) c->meas_part = static_cast<double *>(dev_alloc((size_t)(2 * nb_total + 2) * sizeof(double)));
+    double *part = c->meas_part;
+    if (!d_out) d_out = part + 2 * nb_total;
+    int nb = 0;
+    measure_fwd_dim<1>(c, x, r, part, nb, s);
+    measure_fwd_dim<2>(c, x, r, part, nb, s);
+    measure_fwd_dim<3>(c, x, r, part, nb, s);
+    measure_fwd_dim<4>(c, x, r, part, nb, s);
+    k_measure_total<<<1, MEASURE_BLOCK, 0, s>>>(part, nb, d_out);
+    LAUNCH_CHECK();
+    return d_out;
+}
+
+template <int K>
+static void measure_bwd_dim(const ac_complex *c, const double *x, const double *r, const double *g, double4 *contrib,
+                            long long &off, hipStream_t s) {
+    const long long m = c->count[K - 1];
+    if (m == 0) return;
+    const unsigned b = (unsigned)((m + MEASURE_BLOCK - 1) / MEASURE_BLOCK);
+    k_measure_bwd<K><<<b, MEASURE_BLOCK, 0, s>>>(c->d_simp[K - 1], m, x, r, g, contrib + off);
+    LAUNCH_CHECK();
+    off += m * K;
+}
+
+// Validated molecule offsets of a batch call.
+static ac_status batch_from(const int64_t *offsets, int64_t n_mol, const int32_t *cell_mA, Batch &bt) {
+    if (!offsets) return set_error(AC_E_INVALID, "offsets is NULL");
+    if (n_mol < 1 || n_mol > (1 << 20)) return set_error(AC_E_INVALID, "n_mol must be in [1, 2^20]");
+    if (offsets[0] != 0) return set_error(AC_E_INVALID, "offsets[0] must be 0");
+    bt.off.assign(offsets, offsets + n_mol + 1);
+    for (int64_t m = 0; m < n_mol; m++)
+        if (bt.off[m + 1] <= bt.off[m]) return set_error(AC_E_INVALID, "offsets must increase strictly (no empty molecule)");
+    if (bt.off[n_mol] >= (1 << 26)) return set_error(AC_E_INVALID, "total balls must be below 2^26");
+    bt.cell_mA.clear();
+    if (cell_mA) {
+        bt.cell_mA.assign(cell_mA, cell_mA + n_mol);
+        for (int32_t c : bt.cell_mA)
+            if (c < 1) return set_error(AC_E_INVALID, "cell sides must be positive");
+    }
+    return AC_OK;
+}
+
+// Device time of one pipeline run: the sum of its stage events (ms).
+static ac_status timed_run(const double *x, const double *r, int64_t n, const Batch &bt, double alpha, Options o,
+                           hipStream_t s, double *ms) {
+    o.profile = 1;
+    ac_complex *c = nullptr;
+    const ac_status st = run_pipeline(x, r, n, bt, alpha, o, s, &c);
+    if (st != AC_OK) return st;
+    double t = 0;
+    for (int i = 0; i < ST_COUNT; i++)
+        if (c->stage_ms[i] > 0) t += c->stage_ms[i];
+    free_complex(c);
+    *ms = t;
     return AC_OK;
 }
 
@@ -593,7 +793,9 @@ ac_status ac_alpha_complex_device(const double *d_xyz, const double *d_radii, in
     *out = nullptr;
     if (!d_xyz || !d_radii) return set_error(AC_E_INVALID, "NULL input pointer");
     try {
-        return run_pipeline(d_xyz, d_radii, n, alpha, parse(opt), static_cast<hipStream_t>(stream), out);
+        Batch bt;
+        bt.off = {0, n};
+        return run_pipeline(d_xyz, d_radii, n, bt, alpha, parse(opt), static_cast<hipStream_t>(stream), out);
     } catch (const HipError &e) {
         return set_error(e.st, e.msg);
     } catch (...) {
@@ -613,7 +815,10 @@ ac_status ac_alpha_complex(const double *xyz, const double *radii, int64_t n, do
         dr = dev_alloc((size_t)n * sizeof(double));
         HIP_TRY(hipMemcpy(dx, xyz, (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(dr, radii, (size_t)n * sizeof(double), hipMemcpyHostToDevice));
-        ac_status st = run_pipeline(static_cast<double *>(dx), static_cast<double *>(dr), n, alpha, parse(opt), nullptr, out);
+        Batch bt;
+        bt.off = {0, n};
+        ac_status st = run_pipeline(static_cast<double *>(dx), static_cast<double *>(dr), n, bt, alpha, parse(opt), nullptr,
+                                    out);
         dev_free(dx);
         dev_free(dr);
         if (st != AC_OK) return st;
@@ -634,6 +839,102 @@ ac_status ac_alpha_complex(const double *xyz, const double *radii, int64_t n, do
         dev_free(dr);
         return set_error(AC_E_DEVICE, "unexpected host exception");
     }
+}
+
+ac_status ac_alpha_complex_batch(const double *d_xyz, const double *d_radii, const int64_t *offsets, int64_t n_mol,
+                                 double alpha, const ac_options *opt, const int32_t *cell_mA, void *stream,
+                                 ac_complex **out) {
+    if (!out) return set_error(AC_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!d_xyz || !d_radii) return set_error(AC_E_INVALID, "NULL input pointer");
+    try {
+        Batch bt;
+        const ac_status st = batch_from(offsets, n_mol, cell_mA, bt);
+        if (st != AC_OK) return st;
+        return run_pipeline(d_xyz, d_radii, bt.off[n_mol], bt, alpha, parse(opt), static_cast<hipStream_t>(stream), out);
+    } catch (const HipError &e) {
+        return set_error(e.st, e.msg);
+    } catch (...) {
+        return set_error(AC_E_DEVICE, "unexpected host exception");
+    }
+}
+
+int64_t ac_molecule_count(const ac_complex *c) { return c ? c->n_mol : -1; }
+
+const int64_t *ac_molecule_rows(const ac_complex *c, int dim) {
+    if (!c || dim < 0 || dim > 3 || c->mol_rows[dim].empty()) return nullptr;
+    return c->mol_rows[dim].data();
+}
+
+ac_status ac_tune_cells(const double *d_xyz, const double *d_radii, const int64_t *offsets, int64_t n_mol, double alpha,
+                        const ac_options *opt, void *stream, int32_t *cell_mA_out, int32_t *bucket_out) {
+    if (!d_xyz || !d_radii || !cell_mA_out) return set_error(AC_E_INVALID, "NULL pointer");
+    try {
+        Batch all;
+        ac_status st = batch_from(offsets, n_mol, nullptr, all);
+        if (st != AC_OK) return st;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const Options o = parse(opt);
+        // grown radius s_g (mA): the default cell side the candidates scale
+        double rmax = 0;
+        {
+            std::vector<double> hr((size_t)all.off[n_mol]);
+            HIP_TRY(hipMemcpyAsync(hr.data(), d_radii, hr.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            for (double v : hr) rmax = std::max(rmax, v);
+        }
+        const double sg = std::sqrt(std::max(rmax * rmax + alpha, 1e-6)) * 1000.0;
+        static const double kFactor[] = {0.5, 0.7, 1.0, 1.4, 2.0};
+        // size buckets: [0, 2k), [2k, 8k), [8k, 32k), [32k, inf)
+        auto bucket_of = [](int64_t nm) { return nm < 2000 ? 0 : nm < 8000 ? 1 : nm < 32000 ? 2 : 3; };
+        for (int b = 0; b < 4; b++) {
+            std::vector<int64_t> mols;
+            for (int64_t m = 0; m < n_mol; m++)
+                if (bucket_of(all.off[m + 1] - all.off[m]) == b) mols.push_back(m);
+            if (mols.empty()) continue;
+            // the bucket's molecules, copied into one contiguous sub-batch
+            Batch sub;
+            sub.off.push_back(0);
+            for (int64_t m : mols) sub.off.push_back(sub.off.back() + all.off[m + 1] - all.off[m]);
+            const int64_t ns = sub.off.back();
+            Scope sc;
+            double *x = sc.get<double>(3 * ns), *r = sc.get<double>(ns);
+            for (size_t k = 0; k < mols.size(); k++) {
+                const int64_t m = mols[k], nm = all.off[m + 1] - all.off[m];
+                HIP_TRY(hipMemcpyAsync(x + 3 * sub.off[k], d_xyz + 3 * all.off[m], 3 * nm * sizeof(double),
+                                       hipMemcpyDeviceToDevice, s));
+                HIP_TRY(hipMemcpyAsync(r + sub.off[k], d_radii + all.off[m], nm * sizeof(double), hipMemcpyDeviceToDevice, s));
+            }
+            double best_t = -1;
+            int32_t best = (int32_t)std::ceil(sg);
+            for (double f : kFactor) {
+                const int32_t side = std::max<int32_t>(1, (int32_t)std::lround(f * sg));
+                sub.cell_mA.assign(mols.size(), side);
+                double t = -1;
+                for (int rep = 0; rep < 3; rep++) {  // first run warms the pool
+                    double tr = 0;
+                    st = timed_run(x, r, ns, sub, alpha, o, s, &tr);
+                    if (st != AC_OK) return st;
+                    if (rep > 0 && (t < 0 || tr < t)) t = tr;
+                }
+                if (best_t < 0 || t < best_t) {
+                    best_t = t;
+                    best = side;
+                }
+            }
+            for (int64_t m : mols) {
+                cell_mA_out[m] = best;
+                if (bucket_out) bucket_out[m] = b;
+            }
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+    } catch (const HipError &e) {
+        return set_error(e.st, e.msg);
+    } catch (...) {
+        return set_error(AC_E_DEVICE, "unexpected host exception");
+    }
+    g_last_error.clear();
+    return AC_OK;
 }
 
 int64_t ac_count(const ac_complex *c, int dim) {
@@ -682,6 +983,74 @@ int64_t ac_candidate_count(const ac_complex *c, int dim) {
 }
 
 int64_t ac_exact_fallbacks(const ac_complex *c) { return c ? c->fallbacks : -1; }
+
+int64_t ac_work_count(const ac_complex *c, int which) {
+    if (!c || which < 0 || which > 1) return -1;
+    return c->work[which];
+}
+
+ac_status ac_union_measure_device(ac_complex *c, const double *d_xyz, const double *d_radii, int64_t n,
+                                  double *d_out, void *stream) {
+    try {
+        check_measure_args(c, d_xyz, d_radii, n);
+        if (!d_out) throw HipError{AC_E_INVALID, "out is NULL"};
+        measure_forward(c, d_xyz, d_radii, d_out, static_cast<hipStream_t>(stream));
+    } catch (const HipError &e) {
+        return set_error(e.st, e.msg);
+    } catch (...) {
+        return set_error(AC_E_DEVICE, "unexpected host exception");
+    }
+    g_last_error.clear();
+    return AC_OK;
+}
+
+ac_status ac_union_measure(ac_complex *c, const double *d_xyz, const double *d_radii, int64_t n, double *V,
+                           double *A, void *stream) {
+    if (!V || !A) return set_error(AC_E_INVALID, "V or A is NULL");
+    try {
+        check_measure_args(c, d_xyz, d_radii, n);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const double *d_out = measure_forward(c, d_xyz, d_radii, nullptr, s);
+        double h[2];
+        HIP_TRY(hipMemcpyAsync(h, d_out, sizeof(h), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        *V = h[0];
+        *A = h[1];
+    } catch (const HipError &e) {
+        return set_error(e.st, e.msg);
+    } catch (...) {
+        return set_error(AC_E_DEVICE, "unexpected host exception");
+    }
+    g_last_error.clear();
+    return AC_OK;
+}
+
+ac_status ac_union_measure_backward(ac_complex *c, const double *d_xyz, const double *d_radii, int64_t n,
+                                    const double *d_grad, double *d_dxyz, double *d_dradii, void *stream) {
+    try {
+        check_measure_args(c, d_xyz, d_radii, n);
+        if (!d_grad || !d_dxyz || !d_dradii) throw HipError{AC_E_INVALID, "NULL gradient pointer"};
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        ensure_incidence(c, s);
+        const long long M = incidence_count(c);
+        if (!c->meas_contrib) c->meas_contrib = static_cast<double4 *>(dev_alloc((size_t)(M > 0 ? M : 1) * sizeof(double4)));
+        double4 *contrib = c->meas_contrib;
+        long long off = 0;
+        measure_bwd_dim<1>(c, d_xyz, d_radii, d_grad, contrib, off, s);
+        measure_bwd_dim<2>(c, d_xyz, d_radii, d_grad, contrib, off, s);
+        measure_bwd_dim<3>(c, d_xyz, d_radii, d_grad, contrib, off, s);
+        measure_bwd_dim<4>(c, d_xyz, d_radii, d_grad, contrib, off, s);
+        k_measure_gather<<<(unsigned)((n + MEASURE_BLOCK - 1) / MEASURE_BLOCK), MEASURE_BLOCK, 0, s>>>(
+            c->inc_start, c->inc_slot, contrib, (int)n, d_dxyz, d_dradii);
+        LAUNCH_CHECK();
+    } catch (const HipError &e) {
+        return set_error(e.st, e.msg);
+    } catch (...) {
+        return set_error(AC_E_DEVICE, "unexpected host exception");
+    }
+    g_last_error.clear();
+    return AC_OK;
+}
 
 void ac_free(ac_complex *c) { free_complex(c); }
 

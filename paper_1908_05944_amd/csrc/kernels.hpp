@@ -30,23 +30,40 @@ struct Stats {
 };
 
 // Uniform grid (Sec. 4.2), cells numbered in row-major order (x fastest), so
-// the cells of one grid row are contiguous in the sorted order.
+// the cells of one grid row are contiguous in the sorted order. A batch of
+// molecules has one grid per molecule; their cells are numbered one after
+// the other in a single table, so no ball ever sees another molecule's balls.
 struct Grid {
     int ox, oy, oz;   // low corner (mA)
     int s;            // cell side (mA)
     int nx, ny, nz;
     int reach;        // cells to scan on each side for neighbours
+    long long base;   // first cell of this grid in the shared cell table
+    int a0, a1;       // the molecule's balls: [a0, a1) in input and in sorted order
 };
+
+// Molecule of ball i (input or sorted index): the last grid with a0 <= i.
+__device__ __forceinline__ int mol_of(const Grid *__restrict__ grids, int n_mol, int i) {
+    int lo = 0, hi = n_mol - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (grids[mid].a0 <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
 
 constexpr int BLOCK = 256;
 
 // ---------------------------------------------------------------------------
-// Quantise: x -> rint(1000 x) (round half to even), W = R^2. Each block writes
-// its partial bounding box and flags; k_stats_reduce folds the partials.
+// Quantise: x -> rint(1000 x) (round half to even), W = R^2. Block b handles
+// the balls [tiles[b].x, tiles[b].y), all of one molecule, and writes their
+// bounding box and flags; k_stats_reduce folds each molecule's tiles.
 __global__ void __launch_bounds__(BLOCK) k_quantise(const double *__restrict__ xyz, const double *__restrict__ r,
-                                                     int n, int4 *__restrict__ q, Stats *__restrict__ part) {
+                                                     const int2 *__restrict__ tiles, int4 *__restrict__ q,
+                                                     Stats *__restrict__ part) {
     int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN}, wmax = 0, flags = 0;
-    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
+    const int2 tile = tiles[blockIdx.x];
+    for (int i = tile.x + threadIdx.x; i < tile.y; i += BLOCK) {
         int c[3];
 #pragma unroll
         for (int a = 0; a < 3; a++) {
@@ -103,10 +120,12 @@ __global__ void __launch_bounds__(BLOCK) k_quantise(const double *__restrict__ x
     }
 }
 
-// One block folds the per-block partials into st.
-__global__ void __launch_bounds__(BLOCK) k_stats_reduce(const Stats *__restrict__ part, int nparts, Stats *st) {
+// Block m folds the partials of molecule m's tiles [tile_first[m],
+// tile_first[m+1]) into st[m].
+__global__ void __launch_bounds__(BLOCK) k_stats_reduce(const Stats *__restrict__ part, const int *__restrict__ tile_first,
+                                                         Stats *st) {
     Stats b{INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN, 0, 0};
-    for (int k = threadIdx.x; k < nparts; k += BLOCK) {
+    for (int k = tile_first[blockIdx.x] + threadIdx.x; k < tile_first[blockIdx.x + 1]; k += BLOCK) {
         const Stats &o = part[k];
         b.minx = min(b.minx, o.minx); b.miny = min(b.miny, o.miny); b.minz = min(b.minz, o.minz);
         b.maxx = max(b.maxx, o.maxx); b.maxy = max(b.maxy, o.maxy); b.maxz = max(b.maxz, o.maxz);
@@ -122,7 +141,7 @@ __global__ void __launch_bounds__(BLOCK) k_stats_reduce(const Stats *__restrict_
             b.maxx = max(b.maxx, o.maxx); b.maxy = max(b.maxy, o.maxy); b.maxz = max(b.maxz, o.maxz);
             b.wmax = max(b.wmax, o.wmax); b.flags |= o.flags;
         }
-        *st = b;
+        st[blockIdx.x] = b;
     }
 }
 
@@ -142,12 +161,13 @@ __device__ __forceinline__ long long cell_of(const Grid &g, int x, int y, int z)
     return cell_id(g, (x - g.ox) / g.s, (y - g.oy) / g.s, (z - g.oz) / g.s);
 }
 
-__global__ void __launch_bounds__(BLOCK) k_cell_key(const int4 *__restrict__ q, int n, Grid g,
-                                                     unsigned *__restrict__ key, unsigned *__restrict__ idx) {
+__global__ void __launch_bounds__(BLOCK) k_cell_key(const int4 *__restrict__ q, int n, const Grid *__restrict__ grids,
+                                                     int n_mol, unsigned *__restrict__ key, unsigned *__restrict__ idx) {
     const int i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= n) return;
     const int4 a = q[i];
-    key[i] = (unsigned)cell_of(g, a.x, a.y, a.z);
+    const Grid &g = grids[mol_of(grids, n_mol, i)];
+    key[i] = (unsigned)(g.base + cell_of(g, a.x, a.y, a.z));
     idx[i] = (unsigned)i;
 }
 
@@ -197,21 +217,39 @@ enum { NB_COUNT = 0, NB_FILL = 1 };
 
 template <int MODE>
 __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ atom, const int *__restrict__ perm, int n,
-                                                       Grid g, const int *__restrict__ cell_start, PredParams pp,
+                                                       const Grid *__restrict__ grids, int n_mol,
+                                                       const int *__restrict__ cell_start, PredParams pp,
                                                        int *__restrict__ deg_n, int *__restrict__ deg_up,
                                                        const int *__restrict__ nbr_start, const int *__restrict__ up_start,
                                                        int *__restrict__ nbr, int *__restrict__ up,
                                                        int *__restrict__ edge_i, unsigned char *__restrict__ vgab) {
     constexpr bool FILL = MODE == NB_FILL;
-    const int i = xcd_block() * BLOCK + threadIdx.x;
-    if (i >= n) return;
-    const int4 a = atom[i];
-    const int ra = a.w + (int)pp.aq;  // |aq| < 2^26 and W < 2^26
+    // The fill pass stages the block's rows in LDS and writes them out as one
+    // contiguous range (the block's rows are adjacent in the CSR arrays);
+    // rows written straight from the scan would be partial-line scattered
+    // stores. A block whose rows exceed the LDS buffers writes directly.
+    constexpr int LDS_N = FILL ? 4096 : 1, LDS_U = FILL ? 2048 : 1;
+    __shared__ int sn[LDS_N];
+    __shared__ int su[LDS_U];
+    const int b0 = xcd_block() * BLOCK;
+    const int i = b0 + threadIdx.x;
+    const bool valid = i < n;
+    int bn = 0, bu = 0, en = 0, eu = 0;
+    bool staged = false;
+    if (FILL) {
+        const int last = min(b0 + BLOCK, n);
+        bn = nbr_start[b0]; en = nbr_start[last];
+        bu = up_start[b0]; eu = up_start[last];
+        staged = en - bn <= LDS_N && eu - bu <= LDS_U;
+    }
+    const int4 a = valid ? atom[i] : make_int4(0, 0, 0, 0);
+    const int ra = valid ? a.w + (int)pp.aq : -1;  // |aq| < 2^26 and W < 2^26
     int cn = 0, cu = 0;
     bool gab = true;
     if (ra >= 0) {
         const int pn = FILL ? nbr_start[i] : 0;
         const int pu = FILL ? up_start[i] : 0;
+        const Grid g = grids[mol_of(grids, n_mol, i)];
         const int cx = (a.x - g.ox) / g.s, cy = (a.y - g.oy) / g.s, cz = (a.z - g.oz) / g.s;
         const int x0 = max(cx - g.reach, 0), x1 = min(cx + g.reach, g.nx - 1);
         const int y0 = max(cy - g.reach, 0), y1 = min(cy + g.reach, g.ny - 1);
@@ -229,7 +267,7 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
                 const int ylo = g.oy + y * g.s, yhi = ylo + g.s - 1;
                 const int dym = a.y < ylo ? ylo - a.y : (a.y > yhi ? a.y - yhi : 0);
                 if (dym > reach1 || rz - dym * dym < 0) continue;
-                const long long rb = ((long long)z * g.ny + y) * g.nx;
+                const long long rb = g.base + ((long long)z * g.ny + y) * g.nx;
                 const int s = cell_start[rb + x0], e = cell_start[rb + x1 + 1];
                 for (int j = s; j < e; j++) {
                     if (j == i) continue;
@@ -244,14 +282,14 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
                     const int L = d2 - ra - rb2;
                     if (L > 0 && (i64)L * L > 4 * (i64)ra * rb2) continue;
                     if (FILL) {
-                        nbr[pn + cn] = j;
+                        if (staged) sn[pn - bn + cn] = j; else nbr[pn + cn] = j;
                         if (gab && vertex_violation_sign(a, i, b, j, perm) < 0) gab = false;
                     }
                     cn++;
                     if (j > i) {
                         const Edge ed = edge_setup(a, b);
                         if (edge_ac3(ed, pp.aq)) {
-                            if (FILL) { up[pu + cu] = j; edge_i[pu + cu] = i; }
+                            if (FILL) { if (staged) su[pu - bu + cu] = j; else up[pu + cu] = j; }
                             cu++;
                         }
                     }
@@ -259,8 +297,30 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
             }
         }
     }
-    if (!FILL) { deg_n[i] = cn; deg_up[i] = cu; }
-    else vgab[i] = (unsigned char)(ra >= 0 && gab);
+    if (!FILL) {
+        if (valid) { deg_n[i] = cn; deg_up[i] = cu; }
+        return;
+    }
+    if (valid) vgab[i] = (unsigned char)(ra >= 0 && gab);
+    if (!staged) {
+        // rows went straight to nbr / up; the upper rows' owner ids remain
+        if (valid) {
+            const int pu = up_start[i];
+            for (int k = 0; k < cu; k++) edge_i[pu + k] = i;
+        }
+        return;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < en - bn; k += BLOCK) nbr[bn + k] = sn[k];
+    for (int k = threadIdx.x; k < eu - bu; k += BLOCK) up[bu + k] = su[k];
+    __syncthreads();
+    // owner of each upper-row slot: a ball writes its id over its own slots
+    if (valid) {
+        const int pu = up_start[i] - bu;
+        for (int k = 0; k < cu; k++) su[pu + k] = i;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < eu - bu; k += BLOCK) edge_i[bu + k] = su[k];
 }
 
 __global__ void k_copy_int(int *__restrict__ dst, const int *__restrict__ src) { *dst = *src; }
@@ -344,6 +404,41 @@ __global__ void __launch_bounds__(BLOCK) k_triangles(const int4 *__restrict__ at
     if (!FILL) tri_cnt[e] = c;
 }
 
+// OrthoSize evaluated with the vertices in input-index order: the rounded
+// float64 value then depends only on the balls, not on the grid, the sorted
+// order or the other molecules of a batch (reported Sizes are bit-identical
+// whatever the cell size).
+__device__ __forceinline__ double edge_size_canon(int4 a, int ia, int4 b, int ib) {
+    return ia < ib ? edge_orthosize(edge_setup(a, b)) : edge_orthosize(edge_setup(b, a));
+}
+
+template <int K>
+__device__ __forceinline__ void sort_by_id(int4 (&v)[K], int (&id)[K]) {
+#pragma unroll
+    for (int a = 1; a < K; a++)
+#pragma unroll
+        for (int b = a; b > 0; b--)
+            if (id[b - 1] > id[b]) {
+                const int t = id[b]; id[b] = id[b - 1]; id[b - 1] = t;
+                const int4 u = v[b]; v[b] = v[b - 1]; v[b - 1] = u;
+            }
+}
+
+__device__ __forceinline__ double tri_size_canon(int4 a, int ia, int4 b, int ib, int4 c, int ic, const PredParams &pp) {
+    int4 v[3] = {a, b, c};
+    int id[3] = {ia, ib, ic};
+    sort_by_id<3>(v, id);
+    return tri_orthosize(tri_setup(v[0], v[1], v[2], pp));
+}
+
+__device__ __forceinline__ double tet_size_canon(int4 a, int ia, int4 b, int ib, int4 c, int ic, int4 d, int id_,
+                                                 const PredParams &pp) {
+    int4 v[4] = {a, b, c, d};
+    int id[4] = {ia, ib, ic, id_};
+    sort_by_id<4>(v, id);
+    return tet_orthosize(tet_setup(v[0], v[1], v[2], v[3], pp));
+}
+
 // Triangles: AC2 at their own ortho-centre and OrthoSize (one thread each).
 __global__ void __launch_bounds__(BLOCK) k_tri_gabriel(const int4 *__restrict__ atom, const int *__restrict__ perm,
                                                         const int *__restrict__ nbr_start, const int *__restrict__ nbr_cnt,
@@ -365,7 +460,7 @@ __global__ void __launch_bounds__(BLOCK) k_tri_gabriel(const int4 *__restrict__ 
         if (tri_violation_sign(tr, i, j, k, atom[q], q, perm, pp, cnt) < 0) { gab = false; break; }
     }
     tgab[t] = (unsigned char)gab;
-    tsize[t] = tri_orthosize(tr);
+    tsize[t] = tri_size_canon(atom[i], perm[i], atom[j], perm[j], atom[k], perm[k], pp);
 }
 
 // ---------------------------------------------------------------------------
@@ -449,7 +544,7 @@ __global__ void __launch_bounds__(BLOCK) k_tet_ac2(const int4 *__restrict__ atom
     }
     qin[c] = (unsigned char)keep;
     if (!keep) return;
-    const double sz = tet_orthosize(te);
+    const double sz = tet_size_canon(atom[i], perm[i], atom[j], perm[j], atom[k], perm[k], atom[l], perm[l], pp);
     qsize[c] = sz;
     const long long key = ordered_from_double(sz);
     mark_face(tgab, tri_att, tri_min, t, key, cnt);
@@ -490,7 +585,8 @@ __global__ void __launch_bounds__(BLOCK) k_tri_final(const int *__restrict__ up_
 }
 
 // Edges (Step 4).
-__global__ void __launch_bounds__(BLOCK) k_edge_final(const int4 *__restrict__ atom, const int *__restrict__ up,
+__global__ void __launch_bounds__(BLOCK) k_edge_final(const int4 *__restrict__ atom, const int *__restrict__ perm,
+                                                       const int *__restrict__ up,
                                                        const int *__restrict__ edge_i, int E,
                                                        const unsigned char *__restrict__ egab,
                                                        const int *__restrict__ edge_att,
@@ -505,7 +601,7 @@ __global__ void __launch_bounds__(BLOCK) k_edge_final(const int4 *__restrict__ a
     ein[e] = (unsigned char)in;
     if (!in) return;
     const int i = edge_i[e], j = up[e];
-    const double sz = gab ? edge_orthosize(edge_setup(atom[i], atom[j])) : double_from_ordered(edge_min[e]);
+    const double sz = gab ? edge_size_canon(atom[i], perm[i], atom[j], perm[j]) : double_from_ordered(edge_min[e]);
     esize[e] = sz;
     const long long key = ordered_from_double(sz);
     if (!vgab[i]) { atomicOr(&vert_att[i], 1); atomicMin(&vert_min[i], key); }
@@ -575,18 +671,25 @@ template <> struct EmitPay<2> { typedef uint2 type; };
 template <> struct EmitPay<3> { typedef uint3 type; };
 template <> struct EmitPay<4> { typedef uint4 type; };
 
-// Kept candidates -> (least input id, rest of the row + candidate index),
-// compacted by the flag scan `fpos`.
+// Every candidate c -> key[c] = least input id of its row and pay[c] = (the
+// other ids, c), or key[c] = n (after every id) when c is not kept, so one
+// sort by key puts the kept rows first, grouped by least id, with no
+// compaction pass.
 template <int K>
-__global__ void __launch_bounds__(BLOCK) k_emit_keys(const unsigned char *__restrict__ in,
-                                                      const int *__restrict__ fpos, int M,
+__global__ void __launch_bounds__(BLOCK) k_emit_keys(const unsigned char *__restrict__ in, int M,
                                                       const int *__restrict__ up, const int *__restrict__ edge_i,
                                                       const int *__restrict__ tri_k, const int *__restrict__ tri_e,
                                                       const int *__restrict__ tet_t, const int *__restrict__ tet_l,
-                                                      const int *__restrict__ perm, unsigned *__restrict__ key,
+                                                      const int *__restrict__ perm, int n, unsigned *__restrict__ key,
                                                       typename EmitPay<K>::type *__restrict__ pay) {
     const int c = xcd_block() * BLOCK + threadIdx.x;
-    if (c >= M || !in[c]) return;
+    if (c >= M) return;
+    typename EmitPay<K>::type q{};
+    if (!in[c]) {
+        key[c] = (unsigned)n;
+        pay[c] = q;
+        return;
+    }
     int v[4];
     candidate_row<K>(c, up, edge_i, tri_k, tri_e, tet_t, tet_l, v);
 #pragma unroll
@@ -596,13 +699,21 @@ __global__ void __launch_bounds__(BLOCK) k_emit_keys(const unsigned char *__rest
 #pragma unroll
         for (int b = a; b > 0; b--)
             if (v[b - 1] > v[b]) { const int t = v[b]; v[b] = v[b - 1]; v[b - 1] = t; }
-    const int p = fpos[c];
-    key[p] = (unsigned)v[0];
-    typename EmitPay<K>::type q;
+    key[c] = (unsigned)v[0];
     if constexpr (K == 2) q = make_uint2((unsigned)v[1], (unsigned)c);
     else if constexpr (K == 3) q = make_uint3((unsigned)v[1], (unsigned)v[2], (unsigned)c);
     else q = make_uint4((unsigned)v[1], (unsigned)v[2], (unsigned)v[3], (unsigned)c);
-    pay[p] = q;
+    pay[c] = q;
+}
+
+// Number of kept rows after the sort: the first position whose key is n.
+__global__ void k_count_kept(const unsigned *__restrict__ key, int M, int n, int *__restrict__ out) {
+    int lo = 0, hi = M;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (key[mid] < (unsigned)n) lo = mid + 1; else hi = mid;
+    }
+    *out = lo;
 }
 
 template <int K>
@@ -617,12 +728,13 @@ __device__ __forceinline__ void pay_row(const typename EmitPay<K>::type &q, unsi
 // ids, and writes itself to the final place.
 template <int K>
 __global__ void __launch_bounds__(BLOCK) k_emit_rank(const unsigned *__restrict__ key,
-                                                      const typename EmitPay<K>::type *__restrict__ pay, int m,
+                                                      const typename EmitPay<K>::type *__restrict__ pay, int m, int n,
                                                       const double *__restrict__ size_in, int *__restrict__ out,
                                                       double *__restrict__ out_size) {
     const int p = blockIdx.x * BLOCK + threadIdx.x;
     if (p >= m) return;
     const unsigned u0 = key[p];
+    if (u0 == (unsigned)n) return;  // not kept (sorted after the kept rows)
     unsigned r[3], c;
     pay_row<K>(pay[p], r, c);
     int s = p;
@@ -642,6 +754,25 @@ __global__ void __launch_bounds__(BLOCK) k_emit_rank(const unsigned *__restrict_
 #pragma unroll
     for (int u = 1; u < K; u++) out[q + u] = (int)r[u - 1];
     out_size[s + rank] = size_in[c] / 1.0e6;  // mA^2 -> A^2
+}
+
+
+// Rows of a simplex array sorted by least id (K ids per row): out[j] = first
+// row whose least id is >= bound[j]; the rows of molecule m of a batch are
+// [out[m], out[m+1]) when bound holds the molecules' first balls.
+template <int K>
+__global__ void __launch_bounds__(BLOCK) k_row_lower_bound(const int *__restrict__ simp, const int *__restrict__ m,
+                                                            const long long *__restrict__ bound, int nb,
+                                                            long long *__restrict__ out) {
+    const int j = blockIdx.x * BLOCK + threadIdx.x;
+    if (j >= nb) return;
+    const long long b = bound[j];
+    long long lo = 0, hi = *m;
+    while (lo < hi) {
+        const long long mid = (lo + hi) >> 1;
+        if ((long long)simp[mid * K] < b) lo = mid + 1; else hi = mid;
+    }
+    out[j] = lo;
 }
 
 }  // namespace acx

@@ -1,0 +1,362 @@
+// Volume and boundary area of the union of the balls, from the alpha complex
+// at alpha = 0, and their gradients (the complex held fixed).
+//
+// The union's measure is the alternating sum, over the simplices of the dual
+// complex, of the measure of the intersection of their balls (the short
+// inclusion-exclusion of Edelsbrunner, 1995); the paper names volume and area
+// as what the alpha complex of a molecule is for (Sec. 1). Per simplex of k
+// balls, with I the intersection:
+//   vol(I)  = (1/3) [ sum_i r_i |P_i| - sum_{i<j} d_ij |F_ij| ]
+// where P_i is the patch of sphere i on the boundary of I and F_ij the flat
+// face of I on the radical plane of i and j once I is split by the farthest-
+// power diagram of its balls (each piece coned from its own centre).
+//   |P_i|  = r_i^2 (2 pi - sum of exterior corner angles) - r_i sum_j t_ij phi_ij
+// by Gauss-Bonnet, t_ij being the signed distance from centre i to the plane
+// and phi_ij the central angle of the boundary arc on the circle S_i & S_j.
+// Gradients: d vol / d r_i = |P_i|; d vol / d p_i = sum_j |F_ij| u_ij; the
+// boundary area moves by (2 / r_i) times the patch's (vector) area plus
+// cot(psi/2) times the length (or int n ds) of each boundary arc of P_i, psi
+// the interior dihedral angle of I there.
+//
+// One thread per simplex; float64 throughout. The coordinates are the
+// caller's float64 ones (not the quantised values the complex was built
+// from), so square roots and arc cosines are clamped to their domain.
+#pragma once
+#include "common.hpp"
+
+namespace acx {
+
+struct D3 {
+    double x, y, z;
+};
+__device__ __forceinline__ D3 d3(double x, double y, double z) { return D3{x, y, z}; }
+__device__ __forceinline__ D3 operator+(D3 a, D3 b) { return d3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ D3 operator-(D3 a, D3 b) { return d3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ D3 operator*(double s, D3 a) { return d3(s * a.x, s * a.y, s * a.z); }
+__device__ __forceinline__ double dot(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ D3 cross(D3 a, D3 b) {
+    return d3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ D3 unit(D3 a) {
+    const double n = sqrt(dot(a, a));
+    return n > 0 ? (1.0 / n) * a : a;
+}
+__device__ __forceinline__ double clamp1(double x) { return fmin(1.0, fmax(-1.0, x)); }
+
+constexpr double PI = 3.14159265358979323846;
+
+// Terms of one simplex of K balls. The arc terms are computed only if GRAD.
+template <int K>
+struct BallTerms {
+    double vol;
+    double area[K];
+    D3 vec[K];
+    double arc_len[K];
+    D3 arc_vec[K];
+};
+
+// Exterior angle at corner v of the patch on sphere (p, r) between the arcs
+// cut by the planes with normals ua and ub.
+__device__ __forceinline__ double corner_angle(D3 v, D3 p, double r, D3 ua, D3 ub) {
+    const D3 n = (1.0 / r) * (v - p);
+    const D3 ga = unit(ua - dot(ua, n) * n);
+    const D3 gb = unit(ub - dot(ub, n) * n);
+    return acos(clamp1(dot(ga, gb)));
+}
+
+template <int K, bool GRAD>
+__device__ void ball_terms(const D3 *P, const double *R, BallTerms<K> &o) {
+    if (K == 1) {
+        o.vol = 4.0 / 3.0 * PI * R[0] * R[0] * R[0];
+        o.area[0] = 4.0 * PI * R[0] * R[0];
+        o.vec[0] = d3(0, 0, 0);
+        o.arc_len[0] = 0;
+        o.arc_vec[0] = d3(0, 0, 0);
+        return;
+    }
+    double corner[K], turn[K];
+    for (int i = 0; i < K; i++) {
+        corner[i] = 0;
+        turn[i] = 0;
+        o.vec[i] = d3(0, 0, 0);
+        o.arc_len[i] = 0;
+        o.arc_vec[i] = d3(0, 0, 0);
+    }
+    // point of equal power (in the plane of the centres when K = 3) and rho^2
+    D3 c = P[0];
+    double rho2 = 0;
+    if (K >= 3) {
+        const D3 e1 = P[1] - P[0], e2 = P[2] - P[0];
+        const double h1 = 0.5 * (dot(e1, e1) - R[1] * R[1] + R[0] * R[0]);
+        const double h2 = 0.5 * (dot(e2, e2) - R[2] * R[2] + R[0] * R[0]);
+        D3 z;
+        if (K == 3) {
+            const double g11 = dot(e1, e1), g12 = dot(e1, e2), g22 = dot(e2, e2);
+            const double det = g11 * g22 - g12 * g12;
+            const double l1 = (h1 * g22 - h2 * g12) / det, l2 = (h2 * g11 - h1 * g12) / det;
+            z = l1 * e1 + l2 * e2;
+        } else {
+            const D3 e3 = P[3] - P[0];
+            const double h3 = 0.5 * (dot(e3, e3) - R[3] * R[3] + R[0] * R[0]);
+            const D3 c23 = cross(e2, e3), c31 = cross(e3, e1), c12 = cross(e1, e2);
+            z = (1.0 / dot(e1, c23)) * (h1 * c23 + h2 * c31 + h3 * c12);
+        }
+        c = P[0] + z;
+        rho2 = R[0] * R[0] - dot(z, z);
+    }
+    const double rho = sqrt(fmax(rho2, 0.0));
+    // K = 4: the vertex of I on each triple's power line, indexed by the
+    // ball opposite the triple (the triple point inside that ball)
+    D3 tv[4];
+    if (K == 4) {
+        for (int f = 0; f < 4; f++) {
+            int t[3], m = 0;
+            for (int x = 0; x < 4; x++)
+                if (x != f) t[m++] = x;
+            D3 nt = unit(cross(P[t[1]] - P[t[0]], P[t[2]] - P[t[0]]));
+            if (dot(nt, P[f] - P[t[0]]) < 0) nt = -1.0 * nt;
+            const double beta = dot(nt, c - P[t[0]]);
+            const double tau = -beta + sqrt(fmax(beta * beta + rho2, 0.0));
+            tv[f] = c + tau * nt;
+        }
+    }
+    double flat = 0;
+    for (int a = 0; a < K; a++) {
+        for (int b = a + 1; b < K; b++) {
+            const D3 dv = P[b] - P[a];
+            const double d = sqrt(dot(dv, dv));
+            const D3 u = (1.0 / d) * dv;
+            const double ta = (d * d + R[a] * R[a] - R[b] * R[b]) / (2 * d);
+            const double tb = d - ta;
+            const D3 oc = P[a] + ta * u;  // centre of the circle S_a & S_b
+            const double a2 = fmax(R[a] * R[a] - ta * ta, 0.0);
+            const double rad = sqrt(a2);
+            double phi, face;
+            D3 mid = d3(0, 0, 0);
+            if (K == 2) {
+                phi = 2 * PI;
+                face = PI * a2;
+            } else if (K == 3) {
+                const int e = 3 - a - b;
+                const D3 w = unit((P[e] - P[a]) - dot(P[e] - P[a], u) * u);
+                const double s = dot(c - oc, w);
+                const double half = rad > 0 ? acos(clamp1(s / rad)) : 0.0;
+                face = a2 * half - s * sqrt(fmax(a2 - s * s, 0.0));
+                phi = 2 * half;
+                mid = w;
+            } else {
+                int e = -1, f = -1;
+                for (int x = 0; x < 4; x++)
+                    if (x != a && x != b) {
+                        if (e < 0) e = x; else f = x;
+                    }
+                const D3 q1 = tv[f], q2 = tv[e];  // triples (a,b,e) and (a,b,f)
+                D3 axis = u;
+                if (dot(cross(q1 - c, q2 - c), u) < 0) axis = -1.0 * u;
+                const D3 r1 = q1 - oc, r2 = q2 - oc;
+                double ang = atan2(dot(cross(r1, r2), axis), dot(r1, r2));
+                if (ang < 0) ang += 2 * PI;
+                phi = rad > 0 ? ang : 0.0;
+                face = 0.5 * (a2 * phi + dot(cross(oc - c, q2 - q1), axis));
+                const D3 e1 = unit(r1);
+                mid = cos(0.5 * phi) * e1 + sin(0.5 * phi) * cross(axis, e1);
+            }
+            flat += d * face;
+            turn[a] += ta * phi;
+            turn[b] += tb * phi;
+            o.vec[a] = o.vec[a] + face * u;
+            o.vec[b] = o.vec[b] - face * u;
+            if (GRAD) {
+                const double cos_psi = -(R[a] * R[a] + R[b] * R[b] - d * d) / (2 * R[a] * R[b]);
+                const double cot_half = sqrt(fmax(1 + cos_psi, 0.0) / fmax(1 - cos_psi, 1e-300));
+                const double len = rad * phi;
+                o.arc_len[a] += cot_half * len;
+                o.arc_len[b] += cot_half * len;
+                const D3 radial = (a2 * 2 * sin(0.5 * phi)) * mid;  // int (x - o) ds over the arc
+                o.arc_vec[a] = o.arc_vec[a] + (cot_half / R[a]) * ((ta * len) * u + radial);
+                o.arc_vec[b] = o.arc_vec[b] + (cot_half / R[b]) * ((-tb * len) * u + radial);
+            }
+        }
+    }
+    if (K == 3) {
+        const D3 nrm = unit(cross(P[1] - P[0], P[2] - P[0]));
+        const D3 vp = c + rho * nrm, vm = c - rho * nrm;
+        for (int i = 0; i < 3; i++) {
+            const int j = i == 0 ? 1 : 0, l = i == 2 ? 1 : 2;
+            const D3 uj = unit(P[j] - P[i]), ul = unit(P[l] - P[i]);
+            corner[i] += corner_angle(vp, P[i], R[i], uj, ul) + corner_angle(vm, P[i], R[i], uj, ul);
+        }
+    }
+    if (K == 4) {
+        for (int f = 0; f < 4; f++) {
+            for (int i = 0; i < 4; i++) {
+                if (i == f) continue;
+                int j = -1, l = -1;
+                for (int x = 0; x < 4; x++)
+                    if (x != f && x != i) {
+                        if (j < 0) j = x; else l = x;
+                    }
+                corner[i] += corner_angle(tv[f], P[i], R[i], unit(P[j] - P[i]), unit(P[l] - P[i]));
+            }
+        }
+    }
+    double rs = 0;
+    for (int i = 0; i < K; i++) {
+        o.area[i] = R[i] * R[i] * (2 * PI - corner[i]) - R[i] * turn[i];
+        rs += R[i] * o.area[i];
+    }
+    o.vol = (rs - flat) / 3.0;
+}
+
+template <int K>
+__device__ __forceinline__ void load_balls(const int *__restrict__ simp, long long s, const double *__restrict__ xyz,
+                                           const double *__restrict__ rad, int *id, D3 *P, double *R) {
+#pragma unroll
+    for (int c = 0; c < K; c++) {
+        id[c] = simp[s * K + c];
+        const double *p = xyz + 3LL * id[c];
+        P[c] = d3(p[0], p[1], p[2]);
+        R[c] = rad[id[c]];
+    }
+}
+
+constexpr int MEASURE_BLOCK = 256;
+
+// Per block: the signed sums of vol and of patch areas over its simplices of
+// dimension K - 1, written to part[2 * block] and part[2 * block + 1].
+template <int K>
+__global__ void __launch_bounds__(MEASURE_BLOCK) k_measure_fwd(const int *__restrict__ simp, long long m,
+                                                                const double *__restrict__ xyz,
+                                                                const double *__restrict__ rad, double *__restrict__ part) {
+    __shared__ double sv[MEASURE_BLOCK / WAVE], sa[MEASURE_BLOCK / WAVE];
+    const long long s = (long long)blockIdx.x * MEASURE_BLOCK + threadIdx.x;
+    double v = 0, a = 0;
+    if (s < m) {
+        int id[K];
+        D3 P[K];
+        double R[K];
+        load_balls<K>(simp, s, xyz, rad, id, P, R);
+        BallTerms<K> t;
+        ball_terms<K, false>(P, R, t);
+        v = t.vol;
+        for (int c = 0; c < K; c++) a += t.area[c];
+        if ((K - 1) & 1) {
+            v = -v;
+            a = -a;
+        }
+    }
+    for (int off = WAVE / 2; off > 0; off >>= 1) {
+        v += __shfl_down(v, off, WAVE);
+        a += __shfl_down(a, off, WAVE);
+    }
+    const int w = threadIdx.x / WAVE;
+    if (lane_id() == 0) {
+        sv[w] = v;
+        sa[w] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tv = 0, ta = 0;
+        for (int k = 0; k < MEASURE_BLOCK / WAVE; k++) {
+            tv += sv[k];
+            ta += sa[k];
+        }
+        part[2 * blockIdx.x] = tv;
+        part[2 * blockIdx.x + 1] = ta;
+    }
+}
+
+// Sum of the block partials in a fixed order (one block): out[0] = V, out[1] = A.
+__global__ void __launch_bounds__(MEASURE_BLOCK) k_measure_total(const double *__restrict__ part, int nb,
+                                                                  double *__restrict__ out) {
+    __shared__ double sv[MEASURE_BLOCK], sa[MEASURE_BLOCK];
+    double v = 0, a = 0;
+    for (int b = threadIdx.x; b < nb; b += MEASURE_BLOCK) {
+        v += part[2 * b];
+        a += part[2 * b + 1];
+    }
+    sv[threadIdx.x] = v;
+    sa[threadIdx.x] = a;
+    __syncthreads();
+    for (int h = MEASURE_BLOCK / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            sv[threadIdx.x] += sv[threadIdx.x + h];
+            sa[threadIdx.x] += sa[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sv[0];
+        out[1] = sa[0];
+    }
+}
+
+// Per incidence slot (simplex s, corner c at slot base + s*K + c): the
+// corner's contribution gV * d(V)/d(p, r) + gA * d(A)/d(p, r), as (x, y, z, r),
+// with (gV, gA) = (g[0], g[1]) read from device memory.
+template <int K>
+__global__ void __launch_bounds__(MEASURE_BLOCK) k_measure_bwd(const int *__restrict__ simp, long long m,
+                                                                const double *__restrict__ xyz,
+                                                                const double *__restrict__ rad,
+                                                                const double *__restrict__ g,
+                                                                double4 *__restrict__ contrib) {
+    const long long s = (long long)blockIdx.x * MEASURE_BLOCK + threadIdx.x;
+    if (s >= m) return;
+    const double gV = g[0], gA = g[1];
+    int id[K];
+    D3 P[K];
+    double R[K];
+    load_balls<K>(simp, s, xyz, rad, id, P, R);
+    BallTerms<K> t;
+    ball_terms<K, true>(P, R, t);
+    const double sg = ((K - 1) & 1) ? -1.0 : 1.0;
+#pragma unroll
+    for (int c = 0; c < K; c++) {
+        const double ir = 2.0 / R[c];
+        const D3 gx = (sg * gV) * t.vec[c] + (sg * gA) * (ir * t.vec[c] + t.arc_vec[c]);
+        const double gr = sg * (gV * t.area[c] + gA * (ir * t.area[c] + t.arc_len[c]));
+        contrib[s * K + c] = make_double4(gx.x, gx.y, gx.z, gr);
+    }
+}
+
+// vstart[i] = first position of vertex i in the sorted incidence keys (i in [0, n]).
+__global__ void __launch_bounds__(MEASURE_BLOCK) k_incidence_start(const unsigned *__restrict__ key, long long M, int n,
+                                                                    int *__restrict__ vstart) {
+    const long long i = (long long)blockIdx.x * MEASURE_BLOCK + threadIdx.x;
+    if (i > n) return;
+    long long lo = 0, hi = M;
+    while (lo < hi) {
+        const long long mid = (lo + hi) >> 1;
+        if ((long long)key[mid] < i) lo = mid + 1; else hi = mid;
+    }
+    vstart[i] = (int)lo;
+}
+
+// Gradient of ball i: the sum of its incidence slots' contributions, in slot
+// order (deterministic).
+__global__ void __launch_bounds__(MEASURE_BLOCK) k_measure_gather(const int *__restrict__ vstart,
+                                                                   const int *__restrict__ slot,
+                                                                   const double4 *__restrict__ contrib, int n,
+                                                                   double *__restrict__ dxyz, double *__restrict__ dr) {
+    const int i = blockIdx.x * MEASURE_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    double gx = 0, gy = 0, gz = 0, gr = 0;
+    for (int q = vstart[i]; q < vstart[i + 1]; q++) {
+        const double4 c = contrib[slot[q]];
+        gx += c.x;
+        gy += c.y;
+        gz += c.z;
+        gr += c.w;
+    }
+    dxyz[3LL * i] = gx;
+    dxyz[3LL * i + 1] = gy;
+    dxyz[3LL * i + 2] = gz;
+    dr[i] = gr;
+}
+
+__global__ void __launch_bounds__(MEASURE_BLOCK) k_iota(int *__restrict__ p, long long m) {
+    const long long i = (long long)blockIdx.x * MEASURE_BLOCK + threadIdx.x;
+    if (i < m) p[i] = (int)i;
+}
+
+}  // namespace acx

@@ -1,0 +1,138 @@
+"""GPU batches of molecules: one call over concatenated molecules must give,
+molecule by molecule, exactly the single-molecule result (ids shifted by the
+molecule's offset; Sizes bit for bit), and the oracle's complex.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import assert_same_complex
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def acx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1908_05944_amd as m
+    return m
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
+
+
+def _concat(mols):
+    xyz = np.concatenate([m.xyz for m in mols])
+    rad = np.concatenate([m.radii for m in mols])
+    off = np.concatenate([[0], np.cumsum([m.n for m in mols])]).astype(np.int64)
+    return xyz, rad, off
+
+
+class _Slice:
+    """One molecule's part of a batch result, ids made local."""
+
+    def __init__(self, c, m, off):
+        self._s = []
+        self._z = []
+        for d in range(4):
+            rows = c.molecule_rows(d)
+            self._s.append(c.simplices(d)[rows[m]:rows[m + 1]] - off[m])
+            self._z.append(c.sizes(d)[rows[m]:rows[m + 1]])
+
+    def count(self, d):
+        return len(self._s[d])
+
+    def counts(self):
+        return [self.count(d) for d in range(4)]
+
+    def simplices(self, d):
+        return self._s[d]
+
+    def sizes(self, d):
+        return self._z[d]
+
+
+def _check_batch(acx, mols, alpha, cells=None, oracle_upto=0):
+    xyz, rad, off = _concat(mols)
+    print(f"[case] batch of {len(mols)} molecules, {len(rad)} balls, alpha={alpha}", flush=True)
+    c = acx.ac_alpha_complex_batch(_dev(xyz), _dev(rad), off, alpha, cell_mA=cells)
+    assert c.molecule_count() == len(mols)
+    for m, mol in enumerate(mols):
+        got = _Slice(c, m, off)
+        single = acx.ac_alpha_complex_device(_dev(mol.xyz), _dev(mol.radii), alpha)
+        for d in range(4):
+            assert np.array_equal(got.simplices(d), single.simplices(d)), (m, d)
+            assert np.array_equal(got.sizes(d), single.sizes(d)), (m, d)
+        if m < oracle_upto:
+            assert_same_complex(got, oracle.alpha_complex(mol.xyz, mol.radii, alpha), f"molecule {m}")
+    return c
+
+
+def test_uneven_sizes(acx):
+    sizes = [60, 500, 2500, 140, 7, 1200, 3000, 1, 400]
+    mols = [synth.molecule(k, 100 + i) for i, k in enumerate(sizes)]
+    _check_batch(acx, mols, 0.0, oracle_upto=len(mols))
+
+
+def test_overlapping_coordinates(acx):
+    # the same molecule three times at the same place, and once with SAS
+    # radii: balls of different molecules must never interact
+    m = synth.molecule(800, 41)
+    _check_batch(acx, [m, m, m.with_sas(1400), m], 0.0, oracle_upto=3)
+
+
+def test_alpha_and_cell_sides(acx):
+    mols = [synth.molecule(k, 200 + i) for i, k in enumerate([300, 1500, 900])]
+    for alpha in (0.0, 1.0):
+        _check_batch(acx, mols, alpha)
+    # per-molecule cell sides change nothing
+    _check_batch(acx, mols, 0.0, cells=np.array([900, 4000, 1700], dtype=np.int32))
+
+
+def test_tuner(acx):
+    mols = [synth.molecule(k, 300 + i) for i, k in enumerate([600, 2500, 900, 9000])]
+    xyz, rad, off = _concat(mols)
+    cells, buckets = acx.ac_tune_cells(_dev(xyz), _dev(rad), off, 0.0)
+    assert cells.min() >= 1
+    assert list(buckets) == [0, 1, 0, 2]
+    assert cells[0] == cells[2]  # one side per bucket
+    _check_batch(acx, mols, 0.0, cells=cells)
+
+
+def test_errors(acx):
+    m = synth.molecule(100, 3)
+    X, R = _dev(m.xyz), _dev(m.radii)
+    for off in ([1, 100], [0, 50, 50, 100], [0, 60, 40, 100]):
+        with pytest.raises(acx.AlphaCxError) as e:
+            acx.ac_alpha_complex_batch(X, R, np.array(off), 0.0)
+        assert e.value.status == 1
+    # a duplicate inside one molecule is an error; across molecules it is not
+    xyz = np.concatenate([m.xyz, m.xyz[:1]])
+    rad = np.concatenate([m.radii, m.radii[:1]])
+    with pytest.raises(acx.AlphaCxError) as e:
+        acx.ac_alpha_complex_batch(_dev(xyz), _dev(rad), np.array([0, 101]), 0.0)
+    assert e.value.status == 2
+    c = acx.ac_alpha_complex_batch(_dev(xyz), _dev(rad), np.array([0, 100, 101]), 0.0)
+    assert c.counts()[0] == 101
+
+
+def test_batch_union_measure(acx):
+    """V and A over a batch complex are the sums of the molecules' own."""
+    mols = [synth.molecule(k, 400 + i) for i, k in enumerate([700, 1300])]
+    xyz, rad, off = _concat(mols)
+    X, R = _dev(xyz), _dev(rad)
+    c = acx.ac_alpha_complex_batch(X, R, off, 0.0)
+    V, A = acx.ac_union_measure(c, X, R)
+    Vs = As = 0.0
+    for mol in mols:
+        Xm, Rm = _dev(mol.xyz), _dev(mol.radii)
+        v, a = acx.ac_union_measure(acx.ac_alpha_complex_device(Xm, Rm, 0.0), Xm, Rm)
+        Vs += v
+        As += a
+    assert V == pytest.approx(Vs, rel=1e-12)
+    assert A == pytest.approx(As, rel=1e-12)

@@ -103,10 +103,17 @@ def test_small_molecule_alphas(acx):
 
 
 def test_options_do_not_change_result(acx):
+    """Exact-only predicates and other cell sizes give the same simplices and
+    bit-identical Sizes (each OrthoSize is evaluated in input-index order)."""
     m = synth.molecule(2000, 11)
     want = oracle.alpha_complex(m.xyz, m.radii, 1.0)
+    base = _run(acx, m.xyz, m.radii, 1.0)
+    assert_same_complex(base, want, "default")
     for opt in ({"force_exact": 1}, {"cell_mA": 900}, {"cell_mA": 4000}, {"cell_mA": 2500, "force_exact": 1}):
-        assert_same_complex(_run(acx, m.xyz, m.radii, 1.0, **opt), want, str(opt))
+        got = _run(acx, m.xyz, m.radii, 1.0, **opt)
+        assert_same_complex(got, want, str(opt))
+        for d in range(4):
+            assert np.array_equal(got.sizes(d), base.sizes(d)), (opt, d)
 
 
 def test_host_path_matches(acx):
