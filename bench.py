@@ -208,6 +208,7 @@ def main():
     ap.add_argument("--cache-dir", default=os.environ.get("ALPHACX_INPUT_CACHE", ""),
                     help="keep the generated input here between runs")
     ap.add_argument("--no-extras", action="store_true", help="skip the batch and union-measure workloads")
+    ap.add_argument("--no-tune", action="store_true", help="default cell side instead of the autotuned one")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain device copy of 1 GiB (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -239,14 +240,24 @@ def main():
     rad = torch.from_numpy(mol.radii).to(dev)
     stream = torch.cuda.current_stream(dev)
 
+    # cell side from the autotuner (outside the timed region; it never changes
+    # the result, only the time)
+    cell_mA = 0
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        cells, _ = acx.ac_tune_cells(xyz, rad, np.array([0, mol.n]), args.alpha)
+        cell_mA = int(cells[0])
+        log(f"[bench] tuner: cell side {cell_mA} mA ({time.perf_counter() - t0:.2f} s)")
+    opts = {"cell_mA": cell_mA}
+
     for w in range(args.warmup):
-        c = acx.ac_alpha_complex_device(xyz, rad, args.alpha)
+        c = acx.ac_alpha_complex_device(xyz, rad, args.alpha, options=opts)
         counts = c.counts()
         c.close()
         log(f"[bench] warmup {w}: counts {counts}")
 
     # timed region: exactly K steps, HIP events recorded between stages
-    prof = {"profile": 1}
+    prof = {"profile": 1, "cell_mA": cell_mA}
     stage_tot = {}
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -263,7 +274,7 @@ def main():
     log(f"[bench] {ms_per_step:.3f} ms/step; stages (ms): " + ", ".join(f"{k}={v:.3f}" for k, v in stage_avg.items()))
 
     # one more build for counts (not timed)
-    c = acx.ac_alpha_complex_device(xyz, rad, args.alpha)
+    c = acx.ac_alpha_complex_device(xyz, rad, args.alpha, options=opts)
     counts = c.counts()
     cand = [c.candidate_count(d) for d in range(4)]
     fallbacks = c.exact_fallbacks()
@@ -340,7 +351,8 @@ def main():
         "dtype": "int64+f64",
         "data": "synthetic",
         "config": {"workload": "3M-atom spherical shell (R_out 279.36 A, R_in 0.7 R_out), 0.05 atoms/A^3, "
-                               "vdW radii, alpha=0", "atoms": n, "alpha": args.alpha, "parallelism": "single GPU"},
+                               "vdW radii, alpha=0", "atoms": n, "alpha": args.alpha, "cell_mA": cell_mA,
+                   "parallelism": "single GPU"},
         "counts": counts,
         "candidates": cand,
         "exact_fallbacks": fallbacks,

@@ -224,38 +224,30 @@ struct Cands {
     const int *up, *edge_i, *tri_k, *tri_e, *tet_t, *tet_l, *perm;
 };
 
-// Stable LSD radix sort of (key, payload) on the low `bits` bits of key.
-// key / pay are set to the buffers that hold the result (the inputs' or
-// scratch of the scope). Digits of 11 bits above 16 key bits (2 passes up
-// to 22 bits), else of 8.
-template <class P, int BITS>
-static void radix_passes(unsigned *&key, P *&pay, int n, int bits, hipStream_t s, Scope &sc) {
-    constexpr int BINS = 1 << BITS;
+// Stable LSD radix sort of (key, payload) on the low `bits` bits of key, 8
+// bits per pass. key / pay are set to the buffers that hold the result (the
+// inputs' or scratch of the scope).
+template <class P>
+static void radix_sort(unsigned *&key, P *&pay, int n, int bits, hipStream_t s, Scope &sc) {
+    if (n <= 1 || bits <= 0) return;
     const int tiles = (n + RS_TILE - 1) / RS_TILE;
     unsigned *k2 = sc.get<unsigned>(n);
     P *p2 = sc.get<P>(n);
-    int *hist = sc.get<int>((size_t)BINS * tiles);
-    int *offs = sc.get<int>((size_t)BINS * tiles + 1);
+    int *hist = sc.get<int>((size_t)RS_BINS * tiles);
+    int *offs = sc.get<int>((size_t)RS_BINS * tiles + 1);
     unsigned *kin = key, *kout = k2;
     P *pin = pay, *pout = p2;
-    for (int shift = 0; shift < bits; shift += BITS) {
-        k_rs_hist<BITS><<<tiles, RS_BLOCK, 0, s>>>(kin, n, shift, hist, tiles);
+    for (int shift = 0; shift < bits; shift += RS_BITS) {
+        k_rs_hist<<<tiles, RS_BLOCK, 0, s>>>(kin, n, shift, hist, tiles);
         LAUNCH_CHECK();
-        scan_i32(hist, offs, (long long)BINS * tiles, s, sc);
-        k_rs_scatter<P, BITS><<<tiles, RS_BLOCK, 0, s>>>(kin, pin, kout, pout, n, shift, offs, tiles);
+        scan_i32(hist, offs, (long long)RS_BINS * tiles, s, sc);
+        k_rs_scatter<P><<<tiles, RS_BLOCK, 0, s>>>(kin, pin, kout, pout, n, shift, offs, hist, tiles);
         LAUNCH_CHECK();
         std::swap(kin, kout);
         std::swap(pin, pout);
     }
     key = kin;
     pay = pin;
-}
-
-template <class P>
-static void radix_sort(unsigned *&key, P *&pay, int n, int bits, hipStream_t s, Scope &sc) {
-    if (n <= 1 || bits <= 0) return;
-    if (bits > 16) radix_passes<P, 11>(key, pay, n, bits, s, sc);
-    else radix_passes<P, 8>(key, pay, n, bits, s, sc);
 }
 
 static int bits_for(long long n) {
@@ -281,7 +273,7 @@ static void emit_dim(const unsigned char *in, const double *sizes, int M, const 
     unsigned *key = sc.get<unsigned>(M);
     P *pay = sc.get<P>(M);
     k_emit_keys<K><<<grid_for(M), BLOCK, 0, s>>>(in, M, cd.up, cd.edge_i, cd.tri_k, cd.tri_e, cd.tet_t, cd.tet_l,
-                                                 cd.perm, n, key, pay);
+                                                 cd.perm, sizes, n, key, pay);
     LAUNCH_CHECK();
     radix_sort<P>(key, pay, M, bits_for((long long)n + 1), s, sc);
     k_emit_rank<K><<<grid_for(M), BLOCK, 0, s>>>(key, pay, M, n, sizes, res->d_simp[d], res->d_size[d]);
@@ -346,7 +338,7 @@ struct Batch {
     std::vector<int32_t> cell_mA;
 };
 
-constexpr int QTILE = 4096;  // balls per block of the quantise kernel
+constexpr int QTILE = 1024;  // balls per block of the quantise kernel
 
 // The whole pipeline from device arrays. Returns AC_OK and *out on success.
 static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n64, const Batch &bt, double alpha,
@@ -573,7 +565,7 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         }
         tm.mark(ST_EDGE_FINAL);
         if (E > 0) {
-            k_edge_final<<<grid_for(E), BLOCK, 0, s>>>(atom, perm, up, edge_i, E, egab, edge_att, edge_min, ein, esize, vgab,
+            k_edge_final<<<grid_for(E), BLOCK, 0, s>>>(atom, up, edge_i, E, egab, edge_att, edge_min, ein, esize, vgab,
                                                       vert_att, vert_min);
             LAUNCH_CHECK();
         }

@@ -404,38 +404,39 @@ __global__ void __launch_bounds__(BLOCK) k_triangles(const int4 *__restrict__ at
     if (!FILL) tri_cnt[e] = c;
 }
 
-// OrthoSize evaluated with the vertices in input-index order: the rounded
+// OrthoSize evaluated with the vertices in lexicographic order of their
+// integer centres (a total order: equal centres are rejected). The rounded
 // float64 value then depends only on the balls, not on the grid, the sorted
-// order or the other molecules of a batch (reported Sizes are bit-identical
-// whatever the cell size).
-__device__ __forceinline__ double edge_size_canon(int4 a, int ia, int4 b, int ib) {
-    return ia < ib ? edge_orthosize(edge_setup(a, b)) : edge_orthosize(edge_setup(b, a));
+// order or the other molecules of a batch, so reported Sizes are
+// bit-identical whatever the cell size; no input-index gather is needed.
+__device__ __forceinline__ bool centre_less(const int4 &a, const int4 &b) {
+    return a.x != b.x ? a.x < b.x : (a.y != b.y ? a.y < b.y : a.z < b.z);
+}
+
+__device__ __forceinline__ double edge_size_canon(int4 a, int4 b) {
+    return centre_less(a, b) ? edge_orthosize(edge_setup(a, b)) : edge_orthosize(edge_setup(b, a));
 }
 
 template <int K>
-__device__ __forceinline__ void sort_by_id(int4 (&v)[K], int (&id)[K]) {
+__device__ __forceinline__ void sort_centres(int4 (&v)[K]) {
 #pragma unroll
     for (int a = 1; a < K; a++)
 #pragma unroll
         for (int b = a; b > 0; b--)
-            if (id[b - 1] > id[b]) {
-                const int t = id[b]; id[b] = id[b - 1]; id[b - 1] = t;
+            if (centre_less(v[b], v[b - 1])) {
                 const int4 u = v[b]; v[b] = v[b - 1]; v[b - 1] = u;
             }
 }
 
-__device__ __forceinline__ double tri_size_canon(int4 a, int ia, int4 b, int ib, int4 c, int ic, const PredParams &pp) {
+__device__ __forceinline__ double tri_size_canon(int4 a, int4 b, int4 c, const PredParams &pp) {
     int4 v[3] = {a, b, c};
-    int id[3] = {ia, ib, ic};
-    sort_by_id<3>(v, id);
+    sort_centres<3>(v);
     return tri_orthosize(tri_setup(v[0], v[1], v[2], pp));
 }
 
-__device__ __forceinline__ double tet_size_canon(int4 a, int ia, int4 b, int ib, int4 c, int ic, int4 d, int id_,
-                                                 const PredParams &pp) {
+__device__ __forceinline__ double tet_size_canon(int4 a, int4 b, int4 c, int4 d, const PredParams &pp) {
     int4 v[4] = {a, b, c, d};
-    int id[4] = {ia, ib, ic, id_};
-    sort_by_id<4>(v, id);
+    sort_centres<4>(v);
     return tet_orthosize(tet_setup(v[0], v[1], v[2], v[3], pp));
 }
 
@@ -460,7 +461,7 @@ __global__ void __launch_bounds__(BLOCK) k_tri_gabriel(const int4 *__restrict__ 
         if (tri_violation_sign(tr, i, j, k, atom[q], q, perm, pp, cnt) < 0) { gab = false; break; }
     }
     tgab[t] = (unsigned char)gab;
-    tsize[t] = tri_size_canon(atom[i], perm[i], atom[j], perm[j], atom[k], perm[k], pp);
+    tsize[t] = tri_size_canon(tr.v0, atom[j], atom[k], pp);
 }
 
 // ---------------------------------------------------------------------------
@@ -544,7 +545,7 @@ __global__ void __launch_bounds__(BLOCK) k_tet_ac2(const int4 *__restrict__ atom
     }
     qin[c] = (unsigned char)keep;
     if (!keep) return;
-    const double sz = tet_size_canon(atom[i], perm[i], atom[j], perm[j], atom[k], perm[k], atom[l], perm[l], pp);
+    const double sz = tet_size_canon(atom[i], atom[j], atom[k], atom[l], pp);
     qsize[c] = sz;
     const long long key = ordered_from_double(sz);
     mark_face(tgab, tri_att, tri_min, t, key, cnt);
@@ -585,8 +586,7 @@ __global__ void __launch_bounds__(BLOCK) k_tri_final(const int *__restrict__ up_
 }
 
 // Edges (Step 4).
-__global__ void __launch_bounds__(BLOCK) k_edge_final(const int4 *__restrict__ atom, const int *__restrict__ perm,
-                                                       const int *__restrict__ up,
+__global__ void __launch_bounds__(BLOCK) k_edge_final(const int4 *__restrict__ atom, const int *__restrict__ up,
                                                        const int *__restrict__ edge_i, int E,
                                                        const unsigned char *__restrict__ egab,
                                                        const int *__restrict__ edge_att,
@@ -601,7 +601,7 @@ __global__ void __launch_bounds__(BLOCK) k_edge_final(const int4 *__restrict__ a
     ein[e] = (unsigned char)in;
     if (!in) return;
     const int i = edge_i[e], j = up[e];
-    const double sz = gab ? edge_size_canon(atom[i], perm[i], atom[j], perm[j]) : double_from_ordered(edge_min[e]);
+    const double sz = gab ? edge_size_canon(atom[i], atom[j]) : double_from_ordered(edge_min[e]);
     esize[e] = sz;
     const long long key = ordered_from_double(sz);
     if (!vgab[i]) { atomicOr(&vert_att[i], 1); atomicMin(&vert_min[i], key); }
@@ -666,21 +666,33 @@ __device__ __forceinline__ void candidate_row(int c, const int *__restrict__ up,
     }
 }
 
+// Sort payload of a row: the ids after the least, then the Size (edges,
+// triangles: read here in candidate order, so the final write needs no
+// gather) or the candidate index (tetrahedra, which are few).
 template <int K> struct EmitPay;
-template <> struct EmitPay<2> { typedef uint2 type; };
-template <> struct EmitPay<3> { typedef uint3 type; };
-template <> struct EmitPay<4> { typedef uint4 type; };
+template <> struct EmitPay<2> { typedef uint3 type; };  // v1, Size bits
+template <> struct EmitPay<3> { typedef uint4 type; };  // v1, v2, Size bits
+template <> struct EmitPay<4> { typedef uint4 type; };  // v1, v2, v3, candidate
+
+__device__ __forceinline__ uint2 bits_of(double x) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    return make_uint2((unsigned)b, (unsigned)(b >> 32));
+}
+__device__ __forceinline__ double double_of(unsigned lo, unsigned hi) {
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
 // Every candidate c -> key[c] = least input id of its row and pay[c] = (the
-// other ids, c), or key[c] = n (after every id) when c is not kept, so one
-// sort by key puts the kept rows first, grouped by least id, with no
+// other ids, Size or c), or key[c] = n (after every id) when c is not kept,
+// so one sort by key puts the kept rows first, grouped by least id, with no
 // compaction pass.
 template <int K>
 __global__ void __launch_bounds__(BLOCK) k_emit_keys(const unsigned char *__restrict__ in, int M,
                                                       const int *__restrict__ up, const int *__restrict__ edge_i,
                                                       const int *__restrict__ tri_k, const int *__restrict__ tri_e,
                                                       const int *__restrict__ tet_t, const int *__restrict__ tet_l,
-                                                      const int *__restrict__ perm, int n, unsigned *__restrict__ key,
+                                                      const int *__restrict__ perm, const double *__restrict__ size,
+                                                      int n, unsigned *__restrict__ key,
                                                       typename EmitPay<K>::type *__restrict__ pay) {
     const int c = xcd_block() * BLOCK + threadIdx.x;
     if (c >= M) return;
@@ -700,9 +712,15 @@ __global__ void __launch_bounds__(BLOCK) k_emit_keys(const unsigned char *__rest
         for (int b = a; b > 0; b--)
             if (v[b - 1] > v[b]) { const int t = v[b]; v[b] = v[b - 1]; v[b - 1] = t; }
     key[c] = (unsigned)v[0];
-    if constexpr (K == 2) q = make_uint2((unsigned)v[1], (unsigned)c);
-    else if constexpr (K == 3) q = make_uint3((unsigned)v[1], (unsigned)v[2], (unsigned)c);
-    else q = make_uint4((unsigned)v[1], (unsigned)v[2], (unsigned)v[3], (unsigned)c);
+    if constexpr (K == 2) {
+        const uint2 z = bits_of(size[c]);
+        q = make_uint3((unsigned)v[1], z.x, z.y);
+    } else if constexpr (K == 3) {
+        const uint2 z = bits_of(size[c]);
+        q = make_uint4((unsigned)v[1], (unsigned)v[2], z.x, z.y);
+    } else {
+        q = make_uint4((unsigned)v[1], (unsigned)v[2], (unsigned)v[3], (unsigned)c);
+    }
     pay[c] = q;
 }
 
@@ -717,35 +735,66 @@ __global__ void k_count_kept(const unsigned *__restrict__ key, int M, int n, int
 }
 
 template <int K>
-__device__ __forceinline__ void pay_row(const typename EmitPay<K>::type &q, unsigned (&r)[3], unsigned &c) {
-    if constexpr (K == 2) { r[0] = q.x; r[1] = 0; r[2] = 0; c = q.y; }
-    else if constexpr (K == 3) { r[0] = q.x; r[1] = q.y; r[2] = 0; c = q.z; }
-    else { r[0] = q.x; r[1] = q.y; r[2] = q.z; c = q.w; }
+__device__ __forceinline__ void pay_ids(const typename EmitPay<K>::type &q, unsigned (&r)[3]) {
+    if constexpr (K == 2) { r[0] = q.x; r[1] = 0; r[2] = 0; }
+    else if constexpr (K == 3) { r[0] = q.x; r[1] = q.y; r[2] = 0; }
+    else { r[0] = q.x; r[1] = q.y; r[2] = q.z; }
+}
+
+template <int K>
+__device__ __forceinline__ double pay_size(const typename EmitPay<K>::type &q, const double *__restrict__ size) {
+    if constexpr (K == 2) return double_of(q.y, q.z);
+    else if constexpr (K == 3) return double_of(q.z, q.w);
+    else return size[q.w];
 }
 
 // After the sort by least id, each row finds its bucket (equal keys are
 // adjacent; buckets are short) and its rank in the bucket by the remaining
-// ids, and writes itself to the final place.
+// ids, and writes itself to the final place. A block stages its 256 rows and
+// RANK_HALO rows on each side in LDS, so the bucket walks are LDS reads; a
+// bucket reaching past the halo is finished from global memory.
+constexpr int RANK_HALO = 64;
+
 template <int K>
 __global__ void __launch_bounds__(BLOCK) k_emit_rank(const unsigned *__restrict__ key,
                                                       const typename EmitPay<K>::type *__restrict__ pay, int m, int n,
                                                       const double *__restrict__ size_in, int *__restrict__ out,
                                                       double *__restrict__ out_size) {
-    const int p = blockIdx.x * BLOCK + threadIdx.x;
+    typedef typename EmitPay<K>::type P;
+    constexpr int SPAN = BLOCK + 2 * RANK_HALO;
+    __shared__ unsigned sk[SPAN];
+    __shared__ P sp[SPAN];
+    const int b0 = blockIdx.x * BLOCK;
+    const int lo = b0 - RANK_HALO;  // global position of sk[0]
+    for (int t = threadIdx.x; t < SPAN; t += BLOCK) {
+        const int g = lo + t;
+        if (g >= 0 && g < m) {
+            sk[t] = key[g];
+            sp[t] = pay[g];
+        } else {
+            sk[t] = 0xffffffffu;  // matches no id and not the sentinel n < 2^26
+        }
+    }
+    __syncthreads();
+    const int p = b0 + threadIdx.x;
     if (p >= m) return;
-    const unsigned u0 = key[p];
+    const int lp = p - lo;
+    const unsigned u0 = sk[lp];
     if (u0 == (unsigned)n) return;  // not kept (sorted after the kept rows)
-    unsigned r[3], c;
-    pay_row<K>(pay[p], r, c);
+    const P me = sp[lp];
+    unsigned r[3];
+    pay_ids<K>(me, r);
+    auto key_at = [&](int g) -> unsigned { const int t = g - lo; return (t >= 0 && t < SPAN) ? sk[t] : key[g]; };
+    auto pay_at = [&](int g) -> P { const int t = g - lo; return (t >= 0 && t < SPAN) ? sp[t] : pay[g]; };
     int s = p;
-    while (s > 0 && key[s - 1] == u0) s--;
+    while (s > 0 && key_at(s - 1) == u0) s--;
     int e = p + 1;
-    while (e < m && key[e] == u0) e++;
+    while (e < m && key_at(e) == u0) e++;
     int rank = 0;
     for (int w = s; w < e; w++) {
         if (w == p) continue;
-        unsigned o[3], oc;
-        pay_row<K>(pay[w], o, oc);
+        unsigned o[3];
+        pay_ids<K>(pay_at(w), o);
         const bool less = o[0] != r[0] ? o[0] < r[0] : (o[1] != r[1] ? o[1] < r[1] : o[2] < r[2]);
         rank += less;
     }
@@ -753,7 +802,7 @@ __global__ void __launch_bounds__(BLOCK) k_emit_rank(const unsigned *__restrict_
     out[q] = (int)u0;
 #pragma unroll
     for (int u = 1; u < K; u++) out[q + u] = (int)r[u - 1];
-    out_size[s + rank] = size_in[c] / 1.0e6;  // mA^2 -> A^2
+    out_size[s + rank] = pay_size<K>(me, size_in) / 1.0e6;  // mA^2 -> A^2
 }
 
 

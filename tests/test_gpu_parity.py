@@ -104,7 +104,8 @@ def test_small_molecule_alphas(acx):
 
 def test_options_do_not_change_result(acx):
     """Exact-only predicates and other cell sizes give the same simplices and
-    bit-identical Sizes (each OrthoSize is evaluated in input-index order)."""
+    bit-identical Sizes (each OrthoSize is evaluated with the vertices in a
+    canonical order of their centres)."""
     m = synth.molecule(2000, 11)
     want = oracle.alpha_complex(m.xyz, m.radii, 1.0)
     base = _run(acx, m.xyz, m.radii, 1.0)
