@@ -39,7 +39,7 @@ KERNEL_OF_STAGE = {
 }
 KERNEL_SOURCES = ["paper_1908_05944_amd/csrc/kernels.hpp", "paper_1908_05944_amd/csrc/predicates.hpp",
                   "paper_1908_05944_amd/csrc/common.hpp", "paper_1908_05944_amd/csrc/radix.hpp",
-                  "paper_1908_05944_amd/csrc/alphacx.hip"]
+                  "paper_1908_05944_amd/csrc/measure.hpp", "paper_1908_05944_amd/csrc/alphacx.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_3Mshell.json")
 
 
@@ -209,6 +209,7 @@ def main():
                     help="keep the generated input here between runs")
     ap.add_argument("--no-extras", action="store_true", help="skip the batch and union-measure workloads")
     ap.add_argument("--no-tune", action="store_true", help="default cell side instead of the autotuned one")
+    ap.add_argument("--cell-mA", type=int, default=0, help="fixed cell side in mA (skips the autotuner)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain device copy of 1 GiB (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -242,8 +243,8 @@ def main():
 
     # cell side from the autotuner (outside the timed region; it never changes
     # the result, only the time)
-    cell_mA = 0
-    if not args.no_tune:
+    cell_mA = args.cell_mA
+    if not args.no_tune and cell_mA <= 0:
         t0 = time.perf_counter()
         cells, _ = acx.ac_tune_cells(xyz, rad, np.array([0, mol.n]), args.alpha)
         cell_mA = int(cells[0])
