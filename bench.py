@@ -29,9 +29,10 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 KERNEL_OF_STAGE = {
     "neighbours_count": "k_neighbours<0>",
     "neighbours_fill": "k_neighbours<1>",
-    "triangles_count": "k_triangles<false>",
-    "triangles_fill": "k_triangles<true>",
-    "triangles_ac2": "k_tri_gabriel",
+    "triangles_count": "k_triangles<0>",
+    "triangles_fill": "k_tri_compact",
+    "triangles_ac2_tetrahedra": "k_tet_candidates<0>",
+    "tetrahedra_fill": "k_tet_compact",
     "tetrahedra_ac2": "k_tet_ac2",
     "triangles_final": "k_tri_final",
     "edges_final": "k_edge_final",
@@ -291,9 +292,10 @@ def main():
     alg_bytes = {
         "neighbours_count": 16 * n + 8 * n,
         "neighbours_fill": 16 * n + 8 * (n + 1) + 4 * Nn + 8 * E + n,
-        "triangles_count": 16 * n + 8 * E + 4 * Nn + 4 * E + E,
-        "triangles_fill": 16 * n + 8 * E + 4 * (E + 1) + 8 * T,
-        "triangles_ac2": 16 * n + 8 * T + 4 * Nn + 9 * T,
+        "triangles_count": 16 * n + 8 * E + 4 * Nn + 4 * E + 5 * E + 4 * T,
+        "triangles_fill": 8 * E + 12 * T,
+        "triangles_ac2_tetrahedra": 16 * n + 4 * Nn + 4 * E + 29 * T + 4 * Q,
+        "tetrahedra_fill": 4 * T + 12 * Q,
         "tetrahedra_ac2": 8 * Q + 8 * T + 16 * n + 9 * Q,
         "triangles_final": 30 * T,
         "edges_final": 30 * E,

@@ -296,7 +296,7 @@ enum Stage {
 };
 static const char *kStageNames[ST_COUNT] = {
     "quantise", "binning", "neighbours_count", "neighbours_scan", "neighbours_fill", "triangles_count",
-    "triangles_scan", "triangles_fill", "triangles_ac2", "tetrahedra_count", "tetrahedra_fill", "tetrahedra_ac2",
+    "triangles_scan", "triangles_fill", "triangles_ac2_tetrahedra", "tetrahedra_scan", "tetrahedra_fill", "tetrahedra_ac2",
     "triangles_final", "edges_final", "vertices_final", "emit"};
 
 struct StageTimer {
@@ -478,21 +478,38 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         LAUNCH_CHECK();
         const int *nbr_cnt = deg_n;
 
-        // ---- candidate triangles (with AC2 of the edges) ----
+        // ---- candidate triangles (with AC2 of the edges): one pass into
+        // per-block slabs, then compaction; two passes if a slab overflows ----
         int *tri_cnt = sc.get<int>(E > 0 ? E : 1);
         int *tri_start = sc.get<int>(E + 1);
         unsigned char *egab = sc.get<unsigned char>(E > 0 ? E : 1);
+        const unsigned nbE = grid_for(E);
+        int *tslab = sc.get<int>((size_t)nbE * TRI_SLAB);
+        int *tbtot = sc.get<int>(nbE);
+        int *tboff = sc.get<int>(nbE + 1);
         tm.mark(ST_TRI_COUNT);
+        fill<int>(&cnt->overflow, 0, 1, s);
         if (E > 0) {
-            k_triangles<false><<<grid_for(E), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i, E, pp,
-                                                            tri_cnt, egab, nullptr, nullptr, nullptr, cnt);
+            k_triangles<TRI_ONEPASS><<<nbE, BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i, E,
+                                                          pp, tri_cnt, egab, tslab, tbtot, nullptr, nullptr, nullptr, cnt);
             LAUNCH_CHECK();
+            tm.mark(ST_TRI_SCAN);
+            scan_i32(tbtot, tboff, nbE, s, sc);
+            k_copy_int<<<1, 1, 0, s>>>(&cnt->T, tboff + nbE);
+            LAUNCH_CHECK();
+        } else {
+            tm.mark(ST_TRI_SCAN);
+            fill<int>(&cnt->T, 0, 1, s);
         }
-        tm.mark(ST_TRI_SCAN);
-        scan_i32(tri_cnt, tri_start, E, s, sc);
-        k_copy_int<<<1, 1, 0, s>>>(&cnt->T, tri_start + E);
-        LAUNCH_CHECK();
-        const int T = read_one(cnt, s).T;
+        Counters ct = read_one(cnt, s);
+        const bool tri_two_pass = ct.overflow != 0;
+        if (tri_two_pass) {
+            scan_i32(tri_cnt, tri_start, E, s, sc);
+            k_copy_int<<<1, 1, 0, s>>>(&cnt->T, tri_start + E);
+            LAUNCH_CHECK();
+            ct = read_one(cnt, s);
+        }
+        const int T = ct.T;
         int *tri_k = sc.get<int>(T > 0 ? T : 1);
         int *tri_e = sc.get<int>(T > 0 ? T : 1);
         unsigned char *tgab = sc.get<unsigned char>(T > 0 ? T : 1);
@@ -500,36 +517,58 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         int *tet_cnt = sc.get<int>(T > 0 ? T : 1);
         int *tet_start = sc.get<int>(T + 1);
         tm.mark(ST_TRI_FILL);
-        if (T > 0) {
-            k_triangles<true><<<grid_for(E), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i, E, pp,
-                                                           nullptr, nullptr, tri_start, tri_k, tri_e, cnt);
+        if (E > 0 && !tri_two_pass) {
+            k_tri_compact<<<nbE, BLOCK, 0, s>>>(tri_cnt, E, tslab, tboff, tri_start, tri_k, tri_e);
+            LAUNCH_CHECK();
+        } else if (T > 0) {
+            k_triangles<TRI_FILL><<<nbE, BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i, E, pp,
+                                                       nullptr, nullptr, nullptr, nullptr, tri_start, tri_k, tri_e, cnt);
             LAUNCH_CHECK();
         }
-        // ---- AC2 of triangles; candidate tetrahedra ----
+        if (E == 0) fill<int>(tri_start, 0, 1, s);
+        // ---- AC2 of triangles and candidate tetrahedra: one pass into
+        // per-block slabs, then compaction; two passes if a slab overflows ----
+        const unsigned nbT = grid_for(T);
+        int *qslab = sc.get<int>((size_t)nbT * TET_SLAB);
+        int *qbtot = sc.get<int>(nbT);
+        int *qboff = sc.get<int>(nbT + 1);
         tm.mark(ST_TRI_GABRIEL);
+        fill<int>(&cnt->overflow, 0, 1, s);
         if (T > 0) {
-            k_tri_gabriel<<<grid_for(T), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up, edge_i, tri_k, tri_e, T, pp,
-                                                       tgab, tsize, cnt);
+            k_tet_candidates<TET_ONEPASS><<<nbT, BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i,
+                                                               tri_k, tri_e, T, pp, tgab, tsize, tet_cnt, qslab, qbtot,
+                                                               nullptr, nullptr, nullptr, cnt);
             LAUNCH_CHECK();
         }
         tm.mark(ST_TET_COUNT);
         if (T > 0) {
-            k_tet_candidates<false><<<grid_for(T), BLOCK, 0, s>>>(atom, up_start, up, edge_i, tri_k, tri_e, T, pp,
-                                                                 tet_cnt, nullptr, nullptr, nullptr, cnt);
+            scan_i32(qbtot, qboff, nbT, s, sc);
+            k_copy_int<<<1, 1, 0, s>>>(&cnt->Q, qboff + nbT);
             LAUNCH_CHECK();
+        } else {
+            fill<int>(&cnt->Q, 0, 1, s);
         }
-        scan_i32(tet_cnt, tet_start, T, s, sc);
-        k_copy_int<<<1, 1, 0, s>>>(&cnt->Q, tet_start + T);
-        LAUNCH_CHECK();
-        const int Q = read_one(cnt, s).Q;
+        Counters cq = read_one(cnt, s);
+        const bool tet_two_pass = cq.overflow != 0;
+        if (tet_two_pass) {
+            scan_i32(tet_cnt, tet_start, T, s, sc);
+            k_copy_int<<<1, 1, 0, s>>>(&cnt->Q, tet_start + T);
+            LAUNCH_CHECK();
+            cq = read_one(cnt, s);
+        }
+        const int Q = cq.Q;
         int *tet_t = sc.get<int>(Q > 0 ? Q : 1);
         int *tet_l = sc.get<int>(Q > 0 ? Q : 1);
         unsigned char *qin = sc.get<unsigned char>(Q > 0 ? Q : 1);
         double *qsize = sc.get<double>(Q > 0 ? Q : 1);
         tm.mark(ST_TET_FILL);
-        if (Q > 0) {
-            k_tet_candidates<true><<<grid_for(T), BLOCK, 0, s>>>(atom, up_start, up, edge_i, tri_k, tri_e, T, pp,
-                                                                nullptr, tet_start, tet_t, tet_l, cnt);
+        if (T > 0 && !tet_two_pass) {
+            k_tet_compact<<<nbT, BLOCK, 0, s>>>(tet_cnt, T, qslab, qboff, tet_t, tet_l);
+            LAUNCH_CHECK();
+        } else if (Q > 0) {
+            k_tet_candidates<TET_FILL><<<nbT, BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i,
+                                                            tri_k, tri_e, T, pp, nullptr, nullptr, nullptr, nullptr,
+                                                            nullptr, tet_start, tet_t, tet_l, cnt);
             LAUNCH_CHECK();
         }
 

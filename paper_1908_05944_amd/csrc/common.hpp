@@ -59,6 +59,26 @@ __device__ __forceinline__ int wave_append(int *counter, bool pred) {
     return pred ? base + rank : -1;
 }
 
+// Exclusive prefix sum over a block of nthreads (a multiple of 64) threads;
+// every thread of the block must call it. *total receives the block's sum.
+template <int NT>
+__device__ __forceinline__ int block_exclusive_scan(int v, int *total) {
+    __shared__ int wsum[NT / WAVE];
+    const int incl = wave_inclusive_scan(v);
+    const int w = threadIdx.x / WAVE;
+    if (lane_id() == WAVE - 1) wsum[w] = incl;
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < NT / WAVE; k++) {
+        off += k < w ? wsum[k] : 0;
+        tot += wsum[k];
+    }
+    __syncthreads();  // wsum may be reused by the next call
+    *total = tot;
+    return off + incl - v;
+}
+
 // ---------------------------------------------------------------------------
 // Device-wide exclusive scan of int32: out[i] = sum(in[0..i)), out[n] = total.
 // Tiles of SCAN_TILE items per 256-thread block; tile totals are scanned

@@ -355,53 +355,104 @@ __device__ __forceinline__ int find_tri(const int *__restrict__ up_start, const 
 
 // ---------------------------------------------------------------------------
 // Candidate triangles (Sec. 4.3): for an edge (i, j), every k > j adjacent to
-// both by a candidate edge, not collinear, with OrthoSize <= alpha. The count
+// both by a candidate edge, not collinear, with OrthoSize <= alpha. The first
 // pass also decides AC2 for the edge at its own ortho-centre (violators of any
 // candidate lie in the neighbour list of each of its vertices).
-template <bool FILL>
+//
+// MODE TRI_ONEPASS: one pass writes each edge's row into an LDS slot of
+// TRI_SLOT entries, the block packs its rows into its own slab of TRI_SLAB
+// entries of a staging array, and k_tri_compact moves every slab to its
+// final place once the block totals are scanned. Exact counts are written
+// either way; if a row or a block does not fit, cnt->overflow is set and the
+// host runs the TRI_FILL pass over scanned counts instead (same result).
+enum { TRI_ONEPASS = 0, TRI_FILL = 1 };
+constexpr int TRI_SLOT = 8;
+constexpr int TRI_SLAB = 1024;
+
+template <int MODE>
 __global__ void __launch_bounds__(BLOCK) k_triangles(const int4 *__restrict__ atom, const int *__restrict__ perm,
                                                       const int *__restrict__ nbr_start, const int *__restrict__ nbr_cnt,
                                                       const int *__restrict__ nbr,
                                                       const int *__restrict__ up_start, const int *__restrict__ up,
                                                       const int *__restrict__ edge_i, int E, PredParams pp,
                                                       int *__restrict__ tri_cnt, unsigned char *__restrict__ egab,
+                                                      int *__restrict__ slab, int *__restrict__ block_tot,
                                                       const int *__restrict__ tri_start, int *__restrict__ tri_k,
                                                       int *__restrict__ tri_e, Counters *cnt) {
-    const int e = xcd_block() * BLOCK + threadIdx.x;
-    if (e >= E) return;
-    const int i = edge_i[e], j = up[e];
-    const int4 vi = atom[i], vj = atom[j];
-    const int ns = nbr_start[i], ne = ns + nbr_cnt[i];
-    if (!FILL) {
-        const Edge ed = edge_setup(vi, vj);
-        bool gab = true;
-        for (int p = ns; p < ne; p++) {
-            const int q = nbr[p];
-            if (q == j) continue;
-            if (edge_violation_sign(ed, i, j, atom[q], q, perm, pp.force_exact) < 0) { gab = false; break; }
-        }
-        egab[e] = (unsigned char)gab;
-    }
-    int pa = e + 1;
-    const int ea = up_start[i + 1];
-    int pb = up_start[j];
-    const int eb = up_start[j + 1];
+    constexpr bool ONE = MODE == TRI_ONEPASS;
+    __shared__ int slot[ONE ? BLOCK * TRI_SLOT : 1];
+    const int b = xcd_block();
+    const int e = b * BLOCK + threadIdx.x;
     int c = 0;
-    const int out = FILL ? tri_start[e] : 0;
-    while (pa < ea && pb < eb) {
-        const int ka = up[pa], kb = up[pb];
-        if (ka < kb) { pa++; continue; }
-        if (kb < ka) { pb++; continue; }
-        pa++; pb++;
-        const Tri t = tri_setup(vi, vj, atom[ka], pp);
-        if (tri_degenerate(t) || !tri_ac3(t, pp, cnt)) continue;
-        if (FILL) {
-            tri_k[out + c] = ka;
-            tri_e[out + c] = e;
+    if (e < E) {
+        const int i = edge_i[e], j = up[e];
+        const int4 vi = atom[i], vj = atom[j];
+        if (ONE) {
+            const int ns = nbr_start[i], ne = ns + nbr_cnt[i];
+            const Edge ed = edge_setup(vi, vj);
+            bool gab = true;
+            for (int p = ns; p < ne; p++) {
+                const int q = nbr[p];
+                if (q == j) continue;
+                if (edge_violation_sign(ed, i, j, atom[q], q, perm, pp.force_exact) < 0) { gab = false; break; }
+            }
+            egab[e] = (unsigned char)gab;
         }
-        c++;
+        int pa = e + 1;
+        const int ea = up_start[i + 1];
+        int pb = up_start[j];
+        const int eb = up_start[j + 1];
+        const int out = ONE ? 0 : tri_start[e];
+        while (pa < ea && pb < eb) {
+            const int ka = up[pa], kb = up[pb];
+            if (ka < kb) { pa++; continue; }
+            if (kb < ka) { pb++; continue; }
+            pa++; pb++;
+            const Tri t = tri_setup(vi, vj, atom[ka], pp);
+            if (tri_degenerate(t) || !tri_ac3(t, pp, cnt)) continue;
+            if (ONE) {
+                if (c < TRI_SLOT) slot[threadIdx.x * TRI_SLOT + c] = ka;
+            } else {
+                tri_k[out + c] = ka;
+                tri_e[out + c] = e;
+            }
+            c++;
+        }
+        if (ONE) tri_cnt[e] = c;
     }
-    if (!FILL) tri_cnt[e] = c;
+    if (!ONE) return;
+    if (c > TRI_SLOT) cnt->overflow = 1;
+    const int kept = min(c, TRI_SLOT);
+    int total;
+    const int off = block_exclusive_scan<BLOCK>(kept, &total);
+    if (threadIdx.x == 0) {
+        block_tot[b] = total;
+        if (total > TRI_SLAB) cnt->overflow = 1;
+    }
+    if (total > TRI_SLAB) return;
+    int *dst = slab + (long long)b * TRI_SLAB + off;
+    for (int u = 0; u < kept; u++) dst[u] = slot[threadIdx.x * TRI_SLOT + u];
+}
+
+// Moves block b's slab to its final place (block_off = exclusive scan of the
+// block totals) and writes the row starts.
+__global__ void __launch_bounds__(BLOCK) k_tri_compact(const int *__restrict__ tri_cnt, int E,
+                                                        const int *__restrict__ slab, const int *__restrict__ block_off,
+                                                        int *__restrict__ tri_start, int *__restrict__ tri_k,
+                                                        int *__restrict__ tri_e) {
+    const int b = blockIdx.x;
+    const int e = b * BLOCK + threadIdx.x;
+    const int c = e < E ? tri_cnt[e] : 0;
+    int total;
+    const int off = block_exclusive_scan<BLOCK>(c, &total);
+    const int g0 = block_off[b];
+    if (e < E) {
+        tri_start[e] = g0 + off;
+        for (int u = 0; u < c; u++) tri_e[g0 + off + u] = e;
+        if (e == E - 1) tri_start[E] = g0 + off + c;
+    }
+    const int *src = slab + (long long)b * TRI_SLAB;
+    for (int k = threadIdx.x; k < total; k += BLOCK) tri_k[g0 + k] = src[k];
 }
 
 // OrthoSize evaluated with the vertices in lexicographic order of their
@@ -440,71 +491,107 @@ __device__ __forceinline__ double tet_size_canon(int4 a, int4 b, int4 c, int4 d,
     return tet_orthosize(tet_setup(v[0], v[1], v[2], v[3], pp));
 }
 
-// Triangles: AC2 at their own ortho-centre and OrthoSize (one thread each).
-__global__ void __launch_bounds__(BLOCK) k_tri_gabriel(const int4 *__restrict__ atom, const int *__restrict__ perm,
-                                                        const int *__restrict__ nbr_start, const int *__restrict__ nbr_cnt,
-                                                      const int *__restrict__ nbr,
-                                                        const int *__restrict__ up, const int *__restrict__ edge_i,
-                                                        const int *__restrict__ tri_k, const int *__restrict__ tri_e,
-                                                        int T, PredParams pp, unsigned char *__restrict__ tgab,
-                                                        double *__restrict__ tsize, Counters *cnt) {
-    const int t = xcd_block() * BLOCK + threadIdx.x;
-    if (t >= T) return;
-    const int e = tri_e[t];
-    const int i = edge_i[e], j = up[e], k = tri_k[t];
-    const Tri tr = tri_setup(atom[i], atom[j], atom[k], pp);
-    bool gab = true;
-    const int ns = nbr_start[i], ne = ns + nbr_cnt[i];
-    for (int p = ns; p < ne; p++) {
-        const int q = nbr[p];
-        if (q == j || q == k) continue;
-        if (tri_violation_sign(tr, i, j, k, atom[q], q, perm, pp, cnt) < 0) { gab = false; break; }
-    }
-    tgab[t] = (unsigned char)gab;
-    tsize[t] = tri_size_canon(tr.v0, atom[j], atom[k], pp);
-}
-
 // ---------------------------------------------------------------------------
 // Candidate tetrahedra (Step 1, d = 3): for a triangle (i, j, k), every l > k
 // adjacent to all three by candidate edges (all six edges in Sigma_ortho^1
 // suffice, since OrthoSize grows from face to coface, Sec. 4.3), not flat,
-// with OrthoSize <= alpha. Count pass, then fill pass into (triangle, l) pairs.
-template <bool FILL>
-__global__ void __launch_bounds__(BLOCK) k_tet_candidates(const int4 *__restrict__ atom,
+// with OrthoSize <= alpha, as (triangle, l) pairs.
+//
+// MODE TET_ONEPASS (one thread per triangle) also decides AC2 for the
+// triangle at its own ortho-centre and its OrthoSize, and writes the pairs
+// through LDS slots and per-block slabs like k_triangles; TET_FILL is the
+// second pass of the two-pass path, over scanned exact counts.
+enum { TET_ONEPASS = 0, TET_FILL = 1 };
+constexpr int TET_SLOT = 4;
+constexpr int TET_SLAB = 256;
+
+template <int MODE>
+__global__ void __launch_bounds__(BLOCK) k_tet_candidates(const int4 *__restrict__ atom, const int *__restrict__ perm,
+                                                           const int *__restrict__ nbr_start,
+                                                           const int *__restrict__ nbr_cnt, const int *__restrict__ nbr,
                                                            const int *__restrict__ up_start, const int *__restrict__ up,
                                                            const int *__restrict__ edge_i, const int *__restrict__ tri_k,
                                                            const int *__restrict__ tri_e, int T, PredParams pp,
-                                                           int *__restrict__ tet_cnt, const int *__restrict__ tet_start,
-                                                           int *__restrict__ tet_t, int *__restrict__ tet_l,
-                                                           Counters *cnt) {
-    const int t = xcd_block() * BLOCK + threadIdx.x;
-    if (t >= T) return;
-    const int e = tri_e[t];
-    const int i = edge_i[e], j = up[e], k = tri_k[t];
-    int pa = e + 1;
-    const int ea = up_start[i + 1];
-    int pb = up_start[j];
-    const int eb = up_start[j + 1];
-    int pc = up_start[k];
-    const int ec = up_start[k + 1];
+                                                           unsigned char *__restrict__ tgab, double *__restrict__ tsize,
+                                                           int *__restrict__ tet_cnt, int *__restrict__ slab,
+                                                           int *__restrict__ block_tot,
+                                                           const int *__restrict__ tet_start, int *__restrict__ tet_t,
+                                                           int *__restrict__ tet_l, Counters *cnt) {
+    constexpr bool ONE = MODE == TET_ONEPASS;
+    __shared__ int slot[ONE ? BLOCK * TET_SLOT : 1];
+    const int b = xcd_block();
+    const int t = b * BLOCK + threadIdx.x;
     int c = 0;
-    const int out = FILL ? tet_start[t] : 0;
-    int4 vi = make_int4(0, 0, 0, 0), vj = vi, vk = vi;
-    bool loaded = false;
-    while (pa < ea && pb < eb && pc < ec) {
-        const int la = up[pa], lb = up[pb], lc = up[pc];
-        const int m = max(la, max(lb, lc));
-        if (la < m) { pa++; continue; }
-        if (lb < m) { pb++; continue; }
-        if (lc < m) { pc++; continue; }
-        pa++; pb++; pc++;
-        if (!loaded) { vi = atom[i]; vj = atom[j]; vk = atom[k]; loaded = true; }
-        const Tet te = tet_setup(vi, vj, vk, atom[m], pp);
-        if (te.D == 0 || !tet_ac3(te, pp, cnt)) continue;
-        if (FILL) { tet_t[out + c] = t; tet_l[out + c] = m; }
-        c++;
+    if (t < T) {
+        const int e = tri_e[t];
+        const int i = edge_i[e], j = up[e], k = tri_k[t];
+        const int4 vi = atom[i], vj = atom[j], vk = atom[k];
+        if (ONE) {
+            const Tri tr = tri_setup(vi, vj, vk, pp);
+            bool gab = true;
+            const int ns = nbr_start[i], ne = ns + nbr_cnt[i];
+            for (int p = ns; p < ne; p++) {
+                const int q = nbr[p];
+                if (q == j || q == k) continue;
+                if (tri_violation_sign(tr, i, j, k, atom[q], q, perm, pp, cnt) < 0) { gab = false; break; }
+            }
+            tgab[t] = (unsigned char)gab;
+            tsize[t] = tri_size_canon(vi, vj, vk, pp);
+        }
+        int pa = e + 1;
+        const int ea = up_start[i + 1];
+        int pb = up_start[j];
+        const int eb = up_start[j + 1];
+        int pc = up_start[k];
+        const int ec = up_start[k + 1];
+        const int out = ONE ? 0 : tet_start[t];
+        while (pa < ea && pb < eb && pc < ec) {
+            const int la = up[pa], lb = up[pb], lc = up[pc];
+            const int m = max(la, max(lb, lc));
+            if (la < m) { pa++; continue; }
+            if (lb < m) { pb++; continue; }
+            if (lc < m) { pc++; continue; }
+            pa++; pb++; pc++;
+            const Tet te = tet_setup(vi, vj, vk, atom[m], pp);
+            if (te.D == 0 || !tet_ac3(te, pp, cnt)) continue;
+            if (ONE) {
+                if (c < TET_SLOT) slot[threadIdx.x * TET_SLOT + c] = m;
+            } else {
+                tet_t[out + c] = t;
+                tet_l[out + c] = m;
+            }
+            c++;
+        }
+        if (ONE) tet_cnt[t] = c;
     }
-    if (!FILL) tet_cnt[t] = c;
+    if (!ONE) return;
+    if (c > TET_SLOT) cnt->overflow = 1;
+    const int kept = min(c, TET_SLOT);
+    int total;
+    const int off = block_exclusive_scan<BLOCK>(kept, &total);
+    if (threadIdx.x == 0) {
+        block_tot[b] = total;
+        if (total > TET_SLAB) cnt->overflow = 1;
+    }
+    if (total > TET_SLAB) return;
+    int *dst = slab + (long long)b * TET_SLAB + off;
+    for (int u = 0; u < kept; u++) dst[u] = slot[threadIdx.x * TET_SLOT + u];
+}
+
+// Moves block b's slab of tetrahedron candidates to its final place.
+__global__ void __launch_bounds__(BLOCK) k_tet_compact(const int *__restrict__ tet_cnt, int T,
+                                                        const int *__restrict__ slab, const int *__restrict__ block_off,
+                                                        int *__restrict__ tet_t, int *__restrict__ tet_l) {
+    const int b = blockIdx.x;
+    const int t = b * BLOCK + threadIdx.x;
+    const int c = t < T ? tet_cnt[t] : 0;
+    int total;
+    const int off = block_exclusive_scan<BLOCK>(c, &total);
+    const int g0 = block_off[b];
+    if (t < T)
+        for (int u = 0; u < c; u++) tet_t[g0 + off + u] = t;
+    const int *src = slab + (long long)b * TET_SLAB;
+    for (int k = threadIdx.x; k < total; k += BLOCK) tet_l[g0 + k] = src[k];
 }
 
 // A face that passes AC2 itself is in K with Size = OrthoSize whatever its

@@ -52,6 +52,7 @@ struct Counters {
     int lookup;    // a facet lookup failed (must not happen)
     int Nn, E, T, Q;  // neighbour entries and candidate counts, copied from scan totals
     int m0, m1, m2, m3;
+    int overflow;  // a single-pass stage ran out of its per-block room (then the two-pass path runs)
 };
 
 __device__ __forceinline__ int sgn128(i128 v) { return (v > 0) - (v < 0); }
