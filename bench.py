@@ -28,7 +28,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 
 KERNEL_OF_STAGE = {
     "neighbours_count": "k_neighbours<0>",
-    "neighbours_fill": "k_neighbours<1>",
+    "neighbours_fill": "k_nbr_compact",
     "triangles_count": "k_triangles<0>",
     "triangles_fill": "k_tri_compact",
     "triangles_ac2_tetrahedra": "k_tet_candidates<0>",
@@ -290,8 +290,8 @@ def main():
     E, T, Q = cand[1], cand[2], cand[3]
     Nn = work[1]
     alg_bytes = {
-        "neighbours_count": 16 * n + 8 * n,
-        "neighbours_fill": 16 * n + 8 * (n + 1) + 4 * Nn + 8 * E + n,
+        "neighbours_count": 16 * n + 9 * n + 4 * Nn + 4 * E,
+        "neighbours_fill": 16 * n + 8 * Nn + 12 * E,
         "triangles_count": 16 * n + 8 * E + 4 * Nn + 4 * E + 5 * E + 4 * T,
         "triangles_fill": 8 * E + 12 * T,
         "triangles_ac2_tetrahedra": 16 * n + 4 * Nn + 4 * E + 29 * T + 4 * Q,

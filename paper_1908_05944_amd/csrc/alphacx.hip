@@ -452,29 +452,51 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         k_gather_atoms<<<grid_for(n), BLOCK, 0, s>>>(q, ckey, cidx, n, atom, perm, cnt);
         LAUNCH_CHECK();
 
-        // ---- neighbours and candidate edges: count, scan, fill ----
+        // ---- neighbours and candidate edges: one pass into per-block slabs,
+        // then compaction; count, scan and fill if a ball's rows overflow ----
         int *deg_n = sc.get<int>(n), *deg_up = sc.get<int>(n);
         int *nbr_start = sc.get<int>(n + 1), *up_start = sc.get<int>(n + 1);
         unsigned char *vgab = sc.get<unsigned char>(n);
+        const unsigned nbN = grid_for(n);
+        int *nslab = sc.get<int>((size_t)nbN * NB_SLAB);
+        unsigned *upmask = sc.get<unsigned>(n);
+        int *nbtot = sc.get<int>(2 * (size_t)nbN);
+        int *nboff = sc.get<int>(nbN + 1), *uboff = sc.get<int>(nbN + 1);
         tm.mark(ST_NBR_COUNT);
-        k_neighbours<NB_COUNT><<<grid_for(n), BLOCK, 0, s>>>(atom, perm, n, d_grids, n_mol, cell_start, pp, deg_n, deg_up, nullptr,
-                                                            nullptr, nullptr, nullptr, nullptr, nullptr);
+        k_neighbours<NB_ONEPASS><<<nbN, BLOCK, 0, s>>>(atom, perm, n, d_grids, n_mol, cell_start, pp, deg_n, deg_up,
+                                                      upmask, nslab, nbtot, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                                      vgab, cnt);
         LAUNCH_CHECK();
         tm.mark(ST_NBR_SCAN);
-        scan_i32(deg_n, nbr_start, n, s, sc);
-        scan_i32(deg_up, up_start, n, s, sc);
-        k_copy_int<<<1, 1, 0, s>>>(&cnt->Nn, nbr_start + n);
-        k_copy_int<<<1, 1, 0, s>>>(&cnt->E, up_start + n);
+        scan_i32(nbtot, nboff, nbN, s, sc);
+        scan_i32(nbtot + nbN, uboff, nbN, s, sc);
+        k_copy_int<<<1, 1, 0, s>>>(&cnt->Nn, nboff + nbN);
+        k_copy_int<<<1, 1, 0, s>>>(&cnt->E, uboff + nbN);
         LAUNCH_CHECK();
-        const Counters c0 = read_one(cnt, s);
+        Counters c0 = read_one(cnt, s);
         if (c0.dup) throw HipError{AC_E_DUPLICATE, "two balls have equal quantised centres"};
+        const bool nbr_two_pass = c0.overflow != 0;
+        if (nbr_two_pass) {
+            scan_i32(deg_n, nbr_start, n, s, sc);
+            scan_i32(deg_up, up_start, n, s, sc);
+            k_copy_int<<<1, 1, 0, s>>>(&cnt->Nn, nbr_start + n);
+            k_copy_int<<<1, 1, 0, s>>>(&cnt->E, up_start + n);
+            LAUNCH_CHECK();
+            c0 = read_one(cnt, s);
+        }
         const int E = c0.E, Nn = c0.Nn;
         int *nbr = sc.get<int>(Nn > 0 ? Nn : 1);
         int *up = sc.get<int>(E > 0 ? E : 1);
         int *edge_i = sc.get<int>(E > 0 ? E : 1);
         tm.mark(ST_NBR_FILL);
-        k_neighbours<NB_FILL><<<grid_for(n), BLOCK, 0, s>>>(atom, perm, n, d_grids, n_mol, cell_start, pp, nullptr, nullptr,
-                                                           nbr_start, up_start, nbr, up, edge_i, vgab);
+        if (!nbr_two_pass) {
+            k_nbr_compact<<<nbN, BLOCK, 0, s>>>(deg_n, deg_up, upmask, n, nslab, nboff, uboff, nbr_start, up_start, nbr,
+                                               up, edge_i);
+        } else {
+            k_neighbours<NB_FILL><<<nbN, BLOCK, 0, s>>>(atom, perm, n, d_grids, n_mol, cell_start, pp, nullptr, nullptr,
+                                                       nullptr, nullptr, nullptr, nbr_start, up_start, nbr, up, edge_i,
+                                                       vgab, cnt);
+        }
         LAUNCH_CHECK();
         const int *nbr_cnt = deg_n;
 

@@ -211,32 +211,46 @@ __global__ void __launch_bounds__(BLOCK) k_gather_atoms(const int4 *__restrict__
 // in the sorted order, so each (dz, dy) row is one contiguous range. The fill
 // pass also decides AC2 for the ball as a vertex (Step 5): every ball that
 // could be strictly closer in power to its centre is in its neighbour list.
-// MODE: NB_COUNT counts the rows; NB_FILL writes them into the CSR rows the
-// counts sized (each thread's row contiguous, consecutive rows adjacent).
-enum { NB_COUNT = 0, NB_FILL = 1 };
+// MODE: NB_ONEPASS writes each ball's neighbour row into an LDS slot of
+// NB_SLOT entries and marks in a 32-bit mask which of them are upper
+// candidate edges (the upper row is a filtered part of the neighbour row);
+// the block packs the rows into a slab of its own, and k_nbr_compact writes
+// both rows into place once the block totals are scanned. Exact counts are
+// kept; a ball with more than NB_SLOT neighbours sets cnt->overflow, after
+// which the host runs NB_FILL over the scanned counts instead (same result).
+// NB_FILL writes the rows into the CSR rows the counts sized (each thread's
+// row contiguous, consecutive rows adjacent).
+enum { NB_ONEPASS = 0, NB_FILL = 1 };
+constexpr int NB_SLOT = 16;  // the largest degree of the van der Waals workloads is 14
+constexpr int NB_SLAB = BLOCK * NB_SLOT;
+static_assert(NB_SLOT <= 32, "one mask bit per slot entry");
 
 template <int MODE>
 __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ atom, const int *__restrict__ perm, int n,
                                                        const Grid *__restrict__ grids, int n_mol,
                                                        const int *__restrict__ cell_start, PredParams pp,
                                                        int *__restrict__ deg_n, int *__restrict__ deg_up,
+                                                       unsigned *__restrict__ upmask, int *__restrict__ nslab,
+                                                       int *__restrict__ block_tot,
                                                        const int *__restrict__ nbr_start, const int *__restrict__ up_start,
                                                        int *__restrict__ nbr, int *__restrict__ up,
-                                                       int *__restrict__ edge_i, unsigned char *__restrict__ vgab) {
-    constexpr bool FILL = MODE == NB_FILL;
-    // The fill pass stages the block's rows in LDS and writes them out as one
+                                                       int *__restrict__ edge_i, unsigned char *__restrict__ vgab,
+                                                       Counters *cnt) {
+    constexpr bool ONE = MODE == NB_ONEPASS;
+    // NB_FILL stages the block's rows in LDS and writes them out as one
     // contiguous range (the block's rows are adjacent in the CSR arrays);
     // rows written straight from the scan would be partial-line scattered
     // stores. A block whose rows exceed the LDS buffers writes directly.
-    constexpr int LDS_N = FILL ? 4096 : 1, LDS_U = FILL ? 2048 : 1;
+    constexpr int LDS_N = ONE ? NB_SLAB : 4096, LDS_U = ONE ? 1 : 2048;
     __shared__ int sn[LDS_N];
     __shared__ int su[LDS_U];
-    const int b0 = xcd_block() * BLOCK;
+    const int b = xcd_block();
+    const int b0 = b * BLOCK;
     const int i = b0 + threadIdx.x;
     const bool valid = i < n;
     int bn = 0, bu = 0, en = 0, eu = 0;
     bool staged = false;
-    if (FILL) {
+    if (!ONE) {
         const int last = min(b0 + BLOCK, n);
         bn = nbr_start[b0]; en = nbr_start[last];
         bu = up_start[b0]; eu = up_start[last];
@@ -245,10 +259,13 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
     const int4 a = valid ? atom[i] : make_int4(0, 0, 0, 0);
     const int ra = valid ? a.w + (int)pp.aq : -1;  // |aq| < 2^26 and W < 2^26
     int cn = 0, cu = 0;
+    unsigned mask = 0;
     bool gab = true;
     if (ra >= 0) {
-        const int pn = FILL ? nbr_start[i] : 0;
-        const int pu = FILL ? up_start[i] : 0;
+        // where this ball's rows go: its LDS slot, or its CSR rows
+        int *const rn = ONE ? sn + threadIdx.x * NB_SLOT : (staged ? sn + (nbr_start[i] - bn) : nbr + nbr_start[i]);
+        int *const ru = ONE ? nullptr : (staged ? su + (up_start[i] - bu) : up + up_start[i]);
+        const int capn = ONE ? NB_SLOT : INT_MAX;
         const Grid g = grids[mol_of(grids, n_mol, i)];
         const int cx = (a.x - g.ox) / g.s, cy = (a.y - g.oy) / g.s, cz = (a.z - g.oz) / g.s;
         const int x0 = max(cx - g.reach, 0), x1 = min(cx + g.reach, g.nx - 1);
@@ -271,37 +288,51 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
                 const int s = cell_start[rb + x0], e = cell_start[rb + x1 + 1];
                 for (int j = s; j < e; j++) {
                     if (j == i) continue;
-                    const int4 b = atom[j];
-                    const int dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
+                    const int4 bb = atom[j];
+                    const int dx = bb.x - a.x, dy = bb.y - a.y, dz = bb.z - a.z;
                     if (abs(dx) > reach1 || abs(dy) > reach1 || abs(dz) > reach1) continue;
                     const int d2 = dx * dx + dy * dy + dz * dz;
                     if (d2 > lim || d2 == 0) continue; /* equal centres are reported by k_gather_atoms */
-                    const int rb2 = b.w + (int)pp.aq;
+                    const int rb2 = bb.w + (int)pp.aq;
                     if (rb2 < 0) continue;
                     // grown balls meet: d <= rho_a + rho_b
                     const int L = d2 - ra - rb2;
                     if (L > 0 && (i64)L * L > 4 * (i64)ra * rb2) continue;
-                    if (FILL) {
-                        if (staged) sn[pn - bn + cn] = j; else nbr[pn + cn] = j;
-                        if (gab && vertex_violation_sign(a, i, b, j, perm) < 0) gab = false;
+                    if (cn < capn) rn[cn] = j;
+                    if (gab && vertex_violation_sign(a, i, bb, j, perm) < 0) gab = false;
+                    if (j > i && edge_ac3(edge_setup(a, bb), pp.aq)) {
+                        if (ONE) {
+                            if (cn < 32) mask |= 1u << cn;
+                        } else {
+                            ru[cu] = j;
+                        }
+                        cu++;
                     }
                     cn++;
-                    if (j > i) {
-                        const Edge ed = edge_setup(a, b);
-                        if (edge_ac3(ed, pp.aq)) {
-                            if (FILL) { if (staged) su[pu - bu + cu] = j; else up[pu + cu] = j; }
-                            cu++;
-                        }
-                    }
                 }
             }
         }
     }
-    if (!FILL) {
-        if (valid) { deg_n[i] = cn; deg_up[i] = cu; }
+    if (valid) vgab[i] = (unsigned char)(ra >= 0 && gab);
+    if (ONE) {
+        if (valid) {
+            deg_n[i] = cn;
+            deg_up[i] = cu;
+            upmask[i] = mask;
+        }
+        if (cn > NB_SLOT) cnt->overflow = 1;
+        const int kn = min(cn, NB_SLOT);
+        int totn, totu;
+        const int offn = block_exclusive_scan<BLOCK>(kn, &totn);
+        (void)block_exclusive_scan<BLOCK>(cu, &totu);
+        if (threadIdx.x == 0) {
+            block_tot[b] = totn;             // neighbour entries of the block
+            block_tot[gridDim.x + b] = totu;  // upper entries of the block
+        }
+        int *dn = nslab + (long long)b * NB_SLAB + offn;
+        for (int k = 0; k < kn; k++) dn[k] = sn[threadIdx.x * NB_SLOT + k];
         return;
     }
-    if (valid) vgab[i] = (unsigned char)(ra >= 0 && gab);
     if (!staged) {
         // rows went straight to nbr / up; the upper rows' owner ids remain
         if (valid) {
@@ -321,6 +352,44 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
     }
     __syncthreads();
     for (int k = threadIdx.x; k < eu - bu; k += BLOCK) edge_i[bu + k] = su[k];
+}
+
+// Writes the rows of block b's balls into place from the block's slab
+// (noff / uoff: exclusive scans of the blocks' neighbour and upper entry
+// totals): each neighbour row, the entries of it that the mask marks as the
+// upper row, the row starts and the owner of every upper entry.
+__global__ void __launch_bounds__(BLOCK) k_nbr_compact(const int *__restrict__ deg_n, const int *__restrict__ deg_up,
+                                                        const unsigned *__restrict__ upmask, int n,
+                                                        const int *__restrict__ nslab, const int *__restrict__ noff,
+                                                        const int *__restrict__ uoff, int *__restrict__ nbr_start,
+                                                        int *__restrict__ up_start, int *__restrict__ nbr,
+                                                        int *__restrict__ up, int *__restrict__ edge_i) {
+    const int b = blockIdx.x;
+    const int i = b * BLOCK + threadIdx.x;
+    const int cn = i < n ? deg_n[i] : 0, cu = i < n ? deg_up[i] : 0;
+    int totn, totu;
+    const int offn = block_exclusive_scan<BLOCK>(cn, &totn);
+    const int offu = block_exclusive_scan<BLOCK>(cu, &totu);
+    const int gn = noff[b], gu = uoff[b];
+    const int *src = nslab + (long long)b * NB_SLAB;
+    // neighbour rows: the block's packed slab, copied with coalesced accesses
+    for (int k = threadIdx.x; k < totn; k += BLOCK) nbr[gn + k] = src[k];
+    if (i >= n) return;
+    nbr_start[i] = gn + offn;
+    up_start[i] = gu + offu;
+    unsigned m = upmask[i];
+    int q = gu + offu;
+    while (m) {
+        const int k = __ffs((int)m) - 1;
+        m &= m - 1;
+        up[q] = src[offn + k];
+        edge_i[q] = i;
+        q++;
+    }
+    if (i == n - 1) {
+        nbr_start[n] = gn + offn + cn;
+        up_start[n] = gu + offu + cu;
+    }
 }
 
 __global__ void k_copy_int(int *__restrict__ dst, const int *__restrict__ src) { *dst = *src; }
