@@ -2,12 +2,14 @@
 //
 // One pass per 8-bit digit: a tile histogram kernel (LDS counters), a
 // device-wide exclusive scan of the digit-major table [256][tiles], and a
-// scatter kernel. The scatter ranks each tile's elements stably by digit
-// (wave-level match by ballots, waves taking their offsets in order), places
-// them in LDS in digit order, and then writes the tile out so that each
-// digit's run (about tile / 256 elements) goes to consecutive addresses:
-// writing each element straight from its lane would scatter partial-line
-// stores over the whole output. No global atomics are used: on MI355X
+// scatter kernel. In the scatter each wave owns a contiguous chunk of the
+// tile and ranks its elements among equal digits with ballots and per-wave
+// LDS counters (no block barrier inside the sweep); one block scan over
+// (digit, wave) counts then gives every element its stable place, the tile
+// is laid out in LDS in digit order and written so that each digit's run
+// (about tile / 256 elements) goes to consecutive addresses: writing each
+// element straight from its lane would scatter partial-line stores over the
+// whole output. No global atomics are used: on MI355X
 // device-scope atomics go through the memory-side fabric and run far below
 // the memory bandwidth.
 #pragma once
@@ -42,67 +44,82 @@ __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const unsigned *__restr
                                                           unsigned *__restrict__ kout, P *__restrict__ pout, int n,
                                                           int shift, const int *__restrict__ offs,
                                                           const int *__restrict__ hist, int tiles) {
-    __shared__ int gbase[RS_BINS];  // output start of each digit for this tile
-    __shared__ int lbase[RS_BINS];  // start of each digit inside the tile
-    __shared__ int run[RS_BINS];
-    __shared__ int grp[RS_BLOCK / WAVE][WAVE];
-    __shared__ int wsum[RS_BLOCK / WAVE];
+    constexpr int NW = RS_BLOCK / WAVE;
+    constexpr int CHUNK = WAVE * RS_IPT;  // each wave owns a contiguous chunk of the tile
+    __shared__ int gbase[RS_BINS];        // output start of each digit for this tile
+    __shared__ int wcnt[NW][RS_BINS];     // per-wave digit counts, then per-wave digit starts
+    __shared__ int wsum[NW];
     __shared__ unsigned skey[RS_TILE];
     __shared__ P spay[RS_TILE];
     const int lane = lane_id(), wave = threadIdx.x / WAVE;
+    (void)hist;  // the tile's counts are recounted per wave below
     gbase[threadIdx.x] = offs[(long long)threadIdx.x * tiles + blockIdx.x];
-    {
-        // tile-local exclusive scan of this tile's digit counts
-        const int h = hist[(long long)threadIdx.x * tiles + blockIdx.x];
-        const int incl = wave_inclusive_scan(h);
-        if (lane == WAVE - 1) wsum[wave] = incl;
-        __syncthreads();
-        int off = 0;
-        for (int w = 0; w < wave; w++) off += wsum[w];
-        lbase[threadIdx.x] = off + incl - h;
-    }
-    run[threadIdx.x] = 0;
+#pragma unroll
+    for (int w = 0; w < NW; w++) wcnt[w][threadIdx.x] = 0;
     __syncthreads();
+    // sweep: rank each element among the equal digits of its wave so far
     const unsigned long long lt = (1ull << lane) - 1ull;
-    const long long base = (long long)blockIdx.x * RS_TILE;
+    const long long base = (long long)blockIdx.x * RS_TILE + (long long)wave * CHUNK;
+    unsigned key[RS_IPT];
+    P pay[RS_IPT];
+    int rank[RS_IPT];
+#pragma unroll
     for (int r = 0; r < RS_IPT; r++) {
-        const long long idx = base + (long long)r * RS_BLOCK + threadIdx.x;
+        const long long idx = base + (long long)r * WAVE + lane;
         const bool valid = idx < n;
-        unsigned key = 0;
-        P pay{};
-        if (valid) { key = kin[idx]; pay = pin[idx]; }
-        const unsigned d = (key >> shift) & (RS_BINS - 1);
+        key[r] = 0;
+        pay[r] = P{};
+        if (valid) { key[r] = kin[idx]; pay[r] = pin[idx]; }
+        const unsigned d = (key[r] >> shift) & (RS_BINS - 1);
         unsigned long long peers = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < RS_BITS; b++) {
-            const unsigned long long m = __ballot((d >> b) & 1u);
-            peers &= ((d >> b) & 1u) ? m : ~m;
+        for (int bit = 0; bit < RS_BITS; bit++) {
+            const unsigned long long m = __ballot((d >> bit) & 1u);
+            peers &= ((d >> bit) & 1u) ? m : ~m;
         }
         const int leader = valid ? __ffsll((long long)peers) - 1 : 0;
-        const int rank = __popcll(peers & lt);
-        // waves take their offsets in order, so equal digits keep input order
-        for (int w = 0; w < RS_BLOCK / WAVE; w++) {
-            if (wave == w && valid && lane == leader) {
-                const int old = run[d];
-                run[d] = old + __popcll(peers);
-                grp[w][lane] = old;
-            }
-            __syncthreads();
+        int old = 0;
+        if (valid && lane == leader) {
+            old = wcnt[wave][d];
+            wcnt[wave][d] = old + __popcll(peers);
         }
-        if (valid) {
-            const int lpos = lbase[d] + grp[wave][leader] + rank;
-            skey[lpos] = key;
-            spay[lpos] = pay;
-        }
-        __syncthreads();
+        old = __shfl(old, leader, WAVE);
+        rank[r] = valid ? old + __popcll(peers & lt) : -1;
     }
-    // the tile in digit order: each digit's run goes to consecutive addresses
-    const int cnt = (int)min((long long)RS_TILE, (long long)n - base);
+    __syncthreads();
+    // tile-local start of (digit, wave): digits in order, waves in order
+    {
+        const int d = threadIdx.x;
+        int c[NW], tot = 0;
+#pragma unroll
+        for (int w = 0; w < NW; w++) { c[w] = wcnt[w][d]; tot += c[w]; }
+        const int incl = wave_inclusive_scan(tot);
+        if (lane == WAVE - 1) wsum[wave] = incl;
+        __syncthreads();
+        int start = incl - tot;
+        for (int w = 0; w < wave; w++) start += wsum[w];
+#pragma unroll
+        for (int w = 0; w < NW; w++) { wcnt[w][d] = start; start += c[w]; }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RS_IPT; r++) {
+        if (rank[r] < 0) continue;
+        const unsigned d = (key[r] >> shift) & (RS_BINS - 1);
+        const int lpos = wcnt[wave][d] + rank[r];
+        skey[lpos] = key[r];
+        spay[lpos] = pay[r];
+    }
+    __syncthreads();
+    // the tile in digit order: each digit's run goes to consecutive addresses;
+    // a digit's tile-local start is the start of its first wave
+    const long long tbase = (long long)blockIdx.x * RS_TILE;
+    const int cnt = (int)min((long long)RS_TILE, (long long)n - tbase);
     for (int p = threadIdx.x; p < cnt; p += RS_BLOCK) {
-        const unsigned key = skey[p];
-        const unsigned d = (key >> shift) & (RS_BINS - 1);
-        const int g = gbase[d] + (p - lbase[d]);
-        kout[g] = key;
+        const unsigned k = skey[p];
+        const unsigned d = (k >> shift) & (RS_BINS - 1);
+        const int g = gbase[d] + (p - wcnt[0][d]);
+        kout[g] = k;
         pout[g] = spay[p];
     }
 }

@@ -186,3 +186,51 @@ def test_100k_frame_finite_differences(acx):
             ga = dxA[i, k] if k < 3 else drA[i]
             assert abs(fv - gv) <= 1e-6 * max(abs(gv), 1e-3 * medV) + 24 * eps * sv / h, (i, k, fv, gv)
             assert abs(fa - ga) <= 1e-6 * max(abs(ga), 1e-3 * medA) + 24 * eps * sa / h, (i, k, fa, ga)
+
+
+def test_graph_replay_of_forward_backward(acx):
+    """With the complex held fixed (as in an optimisation loop), V, A and the
+    backward allocate nothing and never synchronise after the first call, so
+    they can be captured once in a HIP graph and replayed with new
+    coordinates written into the same buffers; every replay must equal the
+    eager calls bit for bit."""
+    import torch
+    m = synth.molecule(3000, 17)
+    X = _dev(m.xyz)
+    R = _dev(m.radii)
+    c = acx.ac_alpha_complex_device(X, R, 0.0)
+    g = torch.tensor([1.0, 0.5], dtype=torch.float64, device="cuda:0")
+    out = torch.empty(2, dtype=torch.float64, device="cuda:0")
+    dx = torch.empty_like(X)
+    dr = torch.empty_like(R)
+    lib = acx.library()
+    s = torch.cuda.Stream()
+
+    def step():
+        st = torch.cuda.current_stream()
+        h = acx.ctypes.c_void_p(st.cuda_stream)
+        assert lib.ac_union_measure_device(c._h, X.data_ptr(), R.data_ptr(), m.n, out.data_ptr(), h) == 0
+        assert lib.ac_union_measure_backward(c._h, X.data_ptr(), R.data_ptr(), m.n, g.data_ptr(), dx.data_ptr(),
+                                             dr.data_ptr(), h) == 0
+
+    with torch.cuda.stream(s):
+        step()  # first call: sorts the incidences, allocates the work buffers
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=s):
+            step()
+    torch.cuda.synchronize()
+    rng = np.random.RandomState(5)
+    for rep in range(4):
+        shift = rng.normal(0.0, 0.01, size=m.xyz.shape)
+        X.copy_(_dev(m.xyz + shift))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        got = (out.clone(), dx.clone(), dr.clone())
+        with torch.cuda.stream(s):
+            step()
+        torch.cuda.synchronize()
+        assert torch.equal(got[0], out) and torch.equal(got[1], dx) and torch.equal(got[2], dr), rep
+        V, A = acx.ac_union_measure(c, X, R)
+        assert (V, A) == tuple(out.cpu().tolist())
