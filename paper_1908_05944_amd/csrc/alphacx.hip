@@ -189,7 +189,7 @@ static void scan_i32(const int *in, int *out, long long n, hipStream_t s, Scope 
         return;
     }
     if (n <= SCAN_SMALL) {
-        k_scan_small<<<1, SCAN_BLOCK, 0, s>>>(in, out, (int)n);
+        k_scan_small<<<1, SCAN_SMALL_BLOCK, 0, s>>>(in, out, (int)n);
         LAUNCH_CHECK();
         return;
     }

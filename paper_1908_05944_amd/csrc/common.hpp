@@ -120,16 +120,23 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_tiles(const int *__restrict
 }
 
 // Single-block exclusive scan for n <= SCAN_SMALL: out[0..n], out[n] = total.
-constexpr int SCAN_SMALL_IPT = 64;
-constexpr int SCAN_SMALL = SCAN_BLOCK * SCAN_SMALL_IPT;
+// 1024 threads with 16 items each: every thread issues its loads together, so
+// the scan costs about one memory latency instead of a serial walk.
+constexpr int SCAN_SMALL_BLOCK = 1024;
+constexpr int SCAN_SMALL_IPT = 16;
+constexpr int SCAN_SMALL = SCAN_SMALL_BLOCK * SCAN_SMALL_IPT;
 
-__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_small(const int *__restrict__ in, int *__restrict__ out, int n) {
-    __shared__ int wsum[SCAN_BLOCK / WAVE];
+__global__ void __launch_bounds__(SCAN_SMALL_BLOCK) k_scan_small(const int *__restrict__ in, int *__restrict__ out,
+                                                                  int n) {
+    __shared__ int wsum[SCAN_SMALL_BLOCK / WAVE];
     const int base = threadIdx.x * SCAN_SMALL_IPT;
+    int v[SCAN_SMALL_IPT];
     int s = 0;
+#pragma unroll
     for (int k = 0; k < SCAN_SMALL_IPT; k++) {
         const int i = base + k;
-        s += i < n ? in[i] : 0;
+        v[k] = i < n ? in[i] : 0;
+        s += v[k];
     }
     const int incl = wave_inclusive_scan(s);
     const int w = threadIdx.x / WAVE;
@@ -137,15 +144,13 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_small(const int *__restrict
     __syncthreads();
     int run = incl - s;
     for (int k = 0; k < w; k++) run += wsum[k];
+#pragma unroll
     for (int k = 0; k < SCAN_SMALL_IPT; k++) {
         const int i = base + k;
-        if (i < n) {
-            const int v = in[i];
-            out[i] = run;
-            run += v;
-        }
+        if (i < n) out[i] = run;
+        run += v[k];
     }
-    if (threadIdx.x == SCAN_BLOCK - 1) out[n] = run;
+    if (threadIdx.x == SCAN_SMALL_BLOCK - 1) out[n] = run;
 }
 
 // Adds tile offsets; block 0 also writes out[n] = total.

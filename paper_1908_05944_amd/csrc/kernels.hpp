@@ -575,7 +575,7 @@ constexpr int TET_SLOT = 4;
 constexpr int TET_SLAB = 256;
 
 template <int MODE>
-__global__ void __launch_bounds__(BLOCK) k_tet_candidates(const int4 *__restrict__ atom, const int *__restrict__ perm,
+__global__ void __launch_bounds__(BLOCK, 4) k_tet_candidates(const int4 *__restrict__ atom, const int *__restrict__ perm,
                                                            const int *__restrict__ nbr_start,
                                                            const int *__restrict__ nbr_cnt, const int *__restrict__ nbr,
                                                            const int *__restrict__ up_start, const int *__restrict__ up,

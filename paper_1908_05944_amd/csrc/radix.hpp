@@ -60,16 +60,15 @@ __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const unsigned *__restr
     // sweep: rank each element among the equal digits of its wave so far
     const unsigned long long lt = (1ull << lane) - 1ull;
     const long long base = (long long)blockIdx.x * RS_TILE + (long long)wave * CHUNK;
+    // keys and ranks stay in registers; payloads are read again (from L2)
+    // when placed, which keeps wide payloads from spilling
     unsigned key[RS_IPT];
-    P pay[RS_IPT];
     int rank[RS_IPT];
 #pragma unroll
     for (int r = 0; r < RS_IPT; r++) {
         const long long idx = base + (long long)r * WAVE + lane;
         const bool valid = idx < n;
-        key[r] = 0;
-        pay[r] = P{};
-        if (valid) { key[r] = kin[idx]; pay[r] = pin[idx]; }
+        key[r] = valid ? kin[idx] : 0u;
         const unsigned d = (key[r] >> shift) & (RS_BINS - 1);
         unsigned long long peers = __ballot(valid);
 #pragma unroll
@@ -108,7 +107,7 @@ __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const unsigned *__restr
         const unsigned d = (key[r] >> shift) & (RS_BINS - 1);
         const int lpos = wcnt[wave][d] + rank[r];
         skey[lpos] = key[r];
-        spay[lpos] = pay[r];
+        spay[lpos] = pin[base + (long long)r * WAVE + lane];
     }
     __syncthreads();
     // the tile in digit order: each digit's run goes to consecutive addresses;
