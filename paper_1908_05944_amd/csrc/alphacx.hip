@@ -234,14 +234,13 @@ static void radix_sort(unsigned *&key, P *&pay, int n, int bits, hipStream_t s, 
     unsigned *k2 = sc.get<unsigned>(n);
     P *p2 = sc.get<P>(n);
     int *hist = sc.get<int>((size_t)RS_BINS * tiles);
-    int *offs = sc.get<int>((size_t)RS_BINS * tiles + 1);
+    int *totals = sc.get<int>(RS_BINS);
     unsigned *kin = key, *kout = k2;
     P *pin = pay, *pout = p2;
     for (int shift = 0; shift < bits; shift += RS_BITS) {
         k_rs_hist<<<tiles, RS_BLOCK, 0, s>>>(kin, n, shift, hist, tiles);
-        LAUNCH_CHECK();
-        scan_i32(hist, offs, (long long)RS_BINS * tiles, s, sc);
-        k_rs_scatter<P><<<tiles, RS_BLOCK, 0, s>>>(kin, pin, kout, pout, n, shift, offs, hist, tiles);
+        k_rs_digit_prefix<<<RS_BINS, RS_PREFIX_BLOCK, 0, s>>>(hist, tiles, totals);
+        k_rs_scatter<P><<<tiles, RS_BLOCK, 0, s>>>(kin, pin, kout, pout, n, shift, hist, totals, tiles);
         LAUNCH_CHECK();
         std::swap(kin, kout);
         std::swap(pin, pout);

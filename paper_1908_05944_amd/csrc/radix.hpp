@@ -1,8 +1,8 @@
 // Stable least-significant-digit radix sort of (uint32 key, payload) pairs.
 //
-// One pass per 8-bit digit: a tile histogram kernel (LDS counters), a
-// device-wide exclusive scan of the digit-major table [256][tiles], and a
-// scatter kernel. In the scatter each wave owns a contiguous chunk of the
+// One pass per 8-bit digit: a tile histogram kernel (LDS counters) into the
+// digit-major table [256][tiles], a prefix kernel over each digit's row, and
+// a scatter kernel. In the scatter each wave owns a contiguous chunk of the
 // tile and ranks its elements among equal digits with ballots and per-wave
 // LDS counters (no block barrier inside the sweep); one block scan over
 // (digit, wave) counts then gives every element its stable place, the tile
@@ -39,11 +39,51 @@ __global__ void __launch_bounds__(RS_BLOCK) k_rs_hist(const unsigned *__restrict
     hist[(long long)threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
 }
 
+// Per digit d (one block each): exclusive prefix over the tiles of the
+// digit's row hist[d][0..tiles), in place, and the digit's total. The digit
+// bases (a scan of the 256 totals) are taken by each scatter block itself.
+constexpr int RS_PREFIX_BLOCK = 1024;
+constexpr int RS_PREFIX_IPT = 8;
+
+__global__ void __launch_bounds__(RS_PREFIX_BLOCK) k_rs_digit_prefix(int *__restrict__ hist, int tiles,
+                                                                      int *__restrict__ totals) {
+    __shared__ int wsum[RS_PREFIX_BLOCK / WAVE];
+    __shared__ int carry_s;
+    int *row = hist + (long long)blockIdx.x * tiles;
+    int carry = 0;
+    for (int c0 = 0; c0 < tiles; c0 += RS_PREFIX_BLOCK * RS_PREFIX_IPT) {
+        const int base = c0 + threadIdx.x * RS_PREFIX_IPT;
+        int v[RS_PREFIX_IPT];
+        int s = 0;
+#pragma unroll
+        for (int k = 0; k < RS_PREFIX_IPT; k++) {
+            v[k] = base + k < tiles ? row[base + k] : 0;
+            s += v[k];
+        }
+        const int incl = wave_inclusive_scan(s);
+        const int w = threadIdx.x / WAVE;
+        if (lane_id() == WAVE - 1) wsum[w] = incl;
+        __syncthreads();
+        int run = carry + incl - s;
+        for (int k = 0; k < w; k++) run += wsum[k];
+#pragma unroll
+        for (int k = 0; k < RS_PREFIX_IPT; k++) {
+            if (base + k < tiles) row[base + k] = run;
+            run += v[k];
+        }
+        if (threadIdx.x == RS_PREFIX_BLOCK - 1) carry_s = run;
+        __syncthreads();
+        carry = carry_s;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+}
+
 template <class P>
 __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const unsigned *__restrict__ kin, const P *__restrict__ pin,
                                                           unsigned *__restrict__ kout, P *__restrict__ pout, int n,
-                                                          int shift, const int *__restrict__ offs,
-                                                          const int *__restrict__ hist, int tiles) {
+                                                          int shift, const int *__restrict__ prefix,
+                                                          const int *__restrict__ totals, int tiles) {
     constexpr int NW = RS_BLOCK / WAVE;
     constexpr int CHUNK = WAVE * RS_IPT;  // each wave owns a contiguous chunk of the tile
     __shared__ int gbase[RS_BINS];        // output start of each digit for this tile
@@ -52,8 +92,17 @@ __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const unsigned *__restr
     __shared__ unsigned skey[RS_TILE];
     __shared__ P spay[RS_TILE];
     const int lane = lane_id(), wave = threadIdx.x / WAVE;
-    (void)hist;  // the tile's counts are recounted per wave below
-    gbase[threadIdx.x] = offs[(long long)threadIdx.x * tiles + blockIdx.x];
+    {
+        // output start of digit d for this tile: the totals of the digits
+        // below d, plus digit d's count in the tiles before this one
+        const int t = totals[threadIdx.x];
+        const int incl = wave_inclusive_scan(t);
+        if (lane == WAVE - 1) wsum[wave] = incl;
+        __syncthreads();
+        int below = incl - t;
+        for (int w = 0; w < wave; w++) below += wsum[w];
+        gbase[threadIdx.x] = below + prefix[(long long)threadIdx.x * tiles + blockIdx.x];
+    }
 #pragma unroll
     for (int w = 0; w < NW; w++) wcnt[w][threadIdx.x] = 0;
     __syncthreads();
