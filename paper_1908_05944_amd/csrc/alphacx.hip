@@ -448,7 +448,8 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         scan_i32(cell_count, cell_start, ncell, s, sc);
         int4 *atom = sc.get<int4>(n);
         int *perm = sc.get<int>(n);
-        k_gather_atoms<<<grid_for(n), BLOCK, 0, s>>>(q, ckey, cidx, n, atom, perm, cnt);
+        k_gather_atoms<<<grid_for(n), BLOCK, 0, s>>>(q, cidx, n, atom, perm);
+        k_dup_check<<<grid_for(n), BLOCK, 0, s>>>(atom, ckey, n, cnt);
         LAUNCH_CHECK();
 
         // ---- neighbours and candidate edges: one pass into per-block slabs,

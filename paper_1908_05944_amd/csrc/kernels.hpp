@@ -184,25 +184,30 @@ __global__ void __launch_bounds__(BLOCK) k_cell_runs(const unsigned *__restrict_
     cell_count[c] = e - p;
 }
 
-// Sorted balls and their input indices; equal centres (which share a cell)
-// are reported.
-__global__ void __launch_bounds__(BLOCK) k_gather_atoms(const int4 *__restrict__ q, const unsigned *__restrict__ key,
-                                                         const unsigned *__restrict__ idx, int n,
-                                                         int4 *__restrict__ atom, int *__restrict__ perm,
-                                                         Counters *cnt) {
+// Sorted balls and their input indices (one gather per ball).
+__global__ void __launch_bounds__(BLOCK) k_gather_atoms(const int4 *__restrict__ q, const unsigned *__restrict__ idx,
+                                                         int n, int4 *__restrict__ atom, int *__restrict__ perm) {
     const int p = blockIdx.x * BLOCK + threadIdx.x;
     if (p >= n) return;
     const int me = (int)idx[p];
-    const int4 a = q[me];
-    atom[p] = a;
+    atom[p] = q[me];
     perm[p] = me;
+}
+
+// Equal centres share a cell, so they are adjacent in the sorted order:
+// each ball compares itself with the following balls of its cell.
+__global__ void __launch_bounds__(BLOCK) k_dup_check(const int4 *__restrict__ atom, const unsigned *__restrict__ key,
+                                                      int n, Counters *cnt) {
+    const int p = blockIdx.x * BLOCK + threadIdx.x;
+    if (p >= n) return;
+    const int4 a = atom[p];
     const unsigned c = key[p];
     bool dup = false;
     for (int k = p + 1; k < n && key[k] == c; k++) {
-        const int4 b = q[idx[k]];
+        const int4 b = atom[k];
         dup |= b.x == a.x && b.y == a.y && b.z == a.z;
     }
-    if (dup) atomicOr(&cnt->dup, 1);
+    if (dup) cnt->dup = 1;
 }
 
 // ---------------------------------------------------------------------------
