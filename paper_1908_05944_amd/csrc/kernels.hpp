@@ -292,17 +292,21 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
                 const long long rb = g.base + ((long long)z * g.ny + y) * g.nx;
                 const int s = cell_start[rb + x0], e = cell_start[rb + x1 + 1];
                 for (int j = s; j < e; j++) {
-                    if (j == i) continue;
                     const int4 bb = atom[j];
-                    const int dx = bb.x - a.x, dy = bb.y - a.y, dz = bb.z - a.z;
-                    if (abs(dx) > reach1 || abs(dy) > reach1 || abs(dz) > reach1) continue;
+                    // one combined test (a branch per condition costs more
+                    // exec-mask work than the arithmetic it would skip);
+                    // offsets clamped to reach1 + 1: d2 then fits int32, and
+                    // a clamped offset alone gives d2 > (2 ceil s_g)^2 >= lim
+                    const int dx = min(max(bb.x - a.x, -reach1 - 1), reach1 + 1);
+                    const int dy = min(max(bb.y - a.y, -reach1 - 1), reach1 + 1);
+                    const int dz = min(max(bb.z - a.z, -reach1 - 1), reach1 + 1);
                     const int d2 = dx * dx + dy * dy + dz * dz;
-                    if (d2 > lim || d2 == 0) continue; /* equal centres are reported by k_gather_atoms */
                     const int rb2 = bb.w + (int)pp.aq;
-                    if (rb2 < 0) continue;
-                    // grown balls meet: d <= rho_a + rho_b
                     const int L = d2 - ra - rb2;
-                    if (L > 0 && (i64)L * L > 4 * (i64)ra * rb2) continue;
+                    // grown balls meet: d <= rho_a + rho_b; equal centres are reported by k_dup_check
+                    const bool meet = (j != i) & (d2 <= lim) & (d2 != 0) & (rb2 >= 0) &
+                                      ((L <= 0) | ((i64)L * L <= 4 * (i64)ra * rb2));
+                    if (!meet) continue;
                     if (cn < capn) rn[cn] = j;
                     if (gab && vertex_violation_sign(a, i, bb, j, perm) < 0) gab = false;
                     if (j > i && edge_ac3(edge_setup(a, bb), pp.aq)) {
@@ -478,10 +482,12 @@ __global__ void __launch_bounds__(BLOCK) k_triangles(const int4 *__restrict__ at
         const int eb = up_start[j + 1];
         const int out = ONE ? 0 : tri_start[e];
         while (pa < ea && pb < eb) {
+            // merge step without divergent branches: advance the smaller
+            // side (both when equal)
             const int ka = up[pa], kb = up[pb];
-            if (ka < kb) { pa++; continue; }
-            if (kb < ka) { pb++; continue; }
-            pa++; pb++;
+            pa += ka <= kb;
+            pb += kb <= ka;
+            if (ka != kb) continue;
             const Tri t = tri_setup(vi, vj, atom[ka], pp);
             if (tri_degenerate(t) || !tri_ac3(t, pp, cnt)) continue;
             if (ONE) {
@@ -620,12 +626,14 @@ __global__ void __launch_bounds__(BLOCK, 4) k_tet_candidates(const int4 *__restr
         const int ec = up_start[k + 1];
         const int out = ONE ? 0 : tet_start[t];
         while (pa < ea && pb < eb && pc < ec) {
+            // three-way merge step without divergent branches
             const int la = up[pa], lb = up[pb], lc = up[pc];
             const int m = max(la, max(lb, lc));
-            if (la < m) { pa++; continue; }
-            if (lb < m) { pb++; continue; }
-            if (lc < m) { pc++; continue; }
-            pa++; pb++; pc++;
+            const bool all = (la == m) & (lb == m) & (lc == m);
+            pa += (la < m) | all;
+            pb += (lb < m) | all;
+            pc += (lc < m) | all;
+            if (!all) continue;
             const Tet te = tet_setup(vi, vj, vk, atom[m], pp);
             if (te.D == 0 || !tet_ac3(te, pp, cnt)) continue;
             if (ONE) {
