@@ -757,7 +757,7 @@ static void measure_fwd_dim(const ac_complex *c, const double *x, const double *
                             hipStream_t s) {
     const long long m = c->count[K - 1];
     if (m == 0) return;
-    const unsigned b = (unsigned)((m + MEASURE_BLOCK - 1) / MEASURE_BLOCK);
+    const unsigned b = (unsigned)((m * K + MEASURE_BLOCK - 1) / MEASURE_BLOCK);
     k_measure_fwd<K><<<b, MEASURE_BLOCK, 0, s>>>(c->d_simp[K - 1], m, x, r, part + 2LL * nb);
     LAUNCH_CHECK();
     nb += (int)b;
@@ -767,7 +767,7 @@ static void measure_fwd_dim(const ac_complex *c, const double *x, const double *
 // NULL; returns where they are.
 static double *measure_forward(ac_complex *c, const double *x, const double *r, double *d_out, hipStream_t s) {
     long long nb_total = 0;
-    for (int d = 0; d < 4; d++) nb_total += (c->count[d] + MEASURE_BLOCK - 1) / MEASURE_BLOCK;
+    for (int d = 0; d < 4; d++) nb_total += (c->count[d] * (d + 1) + MEASURE_BLOCK - 1) / MEASURE_BLOCK;
     if (!c->meas_part) c->meas_part = static_cast<double *>(dev_alloc((size_t)(2 * nb_total + 2) * sizeof(double)));
     double *part = c->meas_part;
     if (!d_out) d_out = part + 2 * nb_total;
@@ -786,7 +786,7 @@ static void measure_bwd_dim(const ac_complex *c, const double *x, const double *
                             long long &off, hipStream_t s) {
     const long long m = c->count[K - 1];
     if (m == 0) return;
-    const unsigned b = (unsigned)((m + MEASURE_BLOCK - 1) / MEASURE_BLOCK);
+    const unsigned b = (unsigned)((m * K + MEASURE_BLOCK - 1) / MEASURE_BLOCK);
     k_measure_bwd<K><<<b, MEASURE_BLOCK, 0, s>>>(c->d_simp[K - 1], m, x, r, g, contrib + off);
     LAUNCH_CHECK();
     off += m * K;

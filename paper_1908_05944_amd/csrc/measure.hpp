@@ -45,14 +45,17 @@ __device__ __forceinline__ double clamp1(double x) { return fmin(1.0, fmax(-1.0,
 
 constexpr double PI = 3.14159265358979323846;
 
-// Terms of one simplex of K balls. The arc terms are computed only if GRAD.
-template <int K>
-struct BallTerms {
-    double vol;
-    double area[K];
-    D3 vec[K];
-    double arc_len[K];
-    D3 arc_vec[K];
+// Terms of corner c (ball c) of one simplex of K balls: what the patch P_c
+// and the faces and arcs around it contribute. Summed over the corners:
+// vol is the intersection's volume (each flat face's d |F| is split evenly
+// between its two balls) and area the boundary area. The arc terms are
+// computed only if GRAD.
+struct CornerTerms {
+    double vol;      // (1/3) [r_c |P_c| - 1/2 sum_b d_cb |F_cb|]
+    double area;     // |P_c|
+    D3 vec;          // vector area of P_c: sum_b |F_cb| u_cb
+    double arc_len;  // sum over the arcs of P_c of cot(psi/2) * length
+    D3 arc_vec;      // sum over the arcs of P_c of cot(psi/2) * int n_c ds
 };
 
 // Exterior angle at corner v of the patch on sphere (p, r) between the arcs
@@ -64,23 +67,29 @@ __device__ __forceinline__ double corner_angle(D3 v, D3 p, double r, D3 ua, D3 u
     return acos(clamp1(dot(ga, gb)));
 }
 
+// Vertex of the intersection of 4 balls on the power line of the triple
+// opposite ball f: the triple point inside ball f. c is the ortho-centre.
+__device__ __forceinline__ D3 triple_vertex(const D3 *P, int f, D3 c, double rho2) {
+    const int t0 = f == 0 ? 1 : 0, t1 = f <= 1 ? 2 : 1, t2 = f == 3 ? 2 : 3;  // the balls other than f, ascending
+    D3 nt = unit(cross(P[t1] - P[t0], P[t2] - P[t0]));
+    if (dot(nt, P[f] - P[t0]) < 0) nt = -1.0 * nt;
+    const double beta = dot(nt, c - P[t0]);
+    const double tau = -beta + sqrt(fmax(beta * beta + rho2, 0.0));
+    return c + tau * nt;
+}
+
+// The corner is ball 0: callers rotate the simplex's balls so that every
+// index below is a compile-time constant (no scratch arrays).
 template <int K, bool GRAD>
-__device__ void ball_terms(const D3 *P, const double *R, BallTerms<K> &o) {
+__device__ void corner_terms(const D3 *P, const double *R, CornerTerms &o) {
+    constexpr int cc = 0;
+    o.vec = d3(0, 0, 0);
+    o.arc_len = 0;
+    o.arc_vec = d3(0, 0, 0);
     if (K == 1) {
         o.vol = 4.0 / 3.0 * PI * R[0] * R[0] * R[0];
-        o.area[0] = 4.0 * PI * R[0] * R[0];
-        o.vec[0] = d3(0, 0, 0);
-        o.arc_len[0] = 0;
-        o.arc_vec[0] = d3(0, 0, 0);
+        o.area = 4.0 * PI * R[0] * R[0];
         return;
-    }
-    double corner[K], turn[K];
-    for (int i = 0; i < K; i++) {
-        corner[i] = 0;
-        turn[i] = 0;
-        o.vec[i] = d3(0, 0, 0);
-        o.arc_len[i] = 0;
-        o.arc_vec[i] = d3(0, 0, 0);
     }
     // point of equal power (in the plane of the centres when K = 3) and rho^2
     D3 c = P[0];
@@ -105,141 +114,116 @@ __device__ void ball_terms(const D3 *P, const double *R, BallTerms<K> &o) {
         rho2 = R[0] * R[0] - dot(z, z);
     }
     const double rho = sqrt(fmax(rho2, 0.0));
-    // K = 4: the vertex of I on each triple's power line, indexed by the
-    // ball opposite the triple (the triple point inside that ball)
+    // K = 4: the triple points the corner's patch and arcs need (triples
+    // containing ball 0), indexed by the ball opposite the triple
     D3 tv[4];
     if (K == 4) {
-        for (int f = 0; f < 4; f++) {
-            int t[3], m = 0;
-            for (int x = 0; x < 4; x++)
-                if (x != f) t[m++] = x;
-            D3 nt = unit(cross(P[t[1]] - P[t[0]], P[t[2]] - P[t[0]]));
-            if (dot(nt, P[f] - P[t[0]]) < 0) nt = -1.0 * nt;
-            const double beta = dot(nt, c - P[t[0]]);
-            const double tau = -beta + sqrt(fmax(beta * beta + rho2, 0.0));
-            tv[f] = c + tau * nt;
+#pragma unroll
+        for (int f = 1; f < 4; f++) tv[f] = triple_vertex(P, f, c, rho2);
+    }
+    const double rc = R[cc];
+    double turn = 0, flat = 0, corner = 0;
+#pragma unroll
+    for (int b = 1; b < K; b++) {
+        const D3 dv = P[b] - P[cc];
+        const double d = sqrt(dot(dv, dv));
+        const D3 u = (1.0 / d) * dv;
+        const double tc = (d * d + rc * rc - R[b] * R[b]) / (2 * d);  // centre c to the plane, towards b
+        const D3 oc = P[cc] + tc * u;                                  // centre of the circle S_c & S_b
+        const double a2 = fmax(rc * rc - tc * tc, 0.0);
+        const double rad = sqrt(a2);
+        double phi, face;
+        D3 mid = d3(0, 0, 0);
+        if (K == 2) {
+            phi = 2 * PI;
+            face = PI * a2;
+        } else if (K == 3) {
+            const int e = 3 - cc - b;
+            const D3 w = unit((P[e] - P[cc]) - dot(P[e] - P[cc], u) * u);
+            const double sw = dot(c - oc, w);
+            const double half = rad > 0 ? acos(clamp1(sw / rad)) : 0.0;
+            face = a2 * half - sw * sqrt(fmax(a2 - sw * sw, 0.0));
+            phi = 2 * half;
+            mid = w;
+        } else {
+            // the other two balls e < f
+            const int e = b == 1 ? 2 : 1, f = b == 3 ? 2 : 3;
+            // the arc runs between the triple points of (c, b, e) and (c, b, f)
+            const D3 q1 = tv[f], q2 = tv[e];
+            D3 axis = u;
+            if (dot(cross(q1 - c, q2 - c), u) < 0) axis = -1.0 * u;
+            const D3 r1 = q1 - oc, r2 = q2 - oc;
+            double ang = atan2(dot(cross(r1, r2), axis), dot(r1, r2));
+            if (ang < 0) ang += 2 * PI;
+            phi = rad > 0 ? ang : 0.0;
+            face = 0.5 * (a2 * phi + dot(cross(oc - c, q2 - q1), axis));
+            const D3 e1 = unit(r1);
+            mid = cos(0.5 * phi) * e1 + sin(0.5 * phi) * cross(axis, e1);
+        }
+        flat += d * face;
+        turn += tc * phi;
+        o.vec = o.vec + face * u;
+        if (GRAD) {
+            const double cos_psi = -(rc * rc + R[b] * R[b] - d * d) / (2 * rc * R[b]);
+            const double cot_half = sqrt(fmax(1 + cos_psi, 0.0) / fmax(1 - cos_psi, 1e-300));
+            const double len = rad * phi;
+            o.arc_len += cot_half * len;
+            const D3 radial = (a2 * 2 * sin(0.5 * phi)) * mid;  // int (x - o) ds over the arc
+            o.arc_vec = o.arc_vec + (cot_half / rc) * ((tc * len) * u + radial);
         }
     }
-    double flat = 0;
-    for (int a = 0; a < K; a++) {
-        for (int b = a + 1; b < K; b++) {
-            const D3 dv = P[b] - P[a];
-            const double d = sqrt(dot(dv, dv));
-            const D3 u = (1.0 / d) * dv;
-            const double ta = (d * d + R[a] * R[a] - R[b] * R[b]) / (2 * d);
-            const double tb = d - ta;
-            const D3 oc = P[a] + ta * u;  // centre of the circle S_a & S_b
-            const double a2 = fmax(R[a] * R[a] - ta * ta, 0.0);
-            const double rad = sqrt(a2);
-            double phi, face;
-            D3 mid = d3(0, 0, 0);
-            if (K == 2) {
-                phi = 2 * PI;
-                face = PI * a2;
-            } else if (K == 3) {
-                const int e = 3 - a - b;
-                const D3 w = unit((P[e] - P[a]) - dot(P[e] - P[a], u) * u);
-                const double s = dot(c - oc, w);
-                const double half = rad > 0 ? acos(clamp1(s / rad)) : 0.0;
-                face = a2 * half - s * sqrt(fmax(a2 - s * s, 0.0));
-                phi = 2 * half;
-                mid = w;
-            } else {
-                int e = -1, f = -1;
-                for (int x = 0; x < 4; x++)
-                    if (x != a && x != b) {
-                        if (e < 0) e = x; else f = x;
-                    }
-                const D3 q1 = tv[f], q2 = tv[e];  // triples (a,b,e) and (a,b,f)
-                D3 axis = u;
-                if (dot(cross(q1 - c, q2 - c), u) < 0) axis = -1.0 * u;
-                const D3 r1 = q1 - oc, r2 = q2 - oc;
-                double ang = atan2(dot(cross(r1, r2), axis), dot(r1, r2));
-                if (ang < 0) ang += 2 * PI;
-                phi = rad > 0 ? ang : 0.0;
-                face = 0.5 * (a2 * phi + dot(cross(oc - c, q2 - q1), axis));
-                const D3 e1 = unit(r1);
-                mid = cos(0.5 * phi) * e1 + sin(0.5 * phi) * cross(axis, e1);
-            }
-            flat += d * face;
-            turn[a] += ta * phi;
-            turn[b] += tb * phi;
-            o.vec[a] = o.vec[a] + face * u;
-            o.vec[b] = o.vec[b] - face * u;
-            if (GRAD) {
-                const double cos_psi = -(R[a] * R[a] + R[b] * R[b] - d * d) / (2 * R[a] * R[b]);
-                const double cot_half = sqrt(fmax(1 + cos_psi, 0.0) / fmax(1 - cos_psi, 1e-300));
-                const double len = rad * phi;
-                o.arc_len[a] += cot_half * len;
-                o.arc_len[b] += cot_half * len;
-                const D3 radial = (a2 * 2 * sin(0.5 * phi)) * mid;  // int (x - o) ds over the arc
-                o.arc_vec[a] = o.arc_vec[a] + (cot_half / R[a]) * ((ta * len) * u + radial);
-                o.arc_vec[b] = o.arc_vec[b] + (cot_half / R[b]) * ((-tb * len) * u + radial);
-            }
-        }
-    }
+    // exterior angles at the corners of P_c
     if (K == 3) {
         const D3 nrm = unit(cross(P[1] - P[0], P[2] - P[0]));
-        const D3 vp = c + rho * nrm, vm = c - rho * nrm;
-        for (int i = 0; i < 3; i++) {
-            const int j = i == 0 ? 1 : 0, l = i == 2 ? 1 : 2;
-            const D3 uj = unit(P[j] - P[i]), ul = unit(P[l] - P[i]);
-            corner[i] += corner_angle(vp, P[i], R[i], uj, ul) + corner_angle(vm, P[i], R[i], uj, ul);
-        }
+        constexpr int j = 1, l = 2;
+        const D3 uj = unit(P[j] - P[cc]), ul = unit(P[l] - P[cc]);
+        corner = corner_angle(c + rho * nrm, P[cc], rc, uj, ul) + corner_angle(c - rho * nrm, P[cc], rc, uj, ul);
     }
     if (K == 4) {
-        for (int f = 0; f < 4; f++) {
-            for (int i = 0; i < 4; i++) {
-                if (i == f) continue;
-                int j = -1, l = -1;
-                for (int x = 0; x < 4; x++)
-                    if (x != f && x != i) {
-                        if (j < 0) j = x; else l = x;
-                    }
-                corner[i] += corner_angle(tv[f], P[i], R[i], unit(P[j] - P[i]), unit(P[l] - P[i]));
-            }
+#pragma unroll
+        for (int f = 1; f < 4; f++) {
+            const int j = f == 1 ? 2 : 1, l = f == 3 ? 2 : 3;  // the balls other than 0 and f
+            corner += corner_angle(tv[f], P[cc], rc, unit(P[j] - P[cc]), unit(P[l] - P[cc]));
         }
     }
-    double rs = 0;
-    for (int i = 0; i < K; i++) {
-        o.area[i] = R[i] * R[i] * (2 * PI - corner[i]) - R[i] * turn[i];
-        rs += R[i] * o.area[i];
-    }
-    o.vol = (rs - flat) / 3.0;
+    o.area = rc * rc * (2 * PI - corner) - rc * turn;
+    o.vol = (rc * o.area - 0.5 * flat) / 3.0;
 }
 
+// Balls of simplex s, rotated so that corner c comes first.
 template <int K>
-__device__ __forceinline__ void load_balls(const int *__restrict__ simp, long long s, const double *__restrict__ xyz,
-                                           const double *__restrict__ rad, int *id, D3 *P, double *R) {
+__device__ __forceinline__ void load_balls(const int *__restrict__ simp, long long s, int c0,
+                                           const double *__restrict__ xyz, const double *__restrict__ rad, D3 *P,
+                                           double *R) {
 #pragma unroll
     for (int c = 0; c < K; c++) {
-        id[c] = simp[s * K + c];
-        const double *p = xyz + 3LL * id[c];
+        const int id = simp[s * K + (c0 + c) % K];
+        const double *p = xyz + 3LL * id;
         P[c] = d3(p[0], p[1], p[2]);
-        R[c] = rad[id[c]];
+        R[c] = rad[id];
     }
 }
 
 constexpr int MEASURE_BLOCK = 256;
 
-// Per block: the signed sums of vol and of patch areas over its simplices of
-// dimension K - 1, written to part[2 * block] and part[2 * block + 1].
+// One thread per (simplex, corner) of dimension K - 1 (thread t: simplex
+// t / K, corner t % K). Per block: the signed sums of the corners' volume
+// and patch-area parts, written to part[2 * block] and part[2 * block + 1].
 template <int K>
 __global__ void __launch_bounds__(MEASURE_BLOCK) k_measure_fwd(const int *__restrict__ simp, long long m,
                                                                 const double *__restrict__ xyz,
                                                                 const double *__restrict__ rad, double *__restrict__ part) {
     __shared__ double sv[MEASURE_BLOCK / WAVE], sa[MEASURE_BLOCK / WAVE];
-    const long long s = (long long)blockIdx.x * MEASURE_BLOCK + threadIdx.x;
+    const long long t = (long long)blockIdx.x * MEASURE_BLOCK + threadIdx.x;
     double v = 0, a = 0;
-    if (s < m) {
-        int id[K];
+    if (t < m * K) {
         D3 P[K];
         double R[K];
-        load_balls<K>(simp, s, xyz, rad, id, P, R);
-        BallTerms<K> t;
-        ball_terms<K, false>(P, R, t);
-        v = t.vol;
-        for (int c = 0; c < K; c++) a += t.area[c];
+        load_balls<K>(simp, t / K, (int)(t % K), xyz, rad, P, R);
+        CornerTerms ct;
+        corner_terms<K, false>(P, R, ct);
+        v = ct.vol;
+        a = ct.area;
         if ((K - 1) & 1) {
             v = -v;
             a = -a;
@@ -266,7 +250,6 @@ __global__ void __launch_bounds__(MEASURE_BLOCK) k_measure_fwd(const int *__rest
     }
 }
 
-// Sum of the block partials in a fixed order (one block): out[0] = V, out[1] = A.
 __global__ void __launch_bounds__(MEASURE_BLOCK) k_measure_total(const double *__restrict__ part, int nb,
                                                                   double *__restrict__ out) {
     __shared__ double sv[MEASURE_BLOCK], sa[MEASURE_BLOCK];
@@ -291,32 +274,28 @@ __global__ void __launch_bounds__(MEASURE_BLOCK) k_measure_total(const double *_
     }
 }
 
-// Per incidence slot (simplex s, corner c at slot base + s*K + c): the
-// corner's contribution gV * d(V)/d(p, r) + gA * d(A)/d(p, r), as (x, y, z, r),
-// with (gV, gA) = (g[0], g[1]) read from device memory.
+// Per incidence slot (simplex s, corner c at slot base + s*K + c; one thread
+// each): the corner's contribution gV * d(V)/d(p, r) + gA * d(A)/d(p, r),
+// as (x, y, z, r), with (gV, gA) = (g[0], g[1]) read from device memory.
 template <int K>
 __global__ void __launch_bounds__(MEASURE_BLOCK) k_measure_bwd(const int *__restrict__ simp, long long m,
                                                                 const double *__restrict__ xyz,
                                                                 const double *__restrict__ rad,
                                                                 const double *__restrict__ g,
                                                                 double4 *__restrict__ contrib) {
-    const long long s = (long long)blockIdx.x * MEASURE_BLOCK + threadIdx.x;
-    if (s >= m) return;
+    const long long t = (long long)blockIdx.x * MEASURE_BLOCK + threadIdx.x;
+    if (t >= m * K) return;
     const double gV = g[0], gA = g[1];
-    int id[K];
     D3 P[K];
     double R[K];
-    load_balls<K>(simp, s, xyz, rad, id, P, R);
-    BallTerms<K> t;
-    ball_terms<K, true>(P, R, t);
+    load_balls<K>(simp, t / K, (int)(t % K), xyz, rad, P, R);
+    CornerTerms ct;
+    corner_terms<K, true>(P, R, ct);
     const double sg = ((K - 1) & 1) ? -1.0 : 1.0;
-#pragma unroll
-    for (int c = 0; c < K; c++) {
-        const double ir = 2.0 / R[c];
-        const D3 gx = (sg * gV) * t.vec[c] + (sg * gA) * (ir * t.vec[c] + t.arc_vec[c]);
-        const double gr = sg * (gV * t.area[c] + gA * (ir * t.area[c] + t.arc_len[c]));
-        contrib[s * K + c] = make_double4(gx.x, gx.y, gx.z, gr);
-    }
+    const double ir = 2.0 / R[0];
+    const D3 gx = (sg * gV) * ct.vec + (sg * gA) * (ir * ct.vec + ct.arc_vec);
+    const double gr = sg * (gV * ct.area + gA * (ir * ct.area + ct.arc_len));
+    contrib[t] = make_double4(gx.x, gx.y, gx.z, gr);
 }
 
 // vstart[i] = first position of vertex i in the sorted incidence keys (i in [0, n]).
