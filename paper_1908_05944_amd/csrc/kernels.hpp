@@ -468,13 +468,17 @@ __global__ void __launch_bounds__(BLOCK) k_triangles(const int4 *__restrict__ at
         if (ONE) {
             const int ns = nbr_start[i], ne = ns + nbr_cnt[i];
             const Edge ed = edge_setup(vi, vj);
-            bool gab = true;
+            // every neighbour is tested (no early exit: most edges pass, and
+            // the loop stays convergent); only filter-undecided ones branch
+            bool viol = false;
             for (int p = ns; p < ne; p++) {
                 const int q = nbr[p];
-                if (q == j) continue;
-                if (edge_violation_sign(ed, i, j, atom[q], q, perm, pp.force_exact) < 0) { gab = false; break; }
+                const int4 aq = atom[q];
+                int sg = pp.force_exact ? 0 : edge_violation_filter(ed, aq);
+                if (sg == 0 && q != j) sg = edge_violation_sign(ed, i, j, aq, q, perm, 1);
+                viol |= (sg < 0) & (q != j);
             }
-            egab[e] = (unsigned char)gab;
+            egab[e] = (unsigned char)!viol;
         }
         int pa = e + 1;
         const int ea = up_start[i + 1];
@@ -608,14 +612,22 @@ __global__ void __launch_bounds__(BLOCK, 4) k_tet_candidates(const int4 *__restr
         const int4 vi = atom[i], vj = atom[j], vk = atom[k];
         if (ONE) {
             const Tri tr = tri_setup(vi, vj, vk, pp);
-            bool gab = true;
+            // every neighbour is tested (no early exit, convergent loop);
+            // only filter-undecided ones take the exact branch
+            bool viol = false;
             const int ns = nbr_start[i], ne = ns + nbr_cnt[i];
             for (int p = ns; p < ne; p++) {
                 const int q = nbr[p];
-                if (q == j || q == k) continue;
-                if (tri_violation_sign(tr, i, j, k, atom[q], q, perm, pp, cnt) < 0) { gab = false; break; }
+                const int4 aq = atom[q];
+                const bool other = (q != j) & (q != k);
+                int sg = pp.force_exact ? 0 : tri_violation_filter(tr, aq);
+                if (sg == 0 && other) {
+                    if (!pp.force_exact) note_fallback(cnt);
+                    sg = tri_violation_exact(tr, i, j, k, aq, q, perm);
+                }
+                viol |= (sg < 0) & other;
             }
-            tgab[t] = (unsigned char)gab;
+            tgab[t] = (unsigned char)!viol;
             tsize[t] = tri_size_canon(vi, vj, vk, pp);
         }
         int pa = e + 1;

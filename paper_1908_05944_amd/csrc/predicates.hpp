@@ -116,6 +116,18 @@ __device__ __forceinline__ double edge_orthosize(const Edge &e) {
     return b * b / (4.0 * (double)e.den) - (double)e.v0.w;
 }
 
+// Floating-point filter of edge_violation_sign: the sign of P when the
+// rounding bound certifies it, 0 when the exact path has to decide.
+__device__ __forceinline__ int edge_violation_filter(const Edge &e, int4 q) {
+    const int bx = q.x - e.v0.x, by = q.y - e.v0.y, bz = q.z - e.v0.z;
+    const int gam = bx * bx + by * by + bz * bz - q.w + e.v0.w;
+    const int t = e.ax * bx + e.ay * by + e.az * bz;
+    const double p1 = (double)e.den * (double)gam, p2 = (double)e.beta * (double)t;
+    const double P = p1 - p2;
+    const double eb = 4.0 * ACX_U * (fabs(p1) + fabs(p2));
+    return (P > eb) - (P < -eb);
+}
+
 // P = |a|^2 gamma - beta (a.b)
 __device__ __forceinline__ int edge_violation_sign(const Edge &e, int s0, int s1, int4 q, int sq, const int *perm,
                                                    int force_exact) {
@@ -209,17 +221,34 @@ __device__ __forceinline__ double tri_orthosize(const Tri &t) {
     return M2 / (4.0 * d * d) - (double)t.v0.w;
 }
 
+// Floating-point filter of tri_violation_sign: the sign of P when the
+// rounding bound certifies it, 0 when the exact path has to decide.
+__device__ __forceinline__ int tri_violation_filter(const Tri &t, int4 q) {
+    const i64 bx = q.x - t.v0.x, by = q.y - t.v0.y, bz = q.z - t.v0.z;
+    const i64 gam = bx * bx + by * by + bz * bz - q.w + t.v0.w;
+    const double P = (double)t.den * (double)gam - (t.Mx * (double)bx + t.My * (double)by + t.Mz * (double)bz);
+    return (P > t.eP) - (P < -t.eP);
+}
+
+// Exact sign of P (int128), with simulation of simplicity on a tie.
+__device__ __forceinline__ int tri_violation_exact(const Tri &t, int s0, int s1, int s2, int4 q, int sq,
+                                                   const int *perm);
+
 // P = |n|^2 gamma - M.b
 __device__ __forceinline__ int tri_violation_sign(const Tri &t, int s0, int s1, int s2, int4 q, int sq, const int *perm,
                                                   const PredParams &pp, Counters *cnt) {
-    const i64 bx = q.x - t.v0.x, by = q.y - t.v0.y, bz = q.z - t.v0.z;
-    const i64 gam = bx * bx + by * by + bz * bz - q.w + t.v0.w;
     if (!pp.force_exact) {
-        const double P = (double)t.den * (double)gam - (t.Mx * (double)bx + t.My * (double)by + t.Mz * (double)bz);
-        if (P > t.eP) return 1;
-        if (P < -t.eP) return -1;
+        const int f = tri_violation_filter(t, q);
+        if (f) return f;
         note_fallback(cnt);
     }
+    return tri_violation_exact(t, s0, s1, s2, q, sq, perm);
+}
+
+__device__ __forceinline__ int tri_violation_exact(const Tri &t, int s0, int s1, int s2, int4 q, int sq,
+                                                   const int *perm) {
+    const i64 bx = q.x - t.v0.x, by = q.y - t.v0.y, bz = q.z - t.v0.z;
+    const i64 gam = bx * bx + by * by + bz * bz - q.w + t.v0.w;
     const i128 Mx = (i128)t.b1 * t.ux + (i128)t.b2 * t.wx;
     const i128 My = (i128)t.b1 * t.uy + (i128)t.b2 * t.wy;
     const i128 Mz = (i128)t.b1 * t.uz + (i128)t.b2 * t.wz;
