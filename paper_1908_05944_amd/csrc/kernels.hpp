@@ -492,8 +492,7 @@ __global__ void __launch_bounds__(BLOCK) k_triangles(const int4 *__restrict__ at
             pa += ka <= kb;
             pb += kb <= ka;
             if (ka != kb) continue;
-            const Tri t = tri_setup(vi, vj, atom[ka], pp);
-            if (tri_degenerate(t) || !tri_ac3(t, pp, cnt)) continue;
+            if (!tri_candidate(vi, vj, atom[ka], pp, cnt)) continue;
             if (ONE) {
                 if (c < TRI_SLOT) slot[threadIdx.x * TRI_SLOT + c] = ka;
             } else {

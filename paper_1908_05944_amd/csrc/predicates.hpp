@@ -214,6 +214,36 @@ __device__ __forceinline__ bool tri_ac3(const Tri &t, const PredParams &pp, Coun
     return Q <= R;
 }
 
+// Candidate test of a triangle (Step 1): not collinear, and AC3 in the Gram
+// form of tri_ac3, from the edge vectors only (the AC2 data of tri_setup is
+// not needed to decide candidacy).
+__device__ __forceinline__ bool tri_candidate(int4 v0, int4 v1, int4 v2, const PredParams &pp, Counters *cnt) {
+    const i64 a1x = v1.x - v0.x, a1y = v1.y - v0.y, a1z = v1.z - v0.z;
+    const i64 a2x = v2.x - v0.x, a2y = v2.y - v0.y, a2z = v2.z - v0.z;
+    const i64 nx = a1y * a2z - a1z * a2y, ny = a1z * a2x - a1x * a2z, nz = a1x * a2y - a1y * a2x;
+    if (nx == 0 && ny == 0 && nz == 0) return false;
+    const i64 den = nx * nx + ny * ny + nz * nz;
+    const i64 g11 = a1x * a1x + a1y * a1y + a1z * a1z;
+    const i64 g12 = a1x * a2x + a1y * a2y + a1z * a2z;
+    const i64 g22 = a2x * a2x + a2y * a2y + a2z * a2z;
+    const i64 b1 = g11 - v1.w + v0.w, b2 = g22 - v2.w + v0.w;
+    const i64 wa = v0.w + pp.aq;
+    if (!pp.force_exact) {
+        const double db1 = (double)b1, db2 = (double)b2;
+        const double q1 = (double)g22 * (db1 * db1), q2 = 2.0 * (double)g12 * (db1 * db2), q3 = (double)g11 * (db2 * db2);
+        const double Q = q1 - q2 + q3;
+        const double R = 4.0 * (double)den * (double)wa;
+        const double e = 16.0 * ACX_U * (fabs(q1) + fabs(q2) + fabs(q3) + fabs(R));
+        const double diff = Q - R;
+        if (diff < -e) return true;
+        if (diff > e) return false;
+        note_fallback(cnt);
+    }
+    const i128 Q = (i128)g22 * b1 * b1 - (i128)2 * g12 * b1 * b2 + (i128)g11 * b2 * b2;
+    const i128 R = (i128)4 * den * wa;
+    return Q <= R;
+}
+
 __device__ __forceinline__ double tri_orthosize(const Tri &t) {
     // |c|^2 = |M|^2 / (4 den^2)
     const double M2 = t.Mx * t.Mx + t.My * t.My + t.Mz * t.Mz;
