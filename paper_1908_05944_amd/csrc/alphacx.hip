@@ -211,6 +211,24 @@ static T read_one(const T *d, hipStream_t s) {
     return h;
 }
 
+// Exact 64-bit sum of n int32 counts (synchronises the stream). The
+// counted-fill fallbacks check their totals with it before 32-bit scans.
+static long long total_i64(const int *x, long long n, hipStream_t s, Scope &sc) {
+    if (n <= 0) return 0;
+    long long b = (n + BLOCK - 1) / BLOCK;
+    if (b > 1024) b = 1024;
+    long long *part = sc.get<long long>(b + 1);
+    k_sum_i64<<<(unsigned)b, BLOCK, 0, s>>>(x, n, part);
+    k_fold_i64<<<1, 1, 0, s>>>(part, (int)b, part + b);
+    LAUNCH_CHECK();
+    return read_one(part + b, s);
+}
+
+static void check_total(long long t, const char *what) {
+    if (t >= (long long)INT_MAX)
+        throw HipError{AC_E_CAPACITY, std::string("more than 2^31 - 1 ") + what + " (32-bit indices)"};
+}
+
 static long long isqrt_ceil(long long v) {
     if (v <= 0) return 0;
     long long r = (long long)std::sqrt((double)v);
@@ -476,6 +494,10 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         Counters c0 = read_one(cnt, s);
         if (c0.dup) throw HipError{AC_E_DUPLICATE, "two balls have equal quantised centres"};
         const bool nbr_two_pass = c0.overflow != 0;
+        if (nbr_two_pass || (long long)nbN * NB_SLAB >= (long long)INT_MAX) {
+            // past this size the slab bound no longer keeps the total in 32 bits
+            check_total(total_i64(deg_n, n, s, sc), "neighbour entries");
+        }
         if (nbr_two_pass) {
             scan_i32(deg_n, nbr_start, n, s, sc);
             scan_i32(deg_up, up_start, n, s, sc);
@@ -525,6 +547,10 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         }
         Counters ct = read_one(cnt, s);
         const bool tri_two_pass = ct.overflow != 0;
+        if (tri_two_pass || (long long)nbE * TRI_SLAB >= (long long)INT_MAX) {
+            // past this size the slab bound no longer keeps the total in 32 bits
+            check_total(total_i64(tri_cnt, E, s, sc), "candidate triangles");
+        }
         if (tri_two_pass) {
             scan_i32(tri_cnt, tri_start, E, s, sc);
             k_copy_int<<<1, 1, 0, s>>>(&cnt->T, tri_start + E);
@@ -573,6 +599,7 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         Counters cq = read_one(cnt, s);
         const bool tet_two_pass = cq.overflow != 0;
         if (tet_two_pass) {
+            check_total(total_i64(tet_cnt, T, s, sc), "candidate tetrahedra");
             scan_i32(tet_cnt, tet_start, T, s, sc);
             k_copy_int<<<1, 1, 0, s>>>(&cnt->Q, tet_start + T);
             LAUNCH_CHECK();

@@ -401,6 +401,28 @@ __global__ void __launch_bounds__(BLOCK) k_nbr_compact(const int *__restrict__ d
     }
 }
 
+// 64-bit sum of n int32 counts: each block writes its partial to
+// out[blockIdx.x]; k_fold_i64 then adds the partials in block order.
+__global__ void __launch_bounds__(BLOCK) k_sum_i64(const int *__restrict__ x, long long n, long long *__restrict__ out) {
+    __shared__ long long ws[BLOCK / WAVE];
+    long long v = 0;
+    for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * BLOCK) v += x[i];
+    for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_down(v, off, WAVE);
+    if (lane_id() == 0) ws[threadIdx.x / WAVE] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long t = 0;
+        for (int k = 0; k < BLOCK / WAVE; k++) t += ws[k];
+        out[blockIdx.x] = t;
+    }
+}
+
+__global__ void k_fold_i64(const long long *__restrict__ part, int nb, long long *__restrict__ out) {
+    long long t = 0;
+    for (int k = 0; k < nb; k++) t += part[k];
+    *out = t;
+}
+
 __global__ void k_copy_int(int *__restrict__ dst, const int *__restrict__ src) { *dst = *src; }
 
 // Position of b in the (sorted) upper-edge list of a, i.e. the edge id; -1 if absent.
