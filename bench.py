@@ -215,8 +215,8 @@ def main():
                     help="first run a plain device copy of 1 GiB (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU design is described "
-              "in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the split over several GPUs "
+              "is a design, not built.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -285,7 +285,8 @@ def main():
 
     # Dominant kernel and its roofline: among the stages that hold exactly one
     # kernel launch, the one with the largest event time. Algorithmic bytes are
-    # what that kernel must move from HBM at least.
+    # what that kernel must move from HBM at least: every input ball, row and
+    # list entry it needs read once, every output written once.
     n = mol.n
     E, T, Q = cand[1], cand[2], cand[3]
     Nn = work[1]
