@@ -267,8 +267,10 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
     unsigned mask = 0;
     bool gab = true;
     if (ra >= 0) {
-        // where this ball's rows go: its LDS slot, or its CSR rows
-        int *const rn = ONE ? sn + threadIdx.x * NB_SLOT : (staged ? sn + (nbr_start[i] - bn) : nbr + nbr_start[i]);
+        // where this ball's rows go: its LDS slot (entry k at k * BLOCK, so
+        // that a wave's lanes hit distinct banks), or its CSR rows
+        constexpr int RS = ONE ? BLOCK : 1;
+        int *const rn = ONE ? sn + threadIdx.x : (staged ? sn + (nbr_start[i] - bn) : nbr + nbr_start[i]);
         int *const ru = ONE ? nullptr : (staged ? su + (up_start[i] - bu) : up + up_start[i]);
         const int capn = ONE ? NB_SLOT : INT_MAX;
         const Grid g = grids[mol_of(grids, n_mol, i)];
@@ -278,48 +280,73 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
         const int z0 = max(cz - g.reach, 0), z1 = min(cz + g.reach, g.nz - 1);
         const int lim = 4 * (int)pp.sg2;     // (2 s_g)^2 < 2^28
         const int reach1 = 2 * (int)pp.sgc;  // 2 ceil(s_g) <= 2^14
-        for (int z = z0; z <= z1; z++) {
-            // rows whose cells all lie farther than 2 s_g are skipped
-            const int zlo = g.oz + z * g.s, zhi = zlo + g.s - 1;
-            const int dzm = a.z < zlo ? zlo - a.z : (a.z > zhi ? a.z - zhi : 0);
-            if (dzm > reach1) continue;
-            const int rz = lim - dzm * dzm;
-            if (rz < 0) continue;
-            for (int y = y0; y <= y1; y++) {
-                const int ylo = g.oy + y * g.s, yhi = ylo + g.s - 1;
-                const int dym = a.y < ylo ? ylo - a.y : (a.y > yhi ? a.y - yhi : 0);
-                if (dym > reach1 || rz - dym * dym < 0) continue;
-                const long long rb = g.base + ((long long)z * g.ny + y) * g.nx;
-                const int s = cell_start[rb + x0], e = cell_start[rb + x1 + 1];
-                for (int j = s; j < e; j++) {
-                    const int4 bb = atom[j];
-                    // one combined test (a branch per condition costs more
-                    // exec-mask work than the arithmetic it would skip);
-                    // offsets clamped to reach1 + 1: d2 then fits int32, and
-                    // a clamped offset alone gives d2 > (2 ceil s_g)^2 >= lim
-                    const int dx = min(max(bb.x - a.x, -reach1 - 1), reach1 + 1);
-                    const int dy = min(max(bb.y - a.y, -reach1 - 1), reach1 + 1);
-                    const int dz = min(max(bb.z - a.z, -reach1 - 1), reach1 + 1);
-                    const int d2 = dx * dx + dy * dy + dz * dz;
-                    const int rb2 = bb.w + (int)pp.aq;
-                    const int L = d2 - ra - rb2;
-                    // grown balls meet: d <= rho_a + rho_b; equal centres are reported by k_dup_check
-                    const bool meet = (j != i) & (d2 <= lim) & (d2 != 0) & (rb2 >= 0) &
-                                      ((L <= 0) | ((i64)L * L <= 4 * (i64)ra * rb2));
-                    if (!meet) continue;
-                    if (cn < capn) rn[cn] = j;
-                    if (gab && vertex_violation_sign(a, i, bb, j, perm) < 0) gab = false;
-                    if (j > i && edge_ac3(edge_setup(a, bb), pp.aq)) {
-                        if (ONE) {
-                            if (cn < 32) mask |= 1u << cn;
-                        } else {
-                            ru[cu] = j;
-                        }
-                        cu++;
+        // the balls whose grown balls meet this one's, in cell order
+        auto scan = [&](auto &&on_meet) {
+            for (int z = z0; z <= z1; z++) {
+                // rows whose cells all lie farther than 2 s_g are skipped
+                const int zlo = g.oz + z * g.s, zhi = zlo + g.s - 1;
+                const int dzm = a.z < zlo ? zlo - a.z : (a.z > zhi ? a.z - zhi : 0);
+                if (dzm > reach1) continue;
+                const int rz = lim - dzm * dzm;
+                if (rz < 0) continue;
+                for (int y = y0; y <= y1; y++) {
+                    const int ylo = g.oy + y * g.s, yhi = ylo + g.s - 1;
+                    const int dym = a.y < ylo ? ylo - a.y : (a.y > yhi ? a.y - yhi : 0);
+                    if (dym > reach1 || rz - dym * dym < 0) continue;
+                    const long long rb = g.base + ((long long)z * g.ny + y) * g.nx;
+                    const int s = cell_start[rb + x0], e = cell_start[rb + x1 + 1];
+                    for (int j = s; j < e; j++) {
+                        const int4 bb = atom[j];
+                        // one combined test (a branch per condition costs more
+                        // exec-mask work than the arithmetic it would skip);
+                        // offsets clamped to reach1 + 1: d2 then fits int32, and
+                        // a clamped offset alone gives d2 > (2 ceil s_g)^2 >= lim
+                        const int dx = min(max(bb.x - a.x, -reach1 - 1), reach1 + 1);
+                        const int dy = min(max(bb.y - a.y, -reach1 - 1), reach1 + 1);
+                        const int dz = min(max(bb.z - a.z, -reach1 - 1), reach1 + 1);
+                        const int d2 = dx * dx + dy * dy + dz * dz;
+                        const int rb2 = bb.w + (int)pp.aq;
+                        const int L = d2 - ra - rb2;
+                        // grown balls meet: d <= rho_a + rho_b; equal centres are reported by k_dup_check
+                        const bool meet = (j != i) & (d2 <= lim) & (d2 != 0) & (rb2 >= 0) &
+                                          ((L <= 0) | ((i64)L * L <= 4 * (i64)ra * rb2));
+                        if (meet) on_meet(j, bb);
                     }
-                    cn++;
                 }
             }
+        };
+        // AC2 of the vertex and AC3 of the edge for neighbour number k
+        auto tests = [&](int j, int4 bb, int k) {
+            if (gab && vertex_violation_sign(a, i, bb, j, perm) < 0) gab = false;
+            if (j > i && edge_ac3(edge_setup(a, bb), pp.aq)) {
+                if (ONE) {
+                    if (k < 32) mask |= 1u << k;
+                } else {
+                    ru[cu] = j;
+                }
+                cu++;
+            }
+        };
+        // the scan only collects the row; the float64 tests then run over the
+        // row, where a wave's lanes are mostly busy (inside the scan they would
+        // run whenever any lane of the wave met a ball)
+        scan([&](int j, int4) {
+            if (cn < capn) rn[cn * RS] = j;
+            cn++;
+        });
+        const int kn = min(cn, capn);
+        for (int k = 0; k < kn; k++) {
+            const int j = rn[k * RS];
+            tests(j, atom[j], k);
+        }
+        if (cn > capn) {
+            // one-pass mode, row longer than the slot: the exact counts still
+            // need the tests of the rest (the fill pass redoes this row)
+            int k = 0;
+            scan([&](int j, int4 bb) {
+                if (k >= capn) tests(j, bb, k);
+                k++;
+            });
         }
     }
     if (valid) vgab[i] = (unsigned char)(ra >= 0 && gab);
@@ -339,7 +366,7 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
             block_tot[gridDim.x + b] = totu;  // upper entries of the block
         }
         int *dn = nslab + (long long)b * NB_SLAB + offn;
-        for (int k = 0; k < kn; k++) dn[k] = sn[threadIdx.x * NB_SLOT + k];
+        for (int k = 0; k < kn; k++) dn[k] = sn[k * BLOCK + threadIdx.x];
         return;
     }
     if (!staged) {
@@ -481,6 +508,7 @@ __global__ void __launch_bounds__(BLOCK) k_triangles(const int4 *__restrict__ at
                                                       int *__restrict__ tri_e, Counters *cnt) {
     constexpr bool ONE = MODE == TRI_ONEPASS;
     __shared__ int slot[ONE ? BLOCK * TRI_SLOT : 1];
+    __shared__ int cand[BLOCK * TRI_SLOT];
     const int b = xcd_block();
     const int e = b * BLOCK + threadIdx.x;
     int c = 0;
@@ -507,21 +535,31 @@ __global__ void __launch_bounds__(BLOCK) k_triangles(const int4 *__restrict__ at
         int pb = up_start[j];
         const int eb = up_start[j + 1];
         const int out = ONE ? 0 : tri_start[e];
-        while (pa < ea && pb < eb) {
-            // merge step without divergent branches: advance the smaller
-            // side (both when equal)
-            const int ka = up[pa], kb = up[pb];
-            pa += ka <= kb;
-            pb += kb <= ka;
-            if (ka != kb) continue;
-            if (!tri_candidate(vi, vj, atom[ka], pp, cnt)) continue;
-            if (ONE) {
-                if (c < TRI_SLOT) slot[threadIdx.x * TRI_SLOT + c] = ka;
-            } else {
-                tri_k[out + c] = ka;
-                tri_e[out + c] = e;
+        // merge of the two upper rows without divergent branches (advance the
+        // smaller side, both when equal). The common entries are collected in
+        // rounds of up to TRI_SLOT and tested after each round, so that the
+        // float64 test runs with the wave's lanes mostly busy.
+        int *const lst = cand + threadIdx.x;  // entry u at u * BLOCK
+        for (;;) {
+            int m = 0;
+            while (pa < ea && pb < eb && m < TRI_SLOT) {
+                const int ka = up[pa], kb = up[pb];
+                pa += ka <= kb;
+                pb += kb <= ka;
+                if (ka == kb) lst[(m++) * BLOCK] = ka;
             }
-            c++;
+            for (int u = 0; u < m; u++) {
+                const int ka = lst[u * BLOCK];
+                if (!tri_candidate(vi, vj, atom[ka], pp, cnt)) continue;
+                if (ONE) {
+                    if (c < TRI_SLOT) slot[c * BLOCK + threadIdx.x] = ka;
+                } else {
+                    tri_k[out + c] = ka;
+                    tri_e[out + c] = e;
+                }
+                c++;
+            }
+            if (m < TRI_SLOT) break;
         }
         if (ONE) tri_cnt[e] = c;
     }
@@ -536,7 +574,7 @@ __global__ void __launch_bounds__(BLOCK) k_triangles(const int4 *__restrict__ at
     }
     if (total > TRI_SLAB) return;
     int *dst = slab + (long long)b * TRI_SLAB + off;
-    for (int u = 0; u < kept; u++) dst[u] = slot[threadIdx.x * TRI_SLOT + u];
+    for (int u = 0; u < kept; u++) dst[u] = slot[u * BLOCK + threadIdx.x];
 }
 
 // Moves block b's slab to its final place (block_off = exclusive scan of the
@@ -624,6 +662,7 @@ __global__ void __launch_bounds__(BLOCK, 4) k_tet_candidates(const int4 *__restr
                                                            int *__restrict__ tet_l, Counters *cnt) {
     constexpr bool ONE = MODE == TET_ONEPASS;
     __shared__ int slot[ONE ? BLOCK * TET_SLOT : 1];
+    __shared__ int cand[BLOCK * TET_SLOT];
     const int b = xcd_block();
     const int t = b * BLOCK + threadIdx.x;
     int c = 0;
@@ -658,24 +697,34 @@ __global__ void __launch_bounds__(BLOCK, 4) k_tet_candidates(const int4 *__restr
         int pc = up_start[k];
         const int ec = up_start[k + 1];
         const int out = ONE ? 0 : tet_start[t];
-        while (pa < ea && pb < eb && pc < ec) {
-            // three-way merge step without divergent branches
-            const int la = up[pa], lb = up[pb], lc = up[pc];
-            const int m = max(la, max(lb, lc));
-            const bool all = (la == m) & (lb == m) & (lc == m);
-            pa += (la < m) | all;
-            pb += (lb < m) | all;
-            pc += (lc < m) | all;
-            if (!all) continue;
-            const Tet te = tet_setup(vi, vj, vk, atom[m], pp);
-            if (te.D == 0 || !tet_ac3(te, pp, cnt)) continue;
-            if (ONE) {
-                if (c < TET_SLOT) slot[threadIdx.x * TET_SLOT + c] = m;
-            } else {
-                tet_t[out + c] = t;
-                tet_l[out + c] = m;
+        // three-way merge step without divergent branches; the common entries
+        // are collected in rounds of up to TET_SLOT and tested after each
+        // round (the float64 test then runs with the wave's lanes mostly busy)
+        int *const lst = cand + threadIdx.x;  // entry u at u * BLOCK
+        for (;;) {
+            int mc = 0;
+            while (pa < ea && pb < eb && pc < ec && mc < TET_SLOT) {
+                const int la = up[pa], lb = up[pb], lc = up[pc];
+                const int m = max(la, max(lb, lc));
+                const bool all = (la == m) & (lb == m) & (lc == m);
+                pa += (la < m) | all;
+                pb += (lb < m) | all;
+                pc += (lc < m) | all;
+                if (all) lst[(mc++) * BLOCK] = m;
             }
-            c++;
+            for (int u = 0; u < mc; u++) {
+                const int l = lst[u * BLOCK];
+                const Tet te = tet_setup(vi, vj, vk, atom[l], pp);
+                if (te.D == 0 || !tet_ac3(te, pp, cnt)) continue;
+                if (ONE) {
+                    if (c < TET_SLOT) slot[c * BLOCK + threadIdx.x] = l;
+                } else {
+                    tet_t[out + c] = t;
+                    tet_l[out + c] = l;
+                }
+                c++;
+            }
+            if (mc < TET_SLOT) break;
         }
         if (ONE) tet_cnt[t] = c;
     }
@@ -690,7 +739,7 @@ __global__ void __launch_bounds__(BLOCK, 4) k_tet_candidates(const int4 *__restr
     }
     if (total > TET_SLAB) return;
     int *dst = slab + (long long)b * TET_SLAB + off;
-    for (int u = 0; u < kept; u++) dst[u] = slot[threadIdx.x * TET_SLOT + u];
+    for (int u = 0; u < kept; u++) dst[u] = slot[u * BLOCK + threadIdx.x];
 }
 
 // Moves block b's slab of tetrahedron candidates to its final place.
