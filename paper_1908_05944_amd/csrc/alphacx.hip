@@ -181,15 +181,17 @@ static void fill(T *p, T v, long long n, hipStream_t s) {
     LAUNCH_CHECK();
 }
 
-// out[0..n] = exclusive scan of in[0..n), out[n] = total. One launch up to
-// SCAN_SMALL items, three above (tile scan, scan of tile sums, add).
-static void scan_i32(const int *in, int *out, long long n, hipStream_t s, Scope &sc) {
+// out[0..n] = exclusive scan of in[0..n), out[n] = total (also stored to
+// *total_to when given). One launch up to SCAN_SMALL items, three above
+// (tile scan, scan of tile sums, add).
+static void scan_i32(const int *in, int *out, long long n, hipStream_t s, Scope &sc, int *total_to = nullptr) {
     if (n <= 0) {
         fill<int>(out, 0, 1, s);
+        if (total_to) fill<int>(total_to, 0, 1, s);
         return;
     }
     if (n <= SCAN_SMALL) {
-        k_scan_small<<<1, SCAN_SMALL_BLOCK, 0, s>>>(in, out, (int)n);
+        k_scan_small<<<1, SCAN_SMALL_BLOCK, 0, s>>>(in, out, (int)n, total_to);
         LAUNCH_CHECK();
         return;
     }
@@ -199,7 +201,7 @@ static void scan_i32(const int *in, int *out, long long n, hipStream_t s, Scope 
     k_scan_tiles<<<(unsigned)tiles, SCAN_BLOCK, 0, s>>>(in, out, sums, n);
     LAUNCH_CHECK();
     scan_i32(sums, offs, tiles, s, sc);
-    k_scan_add_total<<<(unsigned)tiles, SCAN_BLOCK, 0, s>>>(out, offs, n, (int)tiles);
+    k_scan_add_total<<<(unsigned)tiles, SCAN_BLOCK, 0, s>>>(out, offs, n, (int)tiles, total_to);
     LAUNCH_CHECK();
 }
 
@@ -293,8 +295,7 @@ static void emit_dim(const unsigned char *in, const double *sizes, int M, const 
                                                  cd.perm, sizes, n, key, pay);
     LAUNCH_CHECK();
     radix_sort<P>(key, pay, M, bits_for((long long)n + 1), s, sc);
-    k_emit_rank<K><<<grid_for(M), BLOCK, 0, s>>>(key, pay, M, n, sizes, res->d_simp[d], res->d_size[d]);
-    k_count_kept<<<1, 1, 0, s>>>(key, M, n, m_out);
+    k_emit_rank<K><<<grid_for(M), BLOCK, 0, s>>>(key, pay, M, n, sizes, res->d_simp[d], res->d_size[d], m_out);
     LAUNCH_CHECK();
 }
 
@@ -486,10 +487,8 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
                                                       vgab, cnt);
         LAUNCH_CHECK();
         tm.mark(ST_NBR_SCAN);
-        scan_i32(nbtot, nboff, nbN, s, sc);
-        scan_i32(nbtot + nbN, uboff, nbN, s, sc);
-        k_copy_int<<<1, 1, 0, s>>>(&cnt->Nn, nboff + nbN);
-        k_copy_int<<<1, 1, 0, s>>>(&cnt->E, uboff + nbN);
+        scan_i32(nbtot, nboff, nbN, s, sc, &cnt->Nn);
+        scan_i32(nbtot + nbN, uboff, nbN, s, sc, &cnt->E);
         LAUNCH_CHECK();
         Counters c0 = read_one(cnt, s);
         if (c0.dup) throw HipError{AC_E_DUPLICATE, "two balls have equal quantised centres"};
@@ -499,10 +498,8 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             check_total(total_i64(deg_n, n, s, sc), "neighbour entries");
         }
         if (nbr_two_pass) {
-            scan_i32(deg_n, nbr_start, n, s, sc);
-            scan_i32(deg_up, up_start, n, s, sc);
-            k_copy_int<<<1, 1, 0, s>>>(&cnt->Nn, nbr_start + n);
-            k_copy_int<<<1, 1, 0, s>>>(&cnt->E, up_start + n);
+            scan_i32(deg_n, nbr_start, n, s, sc, &cnt->Nn);
+            scan_i32(deg_up, up_start, n, s, sc, &cnt->E);
             LAUNCH_CHECK();
             c0 = read_one(cnt, s);
         }
@@ -538,8 +535,7 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
                                                           pp, tri_cnt, egab, tslab, tbtot, nullptr, nullptr, nullptr, cnt);
             LAUNCH_CHECK();
             tm.mark(ST_TRI_SCAN);
-            scan_i32(tbtot, tboff, nbE, s, sc);
-            k_copy_int<<<1, 1, 0, s>>>(&cnt->T, tboff + nbE);
+            scan_i32(tbtot, tboff, nbE, s, sc, &cnt->T);
             LAUNCH_CHECK();
         } else {
             tm.mark(ST_TRI_SCAN);
@@ -552,8 +548,7 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             check_total(total_i64(tri_cnt, E, s, sc), "candidate triangles");
         }
         if (tri_two_pass) {
-            scan_i32(tri_cnt, tri_start, E, s, sc);
-            k_copy_int<<<1, 1, 0, s>>>(&cnt->T, tri_start + E);
+            scan_i32(tri_cnt, tri_start, E, s, sc, &cnt->T);
             LAUNCH_CHECK();
             ct = read_one(cnt, s);
         }
@@ -590,8 +585,7 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         }
         tm.mark(ST_TET_COUNT);
         if (T > 0) {
-            scan_i32(qbtot, qboff, nbT, s, sc);
-            k_copy_int<<<1, 1, 0, s>>>(&cnt->Q, qboff + nbT);
+            scan_i32(qbtot, qboff, nbT, s, sc, &cnt->Q);
             LAUNCH_CHECK();
         } else {
             fill<int>(&cnt->Q, 0, 1, s);
@@ -600,8 +594,7 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         const bool tet_two_pass = cq.overflow != 0;
         if (tet_two_pass) {
             check_total(total_i64(tet_cnt, T, s, sc), "candidate tetrahedra");
-            scan_i32(tet_cnt, tet_start, T, s, sc);
-            k_copy_int<<<1, 1, 0, s>>>(&cnt->Q, tet_start + T);
+            scan_i32(tet_cnt, tet_start, T, s, sc, &cnt->Q);
             LAUNCH_CHECK();
             cq = read_one(cnt, s);
         }
@@ -633,12 +626,12 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         double *esize = sc.get<double>(E > 0 ? E : 1);
         int *vin_in = sc.get<int>(n);
         double *vsize_in = sc.get<double>(n);
-        fill<int>(tri_att, 0, T, s);
-        fill<long long>(tri_min, ORDERED_POS_INF, T, s);
-        fill<int>(edge_att, 0, E, s);
-        fill<long long>(edge_min, ORDERED_POS_INF, E, s);
-        fill<int>(vert_att, 0, n, s);
-        fill<long long>(vert_min, ORDERED_POS_INF, n, s);
+        {
+            const long long mx = std::max<long long>(std::max<long long>(T, E), n);
+            const long long nb = std::min<long long>((mx + BLOCK - 1) / BLOCK, 65536);
+            k_prune_init<<<(unsigned)nb, BLOCK, 0, s>>>(T, E, n, tri_att, tri_min, edge_att, edge_min, vert_att, vert_min);
+            LAUNCH_CHECK();
+        }
         tm.mark(ST_TETRA);
         if (Q > 0) {
             k_tet_ac2<<<grid_for(Q), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i, tri_start, tri_k,
@@ -665,8 +658,7 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         // ---- emit ----
         tm.mark(ST_EMIT);
         int *vpos = sc.get<int>(n + 1);
-        scan_i32(vin_in, vpos, n, s, sc);
-        k_copy_int<<<1, 1, 0, s>>>(&cnt->m0, vpos + n);
+        scan_i32(vin_in, vpos, n, s, sc, &cnt->m0);
         LAUNCH_CHECK();
         res->d_simp[0] = static_cast<int32_t *>(dev_alloc((size_t)n * sizeof(int32_t)));
         res->d_size[0] = static_cast<double *>(dev_alloc((size_t)n * sizeof(double)));
@@ -679,8 +671,9 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         tm.mark(ST_COUNT);
         // rows of each molecule in the sorted outputs
         res->n_mol = n_mol;
-        long long *d_rows = sc.get<long long>(4 * (n_mol + 1));
-        {
+        // (one molecule: all rows, from the counts below)
+        long long *d_rows = n_mol > 1 ? sc.get<long long>(4 * (n_mol + 1)) : nullptr;
+        if (n_mol > 1) {
             long long *d_bound = sc.get<long long>(n_mol + 1);
             HIP_TRY(hipMemcpyAsync(d_bound, bt.off.data(), (n_mol + 1) * sizeof(long long), hipMemcpyHostToDevice, s));
             const unsigned nb = (unsigned)((n_mol + 1 + BLOCK - 1) / BLOCK);
@@ -692,8 +685,9 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         }
         for (int d = 0; d < 4; d++) {
             res->mol_rows[d].resize(n_mol + 1);
-            HIP_TRY(hipMemcpyAsync(res->mol_rows[d].data(), d_rows + d * (n_mol + 1), (n_mol + 1) * sizeof(long long),
-                                   hipMemcpyDeviceToHost, s));
+            if (n_mol > 1)
+                HIP_TRY(hipMemcpyAsync(res->mol_rows[d].data(), d_rows + d * (n_mol + 1), (n_mol + 1) * sizeof(long long),
+                                       hipMemcpyDeviceToHost, s));
         }
         Counters cf;
         HIP_TRY(hipMemcpyAsync(&cf, cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
@@ -712,6 +706,8 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         res->count[1] = cf.m1;
         res->count[2] = cf.m2;
         res->count[3] = cf.m3;
+        if (n_mol == 1)
+            for (int d = 0; d < 4; d++) res->mol_rows[d] = {0, res->count[d]};
     } catch (const HipError &e) {
         (void)hipStreamSynchronize(s);
         free_complex(res);

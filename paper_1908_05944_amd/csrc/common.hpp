@@ -127,7 +127,7 @@ constexpr int SCAN_SMALL_IPT = 16;
 constexpr int SCAN_SMALL = SCAN_SMALL_BLOCK * SCAN_SMALL_IPT;
 
 __global__ void __launch_bounds__(SCAN_SMALL_BLOCK) k_scan_small(const int *__restrict__ in, int *__restrict__ out,
-                                                                  int n) {
+                                                                  int n, int *__restrict__ total_to) {
     __shared__ int wsum[SCAN_SMALL_BLOCK / WAVE];
     const int base = threadIdx.x * SCAN_SMALL_IPT;
     int v[SCAN_SMALL_IPT];
@@ -150,19 +150,25 @@ __global__ void __launch_bounds__(SCAN_SMALL_BLOCK) k_scan_small(const int *__re
         if (i < n) out[i] = run;
         run += v[k];
     }
-    if (threadIdx.x == SCAN_SMALL_BLOCK - 1) out[n] = run;
+    if (threadIdx.x == SCAN_SMALL_BLOCK - 1) {
+        out[n] = run;
+        if (total_to) *total_to = run;
+    }
 }
 
-// Adds tile offsets; block 0 also writes out[n] = total.
+// Adds tile offsets; block 0 also writes out[n] = total (and *total_to if set).
 __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_add_total(int *__restrict__ out, const int *__restrict__ tile_off,
-                                                                long long n, int tiles) {
+                                                                long long n, int tiles, int *__restrict__ total_to) {
     const long long base = (long long)blockIdx.x * SCAN_TILE;
     const int add = tile_off[blockIdx.x];
     for (int k = threadIdx.x; k < SCAN_TILE; k += SCAN_BLOCK) {
         const long long i = base + k;
         if (i < n) out[i] += add;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = tile_off[tiles];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        out[n] = tile_off[tiles];
+        if (total_to) *total_to = tile_off[tiles];
+    }
 }
 
 }  // namespace acx

@@ -150,6 +150,27 @@ __global__ void __launch_bounds__(BLOCK) k_fill(T *__restrict__ p, T v, long lon
     for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * BLOCK) p[i] = v;
 }
 
+// Start values of the pruning stage's attachment flags (0) and minima (+inf
+// in the ordered-integer encoding) for T triangles, E edges and n vertices.
+__global__ void __launch_bounds__(BLOCK) k_prune_init(long long T, long long E, long long n, int *__restrict__ tri_att,
+                                                       long long *__restrict__ tri_min, int *__restrict__ edge_att,
+                                                       long long *__restrict__ edge_min, int *__restrict__ vert_att,
+                                                       long long *__restrict__ vert_min) {
+    const long long stride = (long long)gridDim.x * BLOCK;
+    for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < T; i += stride) {
+        tri_att[i] = 0;
+        tri_min[i] = ORDERED_POS_INF;
+    }
+    for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < E; i += stride) {
+        edge_att[i] = 0;
+        edge_min[i] = ORDERED_POS_INF;
+    }
+    for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += stride) {
+        vert_att[i] = 0;
+        vert_min[i] = ORDERED_POS_INF;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Binning (Sec. 4.2): cell key per ball, a stable radix sort by key (inside a
 // cell the balls keep input order), then the dense cell table.
@@ -449,8 +470,6 @@ __global__ void k_fold_i64(const long long *__restrict__ part, int nb, long long
     for (int k = 0; k < nb; k++) t += part[k];
     *out = t;
 }
-
-__global__ void k_copy_int(int *__restrict__ dst, const int *__restrict__ src) { *dst = *src; }
 
 // Position of b in the (sorted) upper-edge list of a, i.e. the edge id; -1 if absent.
 __device__ __forceinline__ int find_edge(const int *__restrict__ up_start, const int *__restrict__ up, int a, int b) {
@@ -976,15 +995,6 @@ __global__ void __launch_bounds__(BLOCK) k_emit_keys(const unsigned char *__rest
 }
 
 // Number of kept rows after the sort: the first position whose key is n.
-__global__ void k_count_kept(const unsigned *__restrict__ key, int M, int n, int *__restrict__ out) {
-    int lo = 0, hi = M;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (key[mid] < (unsigned)n) lo = mid + 1; else hi = mid;
-    }
-    *out = lo;
-}
-
 template <int K>
 __device__ __forceinline__ void pay_ids(const typename EmitPay<K>::type &q, unsigned (&r)[3]) {
     if constexpr (K == 2) { r[0] = q.x; r[1] = 0; r[2] = 0; }
@@ -1010,7 +1020,7 @@ template <int K>
 __global__ void __launch_bounds__(BLOCK) k_emit_rank(const unsigned *__restrict__ key,
                                                       const typename EmitPay<K>::type *__restrict__ pay, int m, int n,
                                                       const double *__restrict__ size_in, int *__restrict__ out,
-                                                      double *__restrict__ out_size) {
+                                                      double *__restrict__ out_size, int *__restrict__ m_out) {
     typedef typename EmitPay<K>::type P;
     constexpr int SPAN = BLOCK + 2 * RANK_HALO;
     __shared__ unsigned sk[SPAN];
@@ -1031,7 +1041,10 @@ __global__ void __launch_bounds__(BLOCK) k_emit_rank(const unsigned *__restrict_
     if (p >= m) return;
     const int lp = p - lo;
     const unsigned u0 = sk[lp];
-    if (u0 == (unsigned)n) return;  // not kept (sorted after the kept rows)
+    // the kept count: where the kept keys (< n) end; lp + 1 < SPAN
+    const bool kept = u0 < (unsigned)n;
+    if (kept ? (p + 1 == m || sk[lp + 1] >= (unsigned)n) : p == 0) *m_out = kept ? p + 1 : 0;
+    if (!kept) return;  // not kept (sorted after the kept rows)
     const P me = sp[lp];
     unsigned r[3];
     pay_ids<K>(me, r);
