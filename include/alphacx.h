@@ -57,7 +57,9 @@ typedef struct {
                                 its own centre (the paper's implementation shortcut, Sec. 4.4); exact
                                 only when no centre lies inside another ball's power cell */
     int64_t capacity_hint;   /* expected simplices per atom for buffer sizing; 0 = adaptive */
-    int32_t profile;         /* 1 = record HIP events between pipeline stages (see ac_stage_ms) */
+    int32_t profile;         /* 1 = record HIP events between pipeline stages (see ac_stage_ms);
+                                2 + i = record only the two events around stage i (each event
+                                adds a few microseconds of device idle time) */
     int32_t reserved;        /* must be 0 */
 } ac_options;
 
@@ -151,9 +153,10 @@ int64_t ac_exact_fallbacks(const ac_complex *c);
  * (each ball's list of balls whose grown ball meets its own). -1 otherwise. */
 int64_t ac_work_count(const ac_complex *c, int which);
 
-/* Per-stage device time of a call made with opt->profile = 1, from HIP events
- * recorded on the call's stream between stages (milliseconds; -1 if not
- * profiled or i out of range). Stage i is named by ac_stage_name(i), for
+/* Per-stage device time of a call made with opt->profile = 1 (every stage)
+ * or 2 + i (stage i only), from HIP events recorded on the call's stream
+ * between stages (milliseconds; -1 if the stage was not recorded or i is out
+ * of range). Stage i is named by ac_stage_name(i), for
  * 0 <= i < ac_stage_count(). */
 int ac_stage_count(void);
 const char *ac_stage_name(int i);

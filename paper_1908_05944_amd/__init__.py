@@ -140,6 +140,12 @@ def library():
     return _load()
 
 
+def stage_names() -> list:
+    """Names of the pipeline stages, in order: stage i of options profile=2+i."""
+    lib = _load()
+    return [lib.ac_stage_name(i).decode() for i in range(lib.ac_stage_count())]
+
+
 def _check(st: int):
     if st != 0:
         raise AlphaCxError(st, _load().ac_last_error().decode(errors="replace"))
@@ -193,7 +199,8 @@ class AlphaComplex:
         return lib.ac_simplices_device(self._h, dim), lib.ac_sizes_device(self._h, dim)
 
     def stage_ms(self) -> dict:
-        """Per-stage device milliseconds of a profiled call (options profile=1)."""
+        """Per-stage device milliseconds of a profiled call (options profile=1:
+        every stage; profile=2+i: stage i only, the others -1)."""
         lib = _load()
         return {lib.ac_stage_name(i).decode(): lib.ac_stage_ms(self._h, i) for i in range(lib.ac_stage_count())}
 

@@ -205,11 +205,38 @@ static void scan_i32(const int *in, int *out, long long n, hipStream_t s, Scope 
     LAUNCH_CHECK();
 }
 
+// Pinned host block of this thread for device-to-host read-backs (a copy to
+// pageable memory takes a slower staged path). Every use synchronises the
+// stream before the block is read or reused, so one block per thread serves
+// all calls; it is kept until the process ends.
+static void *pinned_block(size_t bytes) {
+    thread_local void *p = nullptr;
+    thread_local size_t cap = 0;
+    if (bytes > cap) {
+        if (p) HIP_TRY(hipHostFree(p));
+        p = nullptr;
+        cap = 0;
+        const size_t c = std::max<size_t>(bytes, 4096);
+        HIP_TRY(hipHostMalloc(&p, c, hipHostMallocPortable));
+        cap = c;
+    }
+    return p;
+}
+
+// Copies n items from the device into h through the pinned block (synchronises s).
+template <class T>
+static void read_back(T *h, const T *d, size_t n, hipStream_t s) {
+    if (n == 0) return;
+    void *b = pinned_block(n * sizeof(T));
+    HIP_TRY(hipMemcpyAsync(b, d, n * sizeof(T), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::memcpy(h, b, n * sizeof(T));
+}
+
 template <class T>
 static T read_one(const T *d, hipStream_t s) {
     T h;
-    HIP_TRY(hipMemcpyAsync(&h, d, sizeof(T), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    read_back(&h, d, 1, s);
     return h;
 }
 
@@ -317,19 +344,24 @@ static const char *kStageNames[ST_COUNT] = {
     "triangles_scan", "triangles_fill", "triangles_ac2_tetrahedra", "tetrahedra_scan", "tetrahedra_fill", "tetrahedra_ac2",
     "triangles_final", "edges_final", "vertices_final", "emit"};
 
+// Events at stage boundaries. Each recorded event costs a few microseconds of
+// idle device time between two kernels, so a caller may ask for one stage
+// only (its two boundary events).
 struct StageTimer {
     bool on = false;
+    int only = -1;  // >= 0: record the boundaries of this stage only
     hipStream_t s = nullptr;
     hipEvent_t ev[ST_COUNT + 1] = {};
     bool rec[ST_COUNT + 1] = {};
-    void start(bool enable, hipStream_t st) {
-        on = enable;
+    void start(int profile, hipStream_t st) {
+        on = profile != 0;
+        only = profile >= 2 ? profile - 2 : -1;
         s = st;
         if (!on) return;
         for (int i = 0; i <= ST_COUNT; i++) HIP_TRY(hipEventCreate(&ev[i]));
     }
     void mark(int i) {
-        if (!on) return;
+        if (!on || (only >= 0 && i != only && i != only + 1)) return;
         HIP_TRY(hipEventRecord(ev[i], s));
         rec[i] = true;
     }
@@ -375,7 +407,7 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
     HIP_TRY(hipGetDevice(&res->device));
     res->device_result = true;
     try {
-        tm.start(o.profile != 0, s);
+        tm.start(o.profile, s);
         // ---- quantise + stats (per molecule) ----
         tm.mark(ST_QUANTISE);
         const int n_mol = (int)bt.off.size() - 1;
@@ -402,8 +434,7 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             LAUNCH_CHECK();
             k_stats_reduce<<<(unsigned)n_mol, BLOCK, 0, s>>>(part, d_tile_first, st);
             LAUNCH_CHECK();
-            HIP_TRY(hipMemcpyAsync(hs.data(), st, n_mol * sizeof(Stats), hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
+            read_back(hs.data(), st, (size_t)n_mol, s);
         }
         int flags = 0, wmax = 0;
         for (const Stats &x : hs) {
@@ -683,15 +714,13 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             k_row_lower_bound<4><<<nb, BLOCK, 0, s>>>(res->d_simp[3], &cnt->m3, d_bound, n_mol + 1, d_rows + 3 * (n_mol + 1));
             LAUNCH_CHECK();
         }
-        for (int d = 0; d < 4; d++) {
-            res->mol_rows[d].resize(n_mol + 1);
-            if (n_mol > 1)
-                HIP_TRY(hipMemcpyAsync(res->mol_rows[d].data(), d_rows + d * (n_mol + 1), (n_mol + 1) * sizeof(long long),
-                                       hipMemcpyDeviceToHost, s));
+        if (n_mol > 1) {
+            std::vector<int64_t> rows(4 * (size_t)(n_mol + 1));
+            read_back(rows.data(), (const int64_t *)d_rows, rows.size(), s);
+            for (int d = 0; d < 4; d++)
+                res->mol_rows[d].assign(rows.begin() + d * (n_mol + 1), rows.begin() + (d + 1) * (n_mol + 1));
         }
-        Counters cf;
-        HIP_TRY(hipMemcpyAsync(&cf, cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        const Counters cf = read_one(cnt, s);
         tm.collect(res->stage_ms);
         if (cf.lookup) throw HipError{AC_E_DEVICE, "internal error: a facet of a kept simplex is not a candidate"};
         res->cand[0] = n;
@@ -854,7 +883,7 @@ static Options parse(const ac_options *opt) {
         o.cell_mA = opt->cell_mA;
         o.force_exact = opt->force_exact != 0;
         o.vertex_shortcut = opt->vertex_shortcut != 0;
-        o.profile = opt->profile != 0;
+        o.profile = opt->profile >= 0 && opt->profile <= ST_COUNT + 1 ? opt->profile : 1;
     }
     return o;
 }
@@ -1088,8 +1117,7 @@ ac_status ac_union_measure(ac_complex *c, const double *d_xyz, const double *d_r
         hipStream_t s = static_cast<hipStream_t>(stream);
         const double *d_out = measure_forward(c, d_xyz, d_radii, nullptr, s);
         double h[2];
-        HIP_TRY(hipMemcpyAsync(h, d_out, sizeof(h), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        read_back(h, d_out, 2, s);
         *V = h[0];
         *A = h[1];
     } catch (const HipError &e) {
