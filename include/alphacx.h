@@ -44,6 +44,9 @@ typedef enum {
     AC_E_CAPACITY = 6   /* a candidate list outgrew its buffer even after the internal retry */
 } ac_status;
 
+/* Largest number of alpha values of one ac_alpha_sweep_device call. */
+#define AC_MAX_SWEEP 1024
+
 /* Opaque result; owned by the library until ac_free(). */
 typedef struct ac_complex ac_complex;
 
@@ -87,6 +90,31 @@ ac_status ac_alpha_complex(const double *xyz, const double *radii, int64_t n, do
  */
 ac_status ac_alpha_complex_device(const double *d_xyz, const double *d_radii, int64_t n, double alpha,
                                   const ac_options *opt, void *stream, ac_complex **out);
+
+/* ---- Alpha sweep ----
+ *
+ * The alpha complexes of one ball set for several alpha values from a single
+ * candidate search at the largest of them. The candidates of a smaller alpha
+ * are exactly the candidates of the larger that pass AC3 at the smaller
+ * (OrthoSize is monotone over faces), and AC2 does not depend on alpha
+ * (Sec. 2.4, 3.1), so each K_alpha is obtained by re-testing AC3 exactly at
+ * that alpha and re-running the pruning (Steps 2-5) on the shared candidate
+ * lists; the output order is sorted once. This is the reuse of a computed
+ * complex for other alpha values that the paper names as future work
+ * (Sec. 6).
+ *   alphas   host, n_alpha values in square angstrom, any order, repeats
+ *            allowed; 1 <= n_alpha <= AC_MAX_SWEEP
+ *   out      host array of n_alpha handles: out[k] receives the complex of
+ *            alphas[k], each to be released with ac_free (all NULL on error)
+ * Other arguments as ac_alpha_complex_device. out[k] holds exactly what
+ * ac_alpha_complex_device returns for alphas[k] (simplices and Sizes bit
+ * for bit); ac_exact_fallbacks reports the whole call and ac_stage_ms of a
+ * profiled call times the search stages and, as "emit", every alpha's
+ * pruning and output together. Errors as ac_alpha_complex_device (the
+ * range check uses the largest alpha).
+ */
+ac_status ac_alpha_sweep_device(const double *d_xyz, const double *d_radii, int64_t n, const double *alphas,
+                                int64_t n_alpha, const ac_options *opt, void *stream, ac_complex **out);
 
 /* ---- Batches of molecules ----
  *

@@ -86,6 +86,9 @@ def _load():
     lib.ac_alpha_complex.restype = ctypes.c_int
     lib.ac_alpha_complex_device.argtypes = [c_p, c_p, i64, dbl, ctypes.POINTER(Options), c_p, ctypes.POINTER(c_p)]
     lib.ac_alpha_complex_device.restype = ctypes.c_int
+    lib.ac_alpha_sweep_device.argtypes = [c_p, c_p, i64, ctypes.POINTER(dbl), i64, ctypes.POINTER(Options), c_p,
+                                          ctypes.POINTER(c_p)]
+    lib.ac_alpha_sweep_device.restype = ctypes.c_int
     lib.ac_count.argtypes = [c_p, ctypes.c_int]
     lib.ac_count.restype = i64
     lib.ac_simplices.argtypes = [c_p, ctypes.c_int]
@@ -270,6 +273,30 @@ def ac_alpha_complex_device(xyz, radii, alpha: float, options=None, stream=None)
                                      ctypes.c_void_p(s.cuda_stream), ctypes.byref(h))
     _check(st)
     return AlphaComplex(h)
+
+
+def ac_alpha_sweep_device(xyz, radii, alphas, options=None, stream=None) -> list:
+    """torch float64 device tensors (n x 3, n) -> one AlphaComplex per value of
+    `alphas` (in that order), all from a single candidate search at the
+    largest; each equals ac_alpha_complex_device at its alpha bit for bit."""
+    import torch
+    lib = _load()
+    if not (xyz.is_cuda and radii.is_cuda):
+        raise ValueError("ac_alpha_sweep_device needs device tensors")
+    if xyz.dtype != torch.float64 or radii.dtype != torch.float64:
+        raise ValueError("float64 tensors expected")
+    xyz = xyz.contiguous()
+    radii = radii.contiguous()
+    if xyz.dim() != 2 or xyz.shape[1] != 3 or radii.shape[0] != xyz.shape[0]:
+        raise ValueError("xyz must be n x 3 and radii n")
+    a = np.ascontiguousarray(np.asarray(alphas, dtype=np.float64).ravel())
+    s = stream if stream is not None else torch.cuda.current_stream(xyz.device)
+    hs = (ctypes.c_void_p * max(len(a), 1))()
+    st = lib.ac_alpha_sweep_device(xyz.data_ptr(), radii.data_ptr(), xyz.shape[0],
+                                   a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(a), _opts(options),
+                                   ctypes.c_void_p(s.cuda_stream), hs)
+    _check(st)
+    return [AlphaComplex(ctypes.c_void_p(h)) for h in hs[:len(a)]]
 
 
 def _batch_args(xyz, radii, offsets):

@@ -5,6 +5,7 @@
 // size allocate nothing from the runtime after the first.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -326,6 +327,23 @@ static void emit_dim(const unsigned char *in, const double *sizes, int M, const 
     LAUNCH_CHECK();
 }
 
+// Output order of every candidate of dimension K - 1 (for a sweep): the
+// rows sorted as emit_dim sorts them (rows_s) and each candidate's place in
+// that order (spos).
+template <int K>
+static void order_dim(int M, const Cands &cd, int n, hipStream_t s, Scope &sc, int *rows_s, int *spos) {
+    typedef typename OrderPay<K>::type P;
+    if (M == 0) return;
+    unsigned *key = sc.get<unsigned>(M);
+    P *pay = sc.get<P>(M);
+    k_order_keys<K><<<grid_for(M), BLOCK, 0, s>>>(M, cd.up, cd.edge_i, cd.tri_k, cd.tri_e, cd.tet_t, cd.tet_l, cd.perm,
+                                                  key, pay);
+    LAUNCH_CHECK();
+    radix_sort<P>(key, pay, M, bits_for((long long)n), s, sc);
+    k_order_rank<K><<<grid_for(M), BLOCK, 0, s>>>(key, pay, M, rows_s, spos);
+    LAUNCH_CHECK();
+}
+
 struct Options {
     int cell_mA = 0;
     int force_exact = 0;
@@ -390,23 +408,39 @@ struct Batch {
 
 constexpr int QTILE = 1024;  // balls per block of the quantise kernel
 
-// The whole pipeline from device arrays. Returns AC_OK and *out on success.
-static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n64, const Batch &bt, double alpha,
-                              const Options &o, hipStream_t s, ac_complex **out) {
-    *out = nullptr;
+// The whole pipeline from device arrays, for n_alpha >= 1 alpha values: one
+// candidate search at the largest, then pruning and output per value (the
+// candidates of a smaller alpha are those of the larger that pass AC3 at the
+// smaller, and AC2 does not depend on alpha). Returns AC_OK and outs[k] for
+// alphas[k] on success; nothing is left allocated on failure.
+static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n64, const Batch &bt,
+                              const double *alphas, int n_alpha, const Options &o, hipStream_t s, ac_complex **outs) {
+    for (int k = 0; k < n_alpha; k++) outs[k] = nullptr;
     if (n64 < 1 || n64 >= (1 << 26)) return set_error(AC_E_INVALID, "n must be in [1, 2^26)");
-    if (!std::isfinite(alpha)) return set_error(AC_E_INVALID, "alpha is not finite");
-    const double as = alpha * 1e6;
-    if (!(std::fabs(as) < 67108864.0)) return set_error(AC_E_RANGE, "|alpha| too large for the exact bit budget");
-    const long long aq = (long long)std::nearbyint(as);
+    if (n_alpha < 1 || n_alpha > AC_MAX_SWEEP) return set_error(AC_E_INVALID, "number of alpha values out of range");
+    std::vector<long long> aqs(n_alpha);
+    for (int k = 0; k < n_alpha; k++) {
+        if (!std::isfinite(alphas[k])) return set_error(AC_E_INVALID, "alpha is not finite");
+        const double as = alphas[k] * 1e6;
+        if (!(std::fabs(as) < 67108864.0)) return set_error(AC_E_RANGE, "|alpha| too large for the exact bit budget");
+        aqs[k] = (long long)std::nearbyint(as);
+    }
+    const long long aq = *std::max_element(aqs.begin(), aqs.end());
     const int n = (int)n64;
     Scope sc;
     StageTimer tm;
-    ac_complex *res = new ac_complex();
-    for (double &x : res->stage_ms) x = -1.0;
-    HIP_TRY(hipGetDevice(&res->device));
-    res->device_result = true;
+    std::vector<ac_complex *> rs(n_alpha, nullptr);
+    auto new_result = [&]() {
+        ac_complex *r = new ac_complex();
+        for (double &x : r->stage_ms) x = -1.0;
+        HIP_TRY(hipGetDevice(&r->device));
+        r->device_result = true;
+        return r;
+    };
+    ac_complex *res = nullptr;
     try {
+        for (int k = 0; k < n_alpha; k++) rs[k] = new_result();
+        res = rs[0];
         tm.start(o.profile, s);
         // ---- quantise + stats (per molecule) ----
         tm.mark(ST_QUANTISE);
@@ -652,99 +686,213 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         long long *edge_min = sc.get<long long>(E > 0 ? E : 1);
         int *vert_att = sc.get<int>(n);
         long long *vert_min = sc.get<long long>(n);
-        unsigned char *tin = sc.get<unsigned char>(T > 0 ? T : 1);
-        unsigned char *ein = sc.get<unsigned char>(E > 0 ? E : 1);
-        double *esize = sc.get<double>(E > 0 ? E : 1);
         int *vin_in = sc.get<int>(n);
         double *vsize_in = sc.get<double>(n);
-        {
+        int *vpos = sc.get<int>(n + 1);
+        auto prune_init = [&]() {
             const long long mx = std::max<long long>(std::max<long long>(T, E), n);
             const long long nb = std::min<long long>((mx + BLOCK - 1) / BLOCK, 65536);
             k_prune_init<<<(unsigned)nb, BLOCK, 0, s>>>(T, E, n, tri_att, tri_min, edge_att, edge_min, vert_att, vert_min);
             LAUNCH_CHECK();
-        }
-        tm.mark(ST_TETRA);
-        if (Q > 0) {
-            k_tet_ac2<<<grid_for(Q), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i, tri_start, tri_k,
-                                                   tri_e, tet_t, tet_l, Q, pp, tgab, tri_att, tri_min, qin, qsize, cnt);
+        };
+        // vertices of one alpha (Step 5), then their output in input order
+        auto vert_final = [&](const PredParams &pa) {
+            k_vert_final<<<grid_for(n), BLOCK, 0, s>>>(atom, perm, n, pa, o.vertex_shortcut, vgab, vert_att, vert_min,
+                                                      vin_in, vsize_in);
             LAUNCH_CHECK();
-        }
-        tm.mark(ST_TRI_FINAL);
-        if (T > 0) {
-            k_tri_final<<<grid_for(T), BLOCK, 0, s>>>(up_start, up, edge_i, tri_k, tri_e, T, tgab, tsize, tri_att,
-                                                     tri_min, tin, egab, edge_att, edge_min, cnt);
+        };
+        auto vert_emit = [&](ac_complex *r, int *m_out) {
+            scan_i32(vin_in, vpos, n, s, sc, m_out);
+            r->d_simp[0] = static_cast<int32_t *>(dev_alloc((size_t)n * sizeof(int32_t)));
+            r->d_size[0] = static_cast<double *>(dev_alloc((size_t)n * sizeof(double)));
+            k_vert_emit<<<grid_for(n), BLOCK, 0, s>>>(vin_in, vpos, vsize_in, n, r->d_simp[0], r->d_size[0]);
             LAUNCH_CHECK();
-        }
-        tm.mark(ST_EDGE_FINAL);
-        if (E > 0) {
-            k_edge_final<<<grid_for(E), BLOCK, 0, s>>>(atom, up, edge_i, E, egab, edge_att, edge_min, ein, esize, vgab,
-                                                      vert_att, vert_min);
-            LAUNCH_CHECK();
-        }
-        tm.mark(ST_VERT_FINAL);
-        k_vert_final<<<grid_for(n), BLOCK, 0, s>>>(atom, perm, n, pp, o.vertex_shortcut, vgab, vert_att, vert_min,
-                                                  vin_in, vsize_in);
-        LAUNCH_CHECK();
-
-        // ---- emit ----
-        tm.mark(ST_EMIT);
-        int *vpos = sc.get<int>(n + 1);
-        scan_i32(vin_in, vpos, n, s, sc, &cnt->m0);
-        LAUNCH_CHECK();
-        res->d_simp[0] = static_cast<int32_t *>(dev_alloc((size_t)n * sizeof(int32_t)));
-        res->d_size[0] = static_cast<double *>(dev_alloc((size_t)n * sizeof(double)));
-        k_vert_emit<<<grid_for(n), BLOCK, 0, s>>>(vin_in, vpos, vsize_in, n, res->d_simp[0], res->d_size[0]);
-        LAUNCH_CHECK();
-        const Cands cd{up, edge_i, tri_k, tri_e, tet_t, tet_l, perm};
-        emit_dim<2>(ein, esize, E, cd, n, s, sc, res, 1, &cnt->m1);
-        emit_dim<3>(tin, tsize, T, cd, n, s, sc, res, 2, &cnt->m2);
-        emit_dim<4>(qin, qsize, Q, cd, n, s, sc, res, 3, &cnt->m3);
-        tm.mark(ST_COUNT);
-        // rows of each molecule in the sorted outputs
-        res->n_mol = n_mol;
-        // (one molecule: all rows, from the counts below)
-        long long *d_rows = n_mol > 1 ? sc.get<long long>(4 * (n_mol + 1)) : nullptr;
-        if (n_mol > 1) {
-            long long *d_bound = sc.get<long long>(n_mol + 1);
-            HIP_TRY(hipMemcpyAsync(d_bound, bt.off.data(), (n_mol + 1) * sizeof(long long), hipMemcpyHostToDevice, s));
+        };
+        // rows of each molecule of a batch in the sorted outputs of r (device)
+        auto mol_rows = [&](ac_complex *r, Counters *cm, long long *d_rows, const long long *d_bound) {
             const unsigned nb = (unsigned)((n_mol + 1 + BLOCK - 1) / BLOCK);
-            k_row_lower_bound<1><<<nb, BLOCK, 0, s>>>(res->d_simp[0], &cnt->m0, d_bound, n_mol + 1, d_rows);
-            k_row_lower_bound<2><<<nb, BLOCK, 0, s>>>(res->d_simp[1], &cnt->m1, d_bound, n_mol + 1, d_rows + (n_mol + 1));
-            k_row_lower_bound<3><<<nb, BLOCK, 0, s>>>(res->d_simp[2], &cnt->m2, d_bound, n_mol + 1, d_rows + 2 * (n_mol + 1));
-            k_row_lower_bound<4><<<nb, BLOCK, 0, s>>>(res->d_simp[3], &cnt->m3, d_bound, n_mol + 1, d_rows + 3 * (n_mol + 1));
+            k_row_lower_bound<1><<<nb, BLOCK, 0, s>>>(r->d_simp[0], &cm->m0, d_bound, n_mol + 1, d_rows);
+            k_row_lower_bound<2><<<nb, BLOCK, 0, s>>>(r->d_simp[1], &cm->m1, d_bound, n_mol + 1, d_rows + (n_mol + 1));
+            k_row_lower_bound<3><<<nb, BLOCK, 0, s>>>(r->d_simp[2], &cm->m2, d_bound, n_mol + 1, d_rows + 2 * (n_mol + 1));
+            k_row_lower_bound<4><<<nb, BLOCK, 0, s>>>(r->d_simp[3], &cm->m3, d_bound, n_mol + 1, d_rows + 3 * (n_mol + 1));
             LAUNCH_CHECK();
-        }
+        };
+        long long *d_bound = nullptr;
         if (n_mol > 1) {
-            std::vector<int64_t> rows(4 * (size_t)(n_mol + 1));
-            read_back(rows.data(), (const int64_t *)d_rows, rows.size(), s);
-            for (int d = 0; d < 4; d++)
-                res->mol_rows[d].assign(rows.begin() + d * (n_mol + 1), rows.begin() + (d + 1) * (n_mol + 1));
+            d_bound = sc.get<long long>(n_mol + 1);
+            HIP_TRY(hipMemcpyAsync(d_bound, bt.off.data(), (n_mol + 1) * sizeof(long long), hipMemcpyHostToDevice, s));
         }
+        // per-alpha kept counts (m0..m3 of cs[k]); the main counters keep the
+        // fallback count and the lookup flag
+        Counters *cs = cnt;
+        if (n_alpha > 1) {
+            cs = sc.get<Counters>(n_alpha);
+            HIP_TRY(hipMemsetAsync(cs, 0, n_alpha * sizeof(Counters), s));
+        }
+        long long *d_rows = n_mol > 1 ? sc.get<long long>((size_t)n_alpha * 4 * (n_mol + 1)) : nullptr;
+
+        if (n_alpha == 1) {
+            unsigned char *tin = sc.get<unsigned char>(T > 0 ? T : 1);
+            unsigned char *ein = sc.get<unsigned char>(E > 0 ? E : 1);
+            double *esize = sc.get<double>(E > 0 ? E : 1);
+            prune_init();
+            tm.mark(ST_TETRA);
+            if (Q > 0) {
+                k_tet_ac2<false><<<grid_for(Q), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i,
+                                                              tri_start, tri_k, tri_e, tet_t, tet_l, Q, pp, tgab, tri_att,
+                                                              tri_min, qin, qsize, nullptr, cnt);
+                LAUNCH_CHECK();
+            }
+            tm.mark(ST_TRI_FINAL);
+            if (T > 0) {
+                k_tri_final<false><<<grid_for(T), BLOCK, 0, s>>>(up_start, up, edge_i, tri_k, tri_e, T, tgab, tsize,
+                                                                tri_att, tri_min, tin, egab, edge_att, edge_min, cnt,
+                                                                nullptr, pp, nullptr, nullptr, nullptr);
+                LAUNCH_CHECK();
+            }
+            tm.mark(ST_EDGE_FINAL);
+            if (E > 0) {
+                k_edge_final<false><<<grid_for(E), BLOCK, 0, s>>>(atom, up, edge_i, E, egab, edge_att, edge_min, ein,
+                                                                 esize, vgab, vert_att, vert_min, pp, nullptr, nullptr,
+                                                                 nullptr);
+                LAUNCH_CHECK();
+            }
+            tm.mark(ST_VERT_FINAL);
+            vert_final(pp);
+            // ---- emit ----
+            tm.mark(ST_EMIT);
+            vert_emit(res, &cnt->m0);
+            const Cands cd{up, edge_i, tri_k, tri_e, tet_t, tet_l, perm};
+            emit_dim<2>(ein, esize, E, cd, n, s, sc, res, 1, &cnt->m1);
+            emit_dim<3>(tin, tsize, T, cd, n, s, sc, res, 2, &cnt->m2);
+            emit_dim<4>(qin, qsize, Q, cd, n, s, sc, res, 3, &cnt->m3);
+            if (n_mol > 1) mol_rows(res, cnt, d_rows, d_bound);
+        } else {
+            // ---- sweep: AC2 of the tetrahedra and the output order of every
+            // candidate once; then per alpha, AC3 at that alpha, pruning and
+            // output by compaction in the fixed order ----
+            tm.mark(ST_TETRA);
+            int4 *tface = sc.get<int4>(Q > 0 ? Q : 1);
+            if (Q > 0) {
+                k_tet_ac2<true><<<grid_for(Q), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i,
+                                                             tri_start, tri_k, tri_e, tet_t, tet_l, Q, pp, tgab, nullptr,
+                                                             nullptr, qin, qsize, tface, cnt);
+                LAUNCH_CHECK();
+            }
+            const Cands cd{up, edge_i, tri_k, tri_e, tet_t, tet_l, perm};
+            const int M[4] = {n, E, T, Q};
+            int *rows_s[4] = {}, *spos[4] = {}, *in_s[4] = {}, *pos[4] = {};
+            double *sz_s[4] = {};
+            for (int d = 1; d <= 3; d++) {
+                const int m = M[d] > 0 ? M[d] : 1;
+                rows_s[d] = sc.get<int>((size_t)m * (d + 1));
+                spos[d] = sc.get<int>(m);
+                in_s[d] = sc.get<int>(m);
+                pos[d] = sc.get<int>((size_t)m + 1);
+                sz_s[d] = sc.get<double>(m);
+            }
+            order_dim<2>(E, cd, n, s, sc, rows_s[1], spos[1]);
+            order_dim<3>(T, cd, n, s, sc, rows_s[2], spos[2]);
+            order_dim<4>(Q, cd, n, s, sc, rows_s[3], spos[3]);
+            tm.mark(ST_EMIT);
+            for (int k = 0; k < n_alpha; k++) {
+                PredParams pa = pp;
+                pa.aq = aqs[k];
+                ac_complex *r = rs[k];
+                prune_init();
+                if (Q > 0) {
+                    k_sweep_tet<<<grid_for(Q), BLOCK, 0, s>>>(atom, up, edge_i, tri_k, tri_e, tet_t, tet_l, Q, pa, qin,
+                                                             qsize, tface, spos[3], tgab, tri_att, tri_min, in_s[3],
+                                                             sz_s[3], cnt);
+                    LAUNCH_CHECK();
+                }
+                if (T > 0) {
+                    k_tri_final<true><<<grid_for(T), BLOCK, 0, s>>>(up_start, up, edge_i, tri_k, tri_e, T, tgab, tsize,
+                                                                   tri_att, tri_min, nullptr, egab, edge_att, edge_min,
+                                                                   cnt, atom, pa, spos[2], in_s[2], sz_s[2]);
+                    LAUNCH_CHECK();
+                }
+                if (E > 0) {
+                    k_edge_final<true><<<grid_for(E), BLOCK, 0, s>>>(atom, up, edge_i, E, egab, edge_att, edge_min,
+                                                                    nullptr, nullptr, vgab, vert_att, vert_min, pa,
+                                                                    spos[1], in_s[1], sz_s[1]);
+                    LAUNCH_CHECK();
+                }
+                vert_final(pa);
+                vert_emit(r, &cs[k].m0);
+                int *m_out[4] = {&cs[k].m0, &cs[k].m1, &cs[k].m2, &cs[k].m3};
+                for (int d = 1; d <= 3; d++) {
+                    const int K = d + 1;
+                    r->d_simp[d] = static_cast<int32_t *>(dev_alloc((size_t)(M[d] > 0 ? M[d] : 1) * K * sizeof(int32_t)));
+                    r->d_size[d] = static_cast<double *>(dev_alloc((size_t)(M[d] > 0 ? M[d] : 1) * sizeof(double)));
+                    scan_i32(in_s[d], pos[d], M[d], s, sc, m_out[d]);
+                    if (M[d] == 0) continue;
+                    if (d == 1)
+                        k_sweep_write<2><<<grid_for(M[d]), BLOCK, 0, s>>>(in_s[d], pos[d], rows_s[d], sz_s[d], M[d],
+                                                                         r->d_simp[d], r->d_size[d]);
+                    else if (d == 2)
+                        k_sweep_write<3><<<grid_for(M[d]), BLOCK, 0, s>>>(in_s[d], pos[d], rows_s[d], sz_s[d], M[d],
+                                                                         r->d_simp[d], r->d_size[d]);
+                    else
+                        k_sweep_write<4><<<grid_for(M[d]), BLOCK, 0, s>>>(in_s[d], pos[d], rows_s[d], sz_s[d], M[d],
+                                                                         r->d_simp[d], r->d_size[d]);
+                    LAUNCH_CHECK();
+                }
+                if (n_mol > 1) mol_rows(r, &cs[k], d_rows + (size_t)k * 4 * (n_mol + 1), d_bound);
+            }
+        }
+        tm.mark(ST_COUNT);
+
+        // ---- results ----
+        std::vector<int64_t> rows;
+        if (n_mol > 1) {
+            rows.resize((size_t)n_alpha * 4 * (n_mol + 1));
+            read_back(rows.data(), (const int64_t *)d_rows, rows.size(), s);
+        }
+        std::vector<Counters> cm(n_alpha);
+        if (n_alpha > 1) read_back(cm.data(), cs, (size_t)n_alpha, s);
         const Counters cf = read_one(cnt, s);
-        tm.collect(res->stage_ms);
+        if (n_alpha == 1) cm[0] = cf;
         if (cf.lookup) throw HipError{AC_E_DEVICE, "internal error: a facet of a kept simplex is not a candidate"};
-        res->cand[0] = n;
-        res->cand[1] = E;
-        res->cand[2] = T;
-        res->cand[3] = Q;
-        res->fallbacks = (int64_t)cf.exact_fallbacks;
-        res->work[0] = ncell;
-        res->work[1] = Nn;
-        res->n = n;
-        res->count[0] = cf.m0;
-        res->count[1] = cf.m1;
-        res->count[2] = cf.m2;
-        res->count[3] = cf.m3;
-        if (n_mol == 1)
-            for (int d = 0; d < 4; d++) res->mol_rows[d] = {0, res->count[d]};
+        tm.collect(res->stage_ms);
+        for (int k = 0; k < n_alpha; k++) {
+            ac_complex *r = rs[k];
+            if (k > 0) std::copy(res->stage_ms, res->stage_ms + 32, r->stage_ms);
+            r->n_mol = n_mol;
+            r->cand[0] = n;
+            r->cand[1] = E;
+            r->cand[2] = T;
+            r->cand[3] = Q;
+            r->fallbacks = (int64_t)cf.exact_fallbacks;
+            r->work[0] = ncell;
+            r->work[1] = Nn;
+            r->n = n;
+            r->count[0] = cm[k].m0;
+            r->count[1] = cm[k].m1;
+            r->count[2] = cm[k].m2;
+            r->count[3] = cm[k].m3;
+            for (int d = 0; d < 4; d++) {
+                if (n_mol > 1) {
+                    const int64_t *b0 = rows.data() + ((size_t)k * 4 + d) * (n_mol + 1);
+                    r->mol_rows[d].assign(b0, b0 + (n_mol + 1));
+                } else {
+                    r->mol_rows[d] = {0, r->count[d]};
+                }
+            }
+        }
     } catch (const HipError &e) {
         (void)hipStreamSynchronize(s);
-        free_complex(res);
+        for (ac_complex *r : rs) free_complex(r);
         return set_error(e.st, e.msg);
     }
-    *out = res;
+    for (int k = 0; k < n_alpha; k++) outs[k] = rs[k];
     g_last_error.clear();
     return AC_OK;
+}
+
+static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n64, const Batch &bt, double alpha,
+                              const Options &o, hipStream_t s, ac_complex **out) {
+    return run_pipeline(d_xyz, d_r, n64, bt, &alpha, 1, o, s, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -901,6 +1049,24 @@ ac_status ac_alpha_complex_device(const double *d_xyz, const double *d_radii, in
         Batch bt;
         bt.off = {0, n};
         return run_pipeline(d_xyz, d_radii, n, bt, alpha, parse(opt), static_cast<hipStream_t>(stream), out);
+    } catch (const HipError &e) {
+        return set_error(e.st, e.msg);
+    } catch (...) {
+        return set_error(AC_E_DEVICE, "unexpected host exception");
+    }
+}
+
+ac_status ac_alpha_sweep_device(const double *d_xyz, const double *d_radii, int64_t n, const double *alphas,
+                                int64_t n_alpha, const ac_options *opt, void *stream, ac_complex **out) {
+    if (!out) return set_error(AC_E_INVALID, "out is NULL");
+    if (n_alpha < 1 || n_alpha > AC_MAX_SWEEP) return set_error(AC_E_INVALID, "number of alpha values out of range");
+    for (int64_t k = 0; k < n_alpha; k++) out[k] = nullptr;
+    if (!d_xyz || !d_radii || !alphas) return set_error(AC_E_INVALID, "NULL input pointer");
+    try {
+        Batch bt;
+        bt.off = {0, n};
+        return run_pipeline(d_xyz, d_radii, n, bt, alphas, (int)n_alpha, parse(opt), static_cast<hipStream_t>(stream),
+                            out);
     } catch (const HipError &e) {
         return set_error(e.st, e.msg);
     } catch (...) {

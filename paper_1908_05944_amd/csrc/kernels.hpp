@@ -789,6 +789,9 @@ __device__ __forceinline__ void mark_face(const unsigned char *gab, int *att, lo
 
 // Tetrahedra (Step 2): kept iff no ball is strictly closer in power to the
 // ortho-centre; a kept tetrahedron records itself on its facets (Step 3).
+// SWEEP (candidates of several alpha values): qin holds AC2 alone, and the
+// facet ids go to tface for the per-alpha passes instead of being marked.
+template <bool SWEEP>
 __global__ void __launch_bounds__(BLOCK) k_tet_ac2(const int4 *__restrict__ atom, const int *__restrict__ perm,
                                                     const int *__restrict__ nbr_start, const int *__restrict__ nbr_cnt,
                                                       const int *__restrict__ nbr,
@@ -799,7 +802,7 @@ __global__ void __launch_bounds__(BLOCK) k_tet_ac2(const int4 *__restrict__ atom
                                                     PredParams pp, const unsigned char *__restrict__ tgab,
                                                     int *__restrict__ tri_att, long long *__restrict__ tri_min,
                                                     unsigned char *__restrict__ qin, double *__restrict__ qsize,
-                                                    Counters *cnt) {
+                                                    int4 *__restrict__ tface, Counters *cnt) {
     const int c = xcd_block() * BLOCK + threadIdx.x;
     if (c >= Q) return;
     const int t = tet_t[c], l = tet_l[c];
@@ -817,16 +820,62 @@ __global__ void __launch_bounds__(BLOCK) k_tet_ac2(const int4 *__restrict__ atom
     if (!keep) return;
     const double sz = tet_size_canon(atom[i], atom[j], atom[k], atom[l], pp);
     qsize[c] = sz;
+    const int f1 = find_tri(up_start, up, tri_start, tri_k, i, j, l);
+    const int f2 = find_tri(up_start, up, tri_start, tri_k, i, k, l);
+    const int f3 = find_tri(up_start, up, tri_start, tri_k, j, k, l);
+    if (SWEEP) {
+        tface[c] = make_int4(t, f1, f2, f3);
+        return;
+    }
     const long long key = ordered_from_double(sz);
     mark_face(tgab, tri_att, tri_min, t, key, cnt);
-    mark_face(tgab, tri_att, tri_min, find_tri(up_start, up, tri_start, tri_k, i, j, l), key, cnt);
-    mark_face(tgab, tri_att, tri_min, find_tri(up_start, up, tri_start, tri_k, i, k, l), key, cnt);
-    mark_face(tgab, tri_att, tri_min, find_tri(up_start, up, tri_start, tri_k, j, k, l), key, cnt);
+    mark_face(tgab, tri_att, tri_min, f1, key, cnt);
+    mark_face(tgab, tri_att, tri_min, f2, key, cnt);
+    mark_face(tgab, tri_att, tri_min, f3, key, cnt);
+}
+
+// One alpha of a sweep, tetrahedra: kept iff AC2 (from k_tet_ac2<true>) and
+// AC3 at this alpha; in and Size go to the row's place in the output order.
+__global__ void __launch_bounds__(BLOCK) k_sweep_tet(const int4 *__restrict__ atom, const int *__restrict__ up,
+                                                      const int *__restrict__ edge_i, const int *__restrict__ tri_k,
+                                                      const int *__restrict__ tri_e, const int *__restrict__ tet_t,
+                                                      const int *__restrict__ tet_l, int Q, PredParams pp,
+                                                      const unsigned char *__restrict__ qgab,
+                                                      const double *__restrict__ qsize,
+                                                      const int4 *__restrict__ tface, const int *__restrict__ spos,
+                                                      const unsigned char *__restrict__ tgab, int *__restrict__ tri_att,
+                                                      long long *__restrict__ tri_min, int *__restrict__ in_s,
+                                                      double *__restrict__ sz_s, Counters *cnt) {
+    const int c = xcd_block() * BLOCK + threadIdx.x;
+    if (c >= Q) return;
+    const int o = spos[c];
+    bool keep = qgab[c];
+    if (keep) {
+        const int t = tet_t[c], l = tet_l[c];
+        const int e = tri_e[t];
+        const Tet te = tet_setup(atom[edge_i[e]], atom[up[e]], atom[tri_k[t]], atom[l], pp);
+        keep = tet_ac3(te, pp, cnt);
+    }
+    in_s[o] = keep;
+    if (!keep) return;
+    const double sz = qsize[c];
+    sz_s[o] = sz;
+    const long long key = ordered_from_double(sz);
+    const int4 f = tface[c];
+    mark_face(tgab, tri_att, tri_min, f.x, key, cnt);
+    mark_face(tgab, tri_att, tri_min, f.y, key, cnt);
+    mark_face(tgab, tri_att, tri_min, f.z, key, cnt);
+    mark_face(tgab, tri_att, tri_min, f.w, key, cnt);
 }
 
 // Triangles (Step 3): kept iff AC2 holds at the ortho-centre or a kept
 // tetrahedron has it as a facet; Size is then the OrthoSize or the least Size
 // of a kept tetrahedron. Kept triangles record themselves on their edges.
+// SWEEP (one alpha of a sweep over candidates of a larger alpha): AC2 alone
+// keeps a triangle only with AC3 at this alpha (a facet of a kept
+// tetrahedron has it already); in and Size go to the row's place spos[t] in
+// the output order, and tsize is left as it is.
+template <bool SWEEP>
 __global__ void __launch_bounds__(BLOCK) k_tri_final(const int *__restrict__ up_start, const int *__restrict__ up,
                                                       const int *__restrict__ edge_i, const int *__restrict__ tri_k,
                                                       const int *__restrict__ tri_e, int T,
@@ -835,27 +884,34 @@ __global__ void __launch_bounds__(BLOCK) k_tri_final(const int *__restrict__ up_
                                                       const long long *__restrict__ tri_min,
                                                       unsigned char *__restrict__ tin,
                                                       const unsigned char *__restrict__ egab, int *__restrict__ edge_att,
-                                                      long long *__restrict__ edge_min, Counters *cnt) {
+                                                      long long *__restrict__ edge_min, Counters *cnt,
+                                                      const int4 *__restrict__ atom, PredParams pp,
+                                                      const int *__restrict__ spos, int *__restrict__ in_s,
+                                                      double *__restrict__ sz_s) {
     const int t = xcd_block() * BLOCK + threadIdx.x;
     if (t >= T) return;
-    const bool gab = tgab[t];
+    const int e = tri_e[t];
+    const int i = edge_i[e], j = up[e], k = tri_k[t];
+    bool gab = tgab[t];
+    if (SWEEP && gab) gab = tri_candidate(atom[i], atom[j], atom[k], pp, cnt);
     const bool in = gab || tri_att[t];
-    tin[t] = (unsigned char)in;
+    if (SWEEP) in_s[spos[t]] = in; else tin[t] = (unsigned char)in;
     if (!in) return;
     double sz = tsize[t];
     if (!gab) {
         sz = double_from_ordered(tri_min[t]);
-        tsize[t] = sz;
+        if (!SWEEP) tsize[t] = sz;
     }
-    const int e = tri_e[t];
-    const int i = edge_i[e], j = up[e], k = tri_k[t];
+    if (SWEEP) sz_s[spos[t]] = sz;
     const long long key = ordered_from_double(sz);
     mark_face(egab, edge_att, edge_min, e, key, cnt);
     mark_face(egab, edge_att, edge_min, find_edge(up_start, up, i, k), key, cnt);
     mark_face(egab, edge_att, edge_min, find_edge(up_start, up, j, k), key, cnt);
 }
 
-// Edges (Step 4).
+// Edges (Step 4). SWEEP as for triangles: AC2 alone keeps an edge only with
+// AC3 at this alpha; in and Size go to the row's place spos[e].
+template <bool SWEEP>
 __global__ void __launch_bounds__(BLOCK) k_edge_final(const int4 *__restrict__ atom, const int *__restrict__ up,
                                                        const int *__restrict__ edge_i, int E,
                                                        const unsigned char *__restrict__ egab,
@@ -863,16 +919,19 @@ __global__ void __launch_bounds__(BLOCK) k_edge_final(const int4 *__restrict__ a
                                                        const long long *__restrict__ edge_min,
                                                        unsigned char *__restrict__ ein, double *__restrict__ esize,
                                                        const unsigned char *__restrict__ vgab,
-                                                       int *__restrict__ vert_att, long long *__restrict__ vert_min) {
+                                                       int *__restrict__ vert_att, long long *__restrict__ vert_min,
+                                                       PredParams pp, const int *__restrict__ spos,
+                                                       int *__restrict__ in_s, double *__restrict__ sz_s) {
     const int e = xcd_block() * BLOCK + threadIdx.x;
     if (e >= E) return;
-    const bool gab = egab[e];
-    const bool in = gab || edge_att[e];
-    ein[e] = (unsigned char)in;
-    if (!in) return;
     const int i = edge_i[e], j = up[e];
+    bool gab = egab[e];
+    if (SWEEP && gab) gab = edge_ac3(edge_setup(atom[i], atom[j]), pp.aq);
+    const bool in = gab || edge_att[e];
+    if (SWEEP) in_s[spos[e]] = in; else ein[e] = (unsigned char)in;
+    if (!in) return;
     const double sz = gab ? edge_size_canon(atom[i], atom[j]) : double_from_ordered(edge_min[e]);
-    esize[e] = sz;
+    if (SWEEP) sz_s[spos[e]] = sz; else esize[e] = sz;
     const long long key = ordered_from_double(sz);
     if (!vgab[i]) { atomicOr(&vert_att[i], 1); atomicMin(&vert_min[i], key); }
     if (!vgab[j]) { atomicOr(&vert_att[j], 1); atomicMin(&vert_min[j], key); }
@@ -944,6 +1003,13 @@ template <> struct EmitPay<2> { typedef uint3 type; };  // v1, Size bits
 template <> struct EmitPay<3> { typedef uint4 type; };  // v1, v2, Size bits
 template <> struct EmitPay<4> { typedef uint4 type; };  // v1, v2, v3, candidate
 
+// Payload of the output-order sort of a sweep (every candidate, no Size):
+// the ids after the least, then the candidate index.
+template <int K> struct OrderPay;
+template <> struct OrderPay<2> { typedef uint2 type; };
+template <> struct OrderPay<3> { typedef uint3 type; };
+template <> struct OrderPay<4> { typedef uint4 type; };
+
 __device__ __forceinline__ uint2 bits_of(double x) {
     const unsigned long long b = (unsigned long long)__double_as_longlong(x);
     return make_uint2((unsigned)b, (unsigned)(b >> 32));
@@ -992,6 +1058,31 @@ __global__ void __launch_bounds__(BLOCK) k_emit_keys(const unsigned char *__rest
         q = make_uint4((unsigned)v[1], (unsigned)v[2], (unsigned)v[3], (unsigned)c);
     }
     pay[c] = q;
+}
+
+// Output-order keys of a sweep: every candidate c, kept at some alpha or
+// not, keyed by the least input id of its row, payload (other ids, c).
+template <int K>
+__global__ void __launch_bounds__(BLOCK) k_order_keys(int M, const int *__restrict__ up, const int *__restrict__ edge_i,
+                                                       const int *__restrict__ tri_k, const int *__restrict__ tri_e,
+                                                       const int *__restrict__ tet_t, const int *__restrict__ tet_l,
+                                                       const int *__restrict__ perm, unsigned *__restrict__ key,
+                                                       typename OrderPay<K>::type *__restrict__ pay) {
+    const int c = xcd_block() * BLOCK + threadIdx.x;
+    if (c >= M) return;
+    int v[4];
+    candidate_row<K>(c, up, edge_i, tri_k, tri_e, tet_t, tet_l, v);
+#pragma unroll
+    for (int u = 0; u < K; u++) v[u] = perm[v[u]];
+#pragma unroll
+    for (int a = 1; a < K; a++)
+#pragma unroll
+        for (int b = a; b > 0; b--)
+            if (v[b - 1] > v[b]) { const int t = v[b]; v[b] = v[b - 1]; v[b - 1] = t; }
+    key[c] = (unsigned)v[0];
+    if constexpr (K == 2) pay[c] = make_uint2((unsigned)v[1], (unsigned)c);
+    else if constexpr (K == 3) pay[c] = make_uint3((unsigned)v[1], (unsigned)v[2], (unsigned)c);
+    else pay[c] = make_uint4((unsigned)v[1], (unsigned)v[2], (unsigned)v[3], (unsigned)c);
 }
 
 // Number of kept rows after the sort: the first position whose key is n.
@@ -1069,6 +1160,79 @@ __global__ void __launch_bounds__(BLOCK) k_emit_rank(const unsigned *__restrict_
     out_size[s + rank] = pay_size<K>(me, size_in) / 1.0e6;  // mA^2 -> A^2
 }
 
+
+// Output order of a sweep: as k_emit_rank over every candidate, writing the
+// sorted rows to rows_s and each candidate's place to spos.
+template <int K>
+__global__ void __launch_bounds__(BLOCK) k_order_rank(const unsigned *__restrict__ key,
+                                                       const typename OrderPay<K>::type *__restrict__ pay, int m,
+                                                       int *__restrict__ rows_s, int *__restrict__ spos) {
+    typedef typename OrderPay<K>::type P;
+    constexpr int SPAN = BLOCK + 2 * RANK_HALO;
+    __shared__ unsigned sk[SPAN];
+    __shared__ P sp[SPAN];
+    const int b0 = blockIdx.x * BLOCK;
+    const int lo = b0 - RANK_HALO;
+    for (int t = threadIdx.x; t < SPAN; t += BLOCK) {
+        const int g = lo + t;
+        if (g >= 0 && g < m) {
+            sk[t] = key[g];
+            sp[t] = pay[g];
+        } else {
+            sk[t] = 0xffffffffu;
+        }
+    }
+    __syncthreads();
+    const int p = b0 + threadIdx.x;
+    if (p >= m) return;
+    const int lp = p - lo;
+    const unsigned u0 = sk[lp];
+    auto ids = [](const P &q, unsigned (&r)[3]) {
+        if constexpr (K == 2) { r[0] = q.x; r[1] = 0; r[2] = 0; }
+        else if constexpr (K == 3) { r[0] = q.x; r[1] = q.y; r[2] = 0; }
+        else { r[0] = q.x; r[1] = q.y; r[2] = q.z; }
+    };
+    const P me = sp[lp];
+    unsigned r[3];
+    ids(me, r);
+    auto key_at = [&](int g) -> unsigned { const int t = g - lo; return (t >= 0 && t < SPAN) ? sk[t] : key[g]; };
+    auto pay_at = [&](int g) -> P { const int t = g - lo; return (t >= 0 && t < SPAN) ? sp[t] : pay[g]; };
+    int s = p;
+    while (s > 0 && key_at(s - 1) == u0) s--;
+    int e = p + 1;
+    while (e < m && key_at(e) == u0) e++;
+    int rank = 0;
+    for (int w = s; w < e; w++) {
+        if (w == p) continue;
+        unsigned o[3];
+        ids(pay_at(w), o);
+        rank += o[0] != r[0] ? o[0] < r[0] : (o[1] != r[1] ? o[1] < r[1] : o[2] < r[2]);
+    }
+    const int pos = s + rank;
+    const long long q = (long long)pos * K;
+    rows_s[q] = (int)u0;
+#pragma unroll
+    for (int u = 1; u < K; u++) rows_s[q + u] = (int)r[u - 1];
+    unsigned c;
+    if constexpr (K == 2) c = me.y;
+    else if constexpr (K == 3) c = me.z;
+    else c = me.w;
+    spos[c] = pos;
+}
+
+// One alpha of a sweep, dimension K - 1: the kept rows in output order
+// (in_s, sz_s at output places; pos = exclusive scan of in_s).
+template <int K>
+__global__ void __launch_bounds__(BLOCK) k_sweep_write(const int *__restrict__ in_s, const int *__restrict__ pos,
+                                                        const int *__restrict__ rows_s, const double *__restrict__ sz_s,
+                                                        int m, int *__restrict__ out, double *__restrict__ out_size) {
+    const int p = blockIdx.x * BLOCK + threadIdx.x;
+    if (p >= m || !in_s[p]) return;
+    const int o = pos[p];
+#pragma unroll
+    for (int u = 0; u < K; u++) out[(long long)o * K + u] = rows_s[(long long)p * K + u];
+    out_size[o] = sz_s[p] / 1.0e6;  // mA^2 -> A^2
+}
 
 // Rows of a simplex array sorted by least id (K ids per row): out[j] = first
 // row whose least id is >= bound[j]; the rows of molecule m of a batch are

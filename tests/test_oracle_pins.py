@@ -253,6 +253,23 @@ def test_closure_monotonicity_and_sizes(small_mol):
             assert _as_sets(lo)[d] <= _as_sets(hi)[d]
 
 
+def test_filtration_by_size(small_mol):
+    """K_alpha is the part of K_alpha_max with Size <= alpha, Sizes unchanged
+    (Size is the least alpha at which a simplex enters, Sec. 2.4): the
+    reading the alpha sweep rests on. Checked on the 1,000-atom molecule, its
+    solvent-accessible form and the brute-force lattice sizes; none of these
+    Sizes lies within rounding of the alpha values used."""
+    cases = [(small_mol.xyz, small_mol.radii), (small_mol.with_sas().xyz, small_mol.with_sas().radii)]
+    for xyz, rad in cases:
+        top = oracle.alpha_complex(xyz, rad, 2.0)
+        for alpha in (-1.0, 0.0, 0.35, 1.0, 2.0):
+            c = oracle.alpha_complex(xyz, rad, alpha)
+            for d in range(4):
+                keep = top.sizes[d] <= alpha
+                assert np.array_equal(top.simplices[d][keep], c.simplices[d]), (alpha, d)
+                assert np.array_equal(top.sizes[d][keep], c.sizes[d]), (alpha, d)
+
+
 def test_rejects_bad_input():
     good = np.zeros((2, 3)), np.ones(2)
     with pytest.raises(oracle.OracleError) as e:
