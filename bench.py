@@ -40,7 +40,8 @@ KERNEL_OF_STAGE = {
 }
 KERNEL_SOURCES = ["paper_1908_05944_amd/csrc/kernels.hpp", "paper_1908_05944_amd/csrc/predicates.hpp",
                   "paper_1908_05944_amd/csrc/common.hpp", "paper_1908_05944_amd/csrc/radix.hpp",
-                  "paper_1908_05944_amd/csrc/measure.hpp", "paper_1908_05944_amd/csrc/alphacx.hip"]
+                  "paper_1908_05944_amd/csrc/measure.hpp", "paper_1908_05944_amd/csrc/sweep.hpp",
+                  "paper_1908_05944_amd/csrc/alphacx.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_3Mshell.json")
 
 
@@ -78,6 +79,40 @@ def _timed(torch, fn, reps):
         fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / reps
+
+
+def bench_sweep(acx, torch, log, xyz, rad, opts, reps=3):
+    """Alpha sweep on the 3M-atom shell: the complexes at alpha = 0, 0.25, ...,
+    2 A^2 from one ac_alpha_sweep_device call against one direct build per
+    value (the results are identical; the tests check that)."""
+    alphas = [0.25 * k for k in range(9)]
+
+    def sweep():
+        for c in acx.ac_alpha_sweep_device(xyz, rad, alphas, options=opts):
+            c.close()
+
+    def direct():
+        for a in alphas:
+            acx.ac_alpha_complex_device(xyz, rad, a, options=opts).close()
+
+    sweep()
+    t_sweep = _timed(torch, sweep, reps)
+    t_direct = _timed(torch, direct, reps)
+    cs = acx.ac_alpha_sweep_device(xyz, rad, [alphas[-1]], options=opts)
+    top = cs[0].counts()
+    cs[0].close()
+    log(f"[bench] sweep: {len(alphas)} alpha values in {t_sweep * 1e3:.2f} ms as one sweep, "
+        f"{t_direct * 1e3:.2f} ms as direct builds ({t_direct / t_sweep:.2f}x)")
+    return {
+        "metric": "alpha sweep ms",
+        "value": t_sweep * 1e3,
+        "unit": "ms for the whole sweep",
+        "higher_is_better": False,
+        "direct_builds_ms": t_direct * 1e3,
+        "speedup_vs_direct": t_direct / t_sweep,
+        "counts_at_alpha_max": top,
+        "config": {"workload": "3M-atom shell, alpha = 0, 0.25, ..., 2 A^2 (9 values)", "alphas": alphas},
+    }
 
 
 def bench_batch(acx, synth, torch, log, reps=5):
@@ -348,6 +383,7 @@ def main():
 
     extras = {}
     if not args.no_extras:
+        extras["alpha_sweep"] = bench_sweep(acx, torch, log, xyz, rad, opts)
         del xyz, rad
         torch.cuda.empty_cache()
         extras["batch"] = bench_batch(acx, synth, torch, log)

@@ -19,6 +19,7 @@
 #include "alphacx.h"
 #include "kernels.hpp"
 #include "measure.hpp"
+#include "sweep.hpp"
 
 using namespace acx;
 
@@ -204,6 +205,24 @@ static void scan_i32(const int *in, int *out, long long n, hipStream_t s, Scope 
     scan_i32(sums, offs, tiles, s, sc);
     k_scan_add_total<<<(unsigned)tiles, SCAN_BLOCK, 0, s>>>(out, offs, n, (int)tiles, total_to);
     LAUNCH_CHECK();
+}
+
+// Exclusive scan of in[0..n) within tiles of SCAN_TILE items: out[i] is the
+// sum over the earlier items of i's tile, and the returned array holds the
+// tiles' offsets (nullptr when n fits one block: out is then the whole
+// scan). The total goes to *total_to.
+static const int *scan_local_i32(const int *in, int *out, long long n, hipStream_t s, Scope &sc, int *total_to) {
+    if (n <= SCAN_SMALL) {
+        scan_i32(in, out, n, s, sc, total_to);
+        return nullptr;
+    }
+    const long long tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    int *sums = sc.get<int>(tiles);
+    int *offs = sc.get<int>(tiles + 1);
+    k_scan_tiles<<<(unsigned)tiles, SCAN_BLOCK, 0, s>>>(in, out, sums, n);
+    LAUNCH_CHECK();
+    scan_i32(sums, offs, tiles, s, sc, total_to);
+    return offs;
 }
 
 // Pinned host block of this thread for device-to-host read-backs (a copy to
@@ -745,16 +764,14 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             }
             tm.mark(ST_TRI_FINAL);
             if (T > 0) {
-                k_tri_final<false><<<grid_for(T), BLOCK, 0, s>>>(up_start, up, edge_i, tri_k, tri_e, T, tgab, tsize,
-                                                                tri_att, tri_min, tin, egab, edge_att, edge_min, cnt,
-                                                                nullptr, pp, nullptr, nullptr, nullptr);
+                k_tri_final<<<grid_for(T), BLOCK, 0, s>>>(up_start, up, edge_i, tri_k, tri_e, T, tgab, tsize, tri_att,
+                                                         tri_min, tin, egab, edge_att, edge_min, cnt);
                 LAUNCH_CHECK();
             }
             tm.mark(ST_EDGE_FINAL);
             if (E > 0) {
-                k_edge_final<false><<<grid_for(E), BLOCK, 0, s>>>(atom, up, edge_i, E, egab, edge_att, edge_min, ein,
-                                                                 esize, vgab, vert_att, vert_min, pp, nullptr, nullptr,
-                                                                 nullptr);
+                k_edge_final<<<grid_for(E), BLOCK, 0, s>>>(atom, up, edge_i, E, egab, edge_att, edge_min, ein, esize, vgab,
+                                                          vert_att, vert_min);
                 LAUNCH_CHECK();
             }
             tm.mark(ST_VERT_FINAL);
@@ -768,9 +785,9 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             emit_dim<4>(qin, qsize, Q, cd, n, s, sc, res, 3, &cnt->m3);
             if (n_mol > 1) mol_rows(res, cnt, d_rows, d_bound);
         } else {
-            // ---- sweep: AC2 of the tetrahedra and the output order of every
-            // candidate once; then per alpha, AC3 at that alpha, pruning and
-            // output by compaction in the fixed order ----
+            // ---- sweep: AC2 of the tetrahedra, the output order of every
+            // candidate and each candidate's AC3 threshold once; then per
+            // alpha, comparisons, pruning and compaction in output order ----
             tm.mark(ST_TETRA);
             int4 *tface = sc.get<int4>(Q > 0 ? Q : 1);
             if (Q > 0) {
@@ -779,10 +796,15 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
                                                              nullptr, qin, qsize, tface, cnt);
                 LAUNCH_CHECK();
             }
+            int2 *tedge = sc.get<int2>(T > 0 ? T : 1);
+            if (T > 0) {
+                k_tri_edges<<<grid_for(T), BLOCK, 0, s>>>(up_start, up, edge_i, tri_k, tri_e, T, tedge);
+                LAUNCH_CHECK();
+            }
             const Cands cd{up, edge_i, tri_k, tri_e, tet_t, tet_l, perm};
             const int M[4] = {n, E, T, Q};
-            int *rows_s[4] = {}, *spos[4] = {}, *in_s[4] = {}, *pos[4] = {};
-            double *sz_s[4] = {};
+            int *rows_s[4] = {}, *spos[4] = {}, *in_s[4] = {}, *pos[4] = {}, *thr[4] = {};
+            double *sz_s[4] = {}, *szp[4] = {};
             for (int d = 1; d <= 3; d++) {
                 const int m = M[d] > 0 ? M[d] : 1;
                 rows_s[d] = sc.get<int>((size_t)m * (d + 1));
@@ -790,10 +812,30 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
                 in_s[d] = sc.get<int>(m);
                 pos[d] = sc.get<int>((size_t)m + 1);
                 sz_s[d] = sc.get<double>(m);
+                thr[d] = sc.get<int>(m);
+                szp[d] = sc.get<double>(m);
             }
+            int2 *ends = sc.get<int2>(E > 0 ? E : 1);
+            int4 *face2 = sc.get<int4>(T > 0 ? T : 1);
+            int4 *face3 = sc.get<int4>(Q > 0 ? Q : 1);
             order_dim<2>(E, cd, n, s, sc, rows_s[1], spos[1]);
             order_dim<3>(T, cd, n, s, sc, rows_s[2], spos[2]);
             order_dim<4>(Q, cd, n, s, sc, rows_s[3], spos[3]);
+            if (E > 0) {
+                k_sweep_prep_edge<<<grid_for(E), BLOCK, 0, s>>>(atom, up, edge_i, E, egab, spos[1], aq, thr[1], szp[1],
+                                                               ends);
+                LAUNCH_CHECK();
+            }
+            if (T > 0) {
+                k_sweep_prep_tri<<<grid_for(T), BLOCK, 0, s>>>(atom, up, edge_i, tri_k, tri_e, T, tgab, tsize, tedge,
+                                                              spos[2], spos[1], pp, thr[2], szp[2], face2, cnt);
+                LAUNCH_CHECK();
+            }
+            if (Q > 0) {
+                k_sweep_prep_tet<<<grid_for(Q), BLOCK, 0, s>>>(atom, up, edge_i, tri_k, tri_e, tet_t, tet_l, Q, qin, qsize,
+                                                              tface, spos[3], spos[2], pp, thr[3], szp[3], face3, cnt);
+                LAUNCH_CHECK();
+            }
             tm.mark(ST_EMIT);
             for (int k = 0; k < n_alpha; k++) {
                 PredParams pa = pp;
@@ -801,21 +843,18 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
                 ac_complex *r = rs[k];
                 prune_init();
                 if (Q > 0) {
-                    k_sweep_tet<<<grid_for(Q), BLOCK, 0, s>>>(atom, up, edge_i, tri_k, tri_e, tet_t, tet_l, Q, pa, qin,
-                                                             qsize, tface, spos[3], tgab, tri_att, tri_min, in_s[3],
-                                                             sz_s[3], cnt);
+                    k_sweep_tets<<<grid_for(Q), BLOCK, 0, s>>>(Q, pa.aq, thr[3], szp[3], face3, thr[2], tri_att, tri_min,
+                                                              in_s[3], sz_s[3], cnt);
                     LAUNCH_CHECK();
                 }
                 if (T > 0) {
-                    k_tri_final<true><<<grid_for(T), BLOCK, 0, s>>>(up_start, up, edge_i, tri_k, tri_e, T, tgab, tsize,
-                                                                   tri_att, tri_min, nullptr, egab, edge_att, edge_min,
-                                                                   cnt, atom, pa, spos[2], in_s[2], sz_s[2]);
+                    k_sweep_tris<<<grid_for(T), BLOCK, 0, s>>>(T, pa.aq, thr[2], szp[2], face2, tri_att, tri_min, thr[1],
+                                                              edge_att, edge_min, in_s[2], sz_s[2], cnt);
                     LAUNCH_CHECK();
                 }
                 if (E > 0) {
-                    k_edge_final<true><<<grid_for(E), BLOCK, 0, s>>>(atom, up, edge_i, E, egab, edge_att, edge_min,
-                                                                    nullptr, nullptr, vgab, vert_att, vert_min, pa,
-                                                                    spos[1], in_s[1], sz_s[1]);
+                    k_sweep_edges<<<grid_for(E), BLOCK, 0, s>>>(E, pa.aq, thr[1], szp[1], ends, edge_att, edge_min, vgab,
+                                                               vert_att, vert_min, in_s[1], sz_s[1]);
                     LAUNCH_CHECK();
                 }
                 vert_final(pa);
@@ -825,16 +864,16 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
                     const int K = d + 1;
                     r->d_simp[d] = static_cast<int32_t *>(dev_alloc((size_t)(M[d] > 0 ? M[d] : 1) * K * sizeof(int32_t)));
                     r->d_size[d] = static_cast<double *>(dev_alloc((size_t)(M[d] > 0 ? M[d] : 1) * sizeof(double)));
-                    scan_i32(in_s[d], pos[d], M[d], s, sc, m_out[d]);
+                    const int *toff = scan_local_i32(in_s[d], pos[d], M[d], s, sc, m_out[d]);
                     if (M[d] == 0) continue;
                     if (d == 1)
-                        k_sweep_write<2><<<grid_for(M[d]), BLOCK, 0, s>>>(in_s[d], pos[d], rows_s[d], sz_s[d], M[d],
+                        k_sweep_write<2><<<grid_for(M[d]), BLOCK, 0, s>>>(in_s[d], pos[d], toff, rows_s[d], sz_s[d], M[d],
                                                                          r->d_simp[d], r->d_size[d]);
                     else if (d == 2)
-                        k_sweep_write<3><<<grid_for(M[d]), BLOCK, 0, s>>>(in_s[d], pos[d], rows_s[d], sz_s[d], M[d],
+                        k_sweep_write<3><<<grid_for(M[d]), BLOCK, 0, s>>>(in_s[d], pos[d], toff, rows_s[d], sz_s[d], M[d],
                                                                          r->d_simp[d], r->d_size[d]);
                     else
-                        k_sweep_write<4><<<grid_for(M[d]), BLOCK, 0, s>>>(in_s[d], pos[d], rows_s[d], sz_s[d], M[d],
+                        k_sweep_write<4><<<grid_for(M[d]), BLOCK, 0, s>>>(in_s[d], pos[d], toff, rows_s[d], sz_s[d], M[d],
                                                                          r->d_simp[d], r->d_size[d]);
                     LAUNCH_CHECK();
                 }

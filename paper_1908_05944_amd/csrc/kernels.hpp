@@ -834,48 +834,9 @@ __global__ void __launch_bounds__(BLOCK) k_tet_ac2(const int4 *__restrict__ atom
     mark_face(tgab, tri_att, tri_min, f3, key, cnt);
 }
 
-// One alpha of a sweep, tetrahedra: kept iff AC2 (from k_tet_ac2<true>) and
-// AC3 at this alpha; in and Size go to the row's place in the output order.
-__global__ void __launch_bounds__(BLOCK) k_sweep_tet(const int4 *__restrict__ atom, const int *__restrict__ up,
-                                                      const int *__restrict__ edge_i, const int *__restrict__ tri_k,
-                                                      const int *__restrict__ tri_e, const int *__restrict__ tet_t,
-                                                      const int *__restrict__ tet_l, int Q, PredParams pp,
-                                                      const unsigned char *__restrict__ qgab,
-                                                      const double *__restrict__ qsize,
-                                                      const int4 *__restrict__ tface, const int *__restrict__ spos,
-                                                      const unsigned char *__restrict__ tgab, int *__restrict__ tri_att,
-                                                      long long *__restrict__ tri_min, int *__restrict__ in_s,
-                                                      double *__restrict__ sz_s, Counters *cnt) {
-    const int c = xcd_block() * BLOCK + threadIdx.x;
-    if (c >= Q) return;
-    const int o = spos[c];
-    bool keep = qgab[c];
-    if (keep) {
-        const int t = tet_t[c], l = tet_l[c];
-        const int e = tri_e[t];
-        const Tet te = tet_setup(atom[edge_i[e]], atom[up[e]], atom[tri_k[t]], atom[l], pp);
-        keep = tet_ac3(te, pp, cnt);
-    }
-    in_s[o] = keep;
-    if (!keep) return;
-    const double sz = qsize[c];
-    sz_s[o] = sz;
-    const long long key = ordered_from_double(sz);
-    const int4 f = tface[c];
-    mark_face(tgab, tri_att, tri_min, f.x, key, cnt);
-    mark_face(tgab, tri_att, tri_min, f.y, key, cnt);
-    mark_face(tgab, tri_att, tri_min, f.z, key, cnt);
-    mark_face(tgab, tri_att, tri_min, f.w, key, cnt);
-}
-
 // Triangles (Step 3): kept iff AC2 holds at the ortho-centre or a kept
 // tetrahedron has it as a facet; Size is then the OrthoSize or the least Size
 // of a kept tetrahedron. Kept triangles record themselves on their edges.
-// SWEEP (one alpha of a sweep over candidates of a larger alpha): AC2 alone
-// keeps a triangle only with AC3 at this alpha (a facet of a kept
-// tetrahedron has it already); in and Size go to the row's place spos[t] in
-// the output order, and tsize is left as it is.
-template <bool SWEEP>
 __global__ void __launch_bounds__(BLOCK) k_tri_final(const int *__restrict__ up_start, const int *__restrict__ up,
                                                       const int *__restrict__ edge_i, const int *__restrict__ tri_k,
                                                       const int *__restrict__ tri_e, int T,
@@ -884,34 +845,39 @@ __global__ void __launch_bounds__(BLOCK) k_tri_final(const int *__restrict__ up_
                                                       const long long *__restrict__ tri_min,
                                                       unsigned char *__restrict__ tin,
                                                       const unsigned char *__restrict__ egab, int *__restrict__ edge_att,
-                                                      long long *__restrict__ edge_min, Counters *cnt,
-                                                      const int4 *__restrict__ atom, PredParams pp,
-                                                      const int *__restrict__ spos, int *__restrict__ in_s,
-                                                      double *__restrict__ sz_s) {
+                                                      long long *__restrict__ edge_min, Counters *cnt) {
     const int t = xcd_block() * BLOCK + threadIdx.x;
     if (t >= T) return;
-    const int e = tri_e[t];
-    const int i = edge_i[e], j = up[e], k = tri_k[t];
-    bool gab = tgab[t];
-    if (SWEEP && gab) gab = tri_candidate(atom[i], atom[j], atom[k], pp, cnt);
+    const bool gab = tgab[t];
     const bool in = gab || tri_att[t];
-    if (SWEEP) in_s[spos[t]] = in; else tin[t] = (unsigned char)in;
+    tin[t] = (unsigned char)in;
     if (!in) return;
     double sz = tsize[t];
     if (!gab) {
         sz = double_from_ordered(tri_min[t]);
-        if (!SWEEP) tsize[t] = sz;
+        tsize[t] = sz;
     }
-    if (SWEEP) sz_s[spos[t]] = sz;
+    const int e = tri_e[t];
+    const int i = edge_i[e], j = up[e], k = tri_k[t];
     const long long key = ordered_from_double(sz);
     mark_face(egab, edge_att, edge_min, e, key, cnt);
     mark_face(egab, edge_att, edge_min, find_edge(up_start, up, i, k), key, cnt);
     mark_face(egab, edge_att, edge_min, find_edge(up_start, up, j, k), key, cnt);
 }
 
-// Edges (Step 4). SWEEP as for triangles: AC2 alone keeps an edge only with
-// AC3 at this alpha; in and Size go to the row's place spos[e].
-template <bool SWEEP>
+// Edge ids (i, k) and (j, k) of every candidate triangle (i, j, k), once per
+// sweep.
+__global__ void __launch_bounds__(BLOCK) k_tri_edges(const int *__restrict__ up_start, const int *__restrict__ up,
+                                                      const int *__restrict__ edge_i, const int *__restrict__ tri_k,
+                                                      const int *__restrict__ tri_e, int T, int2 *__restrict__ tedge) {
+    const int t = xcd_block() * BLOCK + threadIdx.x;
+    if (t >= T) return;
+    const int e = tri_e[t];
+    const int i = edge_i[e], j = up[e], k = tri_k[t];
+    tedge[t] = make_int2(find_edge(up_start, up, i, k), find_edge(up_start, up, j, k));
+}
+
+// Edges (Step 4).
 __global__ void __launch_bounds__(BLOCK) k_edge_final(const int4 *__restrict__ atom, const int *__restrict__ up,
                                                        const int *__restrict__ edge_i, int E,
                                                        const unsigned char *__restrict__ egab,
@@ -919,19 +885,16 @@ __global__ void __launch_bounds__(BLOCK) k_edge_final(const int4 *__restrict__ a
                                                        const long long *__restrict__ edge_min,
                                                        unsigned char *__restrict__ ein, double *__restrict__ esize,
                                                        const unsigned char *__restrict__ vgab,
-                                                       int *__restrict__ vert_att, long long *__restrict__ vert_min,
-                                                       PredParams pp, const int *__restrict__ spos,
-                                                       int *__restrict__ in_s, double *__restrict__ sz_s) {
+                                                       int *__restrict__ vert_att, long long *__restrict__ vert_min) {
     const int e = xcd_block() * BLOCK + threadIdx.x;
     if (e >= E) return;
-    const int i = edge_i[e], j = up[e];
-    bool gab = egab[e];
-    if (SWEEP && gab) gab = edge_ac3(edge_setup(atom[i], atom[j]), pp.aq);
+    const bool gab = egab[e];
     const bool in = gab || edge_att[e];
-    if (SWEEP) in_s[spos[e]] = in; else ein[e] = (unsigned char)in;
+    ein[e] = (unsigned char)in;
     if (!in) return;
+    const int i = edge_i[e], j = up[e];
     const double sz = gab ? edge_size_canon(atom[i], atom[j]) : double_from_ordered(edge_min[e]);
-    if (SWEEP) sz_s[spos[e]] = sz; else esize[e] = sz;
+    esize[e] = sz;
     const long long key = ordered_from_double(sz);
     if (!vgab[i]) { atomicOr(&vert_att[i], 1); atomicMin(&vert_min[i], key); }
     if (!vgab[j]) { atomicOr(&vert_att[j], 1); atomicMin(&vert_min[j], key); }
@@ -1218,20 +1181,6 @@ __global__ void __launch_bounds__(BLOCK) k_order_rank(const unsigned *__restrict
     else if constexpr (K == 3) c = me.z;
     else c = me.w;
     spos[c] = pos;
-}
-
-// One alpha of a sweep, dimension K - 1: the kept rows in output order
-// (in_s, sz_s at output places; pos = exclusive scan of in_s).
-template <int K>
-__global__ void __launch_bounds__(BLOCK) k_sweep_write(const int *__restrict__ in_s, const int *__restrict__ pos,
-                                                        const int *__restrict__ rows_s, const double *__restrict__ sz_s,
-                                                        int m, int *__restrict__ out, double *__restrict__ out_size) {
-    const int p = blockIdx.x * BLOCK + threadIdx.x;
-    if (p >= m || !in_s[p]) return;
-    const int o = pos[p];
-#pragma unroll
-    for (int u = 0; u < K; u++) out[(long long)o * K + u] = rows_s[(long long)p * K + u];
-    out_size[o] = sz_s[p] / 1.0e6;  // mA^2 -> A^2
 }
 
 // Rows of a simplex array sorted by least id (K ids per row): out[j] = first
