@@ -115,6 +115,66 @@ def bench_sweep(acx, torch, log, xyz, rad, opts, reps=3):
     }
 
 
+# Table 2 of the paper splits a build into eight categories; the stages of
+# this pipeline fall into them as follows (edge AC2 runs inside the triangle
+# pass and triangle AC2 inside the tetrahedron pass, so those two AC2 steps
+# are counted with the passes that hold them). "output" (sorting the result
+# by input ids) has no category of its own there.
+TABLE2_CATEGORIES = {
+    "grid": ["quantise", "binning"],
+    "potential_edges": ["neighbours_count", "neighbours_scan", "neighbours_fill"],
+    "potential_triangles": ["triangles_count", "triangles_scan", "triangles_fill"],
+    "potential_tetrahedra": ["triangles_ac2_tetrahedra", "tetrahedra_scan", "tetrahedra_fill"],
+    "ac2_tetrahedra": ["tetrahedra_ac2"],
+    "ac2_triangles": ["triangles_final"],
+    "ac2_edges_vertices": ["edges_final", "vertices_final"],
+    "output": ["emit"],
+}
+
+
+def bench_table2(acx, synth, torch, log, reps=5):
+    """Per-stage split in the categories of the paper's Table 2 on synthetic
+    molecules of the sizes of its PDB molecules (seeds 500 + k), alpha = 0, 1
+    and 2 A^2. Stage times are HIP events of profiled builds (median of
+    `reps`); "memory" is the host-array call minus the device-array call
+    (inputs up, every result array down)."""
+    import numpy as np
+    sizes = [260, 1505, 1509, 4384, 8142, 16068, 16647, 58674]
+    rows = []
+    for k, n in enumerate(sizes):
+        m = synth.molecule(n, 500 + k)
+        X = torch.from_numpy(m.xyz).cuda()
+        R = torch.from_numpy(m.radii).cuda()
+        for alpha in (0.0, 1.0, 2.0):
+            acx.ac_alpha_complex_device(X, R, alpha).close()
+            stages = []
+            for _ in range(reps):
+                c = acx.ac_alpha_complex_device(X, R, alpha, options={"profile": 1})
+                stages.append(c.stage_ms())
+                counts = c.counts()
+                c.close()
+            t_dev = _timed(torch, lambda: acx.ac_alpha_complex_device(X, R, alpha).close(), reps)
+            t_host = _timed(torch, lambda: acx.ac_alpha_complex(m.xyz, m.radii, alpha).close(), reps)
+            med = {key: float(np.median([st[key] for st in stages])) for key in stages[0]}
+            cat = {name: sum(med[x] for x in parts) for name, parts in TABLE2_CATEGORIES.items()}
+            cat["memory"] = max(t_host - t_dev, 0.0) * 1e3
+            rows.append({"atoms": n, "alpha": alpha, "simplices": sum(counts), "device_ms": t_dev * 1e3,
+                         "ms": {key: round(v, 4) for key, v in cat.items()}})
+    est = ["potential_edges", "potential_triangles", "potential_tetrahedra"]
+    pru = ["ac2_tetrahedra", "ac2_triangles", "ac2_edges_vertices"]
+    share = {}
+    for name, parts in (("memory_grid", ["memory", "grid"]), ("estimation", est), ("pruning", pru),
+                        ("ac2_tetrahedra", ["ac2_tetrahedra"]), ("output", ["output"])):
+        share[name] = float(np.mean([sum(r["ms"][x] for x in parts) / sum(r["ms"].values()) for r in rows]))
+    for r in rows:
+        log(f"[bench] table2: {r['atoms']:6d} atoms alpha {r['alpha']:.1f}: {r['device_ms']:.3f} ms device, "
+            + ", ".join(f"{key} {v:.3f}" for key, v in r["ms"].items()))
+    log("[bench] table2 mean shares: " + ", ".join(f"{key} {v:.2f}" for key, v in share.items()))
+    return {"rows": rows, "mean_share": share,
+            "config": {"workload": "synthetic molecules of the paper's Table 1-2 sizes, alpha = 0, 1, 2 A^2",
+                       "categories": TABLE2_CATEGORIES}}
+
+
 def bench_batch(acx, synth, torch, log, reps=5):
     """512 molecules, sizes log-uniform in [500, 50000] atoms (seed 999), one
     batched call against 512 sequential single-molecule calls."""
@@ -388,6 +448,7 @@ def main():
         torch.cuda.empty_cache()
         extras["batch"] = bench_batch(acx, synth, torch, log)
         extras["union_measure"] = bench_union(acx, synth, torch, log)
+        extras["table2_split"] = bench_table2(acx, synth, torch, log)
 
     out = {
         "metric": "alpha-complex atoms/s at 3M atoms",
