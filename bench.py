@@ -27,8 +27,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 
 KERNEL_OF_STAGE = {
-    "neighbours_count": "k_neighbours<0>",
-    "neighbours_fill": "k_nbr_compact",
+    "neighbours_count": "k_neighbours<0, 16>",
+    "neighbours_fill": "k_nbr_compact<16>",
     "triangles_count": "k_triangles<0>",
     "triangles_fill": "k_tri_compact",
     "triangles_ac2_tetrahedra": "k_tet_candidates<0>",

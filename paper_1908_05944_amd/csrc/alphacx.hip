@@ -561,14 +561,24 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         int *nbr_start = sc.get<int>(n + 1), *up_start = sc.get<int>(n + 1);
         unsigned char *vgab = sc.get<unsigned char>(n);
         const unsigned nbN = grid_for(n);
-        int *nslab = sc.get<int>((size_t)nbN * NB_SLAB);
+        // slot per ball: wide for grown radii between 1.9 and 2.6 A (alpha > 0
+        // with van der Waals radii), where rows outgrow 16 entries; beyond,
+        // rows outgrow 32 too and the counted fill runs anyway
+        const int slot = (pp.sgc > 1900 && pp.sgc <= 2600) ? NB_SLOT_WIDE : NB_SLOT;
+        const long long nb_slab = (long long)BLOCK * slot;
+        int *nslab = sc.get<int>((size_t)nbN * nb_slab);
         unsigned *upmask = sc.get<unsigned>(n);
         int *nbtot = sc.get<int>(2 * (size_t)nbN);
         int *nboff = sc.get<int>(nbN + 1), *uboff = sc.get<int>(nbN + 1);
         tm.mark(ST_NBR_COUNT);
-        k_neighbours<NB_ONEPASS><<<nbN, BLOCK, 0, s>>>(atom, perm, n, d_grids, n_mol, cell_start, pp, deg_n, deg_up,
-                                                      upmask, nslab, nbtot, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                                      vgab, cnt);
+        if (slot == NB_SLOT_WIDE)
+            k_neighbours<NB_ONEPASS, NB_SLOT_WIDE><<<nbN, BLOCK, 0, s>>>(atom, perm, n, d_grids, n_mol, cell_start, pp,
+                                                                        deg_n, deg_up, upmask, nslab, nbtot, nullptr,
+                                                                        nullptr, nullptr, nullptr, nullptr, vgab, cnt);
+        else
+            k_neighbours<NB_ONEPASS, NB_SLOT><<<nbN, BLOCK, 0, s>>>(atom, perm, n, d_grids, n_mol, cell_start, pp, deg_n,
+                                                                   deg_up, upmask, nslab, nbtot, nullptr, nullptr,
+                                                                   nullptr, nullptr, nullptr, vgab, cnt);
         LAUNCH_CHECK();
         tm.mark(ST_NBR_SCAN);
         scan_i32(nbtot, nboff, nbN, s, sc, &cnt->Nn);
@@ -577,7 +587,7 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         Counters c0 = read_one(cnt, s);
         if (c0.dup) throw HipError{AC_E_DUPLICATE, "two balls have equal quantised centres"};
         const bool nbr_two_pass = c0.overflow != 0;
-        if (nbr_two_pass || (long long)nbN * NB_SLAB >= (long long)INT_MAX) {
+        if (nbr_two_pass || (long long)nbN * nb_slab >= (long long)INT_MAX) {
             // past this size the slab bound no longer keeps the total in 32 bits
             check_total(total_i64(deg_n, n, s, sc), "neighbour entries");
         }
@@ -593,12 +603,16 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         int *edge_i = sc.get<int>(E > 0 ? E : 1);
         tm.mark(ST_NBR_FILL);
         if (!nbr_two_pass) {
-            k_nbr_compact<<<nbN, BLOCK, 0, s>>>(deg_n, deg_up, upmask, n, nslab, nboff, uboff, nbr_start, up_start, nbr,
-                                               up, edge_i);
+            if (slot == NB_SLOT_WIDE)
+                k_nbr_compact<NB_SLOT_WIDE><<<nbN, BLOCK, 0, s>>>(deg_n, deg_up, upmask, n, nslab, nboff, uboff,
+                                                                 nbr_start, up_start, nbr, up, edge_i);
+            else
+                k_nbr_compact<NB_SLOT><<<nbN, BLOCK, 0, s>>>(deg_n, deg_up, upmask, n, nslab, nboff, uboff, nbr_start,
+                                                            up_start, nbr, up, edge_i);
         } else {
-            k_neighbours<NB_FILL><<<nbN, BLOCK, 0, s>>>(atom, perm, n, d_grids, n_mol, cell_start, pp, nullptr, nullptr,
-                                                       nullptr, nullptr, nullptr, nbr_start, up_start, nbr, up, edge_i,
-                                                       vgab, cnt);
+            k_neighbours<NB_FILL, NB_SLOT><<<nbN, BLOCK, 0, s>>>(atom, perm, n, d_grids, n_mol, cell_start, pp, nullptr,
+                                                                nullptr, nullptr, nullptr, nullptr, nbr_start, up_start,
+                                                                nbr, up, edge_i, vgab, cnt);
         }
         LAUNCH_CHECK();
         const int *nbr_cnt = deg_n;

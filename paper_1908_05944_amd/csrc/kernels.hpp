@@ -238,20 +238,21 @@ __global__ void __launch_bounds__(BLOCK) k_dup_check(const int4 *__restrict__ at
 // pass also decides AC2 for the ball as a vertex (Step 5): every ball that
 // could be strictly closer in power to its centre is in its neighbour list.
 // MODE: NB_ONEPASS writes each ball's neighbour row into an LDS slot of
-// NB_SLOT entries and marks in a 32-bit mask which of them are upper
+// SLOT entries and marks in a 32-bit mask which of them are upper
 // candidate edges (the upper row is a filtered part of the neighbour row);
 // the block packs the rows into a slab of its own, and k_nbr_compact writes
 // both rows into place once the block totals are scanned. Exact counts are
-// kept; a ball with more than NB_SLOT neighbours sets cnt->overflow, after
+// kept; a ball with more than SLOT neighbours sets cnt->overflow, after
 // which the host runs NB_FILL over the scanned counts instead (same result).
 // NB_FILL writes the rows into the CSR rows the counts sized (each thread's
 // row contiguous, consecutive rows adjacent).
 enum { NB_ONEPASS = 0, NB_FILL = 1 };
-constexpr int NB_SLOT = 16;  // the largest degree of the van der Waals workloads is 14
-constexpr int NB_SLAB = BLOCK * NB_SLOT;
-static_assert(NB_SLOT <= 32, "one mask bit per slot entry");
+// Slot sizes: 16 holds every row of the van der Waals workloads at alpha = 0
+// (largest degree 14); 32 serves grown radii up to about 2.6 A.
+constexpr int NB_SLOT = 16;
+constexpr int NB_SLOT_WIDE = 32;
 
-template <int MODE>
+template <int MODE, int SLOT>
 __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ atom, const int *__restrict__ perm, int n,
                                                        const Grid *__restrict__ grids, int n_mol,
                                                        const int *__restrict__ cell_start, PredParams pp,
@@ -262,6 +263,8 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
                                                        int *__restrict__ nbr, int *__restrict__ up,
                                                        int *__restrict__ edge_i, unsigned char *__restrict__ vgab,
                                                        Counters *cnt) {
+    static_assert(SLOT <= 32, "one mask bit per slot entry");
+    constexpr int NB_SLAB = BLOCK * SLOT;
     constexpr bool ONE = MODE == NB_ONEPASS;
     // NB_FILL stages the block's rows in LDS and writes them out as one
     // contiguous range (the block's rows are adjacent in the CSR arrays);
@@ -293,7 +296,7 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
         constexpr int RS = ONE ? BLOCK : 1;
         int *const rn = ONE ? sn + threadIdx.x : (staged ? sn + (nbr_start[i] - bn) : nbr + nbr_start[i]);
         int *const ru = ONE ? nullptr : (staged ? su + (up_start[i] - bu) : up + up_start[i]);
-        const int capn = ONE ? NB_SLOT : INT_MAX;
+        const int capn = ONE ? SLOT : INT_MAX;
         const Grid g = grids[mol_of(grids, n_mol, i)];
         const int cx = (a.x - g.ox) / g.s, cy = (a.y - g.oy) / g.s, cz = (a.z - g.oz) / g.s;
         const int x0 = max(cx - g.reach, 0), x1 = min(cx + g.reach, g.nx - 1);
@@ -377,8 +380,8 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
             deg_up[i] = cu;
             upmask[i] = mask;
         }
-        if (cn > NB_SLOT) cnt->overflow = 1;
-        const int kn = min(cn, NB_SLOT);
+        if (cn > SLOT) cnt->overflow = 1;
+        const int kn = min(cn, SLOT);
         int totn, totu;
         const int offn = block_exclusive_scan<BLOCK>(kn, &totn);
         (void)block_exclusive_scan<BLOCK>(cu, &totu);
@@ -415,6 +418,7 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
 // (noff / uoff: exclusive scans of the blocks' neighbour and upper entry
 // totals): each neighbour row, the entries of it that the mask marks as the
 // upper row, the row starts and the owner of every upper entry.
+template <int SLOT>
 __global__ void __launch_bounds__(BLOCK) k_nbr_compact(const int *__restrict__ deg_n, const int *__restrict__ deg_up,
                                                         const unsigned *__restrict__ upmask, int n,
                                                         const int *__restrict__ nslab, const int *__restrict__ noff,
@@ -428,7 +432,7 @@ __global__ void __launch_bounds__(BLOCK) k_nbr_compact(const int *__restrict__ d
     const int offn = block_exclusive_scan<BLOCK>(cn, &totn);
     const int offu = block_exclusive_scan<BLOCK>(cu, &totu);
     const int gn = noff[b], gu = uoff[b];
-    const int *src = nslab + (long long)b * NB_SLAB;
+    const int *src = nslab + (long long)b * (BLOCK * SLOT);
     // neighbour rows: the block's packed slab, copied with coalesced accesses
     for (int k = threadIdx.x; k < totn; k += BLOCK) nbr[gn + k] = src[k];
     if (i >= n) return;
