@@ -19,8 +19,8 @@ def declared_functions():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for must in ("ac_alpha_complex", "ac_alpha_complex_device", "ac_count", "ac_simplices", "ac_sizes",
-                 "ac_free", "ac_status_str", "ac_last_error"):
+    for must in ("ac_alpha_complex", "ac_alpha_complex_device", "ac_alpha_sweep_device", "ac_count", "ac_simplices",
+                 "ac_sizes", "ac_free", "ac_status_str", "ac_last_error"):
         assert must in names
 
 
@@ -40,3 +40,18 @@ def test_status_strings_without_device():
         assert lib.ac_status_str(st)
     assert lib.ac_count(None, 0) == -1
     assert lib.ac_count(None, 9) == -1
+
+
+def test_sweep_argument_checks_without_device():
+    """Argument errors of the sweep are reported before any device work."""
+    import paper_1908_05944_amd as acx
+    lib = acx.library()
+    outs = (ctypes.c_void_p * 4)()
+    alphas = (ctypes.c_double * 4)(0.0, 1.0, 2.0, 3.0)
+    # no value, too many values, NULL inputs, NULL output array
+    assert lib.ac_alpha_sweep_device(None, None, 10, alphas, 0, None, None, outs) == 1
+    assert lib.ac_alpha_sweep_device(None, None, 10, alphas, 1025, None, None, outs) == 1
+    assert lib.ac_alpha_sweep_device(None, None, 10, alphas, 4, None, None, outs) == 1
+    assert all(h is None for h in outs)
+    assert lib.ac_alpha_sweep_device(None, None, 10, alphas, 4, None, None, None) == 1
+    assert b"NULL" in lib.ac_last_error() or b"null" in lib.ac_last_error().lower()
