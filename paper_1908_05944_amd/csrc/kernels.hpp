@@ -1106,19 +1106,28 @@ __global__ void __launch_bounds__(BLOCK) k_emit_rank(const unsigned *__restrict_
     const P me = sp[lp];
     unsigned r[3];
     pay_ids<K>(me, r);
-    auto key_at = [&](int g) -> unsigned { const int t = g - lo; return (t >= 0 && t < SPAN) ? sk[t] : key[g]; };
-    auto pay_at = [&](int g) -> P { const int t = g - lo; return (t >= 0 && t < SPAN) ? sp[t] : pay[g]; };
-    int s = p;
-    while (s > 0 && key_at(s - 1) == u0) s--;
-    int e = p + 1;
-    while (e < m && key_at(e) == u0) e++;
-    int rank = 0;
-    for (int w = s; w < e; w++) {
-        if (w == p) continue;
+    auto before = [&](const P &x) -> int {
         unsigned o[3];
-        pay_ids<K>(pay_at(w), o);
-        const bool less = o[0] != r[0] ? o[0] < r[0] : (o[1] != r[1] ? o[1] < r[1] : o[2] < r[2]);
-        rank += less;
+        pay_ids<K>(x, o);
+        return o[0] != r[0] ? o[0] < r[0] : (o[1] != r[1] ? o[1] < r[1] : o[2] < r[2]);
+    };
+    // the bucket inside the staged span (positions outside [0, m) hold a key
+    // no id has); a bucket reaching an end of the span is walked in global
+    // memory instead
+    int ls = lp;
+    while (ls > 0 && sk[ls - 1] == u0) ls--;
+    int le = lp + 1;
+    while (le < SPAN && sk[le] == u0) le++;
+    int s, rank = 0;
+    if ((ls > 0 || lo + ls == 0) && (le < SPAN || lo + le == m)) {
+        s = lo + ls;
+        for (int w = ls; w < le; w++) rank += (w != lp) && before(sp[w]);
+    } else {
+        s = p;
+        while (s > 0 && key[s - 1] == u0) s--;
+        int e = p + 1;
+        while (e < m && key[e] == u0) e++;
+        for (int w = s; w < e; w++) rank += (w != p) && before(pay[w]);
     }
     const long long q = (long long)(s + rank) * K;
     out[q] = (int)u0;
@@ -1162,18 +1171,26 @@ __global__ void __launch_bounds__(BLOCK) k_order_rank(const unsigned *__restrict
     const P me = sp[lp];
     unsigned r[3];
     ids(me, r);
-    auto key_at = [&](int g) -> unsigned { const int t = g - lo; return (t >= 0 && t < SPAN) ? sk[t] : key[g]; };
-    auto pay_at = [&](int g) -> P { const int t = g - lo; return (t >= 0 && t < SPAN) ? sp[t] : pay[g]; };
-    int s = p;
-    while (s > 0 && key_at(s - 1) == u0) s--;
-    int e = p + 1;
-    while (e < m && key_at(e) == u0) e++;
-    int rank = 0;
-    for (int w = s; w < e; w++) {
-        if (w == p) continue;
+    auto before = [&](const P &x) -> int {
         unsigned o[3];
-        ids(pay_at(w), o);
-        rank += o[0] != r[0] ? o[0] < r[0] : (o[1] != r[1] ? o[1] < r[1] : o[2] < r[2]);
+        ids(x, o);
+        return o[0] != r[0] ? o[0] < r[0] : (o[1] != r[1] ? o[1] < r[1] : o[2] < r[2]);
+    };
+    // the bucket inside the staged span, else walked in global memory
+    int ls = lp;
+    while (ls > 0 && sk[ls - 1] == u0) ls--;
+    int le = lp + 1;
+    while (le < SPAN && sk[le] == u0) le++;
+    int s, rank = 0;
+    if ((ls > 0 || lo + ls == 0) && (le < SPAN || lo + le == m)) {
+        s = lo + ls;
+        for (int w = ls; w < le; w++) rank += (w != lp) && before(sp[w]);
+    } else {
+        s = p;
+        while (s > 0 && key[s - 1] == u0) s--;
+        int e = p + 1;
+        while (e < m && key[e] == u0) e++;
+        for (int w = s; w < e; w++) rank += (w != p) && before(pay[w]);
     }
     const int pos = s + rank;
     const long long q = (long long)pos * K;
