@@ -270,6 +270,31 @@ def test_filtration_by_size(small_mol):
                 assert np.array_equal(top.sizes[d][keep], c.sizes[d]), (alpha, d)
 
 
+def test_locality_of_regions():
+    """Membership and Size of a simplex depend only on balls within a few
+    grown radii of its vertices (AC2 violators meet its ortho-centre; its
+    cofaces and their violators lie within 4 s_g): the oracle on the balls
+    within 12 A of a cube of half-width 8 A agrees with the oracle on all
+    100,000 balls on every simplex inside the cube. The full-size GPU test
+    relies on this."""
+    m = synth.config_100k()
+    full = oracle.alpha_complex(m.xyz, m.radii, 0.0)
+    rng = np.random.RandomState(7)
+    for ca in rng.choice(m.n, 4, replace=False):
+        dist = np.abs(m.xyz - m.xyz[ca]).max(axis=1)
+        sel = np.nonzero(dist <= 20.0)[0]
+        inner = dist <= 8.0
+        part = oracle.alpha_complex(m.xyz[sel], m.radii[sel], 0.0)
+        for d in range(4):
+            g = full.simplices[d].astype(np.int64)
+            keep = np.all(inner[g], axis=1)
+            w = sel[part.simplices[d]]
+            wk = np.all(inner[w], axis=1)
+            assert keep.sum() > 0 or d == 3
+            assert np.array_equal(g[keep], w[wk]), (ca, d)
+            assert np.array_equal(full.sizes[d][keep], part.sizes[d][wk]), (ca, d)
+
+
 def test_rejects_bad_input():
     good = np.zeros((2, 3)), np.ones(2)
     with pytest.raises(oracle.OracleError) as e:
