@@ -207,24 +207,6 @@ static void scan_i32(const int *in, int *out, long long n, hipStream_t s, Scope 
     LAUNCH_CHECK();
 }
 
-// Exclusive scan of in[0..n) within tiles of SCAN_TILE items: out[i] is the
-// sum over the earlier items of i's tile, and the returned array holds the
-// tiles' offsets (nullptr when n fits one block: out is then the whole
-// scan). The total goes to *total_to.
-static const int *scan_local_i32(const int *in, int *out, long long n, hipStream_t s, Scope &sc, int *total_to) {
-    if (n <= SCAN_SMALL) {
-        scan_i32(in, out, n, s, sc, total_to);
-        return nullptr;
-    }
-    const long long tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
-    int *sums = sc.get<int>(tiles);
-    int *offs = sc.get<int>(tiles + 1);
-    k_scan_tiles<<<(unsigned)tiles, SCAN_BLOCK, 0, s>>>(in, out, sums, n);
-    LAUNCH_CHECK();
-    scan_i32(sums, offs, tiles, s, sc, total_to);
-    return offs;
-}
-
 // Pinned host block of this thread for device-to-host read-backs (a copy to
 // pageable memory takes a slower staged path). Every use synchronises the
 // stream before the block is read or reused, so one block per thread serves
@@ -817,14 +799,17 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             }
             const Cands cd{up, edge_i, tri_k, tri_e, tet_t, tet_l, perm};
             const int M[4] = {n, E, T, Q};
-            int *rows_s[4] = {}, *spos[4] = {}, *in_s[4] = {}, *pos[4] = {}, *thr[4] = {};
+            int *rows_s[4] = {}, *spos[4] = {}, *thr[4] = {}, *tsum[4] = {}, *toff[4] = {};
+            unsigned char *in_s[4] = {};
             double *sz_s[4] = {}, *szp[4] = {};
             for (int d = 1; d <= 3; d++) {
                 const int m = M[d] > 0 ? M[d] : 1;
+                const unsigned nb = grid_for(m);
                 rows_s[d] = sc.get<int>((size_t)m * (d + 1));
                 spos[d] = sc.get<int>(m);
-                in_s[d] = sc.get<int>(m);
-                pos[d] = sc.get<int>((size_t)m + 1);
+                in_s[d] = sc.get<unsigned char>(m);
+                tsum[d] = sc.get<int>(nb);
+                toff[d] = sc.get<int>((size_t)nb + 1);
                 sz_s[d] = sc.get<double>(m);
                 thr[d] = sc.get<int>(m);
                 szp[d] = sc.get<double>(m);
@@ -858,17 +843,17 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
                 prune_init();
                 if (Q > 0) {
                     k_sweep_tets<<<grid_for(Q), BLOCK, 0, s>>>(Q, pa.aq, thr[3], szp[3], face3, thr[2], tri_att, tri_min,
-                                                              in_s[3], sz_s[3], cnt);
+                                                              in_s[3], sz_s[3], tsum[3], cnt);
                     LAUNCH_CHECK();
                 }
                 if (T > 0) {
                     k_sweep_tris<<<grid_for(T), BLOCK, 0, s>>>(T, pa.aq, thr[2], szp[2], face2, tri_att, tri_min, thr[1],
-                                                              edge_att, edge_min, in_s[2], sz_s[2], cnt);
+                                                              edge_att, edge_min, in_s[2], sz_s[2], tsum[2], cnt);
                     LAUNCH_CHECK();
                 }
                 if (E > 0) {
                     k_sweep_edges<<<grid_for(E), BLOCK, 0, s>>>(E, pa.aq, thr[1], szp[1], ends, edge_att, edge_min, vgab,
-                                                               vert_att, vert_min, in_s[1], sz_s[1]);
+                                                               vert_att, vert_min, in_s[1], sz_s[1], tsum[1]);
                     LAUNCH_CHECK();
                 }
                 vert_final(pa);
@@ -878,17 +863,21 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
                     const int K = d + 1;
                     r->d_simp[d] = static_cast<int32_t *>(dev_alloc((size_t)(M[d] > 0 ? M[d] : 1) * K * sizeof(int32_t)));
                     r->d_size[d] = static_cast<double *>(dev_alloc((size_t)(M[d] > 0 ? M[d] : 1) * sizeof(double)));
-                    const int *toff = scan_local_i32(in_s[d], pos[d], M[d], s, sc, m_out[d]);
-                    if (M[d] == 0) continue;
+                    if (M[d] == 0) {
+                        fill<int>(m_out[d], 0, 1, s);
+                        continue;
+                    }
+                    const unsigned nb = grid_for(M[d]);
+                    scan_i32(tsum[d], toff[d], nb, s, sc, m_out[d]);
                     if (d == 1)
-                        k_sweep_write<2><<<grid_for(M[d]), BLOCK, 0, s>>>(in_s[d], pos[d], toff, rows_s[d], sz_s[d], M[d],
-                                                                         r->d_simp[d], r->d_size[d]);
+                        k_sweep_write<2><<<nb, BLOCK, 0, s>>>(in_s[d], toff[d], rows_s[d], sz_s[d], M[d], r->d_simp[d],
+                                                             r->d_size[d]);
                     else if (d == 2)
-                        k_sweep_write<3><<<grid_for(M[d]), BLOCK, 0, s>>>(in_s[d], pos[d], toff, rows_s[d], sz_s[d], M[d],
-                                                                         r->d_simp[d], r->d_size[d]);
+                        k_sweep_write<3><<<nb, BLOCK, 0, s>>>(in_s[d], toff[d], rows_s[d], sz_s[d], M[d], r->d_simp[d],
+                                                             r->d_size[d]);
                     else
-                        k_sweep_write<4><<<grid_for(M[d]), BLOCK, 0, s>>>(in_s[d], pos[d], toff, rows_s[d], sz_s[d], M[d],
-                                                                         r->d_simp[d], r->d_size[d]);
+                        k_sweep_write<4><<<nb, BLOCK, 0, s>>>(in_s[d], toff[d], rows_s[d], sz_s[d], M[d], r->d_simp[d],
+                                                             r->d_size[d]);
                     LAUNCH_CHECK();
                 }
                 if (n_mol > 1) mol_rows(r, &cs[k], d_rows + (size_t)k * 4 * (n_mol + 1), d_bound);

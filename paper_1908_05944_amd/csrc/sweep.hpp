@@ -132,25 +132,33 @@ __device__ __forceinline__ void sweep_mark(const int *__restrict__ thr, int *att
     atomicMin(&mins[f], key);
 }
 
+// The kernels of one alpha run one thread per row of the output order, in
+// blocks of BLOCK rows; each writes its rows' kept flags and its block's
+// kept total (tsum), whose scan places the kept rows in k_sweep_write.
+
 // One alpha (aq in mA^2), tetrahedra in output order (Step 2).
 __global__ void __launch_bounds__(BLOCK) k_sweep_tets(int Q, i64 aq, const int *__restrict__ thr3,
                                                        const double *__restrict__ sz3, const int4 *__restrict__ face3,
                                                        const int *__restrict__ thr2, int *__restrict__ tri_att,
-                                                       long long *__restrict__ tri_min, int *__restrict__ in_s,
-                                                       double *__restrict__ sz_s, Counters *cnt) {
+                                                       long long *__restrict__ tri_min, unsigned char *__restrict__ in_s,
+                                                       double *__restrict__ sz_s, int *__restrict__ tsum,
+                                                       Counters *cnt) {
     const int p = blockIdx.x * BLOCK + threadIdx.x;
-    if (p >= Q) return;
-    const bool in = thr3[p] <= aq;
-    in_s[p] = in;
-    if (!in) return;
-    const double sz = sz3[p];
-    sz_s[p] = sz;
-    const long long key = ordered_from_double(sz);
-    const int4 f = face3[p];
-    sweep_mark(thr2, tri_att, tri_min, f.x, key, cnt);
-    sweep_mark(thr2, tri_att, tri_min, f.y, key, cnt);
-    sweep_mark(thr2, tri_att, tri_min, f.z, key, cnt);
-    sweep_mark(thr2, tri_att, tri_min, f.w, key, cnt);
+    const bool in = p < Q && thr3[p] <= aq;
+    if (p < Q) in_s[p] = in;
+    if (in) {
+        const double sz = sz3[p];
+        sz_s[p] = sz;
+        const long long key = ordered_from_double(sz);
+        const int4 f = face3[p];
+        sweep_mark(thr2, tri_att, tri_min, f.x, key, cnt);
+        sweep_mark(thr2, tri_att, tri_min, f.y, key, cnt);
+        sweep_mark(thr2, tri_att, tri_min, f.z, key, cnt);
+        sweep_mark(thr2, tri_att, tri_min, f.w, key, cnt);
+    }
+    int tot;
+    (void)block_exclusive_scan<BLOCK>(in, &tot);
+    if (threadIdx.x == 0) tsum[blockIdx.x] = tot;
 }
 
 // One alpha, triangles in output order (Step 3).
@@ -159,21 +167,28 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_tris(int T, i64 aq, const int *
                                                        const int *__restrict__ tri_att,
                                                        const long long *__restrict__ tri_min,
                                                        const int *__restrict__ thr1, int *__restrict__ edge_att,
-                                                       long long *__restrict__ edge_min, int *__restrict__ in_s,
-                                                       double *__restrict__ sz_s, Counters *cnt) {
+                                                       long long *__restrict__ edge_min,
+                                                       unsigned char *__restrict__ in_s, double *__restrict__ sz_s,
+                                                       int *__restrict__ tsum, Counters *cnt) {
     const int p = blockIdx.x * BLOCK + threadIdx.x;
-    if (p >= T) return;
-    const bool gab = thr2[p] <= aq;
-    const bool in = gab || tri_att[p];
-    in_s[p] = in;
-    if (!in) return;
-    const double sz = gab ? sz2[p] : double_from_ordered(tri_min[p]);
-    sz_s[p] = sz;
-    const long long key = ordered_from_double(sz);
-    const int4 f = face2[p];
-    sweep_mark(thr1, edge_att, edge_min, f.x, key, cnt);
-    sweep_mark(thr1, edge_att, edge_min, f.y, key, cnt);
-    sweep_mark(thr1, edge_att, edge_min, f.z, key, cnt);
+    bool in = false;
+    if (p < T) {
+        const bool gab = thr2[p] <= aq;
+        in = gab || tri_att[p];
+        in_s[p] = in;
+        if (in) {
+            const double sz = gab ? sz2[p] : double_from_ordered(tri_min[p]);
+            sz_s[p] = sz;
+            const long long key = ordered_from_double(sz);
+            const int4 f = face2[p];
+            sweep_mark(thr1, edge_att, edge_min, f.x, key, cnt);
+            sweep_mark(thr1, edge_att, edge_min, f.y, key, cnt);
+            sweep_mark(thr1, edge_att, edge_min, f.z, key, cnt);
+        }
+    }
+    int tot;
+    (void)block_exclusive_scan<BLOCK>(in, &tot);
+    if (threadIdx.x == 0) tsum[blockIdx.x] = tot;
 }
 
 // One alpha, edges in output order (Step 4); kept edges record themselves on
@@ -184,32 +199,42 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_edges(int E, i64 aq, const int 
                                                         const long long *__restrict__ edge_min,
                                                         const unsigned char *__restrict__ vgab,
                                                         int *__restrict__ vert_att, long long *__restrict__ vert_min,
-                                                        int *__restrict__ in_s, double *__restrict__ sz_s) {
+                                                        unsigned char *__restrict__ in_s, double *__restrict__ sz_s,
+                                                        int *__restrict__ tsum) {
     const int p = blockIdx.x * BLOCK + threadIdx.x;
-    if (p >= E) return;
-    const bool gab = thr1[p] <= aq;
-    const bool in = gab || edge_att[p];
-    in_s[p] = in;
-    if (!in) return;
-    const double sz = gab ? sz1[p] : double_from_ordered(edge_min[p]);
-    sz_s[p] = sz;
-    const long long key = ordered_from_double(sz);
-    const int2 v = ends[p];
-    if (!vgab[v.x]) { atomicOr(&vert_att[v.x], 1); atomicMin(&vert_min[v.x], key); }
-    if (!vgab[v.y]) { atomicOr(&vert_att[v.y], 1); atomicMin(&vert_min[v.y], key); }
+    bool in = false;
+    if (p < E) {
+        const bool gab = thr1[p] <= aq;
+        in = gab || edge_att[p];
+        in_s[p] = in;
+        if (in) {
+            const double sz = gab ? sz1[p] : double_from_ordered(edge_min[p]);
+            sz_s[p] = sz;
+            const long long key = ordered_from_double(sz);
+            const int2 v = ends[p];
+            if (!vgab[v.x]) { atomicOr(&vert_att[v.x], 1); atomicMin(&vert_min[v.x], key); }
+            if (!vgab[v.y]) { atomicOr(&vert_att[v.y], 1); atomicMin(&vert_min[v.y], key); }
+        }
+    }
+    int tot;
+    (void)block_exclusive_scan<BLOCK>(in, &tot);
+    if (threadIdx.x == 0) tsum[blockIdx.x] = tot;
 }
 
-// One alpha, output of dimension K - 1: the kept rows in output order.
-// pos holds the scan of in_s within SCAN_TILE tiles and toff the tiles'
-// offsets (toff = nullptr: pos is the whole scan).
+// One alpha, output of dimension K - 1: the kept rows in output order, each
+// at its block's offset (toff: exclusive scan of the block totals) plus its
+// place among the block's kept rows.
 template <int K>
-__global__ void __launch_bounds__(BLOCK) k_sweep_write(const int *__restrict__ in_s, const int *__restrict__ pos,
+__global__ void __launch_bounds__(BLOCK) k_sweep_write(const unsigned char *__restrict__ in_s,
                                                         const int *__restrict__ toff, const int *__restrict__ rows_s,
                                                         const double *__restrict__ sz_s, int m, int *__restrict__ out,
                                                         double *__restrict__ out_size) {
     const int p = blockIdx.x * BLOCK + threadIdx.x;
-    if (p >= m || !in_s[p]) return;
-    const int o = pos[p] + (toff ? toff[p / SCAN_TILE] : 0);
+    const bool in = p < m && in_s[p];
+    int tot;
+    const int local = block_exclusive_scan<BLOCK>(in, &tot);
+    if (!in) return;
+    const int o = toff[blockIdx.x] + local;
 #pragma unroll
     for (int u = 0; u < K; u++) out[(long long)o * K + u] = rows_s[(long long)p * K + u];
     out_size[o] = sz_s[p] / 1.0e6;  // mA^2 -> A^2
