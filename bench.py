@@ -383,7 +383,7 @@ def main():
     Nn = work[1]
     alg_bytes = {
         "neighbours_count": 16 * n + 9 * n + 4 * Nn + 4 * E,
-        "neighbours_fill": 16 * n + 8 * Nn + 12 * E,
+        "neighbours_fill": 20 * n + 12 * E,
         "triangles_count": 16 * n + 8 * E + 4 * Nn + 4 * E + 5 * E + 4 * T,
         "triangles_fill": 8 * E + 12 * T,
         "triangles_ac2_tetrahedra": 16 * n + 4 * Nn + 4 * E + 29 * T + 4 * Q,

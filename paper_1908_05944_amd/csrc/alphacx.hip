@@ -580,17 +580,18 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             c0 = read_one(cnt, s);
         }
         const int E = c0.E, Nn = c0.Nn;
-        int *nbr = sc.get<int>(Nn > 0 ? Nn : 1);
+        // neighbour rows: in the slabs after the one-pass search, else in CSR
+        int *nbr = nbr_two_pass ? sc.get<int>(Nn > 0 ? Nn : 1) : nslab;
         int *up = sc.get<int>(E > 0 ? E : 1);
         int *edge_i = sc.get<int>(E > 0 ? E : 1);
         tm.mark(ST_NBR_FILL);
         if (!nbr_two_pass) {
             if (slot == NB_SLOT_WIDE)
-                k_nbr_compact<NB_SLOT_WIDE><<<nbN, BLOCK, 0, s>>>(deg_n, deg_up, upmask, n, nslab, nboff, uboff,
-                                                                 nbr_start, up_start, nbr, up, edge_i);
+                k_nbr_compact<NB_SLOT_WIDE><<<nbN, BLOCK, 0, s>>>(deg_n, deg_up, upmask, n, nslab, uboff, nbr_start,
+                                                                 up_start, up, edge_i);
             else
-                k_nbr_compact<NB_SLOT><<<nbN, BLOCK, 0, s>>>(deg_n, deg_up, upmask, n, nslab, nboff, uboff, nbr_start,
-                                                            up_start, nbr, up, edge_i);
+                k_nbr_compact<NB_SLOT><<<nbN, BLOCK, 0, s>>>(deg_n, deg_up, upmask, n, nslab, uboff, nbr_start, up_start,
+                                                            up, edge_i);
         } else {
             k_neighbours<NB_FILL, NB_SLOT><<<nbN, BLOCK, 0, s>>>(atom, perm, n, d_grids, n_mol, cell_start, pp, nullptr,
                                                                 nullptr, nullptr, nullptr, nullptr, nbr_start, up_start,

@@ -414,16 +414,17 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
     for (int k = threadIdx.x; k < eu - bu; k += BLOCK) edge_i[bu + k] = su[k];
 }
 
-// Writes the rows of block b's balls into place from the block's slab
-// (noff / uoff: exclusive scans of the blocks' neighbour and upper entry
-// totals): each neighbour row, the entries of it that the mask marks as the
-// upper row, the row starts and the owner of every upper entry.
+// After a one-pass neighbour search: the neighbour rows stay where the pass
+// packed them, in the block's slab (nbr_start[i] points there; the rows of a
+// ball are read with its count deg_n[i], so they need not be adjacent across
+// blocks). The upper rows, whose entries are the dense candidate-edge ids,
+// are written into place (uoff: exclusive scan of the blocks' upper totals)
+// with the owner of every upper entry.
 template <int SLOT>
 __global__ void __launch_bounds__(BLOCK) k_nbr_compact(const int *__restrict__ deg_n, const int *__restrict__ deg_up,
                                                         const unsigned *__restrict__ upmask, int n,
-                                                        const int *__restrict__ nslab, const int *__restrict__ noff,
-                                                        const int *__restrict__ uoff, int *__restrict__ nbr_start,
-                                                        int *__restrict__ up_start, int *__restrict__ nbr,
+                                                        const int *__restrict__ nslab, const int *__restrict__ uoff,
+                                                        int *__restrict__ nbr_start, int *__restrict__ up_start,
                                                         int *__restrict__ up, int *__restrict__ edge_i) {
     const int b = blockIdx.x;
     const int i = b * BLOCK + threadIdx.x;
@@ -431,26 +432,21 @@ __global__ void __launch_bounds__(BLOCK) k_nbr_compact(const int *__restrict__ d
     int totn, totu;
     const int offn = block_exclusive_scan<BLOCK>(cn, &totn);
     const int offu = block_exclusive_scan<BLOCK>(cu, &totu);
-    const int gn = noff[b], gu = uoff[b];
-    const int *src = nslab + (long long)b * (BLOCK * SLOT);
-    // neighbour rows: the block's packed slab, copied with coalesced accesses
-    for (int k = threadIdx.x; k < totn; k += BLOCK) nbr[gn + k] = src[k];
+    const int gu = uoff[b];
+    const int base = b * (BLOCK * SLOT);  // the block's slab
     if (i >= n) return;
-    nbr_start[i] = gn + offn;
+    nbr_start[i] = base + offn;
     up_start[i] = gu + offu;
     unsigned m = upmask[i];
     int q = gu + offu;
     while (m) {
         const int k = __ffs((int)m) - 1;
         m &= m - 1;
-        up[q] = src[offn + k];
+        up[q] = nslab[base + offn + k];
         edge_i[q] = i;
         q++;
     }
-    if (i == n - 1) {
-        nbr_start[n] = gn + offn + cn;
-        up_start[n] = gu + offu + cu;
-    }
+    if (i == n - 1) up_start[n] = gu + offu + cu;
 }
 
 // 64-bit sum of n int32 counts: each block writes its partial to
