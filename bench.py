@@ -41,6 +41,7 @@ KERNEL_OF_STAGE = {
 KERNEL_SOURCES = ["paper_1908_05944_amd/csrc/kernels.hpp", "paper_1908_05944_amd/csrc/predicates.hpp",
                   "paper_1908_05944_amd/csrc/common.hpp", "paper_1908_05944_amd/csrc/radix.hpp",
                   "paper_1908_05944_amd/csrc/measure.hpp", "paper_1908_05944_amd/csrc/sweep.hpp",
+                  "paper_1908_05944_amd/csrc/partition.hpp",
                   "paper_1908_05944_amd/csrc/alphacx.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_3Mshell.json")
 

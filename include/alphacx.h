@@ -91,6 +91,27 @@ ac_status ac_alpha_complex(const double *xyz, const double *radii, int64_t n, do
 ac_status ac_alpha_complex_device(const double *d_xyz, const double *d_radii, int64_t n, double alpha,
                                   const ac_options *opt, void *stream, ac_complex **out);
 
+/* ---- Partitioned build ----
+ *
+ * The same complex built slab by slab: the balls are cut into `parts` slabs
+ * of equal width along x; each slab is built with every ball within
+ * 4 sqrt(r_max^2 + alpha) + 2 A of it, and keeps the simplices whose owner
+ * vertex (least quantised x, ties to the least input id) lies in it; the
+ * kept rows of all slabs are then merged into output order. Membership and
+ * Size of a simplex depend only on balls within 4 sqrt(r_max^2 + alpha) of
+ * any of its vertices (Sec. 3.1 Steps 1-5 with the neighbour bound of
+ * Sec. 4.3), so the result equals ac_alpha_complex_device bit for bit, while
+ * the scratch memory of a call is that of one slab's build. This is the
+ * split the library would use across GPUs, and for inputs whose build does
+ * not fit at once (the paper processes chunks of the sorted atom list,
+ * Sec. 4.6).
+ *   parts    1 <= parts <= 64
+ * Other arguments and errors as ac_alpha_complex_device. ac_candidate_count
+ * and ac_work_count report -1; ac_exact_fallbacks sums over the slabs.
+ */
+ac_status ac_alpha_complex_partitioned(const double *d_xyz, const double *d_radii, int64_t n, double alpha,
+                                       int32_t parts, const ac_options *opt, void *stream, ac_complex **out);
+
 /* ---- Alpha sweep ----
  *
  * The alpha complexes of one ball set for several alpha values from a single

@@ -89,6 +89,9 @@ def _load():
     lib.ac_alpha_sweep_device.argtypes = [c_p, c_p, i64, ctypes.POINTER(dbl), i64, ctypes.POINTER(Options), c_p,
                                           ctypes.POINTER(c_p)]
     lib.ac_alpha_sweep_device.restype = ctypes.c_int
+    lib.ac_alpha_complex_partitioned.argtypes = [c_p, c_p, i64, dbl, ctypes.c_int32, ctypes.POINTER(Options), c_p,
+                                                 ctypes.POINTER(c_p)]
+    lib.ac_alpha_complex_partitioned.restype = ctypes.c_int
     lib.ac_count.argtypes = [c_p, ctypes.c_int]
     lib.ac_count.restype = i64
     lib.ac_simplices.argtypes = [c_p, ctypes.c_int]
@@ -271,6 +274,27 @@ def ac_alpha_complex_device(xyz, radii, alpha: float, options=None, stream=None)
     h = ctypes.c_void_p()
     st = lib.ac_alpha_complex_device(xyz.data_ptr(), radii.data_ptr(), xyz.shape[0], float(alpha), _opts(options),
                                      ctypes.c_void_p(s.cuda_stream), ctypes.byref(h))
+    _check(st)
+    return AlphaComplex(h)
+
+
+def ac_alpha_complex_partitioned(xyz, radii, alpha: float, parts: int, options=None, stream=None) -> AlphaComplex:
+    """As ac_alpha_complex_device, built slab by slab (`parts` slabs along x,
+    each with a halo) and merged; equal to the single build bit for bit."""
+    import torch
+    lib = _load()
+    if not (xyz.is_cuda and radii.is_cuda):
+        raise ValueError("ac_alpha_complex_partitioned needs device tensors")
+    if xyz.dtype != torch.float64 or radii.dtype != torch.float64:
+        raise ValueError("float64 tensors expected")
+    xyz = xyz.contiguous()
+    radii = radii.contiguous()
+    if xyz.dim() != 2 or xyz.shape[1] != 3 or radii.shape[0] != xyz.shape[0]:
+        raise ValueError("xyz must be n x 3 and radii n")
+    s = stream if stream is not None else torch.cuda.current_stream(xyz.device)
+    h = ctypes.c_void_p()
+    st = lib.ac_alpha_complex_partitioned(xyz.data_ptr(), radii.data_ptr(), xyz.shape[0], float(alpha), int(parts),
+                                          _opts(options), ctypes.c_void_p(s.cuda_stream), ctypes.byref(h))
     _check(st)
     return AlphaComplex(h)
 

@@ -20,6 +20,7 @@
 #include "kernels.hpp"
 #include "measure.hpp"
 #include "sweep.hpp"
+#include "partition.hpp"
 
 using namespace acx;
 
@@ -939,6 +940,189 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
 }
 
 // ---------------------------------------------------------------------------
+// Partitioned build (partition.hpp): slabs along x with a halo of 4 s_g plus
+// 2 A, one pipeline run per slab, owned rows kept, then merged in output
+// order. Peak scratch memory is that of the largest slab's build.
+
+// Sorts the rows of dimension K - 1 gathered from all slabs into output
+// order and stores them in r (d_simp / d_size of dimension K - 1).
+template <int K>
+static void merge_rows(const int *rows, const double *size, int m, int n, hipStream_t s, Scope &sc, ac_complex *r) {
+    typedef typename OrderPay<K>::type P;
+    const int d = K - 1;
+    r->d_simp[d] = static_cast<int32_t *>(dev_alloc((size_t)(m > 0 ? m : 1) * K * sizeof(int32_t)));
+    r->d_size[d] = static_cast<double *>(dev_alloc((size_t)(m > 0 ? m : 1) * sizeof(double)));
+    if (m == 0) return;
+    unsigned *key = sc.get<unsigned>(m);
+    P *pay = sc.get<P>(m);
+    int *spos = sc.get<int>(m);
+    k_rows_keys<K><<<grid_for(m), BLOCK, 0, s>>>(rows, m, key, pay);
+    LAUNCH_CHECK();
+    radix_sort<P>(key, pay, m, bits_for((long long)n), s, sc);
+    k_order_rank<K><<<grid_for(m), BLOCK, 0, s>>>(key, pay, m, r->d_simp[d], spos);
+    k_place_sizes<<<grid_for(m), BLOCK, 0, s>>>(spos, size, m, r->d_size[d]);
+    LAUNCH_CHECK();
+}
+
+template <int K>
+static void own_rows(const ac_complex *ck, const int *sel, const int4 *q, int x0, int w, int parts, int k,
+                     hipStream_t s, Scope &sc, std::vector<int *> &rows, std::vector<double *> &sizes,
+                     std::vector<int *> &counts) {
+    const int d = K - 1;
+    const int m = (int)ck->count[d];
+    if (m == 0) return;
+    int *flag = sc.get<int>(m);
+    int *pos = sc.get<int>((size_t)m + 1);
+    int *cnt = sc.get<int>(1);
+    int *out = sc.get<int>((size_t)m * K);
+    double *out_size = sc.get<double>(m);
+    k_own_flags<K><<<grid_for(m), BLOCK, 0, s>>>(ck->d_simp[d], m, sel, q, x0, w, parts, k, flag);
+    LAUNCH_CHECK();
+    scan_i32(flag, pos, m, s, sc, cnt);
+    k_own_write<K><<<grid_for(m), BLOCK, 0, s>>>(ck->d_simp[d], ck->d_size[d], m, flag, pos, sel, out, out_size);
+    LAUNCH_CHECK();
+    rows.push_back(out);
+    sizes.push_back(out_size);
+    counts.push_back(cnt);
+}
+
+static ac_status run_partitioned(const double *d_xyz, const double *d_r, int64_t n64, double alpha, int parts,
+                                 const Options &o, hipStream_t s, ac_complex **out) {
+    *out = nullptr;
+    if (n64 < 1 || n64 >= (1 << 26)) return set_error(AC_E_INVALID, "n must be in [1, 2^26)");
+    if (parts < 1 || parts > 64) return set_error(AC_E_INVALID, "parts must be in [1, 64]");
+    if (!std::isfinite(alpha)) return set_error(AC_E_INVALID, "alpha is not finite");
+    const double as = alpha * 1e6;
+    if (!(std::fabs(as) < 67108864.0)) return set_error(AC_E_RANGE, "|alpha| too large for the exact bit budget");
+    const long long aq = (long long)std::nearbyint(as);
+    const int n = (int)n64;
+    Scope sc;
+    ac_complex *res = nullptr;
+    ac_complex *ck = nullptr;
+    try {
+        // quantised centres, bounding box and the largest weight
+        int4 *q = sc.get<int4>(n);
+        std::vector<int2> tiles;
+        for (int a = 0; a < n; a += QTILE) tiles.push_back(make_int2(a, std::min(a + QTILE, n)));
+        int2 *d_tiles = sc.get<int2>(tiles.size());
+        int *d_tile_first = sc.get<int>(2);
+        const int tf[2] = {0, (int)tiles.size()};
+        Stats *part = sc.get<Stats>(tiles.size());
+        Stats *st = sc.get<Stats>(1);
+        HIP_TRY(hipMemcpyAsync(d_tiles, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(d_tile_first, tf, sizeof(tf), hipMemcpyHostToDevice, s));
+        k_quantise<<<(unsigned)tiles.size(), BLOCK, 0, s>>>(d_xyz, d_r, d_tiles, q, part);
+        k_stats_reduce<<<1, BLOCK, 0, s>>>(part, d_tile_first, st);
+        LAUNCH_CHECK();
+        const Stats h = read_one(st, s);
+        if (h.flags & 1) throw HipError{AC_E_INVALID, "non-finite coordinate, or radius not positive"};
+        if (h.flags & 2) throw HipError{AC_E_RANGE, "coordinate or radius outside the exact bit budget"};
+        const long long sg2 = (long long)h.wmax + aq;
+        if (sg2 >= (1LL << 26)) throw HipError{AC_E_RANGE, "r_max^2 + alpha too large for the exact bit budget"};
+        const int halo = (int)(4 * isqrt_ceil(sg2 < 0 ? 0 : sg2) + 2000);
+        const int x0 = h.minx;
+        const int w = (int)(((long long)h.maxx - h.minx + parts) / parts);  // ceil((extent + 1) / parts)
+
+        std::vector<int *> rows[4], counts[4];
+        std::vector<double *> sizes[4];
+        int *kept = sc.get<int>(n);
+        double *vsize = sc.get<double>(n);
+        fill<int>(kept, 0, n, s);
+        int *flag = sc.get<int>(n);
+        int *pos = sc.get<int>((size_t)n + 1);
+        int *m_sub = sc.get<int>(1);
+        long long fallbacks = 0;
+        for (int k = 0; k < parts; k++) {
+            const int lo = x0 + k * w, hi = k == parts - 1 ? INT_MAX - halo : lo + w;
+            k_slab_flags<<<grid_for(n), BLOCK, 0, s>>>(q, n, lo, hi, halo, flag);
+            LAUNCH_CHECK();
+            scan_i32(flag, pos, n, s, sc, m_sub);
+            const int ms = read_one(m_sub, s);
+            if (ms == 0) continue;
+            double *sub_xyz = sc.get<double>((size_t)ms * 3);
+            double *sub_r = sc.get<double>(ms);
+            int *sel = sc.get<int>(ms);
+            k_slab_gather<<<grid_for(n), BLOCK, 0, s>>>(flag, pos, n, d_xyz, d_r, sub_xyz, sub_r, sel);
+            LAUNCH_CHECK();
+            Batch bt;
+            bt.off = {0, ms};
+            Options ok = o;
+            ok.profile = 0;
+            const ac_status stp = run_pipeline(sub_xyz, sub_r, ms, bt, alpha, ok, s, &ck);
+            if (stp != AC_OK) throw HipError{stp, g_last_error};
+            fallbacks += ck->fallbacks;
+            if (ck->count[0] > 0) {
+                k_own_vertices<<<grid_for(ck->count[0]), BLOCK, 0, s>>>(ck->d_simp[0], ck->d_size[0],
+                                                                        (int)ck->count[0], sel, q, x0, w, parts, k,
+                                                                        kept, vsize);
+                LAUNCH_CHECK();
+            }
+            own_rows<2>(ck, sel, q, x0, w, parts, k, s, sc, rows[1], sizes[1], counts[1]);
+            own_rows<3>(ck, sel, q, x0, w, parts, k, s, sc, rows[2], sizes[2], counts[2]);
+            own_rows<4>(ck, sel, q, x0, w, parts, k, s, sc, rows[3], sizes[3], counts[3]);
+            HIP_TRY(hipStreamSynchronize(s));  // the slab's result is consumed; free it
+            free_complex(ck);
+            ck = nullptr;
+        }
+        res = new ac_complex();
+        for (double &x : res->stage_ms) x = -1.0;
+        HIP_TRY(hipGetDevice(&res->device));
+        res->device_result = true;
+        // vertices: kept flags by input id
+        int *m0 = sc.get<int>(1);
+        scan_i32(kept, pos, n, s, sc, m0);
+        res->d_simp[0] = static_cast<int32_t *>(dev_alloc((size_t)n * sizeof(int32_t)));
+        res->d_size[0] = static_cast<double *>(dev_alloc((size_t)n * sizeof(double)));
+        k_vertex_rows<<<grid_for(n), BLOCK, 0, s>>>(kept, pos, vsize, n, res->d_simp[0], res->d_size[0]);
+        LAUNCH_CHECK();
+        res->count[0] = read_one(m0, s);
+        // higher dimensions: gather every slab's owned rows, then one sort
+        for (int d = 1; d <= 3; d++) {
+            const int K = d + 1;
+            std::vector<int> c(counts[d].size());
+            long long total = 0;
+            for (size_t j = 0; j < counts[d].size(); j++) {
+                c[j] = read_one(counts[d][j], s);
+                total += c[j];
+            }
+            check_total(total, "simplices of one dimension");
+            int *all = sc.get<int>((size_t)(total > 0 ? total : 1) * K);
+            double *all_size = sc.get<double>(total > 0 ? total : 1);
+            long long off = 0;
+            for (size_t j = 0; j < c.size(); j++) {
+                if (!c[j]) continue;
+                HIP_TRY(hipMemcpyAsync(all + off * K, rows[d][j], (size_t)c[j] * K * sizeof(int), hipMemcpyDeviceToDevice,
+                                       s));
+                HIP_TRY(hipMemcpyAsync(all_size + off, sizes[d][j], (size_t)c[j] * sizeof(double),
+                                       hipMemcpyDeviceToDevice, s));
+                off += c[j];
+            }
+            if (d == 1) merge_rows<2>(all, all_size, (int)total, n, s, sc, res);
+            else if (d == 2) merge_rows<3>(all, all_size, (int)total, n, s, sc, res);
+            else merge_rows<4>(all, all_size, (int)total, n, s, sc, res);
+            res->count[d] = total;
+        }
+        HIP_TRY(hipStreamSynchronize(s));
+        res->n = n;
+        res->n_mol = 1;
+        for (int d = 0; d < 4; d++) {
+            res->cand[d] = -1;
+            res->mol_rows[d] = {0, res->count[d]};
+        }
+        res->fallbacks = fallbacks;
+        res->work[0] = res->work[1] = -1;
+    } catch (const HipError &e) {
+        (void)hipStreamSynchronize(s);
+        free_complex(ck);
+        free_complex(res);
+        return set_error(e.st, e.msg);
+    }
+    *out = res;
+    g_last_error.clear();
+    return AC_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Union volume / area (measure.hpp)
 
 static long long incidence_count(const ac_complex *c) {
@@ -1092,6 +1276,20 @@ ac_status ac_alpha_complex_device(const double *d_xyz, const double *d_radii, in
         Batch bt;
         bt.off = {0, n};
         return run_pipeline(d_xyz, d_radii, n, bt, alpha, parse(opt), static_cast<hipStream_t>(stream), out);
+    } catch (const HipError &e) {
+        return set_error(e.st, e.msg);
+    } catch (...) {
+        return set_error(AC_E_DEVICE, "unexpected host exception");
+    }
+}
+
+ac_status ac_alpha_complex_partitioned(const double *d_xyz, const double *d_radii, int64_t n, double alpha,
+                                       int32_t parts, const ac_options *opt, void *stream, ac_complex **out) {
+    if (!out) return set_error(AC_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!d_xyz || !d_radii) return set_error(AC_E_INVALID, "NULL input pointer");
+    try {
+        return run_partitioned(d_xyz, d_radii, n, alpha, parts, parse(opt), static_cast<hipStream_t>(stream), out);
     } catch (const HipError &e) {
         return set_error(e.st, e.msg);
     } catch (...) {
