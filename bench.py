@@ -82,6 +82,19 @@ def _timed(torch, fn, reps):
     return (time.perf_counter() - t0) / reps
 
 
+def bench_partition(acx, torch, log, xyz, rad, opts, reps=3):
+    """Partitioned builds of the 3M-atom shell (slabs along x with a halo),
+    against the single build: the time a slab-by-slab build costs."""
+    out = {}
+    for parts in (4, 16):
+        acx.ac_alpha_complex_partitioned(xyz, rad, 0.0, parts, options=opts).close()
+        t = _timed(torch, lambda: acx.ac_alpha_complex_partitioned(xyz, rad, 0.0, parts, options=opts).close(), reps)
+        out[str(parts)] = t * 1e3
+    log("[bench] partitioned: " + ", ".join(f"{p} slabs {v:.2f} ms" for p, v in out.items()))
+    return {"metric": "partitioned build ms", "unit": "ms per build", "higher_is_better": False, "ms_by_slabs": out,
+            "config": {"workload": "3M-atom shell, alpha = 0, slabs of equal width along x"}}
+
+
 def bench_sweep(acx, torch, log, xyz, rad, opts, reps=3):
     """Alpha sweep on the 3M-atom shell: the complexes at alpha = 0, 0.25, ...,
     2 A^2 from one ac_alpha_sweep_device call against one direct build per
@@ -445,6 +458,7 @@ def main():
     extras = {}
     if not args.no_extras:
         extras["alpha_sweep"] = bench_sweep(acx, torch, log, xyz, rad, opts)
+        extras["partitioned"] = bench_partition(acx, torch, log, xyz, rad, opts)
         del xyz, rad
         torch.cuda.empty_cache()
         extras["batch"] = bench_batch(acx, synth, torch, log)
