@@ -117,6 +117,24 @@ def test_options_do_not_change_result(acx):
             assert np.array_equal(got.sizes(d), base.sizes(d)), (opt, d)
 
 
+def test_stage_events(acx):
+    """profile=1 times every stage; profile=2+i only stage i (the others -1);
+    neither changes the result."""
+    m = synth.molecule(2000, 13)
+    base = _run(acx, m.xyz, m.radii, 0.0)
+    names = acx.stage_names()
+    full = _run(acx, m.xyz, m.radii, 0.0, profile=1)
+    assert all(v >= 0 for v in full.stage_ms().values())
+    for i in (0, names.index("triangles_count"), len(names) - 1):
+        one = _run(acx, m.xyz, m.radii, 0.0, profile=2 + i)
+        ms = one.stage_ms()
+        assert ms[names[i]] >= 0
+        assert all(v == -1.0 for k, v in ms.items() if k != names[i])
+        for d in range(4):
+            assert np.array_equal(one.simplices(d), base.simplices(d))
+            assert np.array_equal(one.sizes(d), base.sizes(d))
+
+
 def test_host_path_matches(acx):
     m = synth.molecule(1500, 12)
     got = acx.ac_alpha_complex(m.xyz, m.radii, 0.0)
