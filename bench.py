@@ -267,9 +267,15 @@ def bench_union(acx, synth, torch, log, frames=64, reps=3):
             acx.ac_union_measure_device(c, x, R)
             acx.ac_union_measure_backward(c, x, R, g)
 
+    def fused():
+        for c, x in zip(cs, Xs):
+            acx.ac_union_measure_fused(c, x, R, g)
+
     fwd_bwd()  # first backward on a complex sorts its incidences (kept)
+    fused()
     t_build = _timed(torch, build, reps) / frames
     t_fb = _timed(torch, fwd_bwd, reps) / frames
+    t_fused = _timed(torch, fused, reps) / frames
     V, A = acx.ac_union_measure(cs[0], Xs[0], R)
     for c in cs:
         c.close()
@@ -288,11 +294,14 @@ def bench_union(acx, synth, torch, log, frames=64, reps=3):
     def build_batch():
         acx.ac_alpha_complex_batch(XB, RB, off, 0.0).close()
 
+    acx.ac_union_measure_fused(cb, XB, RB, g)
     t_fb_batch = _timed(torch, fwd_bwd_batch, reps) / frames
+    t_fused_batch = _timed(torch, lambda: acx.ac_union_measure_fused(cb, XB, RB, g), reps) / frames
     t_build_batch = _timed(torch, build_batch, reps) / frames
     cb.close()
-    log(f"[bench] union: per frame build {t_build * 1e3:.3f} ms, V+A fwd+bwd {t_fb * 1e3:.3f} ms; "
-        f"batched over {frames} frames: build {t_build_batch * 1e3:.3f} ms, fwd+bwd {t_fb_batch * 1e3:.3f} ms per frame")
+    log(f"[bench] union: per frame build {t_build * 1e3:.3f} ms, V+A fwd+bwd {t_fb * 1e3:.3f} ms "
+        f"(fused {t_fused * 1e3:.3f}); batched over {frames} frames: build {t_build_batch * 1e3:.3f} ms, "
+        f"fwd+bwd {t_fb_batch * 1e3:.3f} ms (fused {t_fused_batch * 1e3:.3f}) per frame")
     return {
         "metric": "V+A fwd+bwd ms",
         "value": t_fb * 1e3,
@@ -300,6 +309,8 @@ def bench_union(acx, synth, torch, log, frames=64, reps=3):
         "higher_is_better": False,
         "build_ms_per_frame": t_build * 1e3,
         "batched_fwd_bwd_ms_per_frame": t_fb_batch * 1e3,
+        "fused_fwd_bwd_ms_per_frame": t_fused * 1e3,
+        "batched_fused_fwd_bwd_ms_per_frame": t_fused_batch * 1e3,
         "batched_build_ms_per_frame": t_build_batch * 1e3,
         "frame0": {"V_A3": V, "A_A2": A},
         "config": {"workload": "64 frames of the 100k-atom molecule (sphere R 78.2 A), Gaussian jitter 0.1 A, vdW "

@@ -249,6 +249,14 @@ ac_status ac_union_measure_device(ac_complex *c, const double *d_xyz, const doub
 ac_status ac_union_measure_backward(ac_complex *c, const double *d_xyz, const double *d_radii, int64_t n,
                                     const double *d_grad, double *d_dxyz, double *d_dradii, void *stream);
 
+/* Forward and backward in one pass (each corner's terms evaluated once):
+ * d_out[0] = V, d_out[1] = A as ac_union_measure_device writes them (equal up
+ * to the rounding of a differently ordered evaluation), and the gradient as
+ * ac_union_measure_backward writes it (bit for bit), for an optimisation
+ * step that needs both. Arguments and rules as those two calls. */
+ac_status ac_union_measure_fused(ac_complex *c, const double *d_xyz, const double *d_radii, int64_t n,
+                                 const double *d_grad, double *d_out, double *d_dxyz, double *d_dradii, void *stream);
+
 /* Releases a result (NULL is allowed). */
 void ac_free(ac_complex *c);
 

@@ -137,6 +137,8 @@ def _load():
     lib.ac_union_measure_device.restype = ctypes.c_int
     lib.ac_union_measure_backward.argtypes = [c_p, c_p, c_p, i64, c_p, c_p, c_p, c_p]
     lib.ac_union_measure_backward.restype = ctypes.c_int
+    lib.ac_union_measure_fused.argtypes = [c_p, c_p, c_p, i64, c_p, c_p, c_p, c_p, c_p]
+    lib.ac_union_measure_fused.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -422,6 +424,22 @@ def ac_union_measure_backward(c: AlphaComplex, xyz, radii, grad, stream=None):
     _check(_load().ac_union_measure_backward(c._h, xyz.data_ptr(), radii.data_ptr(), xyz.shape[0], grad.data_ptr(),
                                              dx.data_ptr(), dr.data_ptr(), _stream(xyz.device, stream)))
     return dx, dr
+
+
+def ac_union_measure_fused(c: AlphaComplex, xyz, radii, grad, stream=None):
+    """V, A (device tensor of 2) and the gradient of grad[0] * V + grad[1] * A
+    with respect to xyz and radii, in one pass."""
+    import torch
+    xyz, radii = _balls(xyz, radii)
+    grad = grad.detach().to(device=xyz.device, dtype=torch.float64).contiguous()
+    if grad.numel() != 2:
+        raise ValueError("grad must hold (gV, gA)")
+    out = torch.empty(2, dtype=torch.float64, device=xyz.device)
+    dx = torch.empty_like(xyz)
+    dr = torch.empty_like(radii)
+    _check(_load().ac_union_measure_fused(c._h, xyz.data_ptr(), radii.data_ptr(), xyz.shape[0], grad.data_ptr(),
+                                          out.data_ptr(), dx.data_ptr(), dr.data_ptr(), _stream(xyz.device, stream)))
+    return out, dx, dr
 
 
 def _autograd_function():

@@ -1208,13 +1208,20 @@ static double *measure_forward(ac_complex *c, const double *x, const double *r, 
     return d_out;
 }
 
+// Backward of dimension K - 1; with part, also the forward's block parts
+// (part + 2 nb onwards, nb advanced as in measure_fwd_dim).
 template <int K>
 static void measure_bwd_dim(const ac_complex *c, const double *x, const double *r, const double *g, double4 *contrib,
-                            long long &off, hipStream_t s) {
+                            long long &off, hipStream_t s, double *part = nullptr, int *nb = nullptr) {
     const long long m = c->count[K - 1];
     if (m == 0) return;
     const unsigned b = (unsigned)((m * K + MEASURE_BLOCK - 1) / MEASURE_BLOCK);
-    k_measure_bwd<K><<<b, MEASURE_BLOCK, 0, s>>>(c->d_simp[K - 1], m, x, r, g, contrib + off);
+    if (part) {
+        k_measure_bwd<K, true><<<b, MEASURE_BLOCK, 0, s>>>(c->d_simp[K - 1], m, x, r, g, contrib + off, part + 2LL * *nb);
+        *nb += (int)b;
+    } else {
+        k_measure_bwd<K, false><<<b, MEASURE_BLOCK, 0, s>>>(c->d_simp[K - 1], m, x, r, g, contrib + off, nullptr);
+    }
     LAUNCH_CHECK();
     off += m * K;
 }
@@ -1536,24 +1543,56 @@ ac_status ac_union_measure(ac_complex *c, const double *d_xyz, const double *d_r
     return AC_OK;
 }
 
+// Backward (and, with d_out, the forward in the same pass) on stream s.
+static void measure_backward(ac_complex *c, const double *x, const double *r, int64_t n, const double *g,
+                             double *dx, double *dr, double *d_out, hipStream_t s) {
+    ensure_incidence(c, s);
+    const long long M = incidence_count(c);
+    if (!c->meas_contrib) c->meas_contrib = static_cast<double4 *>(dev_alloc((size_t)(M > 0 ? M : 1) * sizeof(double4)));
+    double4 *contrib = c->meas_contrib;
+    double *part = nullptr;
+    if (d_out) {
+        long long nb_total = 0;
+        for (int d = 0; d < 4; d++) nb_total += (c->count[d] * (d + 1) + MEASURE_BLOCK - 1) / MEASURE_BLOCK;
+        if (!c->meas_part) c->meas_part = static_cast<double *>(dev_alloc((size_t)(2 * nb_total + 2) * sizeof(double)));
+        part = c->meas_part;
+    }
+    long long off = 0;
+    int nb = 0;
+    measure_bwd_dim<1>(c, x, r, g, contrib, off, s, part, &nb);
+    measure_bwd_dim<2>(c, x, r, g, contrib, off, s, part, &nb);
+    measure_bwd_dim<3>(c, x, r, g, contrib, off, s, part, &nb);
+    measure_bwd_dim<4>(c, x, r, g, contrib, off, s, part, &nb);
+    if (d_out) {
+        k_measure_total<<<1, MEASURE_BLOCK, 0, s>>>(part, nb, d_out);
+        LAUNCH_CHECK();
+    }
+    k_measure_gather<<<(unsigned)((n + MEASURE_BLOCK - 1) / MEASURE_BLOCK), MEASURE_BLOCK, 0, s>>>(
+        c->inc_start, c->inc_slot, contrib, (int)n, dx, dr);
+    LAUNCH_CHECK();
+}
+
+ac_status ac_union_measure_fused(ac_complex *c, const double *d_xyz, const double *d_radii, int64_t n,
+                                 const double *d_grad, double *d_out, double *d_dxyz, double *d_dradii, void *stream) {
+    try {
+        check_measure_args(c, d_xyz, d_radii, n);
+        if (!d_grad || !d_out || !d_dxyz || !d_dradii) throw HipError{AC_E_INVALID, "NULL output or gradient pointer"};
+        measure_backward(c, d_xyz, d_radii, n, d_grad, d_dxyz, d_dradii, d_out, static_cast<hipStream_t>(stream));
+    } catch (const HipError &e) {
+        return set_error(e.st, e.msg);
+    } catch (...) {
+        return set_error(AC_E_DEVICE, "unexpected host exception");
+    }
+    g_last_error.clear();
+    return AC_OK;
+}
+
 ac_status ac_union_measure_backward(ac_complex *c, const double *d_xyz, const double *d_radii, int64_t n,
                                     const double *d_grad, double *d_dxyz, double *d_dradii, void *stream) {
     try {
         check_measure_args(c, d_xyz, d_radii, n);
         if (!d_grad || !d_dxyz || !d_dradii) throw HipError{AC_E_INVALID, "NULL gradient pointer"};
-        hipStream_t s = static_cast<hipStream_t>(stream);
-        ensure_incidence(c, s);
-        const long long M = incidence_count(c);
-        if (!c->meas_contrib) c->meas_contrib = static_cast<double4 *>(dev_alloc((size_t)(M > 0 ? M : 1) * sizeof(double4)));
-        double4 *contrib = c->meas_contrib;
-        long long off = 0;
-        measure_bwd_dim<1>(c, d_xyz, d_radii, d_grad, contrib, off, s);
-        measure_bwd_dim<2>(c, d_xyz, d_radii, d_grad, contrib, off, s);
-        measure_bwd_dim<3>(c, d_xyz, d_radii, d_grad, contrib, off, s);
-        measure_bwd_dim<4>(c, d_xyz, d_radii, d_grad, contrib, off, s);
-        k_measure_gather<<<(unsigned)((n + MEASURE_BLOCK - 1) / MEASURE_BLOCK), MEASURE_BLOCK, 0, s>>>(
-            c->inc_start, c->inc_slot, contrib, (int)n, d_dxyz, d_dradii);
-        LAUNCH_CHECK();
+        measure_backward(c, d_xyz, d_radii, n, d_grad, d_dxyz, d_dradii, nullptr, static_cast<hipStream_t>(stream));
     } catch (const HipError &e) {
         return set_error(e.st, e.msg);
     } catch (...) {

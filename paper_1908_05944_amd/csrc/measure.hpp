@@ -277,25 +277,53 @@ __global__ void __launch_bounds__(MEASURE_BLOCK) k_measure_total(const double *_
 // Per incidence slot (simplex s, corner c at slot base + s*K + c; one thread
 // each): the corner's contribution gV * d(V)/d(p, r) + gA * d(A)/d(p, r),
 // as (x, y, z, r), with (gV, gA) = (g[0], g[1]) read from device memory.
-template <int K>
+// VA: the block's signed volume and area parts too, as k_measure_fwd writes
+// them (forward and backward in one pass).
+template <int K, bool VA>
 __global__ void __launch_bounds__(MEASURE_BLOCK) k_measure_bwd(const int *__restrict__ simp, long long m,
                                                                 const double *__restrict__ xyz,
                                                                 const double *__restrict__ rad,
                                                                 const double *__restrict__ g,
-                                                                double4 *__restrict__ contrib) {
+                                                                double4 *__restrict__ contrib,
+                                                                double *__restrict__ part) {
     const long long t = (long long)blockIdx.x * MEASURE_BLOCK + threadIdx.x;
-    if (t >= m * K) return;
-    const double gV = g[0], gA = g[1];
-    D3 P[K];
-    double R[K];
-    load_balls<K>(simp, t / K, (int)(t % K), xyz, rad, P, R);
-    CornerTerms ct;
-    corner_terms<K, true>(P, R, ct);
     const double sg = ((K - 1) & 1) ? -1.0 : 1.0;
-    const double ir = 2.0 / R[0];
-    const D3 gx = (sg * gV) * ct.vec + (sg * gA) * (ir * ct.vec + ct.arc_vec);
-    const double gr = sg * (gV * ct.area + gA * (ir * ct.area + ct.arc_len));
-    contrib[t] = make_double4(gx.x, gx.y, gx.z, gr);
+    double v = 0, a = 0;
+    if (t < m * K) {
+        const double gV = g[0], gA = g[1];
+        D3 P[K];
+        double R[K];
+        load_balls<K>(simp, t / K, (int)(t % K), xyz, rad, P, R);
+        CornerTerms ct;
+        corner_terms<K, true>(P, R, ct);
+        const double ir = 2.0 / R[0];
+        const D3 gx = (sg * gV) * ct.vec + (sg * gA) * (ir * ct.vec + ct.arc_vec);
+        const double gr = sg * (gV * ct.area + gA * (ir * ct.area + ct.arc_len));
+        contrib[t] = make_double4(gx.x, gx.y, gx.z, gr);
+        v = sg * ct.vol;
+        a = sg * ct.area;
+    }
+    if (!VA) return;
+    __shared__ double sv[MEASURE_BLOCK / WAVE], sa[MEASURE_BLOCK / WAVE];
+    for (int off = WAVE / 2; off > 0; off >>= 1) {
+        v += __shfl_down(v, off, WAVE);
+        a += __shfl_down(a, off, WAVE);
+    }
+    const int w = threadIdx.x / WAVE;
+    if (lane_id() == 0) {
+        sv[w] = v;
+        sa[w] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tv = 0, ta = 0;
+        for (int k = 0; k < MEASURE_BLOCK / WAVE; k++) {
+            tv += sv[k];
+            ta += sa[k];
+        }
+        part[2 * blockIdx.x] = tv;
+        part[2 * blockIdx.x + 1] = ta;
+    }
 }
 
 // vstart[i] = first position of vertex i in the sorted incidence keys (i in [0, n]).

@@ -114,6 +114,22 @@ def test_repeat_calls_are_bitwise_equal(acx):
     assert torch.equal(acx.ac_union_measure_device(c, X, R).cpu(), torch.tensor(first, dtype=torch.float64))
 
 
+def test_fused_forward_backward(acx):
+    """One pass gives the forward's V, A (to rounding) and the backward's
+    gradient bit for bit."""
+    import torch
+    m = synth.molecule(3000, 8).with_sas(1400)
+    X, R = _dev(m.xyz), _dev(m.radii)
+    c = acx.ac_alpha_complex_device(X, R, 0.0)
+    for gv, ga in ((1.0, 0.0), (0.3, -2.0)):
+        g = torch.tensor([gv, ga], dtype=torch.float64, device="cuda:0")
+        va, dx, dr = acx.ac_union_measure_fused(c, X, R, g)
+        V, A = acx.ac_union_measure(c, X, R)
+        dx1, dr1 = acx.ac_union_measure_backward(c, X, R, g)
+        assert abs(va[0].item() - V) <= 1e-13 * abs(V) and abs(va[1].item() - A) <= 1e-13 * abs(A)
+        assert torch.equal(dx, dx1) and torch.equal(dr, dr1)
+
+
 def test_autograd_function(acx):
     import torch
     m = synth.molecule(2000, 6)
