@@ -513,6 +513,7 @@ __device__ __forceinline__ int find_tri(const int *__restrict__ up_start, const 
 // host runs the TRI_FILL pass over scanned counts instead (same result).
 enum { TRI_ONEPASS = 0, TRI_FILL = 1 };
 constexpr int TRI_SLOT = 8;
+constexpr int AC2_GROUP = 4;  // neighbours loaded together in the edge AC2 loop
 constexpr int TRI_SLAB = 1024;
 
 template <int MODE>
@@ -538,14 +539,24 @@ __global__ void __launch_bounds__(BLOCK) k_triangles(const int4 *__restrict__ at
             const int ns = nbr_start[i], ne = ns + nbr_cnt[i];
             const Edge ed = edge_setup(vi, vj);
             // every neighbour is tested (no early exit: most edges pass, and
-            // the loop stays convergent); only filter-undecided ones branch
+            // the loop stays convergent); only filter-undecided ones branch.
+            // Neighbours go in groups of AC2_GROUP whose loads are all issued
+            // before the first test, so a wave has several in flight.
             bool viol = false;
-            for (int p = ns; p < ne; p++) {
-                const int q = nbr[p];
-                const int4 aq = atom[q];
-                int sg = pp.force_exact ? 0 : edge_violation_filter(ed, aq);
-                if (sg == 0 && q != j) sg = edge_violation_sign(ed, i, j, aq, q, perm, 1);
-                viol |= (sg < 0) & (q != j);
+            for (int p0 = ns; p0 < ne; p0 += AC2_GROUP) {
+                int qs[AC2_GROUP];
+                int4 aqs[AC2_GROUP];
+#pragma unroll
+                for (int u = 0; u < AC2_GROUP; u++) qs[u] = p0 + u < ne ? nbr[p0 + u] : j;
+#pragma unroll
+                for (int u = 0; u < AC2_GROUP; u++) aqs[u] = atom[qs[u]];
+#pragma unroll
+                for (int u = 0; u < AC2_GROUP; u++) {
+                    const int q = qs[u];  // padding entries repeat j, which is never tested
+                    int sg = pp.force_exact ? 0 : edge_violation_filter(ed, aqs[u]);
+                    if (sg == 0 && q != j) sg = edge_violation_sign(ed, i, j, aqs[u], q, perm, 1);
+                    viol |= (sg < 0) & (q != j);
+                }
             }
             egab[e] = (unsigned char)!viol;
         }
