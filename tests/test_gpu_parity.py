@@ -159,6 +159,15 @@ def test_errors(acx):
     assert c.counts() == [0, 0, 0, 0]
 
 
+@pytest.mark.parametrize("sas,alpha", [(False, 1.0), (False, 2.5), (True, 0.5)])
+def test_100k_alpha_parity(acx, sas, alpha):
+    """alpha > 0 at full 100k size: the wide neighbour slots (grown radius
+    1.9-2.6 A) and, with SAS radii, the counted-fill path."""
+    m = synth.config_100k(sas=sas)
+    got = _run(acx, m.xyz, m.radii, alpha)
+    assert_same_complex(got, oracle.alpha_complex(m.xyz, m.radii, alpha), f"100k sas={sas} alpha={alpha}")
+
+
 @pytest.mark.parametrize("sas", [False, True])
 def test_100k_full_parity(acx, sas):
     m = synth.config_100k(sas=sas)
