@@ -31,6 +31,7 @@
  * <= 2 sqrt(W_max + alpha_q) < 2^14 (a face's OrthoSize never exceeds its
  * coface's, Sec. 4.3); only for those are ortho-centres formed.
  */
+#define _GNU_SOURCE /* qsort_r: comparators take their context as an argument (thread safety) */
 #include "oracle.h"
 
 #include <math.h>
@@ -567,10 +568,11 @@ static int viol_tri(const opt *P, int p0, int p1, int p2, int q) {
 /* Sorting helpers                                                           */
 
 typedef struct { int v[4]; long double s; } orow;
-static int g_cmp_dim;
-static int cmp_row(const void *a, const void *b) {
+/* ctx: the dimension of the rows (compared on their first dim + 1 ids) */
+static int cmp_row(const void *a, const void *b, void *ctx) {
     const orow *x = (const orow *)a, *y = (const orow *)b;
-    for (int k = 0; k <= g_cmp_dim; k++)
+    const int dim = *(const int *)ctx;
+    for (int k = 0; k <= dim; k++)
         if (x->v[k] != y->v[k]) return x->v[k] < y->v[k] ? -1 : 1;
     return 0;
 }
@@ -625,17 +627,17 @@ static int quantise(int64_t n, const double *xyz, const double *radii, double al
     return ORACLE_OK;
 }
 
-static const opt *g_sortP;
-static int cmp_pt(const void *a, const void *b) {
-    const opt *p = g_sortP + *(const int *)a, *q = g_sortP + *(const int *)b;
+/* ctx: the point array the indices refer to */
+static int cmp_pt(const void *a, const void *b, void *ctx) {
+    const opt *P = (const opt *)ctx;
+    const opt *p = P + *(const int *)a, *q = P + *(const int *)b;
     if (p->x != q->x) return p->x < q->x ? -1 : 1;
     if (p->y != q->y) return p->y < q->y ? -1 : 1;
     return (p->z > q->z) - (p->z < q->z);
 }
 
 static int emit(oracle_result *out, int d, orow *rows, int64_t m) {
-    g_cmp_dim = d;
-    qsort(rows, (size_t)m, sizeof(orow), cmp_row);
+    qsort_r(rows, (size_t)m, sizeof(orow), cmp_row, &d);
     out->count[d] = m;
     out->simp[d] = (int32_t *)malloc((size_t)(m ? m : 1) * (d + 1) * sizeof(int32_t));
     out->size[d] = (double *)malloc((size_t)(m ? m : 1) * sizeof(double));
@@ -647,6 +649,7 @@ static int emit(oracle_result *out, int d, orow *rows, int64_t m) {
     return 1;
 }
 
+#define SMALL_ROUTE_MAX 4096 /* largest input taken by the low-dimensional route */
 static int small_route(const opt *P, int n, i64 aq, oracle_result *out);
 
 int oracle_alpha_complex(int64_t n64, const double *xyz, const double *radii, double alpha, uint64_t order_seed,
@@ -663,10 +666,9 @@ int oracle_alpha_complex(int64_t n64, const double *xyz, const double *radii, do
         int *ix = (int *)malloc((size_t)n * sizeof(int));
         if (!ix) { free(P); return ORACLE_E_NOMEM; }
         for (int i = 0; i < n; i++) ix[i] = i;
-        g_sortP = P;
-        qsort(ix, (size_t)n, sizeof(int), cmp_pt);
+        qsort_r(ix, (size_t)n, sizeof(int), cmp_pt, P);
         for (int i = 1; i < n; i++)
-            if (cmp_pt(ix + i - 1, ix + i) == 0) { free(ix); free(P); return ORACLE_E_DUPLICATE; }
+            if (cmp_pt(ix + i - 1, ix + i, P) == 0) { free(ix); free(P); return ORACLE_E_DUPLICATE; }
         free(ix);
     }
 
@@ -679,12 +681,16 @@ int oracle_alpha_complex(int64_t n64, const double *xyz, const double *radii, do
     int *order = (int *)malloc((size_t)n * sizeof(int));
     int *used = (int *)calloc((size_t)n, sizeof(int));
     if (!order || !used) { free(order); free(used); free(P); return ORACLE_E_NOMEM; }
-    int ok = n >= 4 && make_order(P, n, order_seed, order);
-    int init = ok ? init_simplex(&T, order, n, used) : 0;
+    if (n >= 4 && !make_order(P, n, order_seed, order)) {
+        free(order); free(used); free(P);
+        return ORACLE_E_NOMEM;
+    }
+    /* init_simplex fails (0) only when no four centres span a tetrahedron */
+    int init = n >= 4 ? init_simplex(&T, order, n, used) : 0;
     if (init <= 0) {
         free(order); free(used); tri_destroy(&T);
         if (init < 0) { free(P); return ORACLE_E_NOMEM; }
-        st = (n <= 64) ? small_route(P, n, aq, out) : ORACLE_E_DEGENERATE;
+        st = (n <= SMALL_ROUTE_MAX) ? small_route(P, n, aq, out) : ORACLE_E_DEGENERATE;
         free(P);
         return st;
     }
@@ -945,13 +951,6 @@ static int64_t edge_lookup(const int64_t *vstart, const int64_t *adj_v, const in
 
 /* ---------------------------------------------------------------------- */
 
-static int tuple_passes(const opt *P, const int *v, int k, i64 aq) {
-    for (int i = 0; i < k; i++)
-        for (int j = i + 1; j < k; j++)
-            if (!edge_passes(P, v[i], v[j], aq)) return 0;
-    return 1;
-}
-
 static int contains_all(const int *big, int nb, const int *small, int ns) {
     for (int i = 0; i < ns; i++) {
         int f = 0;
@@ -961,93 +960,99 @@ static int contains_all(const int *big, int nb, const int *small, int ns) {
     return 1;
 }
 
-/* Inputs whose D is not three-dimensional (n < 4, or all centres coplanar),
- * n <= 64: every subset of up to four balls is examined directly. A simplex
- * is in K_alpha iff its ortho-centre is a witness with OrthoSize <= alpha, or
- * one of its immediate cofaces is in K_alpha (its Size is then the least Size
- * of such a coface). Counts of D are not produced on this route (-1). */
-static int small_route(const opt *P, int n, i64 aq, oracle_result *out) {
-    int64_t cap = 1;
-    for (int k = 0; k < 4; k++) cap = cap * (n + 1) / (k + 1) + 1;
-    orow *rows[4];
-    int64_t cnt[4] = {0, 0, 0, 0};
-    for (int d = 0; d < 4; d++) rows[d] = (orow *)malloc((size_t)(cap + 1) * sizeof(orow));
-    for (int d = 0; d < 4; d++)
-        if (!rows[d]) { for (int k = 0; k < 4; k++) free(rows[k]); return ORACLE_E_NOMEM; }
-    for (int a = 0; a < n; a++)
-        for (int b = a + 1; b < n; b++)
-            for (int c = b + 1; c < n; c++)
-                for (int d = c + 1; d < n; d++) {
-                    int v[4] = {a, b, c, d};
-                    if (orient(P, a, b, c, d) == 0 || !tuple_passes(P, v, 4, aq)) continue;
-                    rat os = os_tet(P, v);
-                    if (!rat_le(os, aq)) continue;
-                    int w[4] = {a, b, c, d};
-                    if (orient(P, a, b, c, d) < 0) { w[0] = b; w[1] = a; }
-                    int gab = 1;
-                    for (int q = 0; q < n && gab; q++)
-                        if (q != a && q != b && q != c && q != d && power_sign(P, w, q) < 0) gab = 0;
-                    if (!gab) continue;
-                    orow *r = &rows[3][cnt[3]++];
-                    memcpy(r->v, v, sizeof v);
-                    r->s = rat_ld(os);
-                }
-    for (int dim = 2; dim >= 0; dim--) {
-        const int k = dim + 1;
-        int v[3] = {0, 1, 2};
-        if (n < k) continue;
-        for (;;) {
-            int skip = !tuple_passes(P, v, k, aq);
-            if (!skip && k == 3) { /* collinear triples span no triangle */
-                i64 ux = P[v[1]].x - P[v[0]].x, uy = P[v[1]].y - P[v[0]].y, uz = P[v[1]].z - P[v[0]].z;
-                i64 wx = P[v[2]].x - P[v[0]].x, wy = P[v[2]].y - P[v[0]].y, wz = P[v[2]].z - P[v[0]].z;
-                skip = (i128)uy * wz - (i128)uz * wy == 0 && (i128)uz * wx - (i128)ux * wz == 0 &&
-                       (i128)ux * wy - (i128)uy * wx == 0;
-            }
-            if (!skip) {
-                int gab = 1;
-                for (int q = 0; q < n && gab; q++) {
-                    if (contains_all(v, k, &q, 1)) continue;
-                    int sg = k == 1 ? viol_vertex(P, v[0], q)
-                                    : (k == 2 ? viol_edge(P, v[0], v[1], q) : viol_tri(P, v[0], v[1], v[2], q));
-                    if (sg < 0) gab = 0;
-                }
-                int in = 0;
-                long double sz = 0;
-                if (gab) {
-                    rat os = k == 1 ? os_vertex(P, v[0]) : (k == 2 ? os_edge(P, v[0], v[1]) : os_tri(P, v[0], v[1], v[2]));
-                    if (rat_le(os, aq)) { in = 1; sz = rat_ld(os); }
-                } else {
-                    for (int64_t t = 0; t < cnt[dim + 1]; t++)
-                        if (contains_all(rows[dim + 1][t].v, k + 1, v, k) && (!in || rows[dim + 1][t].s < sz)) {
-                            in = 1;
-                            sz = rows[dim + 1][t].s;
-                        }
-                }
-                if (in) {
-                    orow *r = &rows[dim][cnt[dim]++];
-                    r->v[0] = v[0]; r->v[1] = k > 1 ? v[1] : 0; r->v[2] = k > 2 ? v[2] : 0; r->v[3] = 0;
-                    r->s = sz;
-                }
-            }
-            /* next k-subset in lexicographic order */
-            int i = k - 1;
-            while (i >= 0 && v[i] == n - k + i) i--;
-            if (i < 0) break;
-            v[i]++;
-            for (int j = i + 1; j < k; j++) v[j] = v[j - 1] + 1;
-        }
+/* Appends row v (k ids, ascending) with Size s to the rows of dimension d. */
+static int push_row(orow **rows, int64_t *cnt, int64_t *cap, int d, const int *v, int k, long double s) {
+    if (cnt[d] == cap[d]) {
+        int64_t nc = cap[d] ? 2 * cap[d] : 64;
+        orow *r = (orow *)realloc(rows[d], (size_t)nc * sizeof(orow));
+        if (!r) return 0;
+        rows[d] = r;
+        cap[d] = nc;
     }
-    for (int d = 0; d < 4; d++) {
-        out->d_count[d] = -1;
-        if (!emit(out, d, rows[d], cnt[d])) {
-            for (int k = 0; k < 4; k++) free(rows[k]);
-            oracle_free(out);
-            return ORACLE_E_NOMEM;
+    orow *r = &rows[d][cnt[d]++];
+    for (int i = 0; i < 4; i++) r->v[i] = i < k ? v[i] : 0;
+    r->s = s;
+    return 1;
+}
+
+static int collinear(const opt *P, int a, int b, int c) {
+    i64 ux = P[b].x - P[a].x, uy = P[b].y - P[a].y, uz = P[b].z - P[a].z;
+    i64 wx = P[c].x - P[a].x, wy = P[c].y - P[a].y, wz = P[c].z - P[a].z;
+    return (i128)uy * wz - (i128)uz * wy == 0 && (i128)uz * wx - (i128)ux * wz == 0 &&
+           (i128)ux * wy - (i128)uy * wx == 0;
+}
+
+/* Membership and Size of the k-subset v (k = 1..3, ascending ids) whose edges
+ * all pass the edge OrthoSize test, given the kept (k+1)-subsets cof[0..ncof).
+ * In K_alpha iff its ortho-centre is a witness (no other ball strictly closer
+ * in power, ties by the perturbation) with OrthoSize <= alpha, or an
+ * immediate coface is in K_alpha; the Size is then the least Size of such a
+ * coface (Sec. 2.3). */
+static int decide_low(const opt *P, int n, i64 aq, const int *v, int k, const orow *cof, int64_t ncof,
+                      long double *sz) {
+    int gab = 1;
+    for (int q = 0; q < n && gab; q++) {
+        if (contains_all(v, k, &q, 1)) continue;
+        int sg = k == 1 ? viol_vertex(P, v[0], q)
+                        : (k == 2 ? viol_edge(P, v[0], v[1], q) : viol_tri(P, v[0], v[1], v[2], q));
+        if (sg < 0) gab = 0;
+    }
+    if (gab) {
+        rat os = k == 1 ? os_vertex(P, v[0]) : (k == 2 ? os_edge(P, v[0], v[1]) : os_tri(P, v[0], v[1], v[2]));
+        if (!rat_le(os, aq)) return 0;
+        *sz = rat_ld(os);
+        return 1;
+    }
+    int in = 0;
+    for (int64_t t = 0; t < ncof; t++)
+        if (contains_all(cof[t].v, k + 1, v, k) && (!in || cof[t].s < *sz)) {
+            in = 1;
+            *sz = cof[t].s;
         }
+    return in;
+}
+
+/* Inputs whose D is not three-dimensional: fewer than four balls, or every
+ * centre on one plane. No four centres then span a tetrahedron, so D has no
+ * tetrahedra, and every triple, pair and single ball is examined directly
+ * (n <= SMALL_ROUTE_MAX) by decide_low, triangles first. A subset with an edge
+ * failing the edge OrthoSize test is skipped: its OrthoSize, and so its Size
+ * and that of any coface, exceeds alpha (a face's OrthoSize never exceeds its
+ * coface's, Sec. 4.3). Counts of D are not produced on this route (-1). */
+static int small_route(const opt *P, int n, i64 aq, oracle_result *out) {
+    orow *rows[4] = {NULL, NULL, NULL, NULL};
+    int64_t cnt[4] = {0, 0, 0, 0}, cap[4] = {0, 0, 0, 0};
+    int ok = 1;
+    long double sz = 0;
+    for (int a = 0; a < n && ok; a++)
+        for (int b = a + 1; b < n && ok; b++) {
+            if (!edge_passes(P, a, b, aq)) continue;
+            for (int c = b + 1; c < n && ok; c++) {
+                if (!edge_passes(P, a, c, aq) || !edge_passes(P, b, c, aq) || collinear(P, a, b, c)) continue;
+                int v[3] = {a, b, c};
+                if (decide_low(P, n, aq, v, 3, rows[3], cnt[3], &sz)) ok = push_row(rows, cnt, cap, 2, v, 3, sz);
+            }
+        }
+    for (int a = 0; a < n && ok; a++)
+        for (int b = a + 1; b < n && ok; b++) {
+            if (!edge_passes(P, a, b, aq)) continue;
+            int v[2] = {a, b};
+            if (decide_low(P, n, aq, v, 2, rows[2], cnt[2], &sz)) ok = push_row(rows, cnt, cap, 1, v, 2, sz);
+        }
+    for (int a = 0; a < n && ok; a++) {
+        int v[1] = {a};
+        if (decide_low(P, n, aq, v, 1, rows[1], cnt[1], &sz)) ok = push_row(rows, cnt, cap, 0, v, 1, sz);
+    }
+    for (int d = 0; d < 4 && ok; d++) {
+        out->d_count[d] = -1;
+        ok = emit(out, d, rows[d], cnt[d]);
+    }
+    for (int d = 0; d < 4; d++) free(rows[d]);
+    if (!ok) {
+        oracle_free(out);
+        return ORACLE_E_NOMEM;
     }
     out->n_hidden = -1;
-    for (int d = 0; d < 4; d++) free(rows[d]);
     return ORACLE_OK;
 }
 

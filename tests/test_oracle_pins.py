@@ -326,3 +326,98 @@ def test_oracle_100k_invariants():
         v, e, f, t = a.d_count
         assert v - e + f - t == 1 and a.n_hidden == 0
         assert a.counts()[0] == mol.n
+
+
+def test_quantisation_rounds_half_to_even():
+    """Coordinates and radii are rounded to integer milli-angstrom, half to
+    even (the reading of the 0.001 A input lattice; the paper fixes no rule).
+    Multiples of 1/16 A are exact binary values whose x 1000 ends in .5, so a
+    half-away-from-zero rounding would change every value below.
+    - one ball of radius 1.0625 A: R = 1062 mA (half-away: 1063), so its
+      vertex Size is -1062^2 mA^2 = -1.127844 A^2; radius 1.1875 A: R = 1188,
+      Size -1.411344 A^2 (ties go up as well as down);
+    - two balls of radius 1.5 A at x = -0.0625 and x = 2.0625 A: centres -62
+      and 2062 mA, d = 2124 mA; equal weights put the radical plane at d / 2,
+      so the edge's Size is (d / 2)^2 - 1500^2 = 1127844 - 2250000 mA^2
+      = -1.122156 A^2 (half-away: d = 2126, -1.120031)."""
+    for r, want in ((1.0625, -1.127844), (1.1875, -1.411344), (0.0625 + 1.5, -(1562 ** 2) / 1e6)):
+        c = oracle.alpha_complex(np.array([[0.0625, -0.1875, 0.3125]]), np.array([r]), 0.0)
+        assert c.counts() == [1, 0, 0, 0]
+        assert c.sizes[0][0] == want, (r, c.sizes[0][0], want)
+    xyz = np.array([[-0.0625, 0.0625, -0.1875], [2.0625, 0.0625, -0.1875]])
+    c = oracle.alpha_complex(xyz, np.array([1.5, 1.5]), 0.0)
+    assert c.simplices[1].tolist() == [[0, 1]]
+    assert abs(c.sizes[1][0] - (-1.122156)) <= 1e-12
+    # the tie along y and z: 2.0625 A apart on y, the pair shifted on z by a tie
+    xyz = np.array([[0.0, -0.0625, 0.1875], [0.0, 2.0625, 0.1875]])
+    c = oracle.alpha_complex(xyz, np.array([1.5, 1.5]), 0.0)
+    assert abs(c.sizes[1][0] - (-1.122156)) <= 1e-12
+
+
+def _planar_molecule(n, seed, spacing=2.4):
+    """n centres on the plane z = 0 (dart throwing with minimum separation
+    `spacing` at 0.1 atoms per A^2 in a disk, on a background grid of cells
+    of side spacing / sqrt(2): at most one centre per cell), vdW radii."""
+    rng = np.random.RandomState(seed)
+    R = math.sqrt(n / (math.pi * 0.1))
+    h = spacing / math.sqrt(2.0)
+    grid = {}
+    pts = []
+    while len(pts) < n:
+        p = rng.uniform(-R, R, 2)
+        if p @ p > R * R:
+            continue
+        cx, cy = int(math.floor(p[0] / h)), int(math.floor(p[1] / h))
+        near = (grid.get((cx + i, cy + j)) for i in range(-2, 3) for j in range(-2, 3))
+        if all(q is None or (p - q) @ (p - q) >= spacing * spacing for q in near):
+            grid[(cx, cy)] = p
+            pts.append(p)
+    xyz = np.zeros((n, 3))
+    xyz[:, :2] = np.round(np.array(pts) * 1000) / 1000
+    rad = rng.choice([1.70, 1.55, 1.52, 1.80], size=n, p=[0.62, 0.17, 0.19, 0.02])
+    return xyz, rad
+
+
+def test_bruteforce_coplanar_molecule():
+    """Twenty coplanar balls of a planar molecule: the low-dimensional route
+    against the definition-level brute force."""
+    xyz, rad = _planar_molecule(20, 31)
+    for alpha in (0.0, 1.0, 4.0):
+        _compare_bruteforce(xyz, rad, alpha)
+
+
+@pytest.mark.parametrize("n", [150, 600, 3000])
+def test_coplanar_route_against_lifted_apex(n):
+    """All centres on one plane, more balls than a brute force can take. Adding
+    one tiny ball 300 A off the plane makes the input three-dimensional (the
+    incremental triangulation then builds it) without changing any simplex of
+    Size <= alpha on the plane: the apex is farther in power than 300^2 A^2
+    from every planar ortho-centre, so it violates none of them, and every
+    simplex through it has OrthoSize above 150^2 A^2. The planar part of the
+    lifted complex must therefore equal the low-dimensional route's result,
+    simplex for simplex and Size for Size."""
+    xyz, rad = _planar_molecule(n, 40 + n)
+    apex = np.vstack([xyz, [[xyz[:, 0].mean(), xyz[:, 1].mean(), 300.0]]])
+    arad = np.append(rad, 0.001)
+    for alpha in (0.0, 1.0, 5.0):
+        flat = oracle.alpha_complex(xyz, rad, alpha)
+        assert flat.d_count[0] == -1  # the low-dimensional route ran
+        lifted = oracle.alpha_complex(apex, arad, alpha)
+        assert lifted.d_count[0] > 0  # the three-dimensional route ran
+        for d in range(4):
+            keep = np.all(lifted.simplices[d] < n, axis=1)
+            assert np.array_equal(flat.simplices[d], lifted.simplices[d][keep]), (n, alpha, d)
+            assert np.array_equal(flat.sizes[d], lifted.sizes[d][keep]), (n, alpha, d)
+        assert flat.counts()[3] == 0
+        if alpha == 5.0:
+            assert flat.counts()[2] > n // 4
+
+
+def test_coplanar_beyond_route_limit_is_reported():
+    """More than 4096 coplanar balls: the oracle reports the input as
+    degenerate instead of answering."""
+    k = np.arange(4097)
+    xyz = np.stack([(k % 64) * 2.5, (k // 64) * 2.5, np.zeros(4097)], axis=1)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.alpha_complex(xyz, np.full(4097, 1.5), 0.0)
+    assert e.value.status == 7
