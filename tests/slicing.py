@@ -98,8 +98,10 @@ def _breakpoints(P, R):
     return np.unique(np.array(zs))
 
 
-def union_volume_area(xyz, radii):
-    """(V, A) of the union of the balls, by quadrature over z."""
+def union_volume_area(xyz, radii, nodes=48):
+    """(V, A) of the union of the balls, by quadrature over z with `nodes`
+    Gauss-Legendre nodes per panel."""
+    gx, gw = (GL_X, GL_W) if nodes == 48 else np.polynomial.legendre.leggauss(nodes)
     P = np.asarray(xyz, dtype=np.float64)
     R = np.asarray(radii, dtype=np.float64)
     zb = _breakpoints(P, R)
@@ -109,8 +111,8 @@ def union_volume_area(xyz, radii):
         if z1 - z0 <= 0:
             continue
         # z = z0 + (z1 - z0) (1 - cos(pi s)) / 2, s in [0, 1]
-        s = 0.5 * (GL_X + 1.0)
-        w = 0.5 * GL_W
+        s = 0.5 * (gx + 1.0)
+        w = 0.5 * gw
         for sk, wk in zip(s, w):
             z = z0 + (z1 - z0) * 0.5 * (1 - math.cos(math.pi * sk))
             jac = (z1 - z0) * 0.5 * math.pi * math.sin(math.pi * sk)

@@ -74,6 +74,38 @@ def test_small_configurations_match_slicing(name):
     assert abs(A - As) <= 1e-11 * As, (c.counts(), A, As)
 
 
+# Near-degenerate four-ball sets (found by a seeded search, kept as data):
+# a common intersection of four balls that is tiny (tetrahedron OrthoSize
+# -0.011 and -0.012 A^2), centres almost coplanar (tetrahedra of 0.029 and
+# 0.018 A^3), and a small ball near the triple region of three large ones.
+DEGENERATE4 = {
+    "tiny_a": ([[1.55, -0.622, -0.522], [0.004, 0.484, -0.661], [0.411, 0.036, 1.11], [-0.622, -0.955, -0.077]],
+               [1.373, 1.712, 1.344, 1.084]),
+    "tiny_b": ([[-0.585, 1.018, -1.017], [-0.291, -0.253, 1.396], [0.406, -0.468, -1.192], [-1.061, -1.515, -0.911]],
+               [1.692, 1.424, 1.316, 1.797]),
+    "flat_a": ([[-0.479, 1.412, 0.244], [1.294, 1.173, 0.242], [0.615, 1.424, -0.807], [1.024, 1.172, -0.123]],
+               [1.402, 1.604, 1.343, 1.393]),
+    "flat_b": ([[0.64, -0.228, -0.319], [-0.093, -0.197, -1.019], [-0.544, -0.575, 1.536], [-1.425, -0.503, 0.065]],
+               [1.006, 1.417, 1.406, 1.521]),
+    "inner_a": ([[1.1, -1.332, -0.634], [0.13, -0.154, -0.938], [0.947, 0.012, -1.057], [0.407, -1.009, 0.485]],
+                [1.26, 1.316, 1.608, 0.536]),
+    "inner_b": ([[-1.557, -0.53, 0.8], [-0.569, -0.676, -0.507], [-0.558, -1.217, 1.341], [-0.205, -0.135, 0.722]],
+                [1.469, 1.158, 1.633, 0.516]),
+}
+
+
+@pytest.mark.parametrize("name", sorted(DEGENERATE4))
+def test_near_degenerate_four_balls_match_slicing(name):
+    """Each set is one tetrahedron with all its faces in K_0; the slicing
+    quadrature at 96 nodes per panel converges to about 1e-15 on them."""
+    xyz, rad = DEGENERATE4[name]
+    c, (V, A) = _measure(xyz, rad)
+    assert c.counts() == [4, 6, 4, 1]
+    Vs, As = union_volume_area(xyz, rad, nodes=96)
+    assert abs(V - Vs) <= 1e-13 * Vs, (V, Vs)
+    assert abs(A - As) <= 1e-13 * As, (A, As)
+
+
 def test_random_sets_match_slicing():
     rng = np.random.RandomState(5)
     dims = np.zeros(4)
