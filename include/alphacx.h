@@ -51,18 +51,20 @@ typedef enum {
 typedef struct ac_complex ac_complex;
 
 /* Tuning knobs; a zeroed struct (or NULL) selects the defaults. None of them
- * changes the result. */
+ * changes the result. Every field is checked: a value outside its stated
+ * range makes the call return AC_E_INVALID before any device work. */
 typedef struct {
-    int32_t cell_mA;         /* uniform-grid cell side in milli-angstrom; 0 = ceil(sqrt(r_max^2 + alpha)) */
-    int32_t wave_tile;       /* reserved for the batched path; 0 = default */
-    int32_t force_exact;     /* 1 = skip the floating-point filter, decide every predicate in exact integers */
-    int32_t vertex_shortcut; /* 1 = take every ball whose OrthoSize -r^2 <= alpha as a vertex without testing
-                                its own centre (the paper's implementation shortcut, Sec. 4.4); exact
+    int32_t cell_mA;         /* uniform-grid cell side in milli-angstrom, >= 0; 0 = ceil(sqrt(r_max^2 + alpha)) */
+    int32_t wave_tile;       /* must be 0: every kernel maps one work item (ball, edge, triangle, tetrahedron,
+                                simplex corner) to one lane, so there is no tile to choose */
+    int32_t force_exact;     /* 0 or 1; 1 = skip the floating-point filter, decide every predicate in exact integers */
+    int32_t vertex_shortcut; /* 0 or 1; 1 = take every ball whose OrthoSize -r^2 <= alpha as a vertex without
+                                testing its own centre (the paper's implementation shortcut, Sec. 4.4); exact
                                 only when no centre lies inside another ball's power cell */
-    int64_t capacity_hint;   /* expected simplices per atom for buffer sizing; 0 = adaptive */
-    int32_t profile;         /* 1 = record HIP events between pipeline stages (see ac_stage_ms);
-                                2 + i = record only the two events around stage i (each event
-                                adds a few microseconds of device idle time) */
+    int64_t capacity_hint;   /* must be 0: candidate and output buffers are sized from exact counts */
+    int32_t profile;         /* 0, 1 or 2 + i (0 <= i < ac_stage_count()); 1 = record HIP events between pipeline
+                                stages (see ac_stage_ms); 2 + i = record only the two events around stage i (each
+                                event adds a few microseconds of device idle time) */
     int32_t reserved;        /* must be 0 */
 } ac_options;
 
@@ -167,6 +169,12 @@ int64_t ac_molecule_count(const ac_complex *c);
  * owns rows [rows[m], rows[m+1]). Valid until ac_free; NULL for a bad dim. */
 const int64_t *ac_molecule_rows(const ac_complex *c, int dim);
 
+/* Molecule of every d-simplex of a batch result: a host array of
+ * ac_count(c, dim) int32 (row k belongs to molecule ac_molecule(c, dim)[k]),
+ * built on first use from ac_molecule_rows and valid until ac_free. NULL for a
+ * result not made by ac_alpha_complex_batch, or a bad dim. */
+const int32_t *ac_molecule(ac_complex *c, int dim);
+
 /* Cell-size autotuner for a batch (same arguments as ac_alpha_complex_batch).
  * The molecules are put in size buckets ([0, 2k), [2k, 8k), [8k, 32k) and
  * [32k, inf) balls); for each bucket its molecules are copied into one
@@ -218,15 +226,16 @@ double ac_stage_ms(const ac_complex *c, int i);
  * same n balls, V and A of the union of the balls are the alternating sums,
  * over the simplices of c, of the volume of the intersection of their balls
  * and of the area of each sphere's part inside the other balls (short
- * inclusion-exclusion over the dual complex, Edelsbrunner 1995). A complex
- * for another alpha gives the measure of the union of the balls grown to
- * sqrt(r^2 + alpha) when passed those grown radii.
+ * inclusion-exclusion over the dual complex, Edelsbrunner 1995).
  *
  * d_xyz (n x 3 row-major float64, angstrom) and d_radii (n float64) are device
  * arrays on the complex's device, read on `stream`; they are used as given
  * (not quantised), so finite differences over them see a smooth function of
  * the coordinates while the complex stays fixed. n must equal the number of
- * balls the complex was built on, else AC_E_INVALID.
+ * balls the complex was built on, and the complex must have been built at
+ * alpha = 0, else AC_E_INVALID (for the union of balls grown to
+ * sqrt(r^2 + alpha), build the complex of those grown radii at alpha = 0: it
+ * has the same simplices).
  *
  * The work buffers are kept with the complex: after the first call on a
  * complex these calls allocate nothing and do not synchronise the host

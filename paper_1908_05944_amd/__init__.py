@@ -129,6 +129,8 @@ def _load():
     lib.ac_molecule_count.restype = i64
     lib.ac_molecule_rows.argtypes = [c_p, ctypes.c_int]
     lib.ac_molecule_rows.restype = ctypes.POINTER(i64)
+    lib.ac_molecule.argtypes = [c_p, ctypes.c_int]
+    lib.ac_molecule.restype = ctypes.POINTER(ctypes.c_int32)
     lib.ac_tune_cells.argtypes = [c_p, c_p, c_p, i64, dbl, ctypes.POINTER(Options), c_p, c_p, c_p]
     lib.ac_tune_cells.restype = ctypes.c_int
     lib.ac_union_measure.argtypes = [c_p, c_p, c_p, i64, ctypes.POINTER(dbl), ctypes.POINTER(dbl), c_p]
@@ -223,6 +225,16 @@ class AlphaComplex:
 
     def molecule_count(self) -> int:
         return int(_load().ac_molecule_count(self._h))
+
+    def molecule(self, dim: int) -> np.ndarray:
+        """Molecule of every dim-simplex of a batch result (ac_molecule)."""
+        p = _load().ac_molecule(self._h, dim)
+        if not p:
+            _check(1)
+        m = self.count(dim)
+        if m == 0:
+            return np.zeros((0,), dtype=np.int32)
+        return np.ctypeslib.as_array(p, shape=(m,)).copy()
 
     def molecule_rows(self, dim: int) -> np.ndarray:
         """Rows [r[m], r[m+1]) of the dim-simplex array belong to molecule m."""

@@ -136,7 +136,10 @@ struct ac_complex {
     int64_t work[2] = {0, 0};
     int64_t n = 0;  // balls in the input
     int64_t n_mol = 1;
+    int64_t alpha_q = 0;  // the alpha the complex was built at (mA^2)
+    bool batch = false;   // made by ac_alpha_complex_batch
     std::vector<int64_t> mol_rows[4];  // per dimension: first row of each molecule, n_mol + 1 entries
+    std::vector<int32_t> h_mol[4];     // per dimension: molecule of each row (built on first ac_molecule)
     int32_t *d_simp[4] = {nullptr, nullptr, nullptr, nullptr};
     double *d_size[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<int32_t> h_simp[4];
@@ -903,6 +906,7 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             ac_complex *r = rs[k];
             if (k > 0) std::copy(res->stage_ms, res->stage_ms + 32, r->stage_ms);
             r->n_mol = n_mol;
+            r->alpha_q = aqs[k];
             r->cand[0] = n;
             r->cand[1] = E;
             r->cand[2] = T;
@@ -1110,6 +1114,7 @@ static ac_status run_partitioned(const double *d_xyz, const double *d_r, int64_t
             res->mol_rows[d] = {0, res->count[d]};
         }
         res->fallbacks = fallbacks;
+        res->alpha_q = aq;
         res->work[0] = res->work[1] = -1;
     } catch (const HipError &e) {
         (void)hipStreamSynchronize(s);
@@ -1135,6 +1140,9 @@ static void check_measure_args(const ac_complex *c, const double *d_xyz, const d
     if (!c) throw HipError{AC_E_INVALID, "complex is NULL"};
     if (!d_xyz || !d_radii) throw HipError{AC_E_INVALID, "NULL input pointer"};
     if (n != c->n) throw HipError{AC_E_INVALID, "n differs from the number of balls the complex was built on"};
+    if (c->alpha_q != 0)
+        throw HipError{AC_E_INVALID, "the complex was built at alpha != 0; for the union of grown balls build the "
+                                     "complex of radii sqrt(r^2 + alpha) at alpha = 0"};
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     if (dev != c->device) throw HipError{AC_E_INVALID, "the complex lives on another device"};
@@ -1259,14 +1267,26 @@ static ac_status timed_run(const double *x, const double *r, int64_t n, const Ba
     return AC_OK;
 }
 
+// Options of a call, validated: every field has a documented range and a
+// value outside it is an argument error, not silently replaced.
 static Options parse(const ac_options *opt) {
     Options o;
-    if (opt) {
-        o.cell_mA = opt->cell_mA;
-        o.force_exact = opt->force_exact != 0;
-        o.vertex_shortcut = opt->vertex_shortcut != 0;
-        o.profile = opt->profile >= 0 && opt->profile <= ST_COUNT + 1 ? opt->profile : 1;
-    }
+    if (!opt) return o;
+    if (opt->reserved != 0) throw HipError{AC_E_INVALID, "ac_options.reserved must be 0"};
+    if (opt->cell_mA < 0) throw HipError{AC_E_INVALID, "ac_options.cell_mA must be >= 0"};
+    if (opt->wave_tile != 0)
+        throw HipError{AC_E_INVALID, "ac_options.wave_tile must be 0 (every kernel maps one item to one lane)"};
+    if (opt->capacity_hint != 0)
+        throw HipError{AC_E_INVALID, "ac_options.capacity_hint must be 0 (buffers are sized from exact counts)"};
+    if (opt->force_exact != 0 && opt->force_exact != 1) throw HipError{AC_E_INVALID, "ac_options.force_exact must be 0 or 1"};
+    if (opt->vertex_shortcut != 0 && opt->vertex_shortcut != 1)
+        throw HipError{AC_E_INVALID, "ac_options.vertex_shortcut must be 0 or 1"};
+    if (opt->profile < 0 || opt->profile > ST_COUNT + 1)
+        throw HipError{AC_E_INVALID, "ac_options.profile must be 0, 1 or 2 + a stage index"};
+    o.cell_mA = opt->cell_mA;
+    o.force_exact = opt->force_exact;
+    o.vertex_shortcut = opt->vertex_shortcut;
+    o.profile = opt->profile;
     return o;
 }
 
@@ -1278,11 +1298,12 @@ ac_status ac_alpha_complex_device(const double *d_xyz, const double *d_radii, in
                                   const ac_options *opt, void *stream, ac_complex **out) {
     if (!out) return set_error(AC_E_INVALID, "out is NULL");
     *out = nullptr;
-    if (!d_xyz || !d_radii) return set_error(AC_E_INVALID, "NULL input pointer");
     try {
+        const Options o = parse(opt);
+        if (!d_xyz || !d_radii) return set_error(AC_E_INVALID, "NULL input pointer");
         Batch bt;
         bt.off = {0, n};
-        return run_pipeline(d_xyz, d_radii, n, bt, alpha, parse(opt), static_cast<hipStream_t>(stream), out);
+        return run_pipeline(d_xyz, d_radii, n, bt, alpha, o, static_cast<hipStream_t>(stream), out);
     } catch (const HipError &e) {
         return set_error(e.st, e.msg);
     } catch (...) {
@@ -1294,9 +1315,10 @@ ac_status ac_alpha_complex_partitioned(const double *d_xyz, const double *d_radi
                                        int32_t parts, const ac_options *opt, void *stream, ac_complex **out) {
     if (!out) return set_error(AC_E_INVALID, "out is NULL");
     *out = nullptr;
-    if (!d_xyz || !d_radii) return set_error(AC_E_INVALID, "NULL input pointer");
     try {
-        return run_partitioned(d_xyz, d_radii, n, alpha, parts, parse(opt), static_cast<hipStream_t>(stream), out);
+        const Options o = parse(opt);
+        if (!d_xyz || !d_radii) return set_error(AC_E_INVALID, "NULL input pointer");
+        return run_partitioned(d_xyz, d_radii, n, alpha, parts, o, static_cast<hipStream_t>(stream), out);
     } catch (const HipError &e) {
         return set_error(e.st, e.msg);
     } catch (...) {
@@ -1309,12 +1331,12 @@ ac_status ac_alpha_sweep_device(const double *d_xyz, const double *d_radii, int6
     if (!out) return set_error(AC_E_INVALID, "out is NULL");
     if (n_alpha < 1 || n_alpha > AC_MAX_SWEEP) return set_error(AC_E_INVALID, "number of alpha values out of range");
     for (int64_t k = 0; k < n_alpha; k++) out[k] = nullptr;
-    if (!d_xyz || !d_radii || !alphas) return set_error(AC_E_INVALID, "NULL input pointer");
     try {
+        const Options o = parse(opt);
+        if (!d_xyz || !d_radii || !alphas) return set_error(AC_E_INVALID, "NULL input pointer");
         Batch bt;
         bt.off = {0, n};
-        return run_pipeline(d_xyz, d_radii, n, bt, alphas, (int)n_alpha, parse(opt), static_cast<hipStream_t>(stream),
-                            out);
+        return run_pipeline(d_xyz, d_radii, n, bt, alphas, (int)n_alpha, o, static_cast<hipStream_t>(stream), out);
     } catch (const HipError &e) {
         return set_error(e.st, e.msg);
     } catch (...) {
@@ -1326,18 +1348,18 @@ ac_status ac_alpha_complex(const double *xyz, const double *radii, int64_t n, do
                            ac_complex **out) {
     if (!out) return set_error(AC_E_INVALID, "out is NULL");
     *out = nullptr;
-    if (!xyz || !radii) return set_error(AC_E_INVALID, "NULL input pointer");
-    if (n < 1 || n >= (1 << 26)) return set_error(AC_E_INVALID, "n must be in [1, 2^26)");
     void *dx = nullptr, *dr = nullptr;
     try {
+        const Options o = parse(opt);
+        if (!xyz || !radii) return set_error(AC_E_INVALID, "NULL input pointer");
+        if (n < 1 || n >= (1 << 26)) return set_error(AC_E_INVALID, "n must be in [1, 2^26)");
         dx = dev_alloc((size_t)n * 3 * sizeof(double));
         dr = dev_alloc((size_t)n * sizeof(double));
         HIP_TRY(hipMemcpy(dx, xyz, (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(dr, radii, (size_t)n * sizeof(double), hipMemcpyHostToDevice));
         Batch bt;
         bt.off = {0, n};
-        ac_status st = run_pipeline(static_cast<double *>(dx), static_cast<double *>(dr), n, bt, alpha, parse(opt), nullptr,
-                                    out);
+        ac_status st = run_pipeline(static_cast<double *>(dx), static_cast<double *>(dr), n, bt, alpha, o, nullptr, out);
         dev_free(dx);
         dev_free(dr);
         if (st != AC_OK) return st;
@@ -1365,12 +1387,15 @@ ac_status ac_alpha_complex_batch(const double *d_xyz, const double *d_radii, con
                                  ac_complex **out) {
     if (!out) return set_error(AC_E_INVALID, "out is NULL");
     *out = nullptr;
-    if (!d_xyz || !d_radii) return set_error(AC_E_INVALID, "NULL input pointer");
     try {
+        const Options o = parse(opt);
+        if (!d_xyz || !d_radii) return set_error(AC_E_INVALID, "NULL input pointer");
         Batch bt;
         const ac_status st = batch_from(offsets, n_mol, cell_mA, bt);
         if (st != AC_OK) return st;
-        return run_pipeline(d_xyz, d_radii, bt.off[n_mol], bt, alpha, parse(opt), static_cast<hipStream_t>(stream), out);
+        const ac_status sp = run_pipeline(d_xyz, d_radii, bt.off[n_mol], bt, alpha, o, static_cast<hipStream_t>(stream), out);
+        if (sp == AC_OK) (*out)->batch = true;
+        return sp;
     } catch (const HipError &e) {
         return set_error(e.st, e.msg);
     } catch (...) {
@@ -1385,15 +1410,27 @@ const int64_t *ac_molecule_rows(const ac_complex *c, int dim) {
     return c->mol_rows[dim].data();
 }
 
+const int32_t *ac_molecule(ac_complex *c, int dim) {
+    if (!c || dim < 0 || dim > 3 || !c->batch || c->mol_rows[dim].size() != (size_t)c->n_mol + 1) return nullptr;
+    std::vector<int32_t> &h = c->h_mol[dim];
+    if (h.empty()) {
+        const std::vector<int64_t> &r = c->mol_rows[dim];
+        h.assign((size_t)c->count[dim] + 1, 0);  // one spare entry: never a zero-length array
+        for (int64_t m = 0; m < c->n_mol; m++)
+            std::fill(h.begin() + r[m], h.begin() + r[m + 1], (int32_t)m);
+    }
+    return h.data();
+}
+
 ac_status ac_tune_cells(const double *d_xyz, const double *d_radii, const int64_t *offsets, int64_t n_mol, double alpha,
                         const ac_options *opt, void *stream, int32_t *cell_mA_out, int32_t *bucket_out) {
-    if (!d_xyz || !d_radii || !cell_mA_out) return set_error(AC_E_INVALID, "NULL pointer");
     try {
+        const Options o = parse(opt);
+        if (!d_xyz || !d_radii || !cell_mA_out) return set_error(AC_E_INVALID, "NULL pointer");
         Batch all;
         ac_status st = batch_from(offsets, n_mol, nullptr, all);
         if (st != AC_OK) return st;
         hipStream_t s = static_cast<hipStream_t>(stream);
-        const Options o = parse(opt);
         // grown radius s_g (mA): the default cell side the candidates scale
         double rmax = 0;
         {

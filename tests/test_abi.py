@@ -55,3 +55,59 @@ def test_sweep_argument_checks_without_device():
     assert all(h is None for h in outs)
     assert lib.ac_alpha_sweep_device(None, None, 10, alphas, 4, None, None, None) == 1
     assert b"NULL" in lib.ac_last_error() or b"null" in lib.ac_last_error().lower()
+
+
+def _opt(acx, **kw):
+    o = acx.Options()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+@pytest.mark.parametrize("field,value", [
+    ("reserved", 1), ("wave_tile", 64), ("capacity_hint", 8), ("profile", -1), ("profile", 99),
+    ("cell_mA", -5), ("force_exact", 2), ("vertex_shortcut", -1),
+])
+def test_options_out_of_range_are_rejected_before_device_work(field, value):
+    """Every ac_options field outside its documented range is AC_E_INVALID,
+    reported before any device call (so this runs without a GPU), on every
+    entry point that takes options."""
+    import paper_1908_05944_amd as acx
+    lib = acx.library()
+    o = _opt(acx, **{field: value})
+    out = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(16)  # never dereferenced: the options are checked first
+    xyz = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    rad = (ctypes.c_double * 1)(1.5)
+    off = (ctypes.c_int64 * 2)(0, 1)
+    alphas = (ctypes.c_double * 1)(0.0)
+    outs = (ctypes.c_void_p * 1)()
+    cells = (ctypes.c_int32 * 1)()
+    calls = [
+        lambda: lib.ac_alpha_complex(xyz, rad, 1, 0.0, ctypes.byref(o), ctypes.byref(out)),
+        lambda: lib.ac_alpha_complex_device(dummy, dummy, 1, 0.0, ctypes.byref(o), None, ctypes.byref(out)),
+        lambda: lib.ac_alpha_complex_partitioned(dummy, dummy, 1, 0.0, 2, ctypes.byref(o), None, ctypes.byref(out)),
+        lambda: lib.ac_alpha_sweep_device(dummy, dummy, 1, alphas, 1, ctypes.byref(o), None, outs),
+        lambda: lib.ac_alpha_complex_batch(dummy, dummy, off, 1, 0.0, ctypes.byref(o), None, None, ctypes.byref(out)),
+        lambda: lib.ac_tune_cells(dummy, dummy, off, 1, 0.0, ctypes.byref(o), None, cells, None),
+    ]
+    for k, call in enumerate(calls):
+        assert call() == 1, (field, value, k)
+        assert b"ac_options." + field.encode() in lib.ac_last_error(), (k, lib.ac_last_error())
+    assert not out.value
+
+
+def test_molecule_accessors_without_a_result():
+    import paper_1908_05944_amd as acx
+    lib = acx.library()
+    assert not lib.ac_molecule(None, 0)
+    assert not lib.ac_molecule_rows(None, 0)
+    assert lib.ac_molecule_count(None) == -1
+
+
+def test_measure_rejects_null_complex_without_device():
+    import paper_1908_05944_amd as acx
+    lib = acx.library()
+    V, A = ctypes.c_double(), ctypes.c_double()
+    dummy = ctypes.c_void_p(16)
+    assert lib.ac_union_measure(None, dummy, dummy, 1, ctypes.byref(V), ctypes.byref(A), None) == 1

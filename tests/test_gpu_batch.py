@@ -62,6 +62,10 @@ def _check_batch(acx, mols, alpha, cells=None, oracle_upto=0):
     print(f"[case] batch of {len(mols)} molecules, {len(rad)} balls, alpha={alpha}", flush=True)
     c = acx.ac_alpha_complex_batch(_dev(xyz), _dev(rad), off, alpha, cell_mA=cells)
     assert c.molecule_count() == len(mols)
+    for d in range(4):
+        rows = c.molecule_rows(d)
+        want = np.repeat(np.arange(len(mols), dtype=np.int32), np.diff(rows))
+        assert np.array_equal(c.molecule(d), want), d
     for m, mol in enumerate(mols):
         got = _Slice(c, m, off)
         single = acx.ac_alpha_complex_device(_dev(mol.xyz), _dev(mol.radii), alpha)
@@ -136,3 +140,50 @@ def test_batch_union_measure(acx):
         As += a
     assert V == pytest.approx(Vs, rel=1e-12)
     assert A == pytest.approx(As, rel=1e-12)
+
+
+def test_molecule_of_rows_only_for_batches(acx):
+    m = synth.molecule(200, 3)
+    c = acx.ac_alpha_complex_device(_dev(m.xyz), _dev(m.radii), 0.0)
+    assert not acx.library().ac_molecule(c._h, 1)
+    cb = acx.ac_alpha_complex_batch(_dev(m.xyz), _dev(m.radii), np.array([0, m.n]), 0.0)
+    assert np.array_equal(cb.molecule(1), np.zeros(cb.count(1), dtype=np.int32))
+
+
+@pytest.mark.timeout(900)
+def test_full_512_molecule_batch_against_oracle(acx):
+    """The batching workload itself: 512 molecules with sizes log-uniform in
+    [500, 50000] atoms (seed 999; molecule k from seed 1000 + k; 5.1M balls),
+    one batched call with the autotuner's cell sides as bench.py makes it,
+    every molecule compared with the oracle simplex for simplex and Size for
+    Size. The oracle runs in 16 threads (its C call releases the interpreter
+    lock and keeps no shared state)."""
+    from concurrent.futures import ThreadPoolExecutor
+    from parity import SIZE_ABS_TOL, SIZE_REL_TOL
+    sizes = synth.batch_sizes()
+    print(f"[case] 512-molecule batch: generating {int(np.sum(sizes))} balls", flush=True)
+    mols = [synth.molecule(int(k), 1000 + i) for i, k in enumerate(sizes)]
+    xyz, rad, off = _concat(mols)
+    X, R = _dev(xyz), _dev(rad)
+    cells, _ = acx.ac_tune_cells(X, R, off, 0.0)
+    c = acx.ac_alpha_complex_batch(X, R, off, 0.0, cell_mA=cells)
+    simp = [c.simplices(d) for d in range(4)]
+    size = [c.sizes(d) for d in range(4)]
+    rows = [c.molecule_rows(d) for d in range(4)]
+    c.close()
+    print("[case] 512-molecule batch: oracle per molecule", flush=True)
+
+    def check(m):
+        want = oracle.alpha_complex(mols[m].xyz, mols[m].radii, 0.0)
+        for d in range(4):
+            got = simp[d][rows[d][m]:rows[d][m + 1]] - off[m]
+            if not np.array_equal(got, want.simplices[d]):
+                return f"molecule {m} dim {d}: {len(got)} vs {len(want.simplices[d])} simplices"
+            z = size[d][rows[d][m]:rows[d][m + 1]]
+            if np.any(np.abs(z - want.sizes[d]) > SIZE_ABS_TOL + SIZE_REL_TOL * np.abs(want.sizes[d])):
+                return f"molecule {m} dim {d}: Sizes differ"
+        return None
+
+    with ThreadPoolExecutor(16) as ex:
+        bad = [r for r in ex.map(check, range(len(mols))) if r]
+    assert not bad, bad[:5]

@@ -46,6 +46,21 @@ def built():
     return mol, simp, size, counts
 
 
+@pytest.mark.timeout(900)
+def test_whole_output_against_oracle(built):
+    """Every simplex and Size of the 3M-atom shell against the oracle run on
+    all 3,000,000 balls (single-threaded, in this process)."""
+    mol, simp, size, counts = built
+    print("[case] 3M shell: oracle on all balls", flush=True)
+    want = oracle.alpha_complex(mol.xyz, mol.radii, 0.0)
+    assert want.counts() == counts, (want.counts(), counts)
+    for d in range(4):
+        assert np.array_equal(simp[d], want.simplices[d]), d
+        err = np.abs(size[d] - want.sizes[d])
+        bad = np.nonzero(err > SIZE_ABS_TOL + SIZE_REL_TOL * np.abs(want.sizes[d]))[0]
+        assert bad.size == 0, (d, want.simplices[d][bad[:3]].tolist(), size[d][bad[:3]], want.sizes[d][bad[:3]])
+
+
 def _rows_in(rows, inside):
     return rows[np.all(inside[rows], axis=1)]
 

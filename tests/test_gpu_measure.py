@@ -257,3 +257,46 @@ def test_graph_replay_of_forward_backward(acx):
         assert torch.equal(got[0], out) and torch.equal(got[1], dx) and torch.equal(got[2], dr), rep
         V, A = acx.ac_union_measure(c, X, R)
         assert (V, A) == tuple(out.cpu().tolist())
+
+
+def test_100k_frame_against_oracle(acx):
+    """The differentiation workload's first frame in full (the 100k-atom
+    molecule with Gaussian jitter 0.1 A, seed 2000): the GPU complex equals the
+    oracle's simplex for simplex, and V, A and both gradients over all 100,000
+    balls agree with the oracle's formulas evaluated on the oracle's complex."""
+    import torch
+    from parity import assert_same_complex
+    f = synth.jittered(synth.config_100k(), 0.1, 2000)
+    print("[case] 100k frame 0: oracle complex and measure", flush=True)
+    want = oracle.alpha_complex(f.xyz, f.radii, 0.0)
+    V0, A0, gVx, gVr, gAx, gAr = measure.union_measure(want.simplices, f.xyz, f.radii, with_grad=True)
+    X, R = _dev(f.xyz), _dev(f.radii)
+    c = acx.ac_alpha_complex_device(X, R, 0.0)
+    assert_same_complex(c, want, "100k frame 0")
+    V, A = acx.ac_union_measure(c, X, R)
+    assert abs(V - V0) <= REL_VA * abs(V0), (V, V0)
+    assert abs(A - A0) <= REL_VA * abs(A0), (A, A0)
+    for (gV, gA), (wx, wr) in (((1.0, 0.0), (gVx, gVr)), ((0.0, 1.0), (gAx, gAr))):
+        g = torch.tensor([gV, gA], dtype=torch.float64, device="cuda:0")
+        dx, dr = acx.ac_union_measure_backward(c, X, R, g)
+        dx, dr = dx.cpu().numpy(), dr.cpu().numpy()
+        assert np.abs(dx - wx).max() <= REL_GRAD * np.abs(wx).max(), (gV, gA)
+        assert np.abs(dr - wr).max() <= REL_GRAD * np.abs(wr).max(), (gV, gA)
+
+
+def test_measure_needs_a_complex_built_at_alpha_zero(acx):
+    """V and A come from K_0; a complex built at another alpha is refused
+    (the union of grown balls is measured from the complex of the grown radii
+    at alpha = 0)."""
+    m = synth.molecule(300, 4)
+    X, R = _dev(m.xyz), _dev(m.radii)
+    for alpha in (1.0, -0.5):
+        c = acx.ac_alpha_complex_device(X, R, alpha)
+        with pytest.raises(acx.AlphaCxError) as e:
+            acx.ac_union_measure(c, X, R)
+        assert e.value.status == 1
+    grown = np.sqrt(m.radii ** 2 + 1.0)
+    c0 = acx.ac_alpha_complex_device(X, _dev(grown), 0.0)
+    c1 = acx.ac_alpha_complex_device(X, R, 1.0)
+    assert c0.counts() == c1.counts()
+    acx.ac_union_measure(c0, X, _dev(grown))

@@ -95,6 +95,50 @@ def test_integer_grid_ties(acx):
         assert_same_complex(_run(acx, pts, rad, alpha), oracle.alpha_complex(pts, rad, alpha), f"grid {trial}")
 
 
+def test_quantisation_ties(acx):
+    """Coordinates and radii on multiples of 1/16 A: x 1000 ends in .5 for odd
+    multiples, so every such value is a rounding tie (half to even on both
+    sides). The hand-derived Sizes of the oracle's pins, then a molecule
+    snapped to the 1/16 A lattice with tie radii, against the oracle."""
+    c = _run(acx, [[0.0625, -0.1875, 0.3125]], [1.0625], 0.0)
+    assert c.sizes(0).tolist() == [-1.127844]
+    c = _run(acx, [[-0.0625, 0.0625, -0.1875], [2.0625, 0.0625, -0.1875]], [1.5, 1.5], 0.0)
+    assert c.simplices(1).tolist() == [[0, 1]] and abs(c.sizes(1)[0] + 1.122156) <= 1e-12
+    m = synth.molecule(2000, 12)
+    snapped = np.round(m.xyz * 16.0) / 16.0
+    rad = np.choose(np.arange(m.n) % 4, [1.5625, 1.6875, 1.5, 1.8125])  # 1562.5 1687.5 1500 1812.5 mA
+    assert np.mean(np.abs(snapped * 1000 - np.round(snapped * 1000)) == 0.5) > 0.4  # mostly ties
+    for alpha in (0.0, 1.0625):
+        assert_same_complex(_run(acx, snapped, rad, alpha), oracle.alpha_complex(snapped, rad, alpha),
+                            f"1/16 A lattice alpha={alpha}")
+
+
+def test_planar_molecule(acx):
+    """3,000 balls on one plane (a planar molecule: the complex has no
+    tetrahedra), against the oracle's low-dimensional route."""
+    rng = np.random.RandomState(77)
+    pts = []
+    grid = {}
+    R = np.sqrt(3000 / (np.pi * 0.1))
+    while len(pts) < 3000:
+        p = rng.uniform(-R, R, 2)
+        if p @ p > R * R:
+            continue
+        key = (int(np.floor(p[0] / 1.7)), int(np.floor(p[1] / 1.7)))
+        near = [grid.get((key[0] + i, key[1] + j)) for i in range(-2, 3) for j in range(-2, 3)]
+        if all(q is None or (p - q) @ (p - q) >= 2.4 ** 2 for q in near):
+            grid[key] = p
+            pts.append(p)
+    xyz = np.zeros((3000, 3))
+    xyz[:, 0], xyz[:, 2] = np.round(np.array(pts) * 1000).T / 1000
+    xyz[:, 1] = -3.21
+    rad = rng.choice([1.70, 1.55, 1.52, 1.80], size=3000, p=[0.62, 0.17, 0.19, 0.02])
+    for alpha in (0.0, 2.0):
+        c = _run(acx, xyz, rad, alpha)
+        assert c.count(3) == 0
+        assert_same_complex(c, oracle.alpha_complex(xyz, rad, alpha), f"plane alpha={alpha}")
+
+
 def test_small_molecule_alphas(acx):
     m = synth.config_small()
     for alpha in (0.0, 0.5, 1.0, 2.0):

@@ -63,10 +63,10 @@ def test_edge_cases(acx):
     _check(acx, m.xyz[:1], m.radii[:1], 0.0, [3], "one ball", oracle_check=True)
     _check(acx, m.xyz, m.radii, -5.0, [4], "empty", oracle_check=True)
     # every centre on one x plane: a single occupied slab (the oracle takes
-    # coplanar inputs of up to 64 balls)
+    # coplanar inputs of up to 4096 balls)
     flat = m.xyz.copy()
     flat[:, 0] = 1.234
-    _check(acx, flat, m.radii, 0.0, [4], "one plane")
+    _check(acx, flat, m.radii, 0.0, [4], "one plane", oracle_check=True)
     _check(acx, flat[:40], m.radii[:40], 0.0, [4], "one plane, 40 balls", oracle_check=True)
     # lattice with ties decided by simulation of simplicity
     g = np.stack(np.meshgrid(*[np.arange(4) * 2.5] * 3, indexing="ij"), -1).reshape(-1, 3)
