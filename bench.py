@@ -44,6 +44,10 @@ KERNEL_SOURCES = ["paper_1908_05944_amd/csrc/kernels.hpp", "paper_1908_05944_amd
                   "paper_1908_05944_amd/csrc/partition.hpp",
                   "paper_1908_05944_amd/csrc/alphacx.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_3Mshell.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_3Mshell.json")
+# vector lane-operations per second at the issue limit: 256 CUs x 4 SIMDs x
+# 16 lanes x 2.4 GHz (a float64 FMA issues at this rate: 78.6 TFLOP/s)
+VALU_ISSUE_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def kernel_source_hash():
@@ -55,18 +59,134 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(stage):
-    """HBM bytes per launch of the stage's kernel from the committed rocprofv3
-    counter summary, or None if it was taken on other kernel sources."""
+def _profile_record(path):
+    """A committed rocprofv3 counter summary (JSON), or None if it is missing
+    or was taken on other kernel sources."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    if rec.get("source_sha") != kernel_source_hash():
-        return None
-    k = rec.get("kernels", {}).get(KERNEL_OF_STAGE.get(stage, stage))
+    return rec if rec.get("source_sha") == kernel_source_hash() else None
+
+
+def measured_traffic(stage):
+    """HBM bytes per launch of the stage's kernel (FETCH_SIZE + WRITE_SIZE,
+    calibrated), or None."""
+    rec = _profile_record(TRAFFIC_FILE)
+    k = None if rec is None else rec.get("kernels", {}).get(KERNEL_OF_STAGE.get(stage, stage))
     return None if k is None else k.get("traffic_bytes")
+
+
+def measured_traffic_total():
+    """HBM bytes of one whole build (every kernel's per-launch traffic times its
+    launches per build), or None."""
+    rec = _profile_record(TRAFFIC_FILE)
+    if rec is None or "builds" not in rec:
+        return None
+    return sum(k["traffic_bytes"] * k["launches"] for k in rec["kernels"].values()) / rec["builds"]
+
+
+def measured_valu_issue(stage):
+    """Vector lane-operations per second of the stage's kernel over the issue
+    limit, from the SQ counters, or None."""
+    rec = _profile_record(VALU_FILE)
+    k = None if rec is None else rec.get("kernels", {}).get(KERNEL_OF_STAGE.get(stage, stage))
+    return None if k is None else k.get("valu_tlane_ops_per_s") / VALU_ISSUE_PEAK_T
+
+
+def neighbour_pairs_tested(X, W, aq, cell_mA):
+    """P_e: ball pairs the neighbour pass tests, replicating its grid on the
+    host (cell side, growth rule and reach as the build takes them; every ball
+    of each scanned cell row whose slab lies within 2 s_g of the ball)."""
+    import numpy as np
+    X = X.astype(np.int64)
+    n = len(X)
+    sg2 = max(int(W.max()) + aq, 0)
+    sgc = math.isqrt(sg2)
+    sgc += sgc * sgc < sg2
+    lo = X.min(0)
+    ext = X.max(0) - lo + 1
+    side = cell_mA if cell_mA > 0 else max(sgc, 1)
+    nc = lambda sd: int(np.prod((ext + sd - 1) // sd))
+    while nc(side) > max(8 * n, 1 << 22):
+        side = side + side // 4 + 1
+    nx, ny, nz = [int(v) for v in (ext + side - 1) // side]
+    reach = (2 * sgc + side - 1) // side
+    c = (X - lo) // side
+    cid = (c[:, 2] * ny + c[:, 1]) * nx + c[:, 0]
+    cs = np.concatenate([[0], np.cumsum(np.bincount(cid, minlength=nx * ny * nz))])
+    lim, reach1 = 4 * sg2, 2 * sgc
+    x0 = np.maximum(c[:, 0] - reach, 0)
+    x1 = np.minimum(c[:, 0] + reach, nx - 1)
+    total = 0
+    for dz in range(-reach, reach + 1):
+        z = c[:, 2] + dz
+        zlo = lo[2] + z * side
+        dzm = np.where(X[:, 2] < zlo, zlo - X[:, 2], np.where(X[:, 2] > zlo + side - 1, X[:, 2] - zlo - side + 1, 0))
+        okz = (z >= 0) & (z < nz) & (dzm <= reach1) & (lim - dzm * dzm >= 0)
+        for dy in range(-reach, reach + 1):
+            y = c[:, 1] + dy
+            ylo = lo[1] + y * side
+            dym = np.where(X[:, 1] < ylo, ylo - X[:, 1], np.where(X[:, 1] > ylo + side - 1, X[:, 1] - ylo - side + 1, 0))
+            ok = okz & (y >= 0) & (y < ny) & (dym <= reach1) & (lim - dzm * dzm - dym * dym >= 0)
+            rb = (np.clip(z, 0, nz - 1) * ny + np.clip(y, 0, ny - 1)) * nx
+            total += int(np.sum(np.where(ok, cs[rb + x1 + 1] - cs[rb + x0], 0)))
+    return total, nx * ny * nz
+
+
+def algorithmic_work(n, C, E, F, Q, K, Nn, Pe):
+    """Algorithmic HBM bytes and float64 operations of one build and of its
+    single-kernel stages, from measured counts (balls n, grid cells C,
+    candidate edges E, triangles F and tetrahedra Q, output counts K[d],
+    neighbour entries Nn, pairs tested Pe). Bytes: inputs read once, every
+    candidate list written once and read once, the output written once; the
+    int32 quantised balls (16 B), sorted balls and order (36 B), cell table
+    (8 B per cell), candidates 8 / 12 / 16 B, output rows 4 (d + 1) + 8 B.
+    Operations: 12 per pair tested, 40 per triple and 80 per quadruple (the
+    examined triples and quadruples are at least the candidates, which are
+    counted here), plus per candidate its ortho-centre setup (30 / 60 / 120)
+    and 12 per neighbour of its AC2 scan (nbr = Nn / n neighbours on average)."""
+    nbr = Nn / n
+    out = sum(K[d] * (4 * (d + 1) + 8) for d in range(4))
+    B = 16 * n + 36 * n + 8 * C + 2 * (8 * E + 12 * F + 16 * Q) + out
+    FL = 12 * Pe + 40 * F + 80 * Q + E * (30 + 12 * nbr) + F * (60 + 12 * nbr) + Q * (120 + 12 * nbr)
+    stage_bytes = {
+        "neighbours_count": 16 * n + 8 * C + 8 * E,
+        "neighbours_fill": 2 * 8 * E,
+        "triangles_count": 16 * n + 8 * E + 12 * F,
+        "triangles_fill": 2 * 12 * F,
+        "triangles_ac2_tetrahedra": 16 * n + 12 * F + 16 * Q,
+        "tetrahedra_fill": 2 * 16 * Q,
+        "tetrahedra_ac2": 16 * n + 16 * Q + 24 * K[3],
+        "triangles_final": 12 * F + 20 * K[2],
+        "edges_final": 8 * E + 16 * K[1],
+        "vertices_final": 16 * n + 12 * K[0],
+    }
+    stage_flops = {
+        "neighbours_count": 12 * Pe + 12 * Nn,
+        "triangles_count": 40 * F + E * (30 + 12 * nbr),
+        "triangles_ac2_tetrahedra": 80 * Q + F * (60 + 12 * nbr),
+        "tetrahedra_ac2": Q * (120 + 12 * nbr),
+    }
+    return B, FL, stage_bytes, stage_flops
+
+
+def host_cpu():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count()
+    return {"nproc": os.cpu_count(), "available_to_process": avail, "cpu_model": model}
 
 
 def log(*a):
@@ -329,6 +449,7 @@ def main():
     ap.add_argument("--cache-dir", default=os.environ.get("ALPHACX_INPUT_CACHE", ""),
                     help="keep the generated input here between runs")
     ap.add_argument("--no-extras", action="store_true", help="skip the batch and union-measure workloads")
+    ap.add_argument("--no-host-to-host", action="store_true", help="skip the host-array build timing")
     ap.add_argument("--no-tune", action="store_true", help="default cell side instead of the autotuned one")
     ap.add_argument("--cell-mA", type=int, default=0, help="fixed cell side in mA (skips the autotuner)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -399,25 +520,16 @@ def main():
     work = [c.work_count(0), c.work_count(1)]
     c.close()
 
-    # Dominant kernel and its roofline: among the stages that hold exactly one
-    # kernel launch, the one with the largest event time. Algorithmic bytes are
-    # what that kernel must move from HBM at least: every input ball, row and
-    # list entry it needs read once, every output written once.
+    # Algorithmic work of the build (bytes and float64 operations) from the
+    # measured counts; the dominant kernel is, among the stages that hold
+    # exactly one kernel launch, the one with the largest event time.
     n = mol.n
     E, T, Q = cand[1], cand[2], cand[3]
     Nn = work[1]
-    alg_bytes = {
-        "neighbours_count": 16 * n + 9 * n + 4 * Nn + 4 * E,
-        "neighbours_fill": 20 * n + 12 * E,
-        "triangles_count": 16 * n + 8 * E + 4 * Nn + 4 * E + 5 * E + 4 * T,
-        "triangles_fill": 8 * E + 12 * T,
-        "triangles_ac2_tetrahedra": 16 * n + 4 * Nn + 4 * E + 29 * T + 4 * Q,
-        "tetrahedra_fill": 4 * T + 12 * Q,
-        "tetrahedra_ac2": 8 * Q + 8 * T + 16 * n + 9 * Q,
-        "triangles_final": 30 * T,
-        "edges_final": 30 * E,
-        "vertices_final": 30 * n,
-    }
+    Pe, C = neighbour_pairs_tested(mol.X_mA, mol.R_mA.astype(np.int64) ** 2, int(round(args.alpha * 1e6)), cell_mA)
+    if C != work[0]:
+        log(f"[bench] host grid replication gave {C} cells, the build {work[0]}")
+    B_build, F_build, alg_bytes, alg_flops = algorithmic_work(n, work[0], E, T, Q, counts, Nn, Pe)
     single = {k: v for k, v in stage_avg.items() if k in alg_bytes and v > 0}
     dom = max(single, key=lambda k: single[k])
 
@@ -437,19 +549,75 @@ def main():
     dom_ms = dom_tot / args.steps
     log(f"[bench] {ms_per_step:.3f} ms/step; {dom} {dom_ms:.3f} ms per launch (timed steps); untimed stages (ms): "
         + ", ".join(f"{k}={v:.3f}" for k, v in stage_avg.items()))
-    achieved = alg_bytes[dom] / (dom_ms * 1e-3) / 1e9
+    # the dominant kernel: bound by what its counters show (vector issue when
+    # its instruction rate is the nearer limit, else HBM), else by the larger
+    # of its algorithmic times
+    t_dom = dom_ms * 1e-3
+    b_dom, f_dom = alg_bytes[dom], alg_flops.get(dom, 0)
     traffic = measured_traffic(dom)
+    issue = measured_valu_issue(dom)
+    hbm_meas = None if traffic is None else traffic / t_dom / (HBM_PEAK_GBS * 1e9)
+    if issue is not None and hbm_meas is not None:
+        bound = "alu" if issue > hbm_meas and f_dom > 0 else "hbm"
+        bound_from = f"counters: vector issue {issue:.2f} of its limit, HBM traffic {hbm_meas:.2f} of peak"
+    else:
+        bound = "alu" if f_dom / (FP64_VECTOR_PEAK_TFLOPS * 1e12) > b_dom / (HBM_PEAK_GBS * 1e9) else "hbm"
+        bound_from = "larger algorithmic time (no counters for these kernel sources)"
+    hbm_view = {"achieved": b_dom / t_dom / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": b_dom / t_dom / (HBM_PEAK_GBS * 1e9), "algorithmic_bytes": b_dom}
+    fp64_view = {"achieved": f_dom / t_dom / 1e12, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                 "frac": f_dom / t_dom / (FP64_VECTOR_PEAK_TFLOPS * 1e12), "algorithmic_flops": f_dom}
+    main_view = fp64_view if bound == "alu" else hbm_view
     roofline = {
         "kernel": KERNEL_OF_STAGE.get(dom, dom),
-        "bound": "hbm",
-        "achieved": achieved,
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": achieved / HBM_PEAK_GBS,
+        "bound": bound,
+        "bound_from": bound_from,
+        "achieved": main_view["achieved"],
+        "peak": main_view["peak"],
+        "unit": main_view["unit"],
+        "frac": main_view["frac"],
         "traffic": traffic,
         "ms_per_launch": dom_ms,
-        "algorithmic_bytes": alg_bytes[dom],
+        "hbm_view": hbm_view,
+        "fp64_view": fp64_view,
+        "valu_issue_frac": issue,
     }
+    # the whole build: max(B / HBM peak, F / float64 peak) over the step time
+    t_step = ms_per_step * 1e-3
+    t_b, t_f = B_build / (HBM_PEAK_GBS * 1e9), F_build / (FP64_VECTOR_PEAK_TFLOPS * 1e12)
+    tr_build = measured_traffic_total()
+    build_roofline = {
+        "bound": "hbm" if t_b >= t_f else "fp64",
+        "frac": max(t_b, t_f) / t_step,
+        "hbm_frac": t_b / t_step,
+        "fp64_frac": t_f / t_step,
+        "algorithmic_bytes": B_build,
+        "algorithmic_flops": F_build,
+        "achieved_GBs": B_build / t_step / 1e9,
+        "traffic_bytes": tr_build,
+        "traffic_GBs": None if tr_build is None else tr_build / t_step / 1e9,
+        "pairs_tested": Pe,
+        "note": "B and F from the measured counts of this build; examined triples and quadruples are "
+                "counted as the candidates (a lower bound of F)",
+    }
+    log(f"[bench] build roofline: B {B_build / 1e6:.1f} MB, F {F_build / 1e9:.2f} GFLOP, "
+        f"frac {build_roofline['frac']:.3f} ({build_roofline['bound']}); dominant {roofline['kernel']} "
+        f"{roofline['frac']:.3f} ({bound})")
+
+    # host-to-host: host arrays in, every result array back on the host (what
+    # the paper's totals include)
+    h2h = None
+    if not args.no_host_to_host:
+        acx.ac_alpha_complex(mol.xyz, mol.radii, args.alpha, options=opts).close()
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            acx.ac_alpha_complex(mol.xyz, mol.radii, args.alpha, options=opts).close()
+            ts.append(time.perf_counter() - t0)
+        h2h = {"ms": float(np.median(ts)) * 1e3, "atoms_per_s": n / float(np.median(ts)),
+               "note": "ac_alpha_complex from host arrays: inputs copied up, every result array copied back "
+                       "(pageable host memory), median of 3"}
+        log(f"[bench] host-to-host: {h2h['ms']:.2f} ms per build")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -463,8 +631,22 @@ def main():
         oc = oracle.alpha_complex(mol.xyz[sel], mol.radii[sel], args.alpha)
         dt = time.perf_counter() - t1
         cpu = {"value": len(sel) / dt, "unit": "atoms/s", "cores": 1, "kind": "oracle",
-               "sample": f"{len(sel)} atoms of the 3M shell (slab x <= {x0 / 1000:.1f} A), {dt:.1f} s single-threaded"}
+               "sample": f"{len(sel)} atoms of the 3M shell (slab x <= {x0 / 1000:.1f} A), {dt:.1f} s single-threaded",
+               **host_cpu()}
         log(f"[bench] oracle sample: {len(sel)} atoms in {dt:.2f} s, counts {oc.counts()}")
+        # the oracle on the small configs: 1 warm-up + 3 runs, median
+        small = {}
+        for name, m in (("1k", synth.config_small()), ("100k_vdw", synth.config_100k()),
+                        ("100k_sas", synth.config_100k(sas=True))):
+            ts = []
+            for rep in range(4):
+                t1 = time.perf_counter()
+                oracle.alpha_complex(m.xyz, m.radii, 0.0)
+                if rep:
+                    ts.append(time.perf_counter() - t1)
+            small[name] = {"atoms": m.n, "ms": float(np.median(ts)) * 1e3, "atoms_per_s": m.n / float(np.median(ts))}
+        cpu["oracle_small_configs"] = small
+        log("[bench] oracle: " + ", ".join(f"{k} {v['ms']:.1f} ms" for k, v in small.items()))
 
     extras = {}
     if not args.no_extras:
@@ -499,6 +681,8 @@ def main():
         "stage_ms": stage_avg,
         "stage_ms_note": "device time per stage, HIP events between all stages, mean of 3 untimed builds",
         "roofline": roofline,
+        "build_roofline": build_roofline,
+        "host_to_host": h2h,
         "cpu_baseline": cpu,
         **extras,
     }
