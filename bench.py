@@ -202,17 +202,47 @@ def _timed(torch, fn, reps):
     return (time.perf_counter() - t0) / reps
 
 
-def bench_partition(acx, torch, log, xyz, rad, opts, reps=3):
-    """Partitioned builds of the 3M-atom shell (slabs along x with a halo),
-    against the single build: the time a slab-by-slab build costs."""
-    out = {}
+def bench_partition(acx, torch, log, xyz, rad, opts, host_xyz, host_rad, reps=3):
+    """Partitioned builds of the 3M-atom shell (slabs along x with a halo):
+    device-resident (inputs and results on the device) against the single
+    device build, and streamed from host memory (one slab on the device at a
+    time, results back on the host) against the single host-array build."""
+    out, out_host = {}, {}
     for parts in (4, 16):
         acx.ac_alpha_complex_partitioned(xyz, rad, 0.0, parts, options=opts).close()
         t = _timed(torch, lambda: acx.ac_alpha_complex_partitioned(xyz, rad, 0.0, parts, options=opts).close(), reps)
         out[str(parts)] = t * 1e3
-    log("[bench] partitioned: " + ", ".join(f"{p} slabs {v:.2f} ms" for p, v in out.items()))
+        t = _timed(torch, lambda: acx.ac_alpha_complex_partitioned_host(host_xyz, host_rad, 0.0, parts,
+                                                                        options=opts).close(), 1)
+        out_host[str(parts)] = t * 1e3
+    log("[bench] partitioned: " + ", ".join(f"{p} slabs {v:.2f} ms" for p, v in out.items())
+        + "; from host memory: " + ", ".join(f"{p} slabs {v:.1f} ms" for p, v in out_host.items()))
     return {"metric": "partitioned build ms", "unit": "ms per build", "higher_is_better": False, "ms_by_slabs": out,
-            "config": {"workload": "3M-atom shell, alpha = 0, slabs of equal width along x"}}
+            "host_streamed_ms_by_slabs": out_host,
+            "config": {"workload": "3M-atom shell, alpha = 0, slabs of equal width along x; host-streamed: host "
+                                   "arrays in and out, one slab on the device at a time"}}
+
+
+def bench_cell_order(acx, torch, log, xyz, rad, opts, reps=5):
+    """The 3M-atom build with grid cells numbered along a Morton curve against
+    row-major numbering (same cell side): whole-build time and the per-stage
+    device times, which show where memory locality changes the cost."""
+    out = {}
+    for name, order in (("row_major", 0), ("morton", 1)):
+        o = dict(opts, cell_order=order)
+        acx.ac_alpha_complex_device(xyz, rad, 0.0, options=o).close()
+        t = _timed(torch, lambda: acx.ac_alpha_complex_device(xyz, rad, 0.0, options=o).close(), reps)
+        stages = {}
+        for _ in range(3):
+            c = acx.ac_alpha_complex_device(xyz, rad, 0.0, options=dict(o, profile=1))
+            for k, v in c.stage_ms().items():
+                stages[k] = stages.get(k, 0.0) + v / 3
+            c.close()
+        out[name] = {"ms_per_build": t * 1e3, "stage_ms": stages}
+    log(f"[bench] cell order: row-major {out['row_major']['ms_per_build']:.3f} ms, "
+        f"Morton {out['morton']['ms_per_build']:.3f} ms per build")
+    return {"metric": "build ms by cell order", "unit": "ms per build", "higher_is_better": False, **out,
+            "config": {"workload": "3M-atom shell, alpha = 0, same cell side, row-major vs Morton cell numbering"}}
 
 
 def bench_sweep(acx, torch, log, xyz, rad, opts, reps=3):
@@ -249,19 +279,20 @@ def bench_sweep(acx, torch, log, xyz, rad, opts, reps=3):
     }
 
 
-# Table 2 of the paper splits a build into eight categories; the stages of
-# this pipeline fall into them as follows (edge AC2 runs inside the triangle
-# pass and triangle AC2 inside the tetrahedron pass, so those two AC2 steps
-# are counted with the passes that hold them). "output" (sorting the result
-# by input ids) has no category of its own there.
+# Table 2 of the paper splits a build into eight categories. The per-step
+# arrangement of a profiled build (profile = stage count + 2) runs the AC2
+# tests of candidate edges and triangles as kernels of their own, so they
+# fall into the paper's pruning categories; vertices (not timed in the paper)
+# are counted with the edges. "output" (sorting the result by input ids) has
+# no category there.
 TABLE2_CATEGORIES = {
     "grid": ["quantise", "binning"],
     "potential_edges": ["neighbours_count", "neighbours_scan", "neighbours_fill"],
     "potential_triangles": ["triangles_count", "triangles_scan", "triangles_fill"],
     "potential_tetrahedra": ["triangles_ac2_tetrahedra", "tetrahedra_scan", "tetrahedra_fill"],
     "ac2_tetrahedra": ["tetrahedra_ac2"],
-    "ac2_triangles": ["triangles_final"],
-    "ac2_edges_vertices": ["edges_final", "vertices_final"],
+    "ac2_triangles": ["triangles_ac2", "triangles_final"],
+    "ac2_edges_vertices": ["edges_ac2", "edges_final", "vertices_final"],
     "output": ["emit"],
 }
 
@@ -269,10 +300,11 @@ TABLE2_CATEGORIES = {
 def bench_table2(acx, synth, torch, log, reps=5):
     """Per-stage split in the categories of the paper's Table 2 on synthetic
     molecules of the sizes of its PDB molecules (seeds 500 + k), alpha = 0, 1
-    and 2 A^2. Stage times are HIP events of profiled builds (median of
-    `reps`); "memory" is the host-array call minus the device-array call
-    (inputs up, every result array down)."""
+    and 2 A^2. Stage times are HIP events of profiled builds in the per-step
+    arrangement (median of `reps`); "memory" is the host-array call minus the
+    device-array call (inputs up, every result array down)."""
     import numpy as np
+    split = len(acx.stage_names()) + 2
     sizes = [260, 1505, 1509, 4384, 8142, 16068, 16647, 58674]
     rows = []
     for k, n in enumerate(sizes):
@@ -283,19 +315,19 @@ def bench_table2(acx, synth, torch, log, reps=5):
             acx.ac_alpha_complex_device(X, R, alpha).close()
             stages = []
             for _ in range(reps):
-                c = acx.ac_alpha_complex_device(X, R, alpha, options={"profile": 1})
+                c = acx.ac_alpha_complex_device(X, R, alpha, options={"profile": split})
                 stages.append(c.stage_ms())
                 counts = c.counts()
                 c.close()
             t_dev = _timed(torch, lambda: acx.ac_alpha_complex_device(X, R, alpha).close(), reps)
             t_host = _timed(torch, lambda: acx.ac_alpha_complex(m.xyz, m.radii, alpha).close(), reps)
-            med = {key: float(np.median([st[key] for st in stages])) for key in stages[0]}
+            med = {key: float(np.median([max(st[key], 0.0) for st in stages])) for key in stages[0]}
             cat = {name: sum(med[x] for x in parts) for name, parts in TABLE2_CATEGORIES.items()}
             cat["memory"] = max(t_host - t_dev, 0.0) * 1e3
             rows.append({"atoms": n, "alpha": alpha, "simplices": sum(counts), "device_ms": t_dev * 1e3,
                          "ms": {key: round(v, 4) for key, v in cat.items()}})
     est = ["potential_edges", "potential_triangles", "potential_tetrahedra"]
-    pru = ["ac2_tetrahedra", "ac2_triangles", "ac2_edges_vertices"]
+    pru = ["ac2_tetrahedra", "ac2_triangles", "ac2_edges_vertices"]  # Steps 2-5
     share = {}
     for name, parts in (("memory_grid", ["memory", "grid"]), ("estimation", est), ("pruning", pru),
                         ("ac2_tetrahedra", ["ac2_tetrahedra"]), ("output", ["output"])):
@@ -650,8 +682,9 @@ def main():
 
     extras = {}
     if not args.no_extras:
+        extras["cell_order"] = bench_cell_order(acx, torch, log, xyz, rad, opts)
         extras["alpha_sweep"] = bench_sweep(acx, torch, log, xyz, rad, opts)
-        extras["partitioned"] = bench_partition(acx, torch, log, xyz, rad, opts)
+        extras["partitioned"] = bench_partition(acx, torch, log, xyz, rad, opts, mol.xyz, mol.radii)
         del xyz, rad
         torch.cuda.empty_cache()
         extras["batch"] = bench_batch(acx, synth, torch, log)

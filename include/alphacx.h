@@ -62,9 +62,15 @@ typedef struct {
                                 testing its own centre (the paper's implementation shortcut, Sec. 4.4); exact
                                 only when no centre lies inside another ball's power cell */
     int64_t capacity_hint;   /* must be 0: candidate and output buffers are sized from exact counts */
-    int32_t profile;         /* 0, 1 or 2 + i (0 <= i < ac_stage_count()); 1 = record HIP events between pipeline
-                                stages (see ac_stage_ms); 2 + i = record only the two events around stage i (each
-                                event adds a few microseconds of device idle time) */
+    int32_t profile;         /* 0, 1, 2 + i (0 <= i < ac_stage_count()) or 2 + ac_stage_count(); 1 = record HIP
+                                events between pipeline stages (see ac_stage_ms); 2 + i = record only the two
+                                events around stage i (each event adds a few microseconds of device idle time);
+                                2 + ac_stage_count() = every stage, with the AC2 tests of candidate edges and
+                                triangles run as kernels of their own ("edges_ac2", "triangles_ac2": the same
+                                result, for a per-step breakdown that separates them as the paper's Table 2
+                                does) */
+    int32_t cell_order;      /* numbering of the grid cells, which orders the balls in memory: 0 = row-major
+                                (x fastest), 1 = Morton / Z-order curve (Sec. 4.2 names space-filling curves) */
     int32_t reserved;        /* must be 0 */
 } ac_options;
 
@@ -113,6 +119,24 @@ ac_status ac_alpha_complex_device(const double *d_xyz, const double *d_radii, in
  */
 ac_status ac_alpha_complex_partitioned(const double *d_xyz, const double *d_radii, int64_t n, double alpha,
                                        int32_t parts, const ac_options *opt, void *stream, ac_complex **out);
+
+/* ---- Partitioned build from host memory (out of core) ----
+ *
+ * As ac_alpha_complex_partitioned, with inputs and results in host memory:
+ * only one slab (its core and halo) is on the device at a time. Each slab's
+ * balls are copied to the device, built, and the rows it owns are copied
+ * back; the slabs' row lists, each already in output order, are then merged
+ * on the host. The device memory of a call is that of the largest slab's
+ * build, so inputs whose build would not fit on the device at once can be
+ * processed (the paper processes chunks of the sorted atom list, Sec. 4.6).
+ * Runs on the current device's null stream and returns when done.
+ *   xyz, radii  host arrays as in ac_alpha_complex (read during the call)
+ *   parts       1 <= parts <= 1024
+ * The result equals ac_alpha_complex's bit for bit; its arrays are host
+ * memory (ac_simplices_device returns NULL); ac_candidate_count and
+ * ac_work_count report -1. Errors as ac_alpha_complex_partitioned. */
+ac_status ac_alpha_complex_partitioned_host(const double *xyz, const double *radii, int64_t n, double alpha,
+                                            int32_t parts, const ac_options *opt, ac_complex **out);
 
 /* ---- Alpha sweep ----
  *
@@ -234,8 +258,9 @@ double ac_stage_ms(const ac_complex *c, int i);
  * the coordinates while the complex stays fixed. n must equal the number of
  * balls the complex was built on, and the complex must have been built at
  * alpha = 0, else AC_E_INVALID (for the union of balls grown to
- * sqrt(r^2 + alpha), build the complex of those grown radii at alpha = 0: it
- * has the same simplices).
+ * sqrt(r^2 + alpha), build the complex of those grown radii at alpha = 0; it
+ * is K_alpha of the original balls up to the rounding of the grown radii to
+ * the milli-angstrom lattice).
  *
  * The work buffers are kept with the complex: after the first call on a
  * complex these calls allocate nothing and do not synchronise the host

@@ -67,6 +67,7 @@ class Options(ctypes.Structure):
         ("vertex_shortcut", ctypes.c_int32),
         ("capacity_hint", ctypes.c_int64),
         ("profile", ctypes.c_int32),
+        ("cell_order", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
     ]
 
@@ -92,6 +93,9 @@ def _load():
     lib.ac_alpha_complex_partitioned.argtypes = [c_p, c_p, i64, dbl, ctypes.c_int32, ctypes.POINTER(Options), c_p,
                                                  ctypes.POINTER(c_p)]
     lib.ac_alpha_complex_partitioned.restype = ctypes.c_int
+    lib.ac_alpha_complex_partitioned_host.argtypes = [c_p, c_p, i64, dbl, ctypes.c_int32, ctypes.POINTER(Options),
+                                                      ctypes.POINTER(c_p)]
+    lib.ac_alpha_complex_partitioned_host.restype = ctypes.c_int
     lib.ac_count.argtypes = [c_p, ctypes.c_int]
     lib.ac_count.restype = i64
     lib.ac_simplices.argtypes = [c_p, ctypes.c_int]
@@ -309,6 +313,22 @@ def ac_alpha_complex_partitioned(xyz, radii, alpha: float, parts: int, options=N
     h = ctypes.c_void_p()
     st = lib.ac_alpha_complex_partitioned(xyz.data_ptr(), radii.data_ptr(), xyz.shape[0], float(alpha), int(parts),
                                           _opts(options), ctypes.c_void_p(s.cuda_stream), ctypes.byref(h))
+    _check(st)
+    return AlphaComplex(h)
+
+
+def ac_alpha_complex_partitioned_host(xyz, radii, alpha: float, parts: int, options=None) -> AlphaComplex:
+    """Host arrays (n x 3, n float64) -> alpha complex with host results, built
+    slab by slab with only one slab on the device at a time (out of core);
+    equal to ac_alpha_complex bit for bit."""
+    lib = _load()
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    radii = np.ascontiguousarray(radii, dtype=np.float64).reshape(-1)
+    if xyz.shape[0] != radii.shape[0]:
+        raise ValueError("xyz and radii disagree in length")
+    h = ctypes.c_void_p()
+    st = lib.ac_alpha_complex_partitioned_host(xyz.ctypes.data, radii.ctypes.data, xyz.shape[0], float(alpha),
+                                               int(parts), _opts(options), ctypes.byref(h))
     _check(st)
     return AlphaComplex(h)
 

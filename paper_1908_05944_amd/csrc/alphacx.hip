@@ -7,13 +7,16 @@
 
 #include <algorithm>
 #include <climits>
+#include <limits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <queue>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "alphacx.h"
@@ -277,29 +280,39 @@ struct Cands {
     const int *up, *edge_i, *tri_k, *tri_e, *tet_t, *tet_l, *perm;
 };
 
-// Stable LSD radix sort of (key, payload) on the low `bits` bits of key, 8
-// bits per pass. key / pay are set to the buffers that hold the result (the
-// inputs' or scratch of the scope).
+// Stable LSD radix sort of (key, payload) on bits [lo, hi) of key, 8 bits per
+// pass. key / pay are set to the buffers that hold the result (the inputs' or
+// scratch of the scope); *spare_key / *spare_pay (if given) to two other
+// buffers of n entries.
 template <class P>
-static void radix_sort(unsigned *&key, P *&pay, int n, int bits, hipStream_t s, Scope &sc) {
-    if (n <= 1 || bits <= 0) return;
-    const int tiles = (n + RS_TILE - 1) / RS_TILE;
-    unsigned *k2 = sc.get<unsigned>(n);
-    P *p2 = sc.get<P>(n);
-    int *hist = sc.get<int>((size_t)RS_BINS * tiles);
-    int *totals = sc.get<int>(RS_BINS);
+static void radix_sort(unsigned *&key, P *&pay, int n, int lo, int hi, hipStream_t s, Scope &sc,
+                       unsigned **spare_key = nullptr, P **spare_pay = nullptr) {
+    unsigned *k2 = sc.get<unsigned>(n > 0 ? n : 1);
+    P *p2 = sc.get<P>(n > 0 ? n : 1);
     unsigned *kin = key, *kout = k2;
     P *pin = pay, *pout = p2;
-    for (int shift = 0; shift < bits; shift += RS_BITS) {
-        k_rs_hist<<<tiles, RS_BLOCK, 0, s>>>(kin, n, shift, hist, tiles);
-        k_rs_digit_prefix<<<RS_BINS, RS_PREFIX_BLOCK, 0, s>>>(hist, tiles, totals);
-        k_rs_scatter<P><<<tiles, RS_BLOCK, 0, s>>>(kin, pin, kout, pout, n, shift, hist, totals, tiles);
-        LAUNCH_CHECK();
-        std::swap(kin, kout);
-        std::swap(pin, pout);
+    if (n > 1 && hi > lo) {
+        const int tiles = (n + RS_TILE - 1) / RS_TILE;
+        int *hist = sc.get<int>((size_t)RS_BINS * tiles);
+        int *totals = sc.get<int>(RS_BINS);
+        for (int shift = lo; shift < hi; shift += RS_BITS) {
+            k_rs_hist<<<tiles, RS_BLOCK, 0, s>>>(kin, n, shift, hist, tiles);
+            k_rs_digit_prefix<<<RS_BINS, RS_PREFIX_BLOCK, 0, s>>>(hist, tiles, totals);
+            k_rs_scatter<P><<<tiles, RS_BLOCK, 0, s>>>(kin, pin, kout, pout, n, shift, hist, totals, tiles);
+            LAUNCH_CHECK();
+            std::swap(kin, kout);
+            std::swap(pin, pout);
+        }
     }
     key = kin;
     pay = pin;
+    if (spare_key) *spare_key = kout;
+    if (spare_pay) *spare_pay = pout;
+}
+
+template <class P>
+static void radix_sort(unsigned *&key, P *&pay, int n, int bits, hipStream_t s, Scope &sc) {
+    radix_sort<P>(key, pay, n, 0, bits, s, sc);
 }
 
 static int bits_for(long long n) {
@@ -308,27 +321,28 @@ static int bits_for(long long n) {
     return b;
 }
 
-// Emit dimension d (K = d + 1 >= 2): every candidate keyed by its least
-// input id (not kept: after all ids), radix-sorted, then ranked inside each
-// bucket by the remaining ids. The output arrays have room for all M
-// candidates; the kept count goes to *m_out on the device.
+// Emit dimension d = K - 1 from the candidates' keys (least input id; not
+// kept: n) and payloads: an LSD radix pass over the key bits above `shift`
+// groups them into coarse buckets (one pass up to 2^22 balls, two above),
+// then k_emit_bucket finishes EB_KEYS keys per block and writes the sorted
+// rows. The output arrays have room for all M candidates; the kept count goes
+// to *m_out on the device.
 template <int K>
-static void emit_dim(const unsigned char *in, const double *sizes, int M, const Cands &cd, int n, hipStream_t s,
-                     Scope &sc, ac_complex *res, int d, int *m_out) {
+static void emit_dim(unsigned *key, typename EmitPay<K>::type *pay, const double *size_in, int M, int n,
+                     hipStream_t s, Scope &sc, ac_complex *res, int d, int *m_out, bool to_A2 = true) {
     typedef typename EmitPay<K>::type P;
     res->d_simp[d] = static_cast<int32_t *>(dev_alloc((size_t)(M > 0 ? M : 1) * K * sizeof(int32_t)));
     res->d_size[d] = static_cast<double *>(dev_alloc((size_t)(M > 0 ? M : 1) * sizeof(double)));
-    if (M == 0) {
-        fill<int>(m_out, 0, 1, s);
-        return;
-    }
-    unsigned *key = sc.get<unsigned>(M);
-    P *pay = sc.get<P>(M);
-    k_emit_keys<K><<<grid_for(M), BLOCK, 0, s>>>(in, M, cd.up, cd.edge_i, cd.tri_k, cd.tri_e, cd.tet_t, cd.tet_l,
-                                                 cd.perm, sizes, n, key, pay);
-    LAUNCH_CHECK();
-    radix_sort<P>(key, pay, M, bits_for((long long)n + 1), s, sc);
-    k_emit_rank<K><<<grid_for(M), BLOCK, 0, s>>>(key, pay, M, n, sizes, res->d_simp[d], res->d_size[d], m_out);
+    fill<int>(m_out, M, 1, s);
+    if (M == 0) return;
+    const int bits = bits_for((long long)n + 1);
+    const int shift = std::min(std::max(bits - RS_BITS, 0), 14);
+    unsigned *gkey = nullptr;
+    P *gpay = nullptr;
+    radix_sort<P>(key, pay, M, shift, bits, s, sc, &gkey, &gpay);
+    const unsigned blocks = (unsigned)(((long long)n + 1 + EB_KEYS - 1) / EB_KEYS);
+    k_emit_bucket<K><<<blocks, EB_BLOCK, 0, s>>>(key, pay, M, n, shift, gkey, gpay, size_in, to_A2 ? 1 : 0,
+                                                 res->d_simp[d], res->d_size[d], m_out);
     LAUNCH_CHECK();
 }
 
@@ -354,18 +368,24 @@ struct Options {
     int force_exact = 0;
     int vertex_shortcut = 0;
     int profile = 0;
+    int cell_order = ORDER_ROW;
 };
 
-// Stages timed by HIP events when profiling (one event before each).
+// Stages timed by HIP events when profiling. A stage lasts from its mark to
+// the next mark; "edges_ac2" and "triangles_ac2" are marked only when the AC2
+// tests of edges and triangles run as kernels of their own.
 enum Stage {
     ST_QUANTISE, ST_BIN, ST_NBR_COUNT, ST_NBR_SCAN, ST_NBR_FILL, ST_TRI_COUNT, ST_TRI_SCAN, ST_TRI_FILL,
     ST_TRI_GABRIEL, ST_TET_COUNT, ST_TET_FILL, ST_TETRA, ST_TRI_FINAL, ST_EDGE_FINAL, ST_VERT_FINAL, ST_EMIT,
-    ST_COUNT
+    ST_EDGE_AC2, ST_TRI_AC2, ST_COUNT
 };
 static const char *kStageNames[ST_COUNT] = {
     "quantise", "binning", "neighbours_count", "neighbours_scan", "neighbours_fill", "triangles_count",
     "triangles_scan", "triangles_fill", "triangles_ac2_tetrahedra", "tetrahedra_scan", "tetrahedra_fill", "tetrahedra_ac2",
-    "triangles_final", "edges_final", "vertices_final", "emit"};
+    "triangles_final", "edges_final", "vertices_final", "emit", "edges_ac2", "triangles_ac2"};
+// profile value of the per-step arrangement: every stage timed, edge and
+// triangle AC2 in kernels of their own
+constexpr int PROFILE_SPLIT = ST_COUNT + 2;
 
 // Events at stage boundaries. Each recorded event costs a few microseconds of
 // idle device time between two kernels, so a caller may ask for one stage
@@ -373,34 +393,42 @@ static const char *kStageNames[ST_COUNT] = {
 struct StageTimer {
     bool on = false;
     int only = -1;  // >= 0: record the boundaries of this stage only
+    int cur = -1;   // stage running since the last mark
     hipStream_t s = nullptr;
-    hipEvent_t ev[ST_COUNT + 1] = {};
-    bool rec[ST_COUNT + 1] = {};
+    std::vector<hipEvent_t> ev;
+    int ev_start[ST_COUNT], ev_end[ST_COUNT];
     void start(int profile, hipStream_t st) {
         on = profile != 0;
-        only = profile >= 2 ? profile - 2 : -1;
+        only = (profile >= 2 && profile < PROFILE_SPLIT) ? profile - 2 : -1;
         s = st;
-        if (!on) return;
-        for (int i = 0; i <= ST_COUNT; i++) HIP_TRY(hipEventCreate(&ev[i]));
+        for (int i = 0; i < ST_COUNT; i++) ev_start[i] = ev_end[i] = -1;
     }
+    // stage i starts now (i = ST_COUNT: the last stage ends)
     void mark(int i) {
-        if (!on || (only >= 0 && i != only && i != only + 1)) return;
-        HIP_TRY(hipEventRecord(ev[i], s));
-        rec[i] = true;
+        if (!on) return;
+        const bool need = only < 0 || i == only || cur == only;
+        if (need) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            ev.push_back(e);
+            HIP_TRY(hipEventRecord(e, s));
+            const int k = (int)ev.size() - 1;
+            if (cur >= 0) ev_end[cur] = k;
+            if (i < ST_COUNT) ev_start[i] = k;
+        }
+        cur = i;
     }
     void collect(double *ms) {
         for (int i = 0; i < ST_COUNT; i++) {
             ms[i] = -1.0;
-            if (on && rec[i] && rec[i + 1]) {
+            if (on && ev_start[i] >= 0 && ev_end[i] >= 0) {
                 float f = 0.f;
-                if (hipEventElapsedTime(&f, ev[i], ev[i + 1]) == hipSuccess) ms[i] = f;
+                if (hipEventElapsedTime(&f, ev[ev_start[i]], ev[ev_end[i]]) == hipSuccess) ms[i] = f;
             }
         }
     }
     ~StageTimer() {
-        if (on)
-            for (int i = 0; i <= ST_COUNT; i++)
-                if (ev[i]) (void)hipEventDestroy(ev[i]);
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     }
 };
 
@@ -447,6 +475,7 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         for (int k = 0; k < n_alpha; k++) rs[k] = new_result();
         res = rs[0];
         tm.start(o.profile, s);
+        const bool split = o.profile == PROFILE_SPLIT;  // AC2 of edges and triangles as kernels of their own
         // ---- quantise + stats (per molecule) ----
         tm.mark(ST_QUANTISE);
         const int n_mol = (int)bt.off.size() - 1;
@@ -506,8 +535,14 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             long long side = !bt.cell_mA.empty() ? bt.cell_mA[m] : (o.cell_mA > 0 ? o.cell_mA : (sgc > 0 ? sgc : 1));
             const long long cell_limit = n_mol == 1 ? std::max<long long>(8LL * nm, 1LL << 22)
                                                     : std::max<long long>(8LL * nm, 1LL << 15);
+            // cells of the grid: the box, or for a Morton order the cube of
+            // 2^L cells a side that holds it (2^(3L) codes)
             auto ncell_of = [&](long long sd) {
-                return ((ex + sd - 1) / sd) * ((ey + sd - 1) / sd) * ((ez + sd - 1) / sd);
+                const long long gx = (ex + sd - 1) / sd, gy = (ey + sd - 1) / sd, gz = (ez + sd - 1) / sd;
+                if (o.cell_order != ORDER_MORTON) return gx * gy * gz;
+                int L = 0;
+                while ((1LL << L) < std::max(gx, std::max(gy, gz))) L++;
+                return L > MORTON_MAX_BITS ? LLONG_MAX : 1LL << (3 * L);
             };
             while (ncell_of(side) > cell_limit) side = side + side / 4 + 1;
             g.s = (int)side;
@@ -516,7 +551,8 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             g.base = ncell;
             g.a0 = (int)bt.off[m];
             g.a1 = (int)bt.off[m + 1];
-            ncell += (long long)g.nx * g.ny * g.nz;
+            g.order = o.cell_order;
+            ncell += ncell_of(side);
         }
         if (ncell >= (long long)INT_MAX) throw HipError{AC_E_CAPACITY, "too many grid cells"};
         Grid *d_grids = sc.get<Grid>(n_mol);
@@ -546,6 +582,7 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         int *deg_n = sc.get<int>(n), *deg_up = sc.get<int>(n);
         int *nbr_start = sc.get<int>(n + 1), *up_start = sc.get<int>(n + 1);
         unsigned char *vgab = sc.get<unsigned char>(n);
+        long long *vert_min = sc.get<long long>(n);
         const unsigned nbN = grid_for(n);
         // slot per ball: wide for grown radii between 1.9 and 2.6 A (alpha > 0
         // with van der Waals radii), where rows outgrow 16 entries; beyond,
@@ -560,11 +597,12 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         if (slot == NB_SLOT_WIDE)
             k_neighbours<NB_ONEPASS, NB_SLOT_WIDE><<<nbN, BLOCK, 0, s>>>(atom, perm, n, d_grids, n_mol, cell_start, pp,
                                                                         deg_n, deg_up, upmask, nslab, nbtot, nullptr,
-                                                                        nullptr, nullptr, nullptr, nullptr, vgab, cnt);
+                                                                        nullptr, nullptr, nullptr, nullptr, vgab, vert_min,
+                                                                        cnt);
         else
             k_neighbours<NB_ONEPASS, NB_SLOT><<<nbN, BLOCK, 0, s>>>(atom, perm, n, d_grids, n_mol, cell_start, pp, deg_n,
                                                                    deg_up, upmask, nslab, nbtot, nullptr, nullptr,
-                                                                   nullptr, nullptr, nullptr, vgab, cnt);
+                                                                   nullptr, nullptr, nullptr, vgab, vert_min, cnt);
         LAUNCH_CHECK();
         tm.mark(ST_NBR_SCAN);
         scan_i32(nbtot, nboff, nbN, s, sc, &cnt->Nn);
@@ -599,16 +637,23 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         } else {
             k_neighbours<NB_FILL, NB_SLOT><<<nbN, BLOCK, 0, s>>>(atom, perm, n, d_grids, n_mol, cell_start, pp, nullptr,
                                                                 nullptr, nullptr, nullptr, nullptr, nbr_start, up_start,
-                                                                nbr, up, edge_i, vgab, cnt);
+                                                                nbr, up, edge_i, vgab, vert_min, cnt);
         }
         LAUNCH_CHECK();
         const int *nbr_cnt = deg_n;
+        unsigned char *egab = sc.get<unsigned char>(E > 0 ? E : 1);
+        long long *edge_min = sc.get<long long>(E > 0 ? E : 1);
+        if (split && E > 0) {
+            tm.mark(ST_EDGE_AC2);
+            k_edge_ac2<<<grid_for(E), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up, edge_i, E, pp, egab,
+                                                    edge_min);
+            LAUNCH_CHECK();
+        }
 
         // ---- candidate triangles (with AC2 of the edges): one pass into
         // per-block slabs, then compaction; two passes if a slab overflows ----
         int *tri_cnt = sc.get<int>(E > 0 ? E : 1);
         int *tri_start = sc.get<int>(E + 1);
-        unsigned char *egab = sc.get<unsigned char>(E > 0 ? E : 1);
         const unsigned nbE = grid_for(E);
         int *tslab = sc.get<int>((size_t)nbE * TRI_SLAB);
         int *tbtot = sc.get<int>(nbE);
@@ -616,8 +661,14 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         tm.mark(ST_TRI_COUNT);
         fill<int>(&cnt->overflow, 0, 1, s);
         if (E > 0) {
-            k_triangles<TRI_ONEPASS><<<nbE, BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i, E,
-                                                          pp, tri_cnt, egab, tslab, tbtot, nullptr, nullptr, nullptr, cnt);
+            if (split)
+                k_triangles<TRI_ONEPASS, false><<<nbE, BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up,
+                                                                     edge_i, E, pp, tri_cnt, egab, edge_min, tslab,
+                                                                     tbtot, nullptr, nullptr, nullptr, cnt);
+            else
+                k_triangles<TRI_ONEPASS><<<nbE, BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i,
+                                                              E, pp, tri_cnt, egab, edge_min, tslab, tbtot, nullptr,
+                                                              nullptr, nullptr, cnt);
             LAUNCH_CHECK();
             tm.mark(ST_TRI_SCAN);
             scan_i32(tbtot, tboff, nbE, s, sc, &cnt->T);
@@ -642,6 +693,7 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         int *tri_e = sc.get<int>(T > 0 ? T : 1);
         unsigned char *tgab = sc.get<unsigned char>(T > 0 ? T : 1);
         double *tsize = sc.get<double>(T > 0 ? T : 1);
+        long long *tri_min = sc.get<long long>(T > 0 ? T : 1);
         int *tet_cnt = sc.get<int>(T > 0 ? T : 1);
         int *tet_start = sc.get<int>(T + 1);
         tm.mark(ST_TRI_FILL);
@@ -650,7 +702,8 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             LAUNCH_CHECK();
         } else if (T > 0) {
             k_triangles<TRI_FILL><<<nbE, BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i, E, pp,
-                                                       nullptr, nullptr, nullptr, nullptr, tri_start, tri_k, tri_e, cnt);
+                                                       nullptr, nullptr, nullptr, nullptr, nullptr, tri_start, tri_k,
+                                                       tri_e, cnt);
             LAUNCH_CHECK();
         }
         if (E == 0) fill<int>(tri_start, 0, 1, s);
@@ -660,12 +713,23 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         int *qslab = sc.get<int>((size_t)nbT * TET_SLAB);
         int *qbtot = sc.get<int>(nbT);
         int *qboff = sc.get<int>(nbT + 1);
+        if (split && T > 0) {
+            tm.mark(ST_TRI_AC2);
+            k_tri_ac2<<<grid_for(T), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up, edge_i, tri_k, tri_e, T, pp,
+                                                   tgab, tsize, tri_min, cnt);
+            LAUNCH_CHECK();
+        }
         tm.mark(ST_TRI_GABRIEL);
         fill<int>(&cnt->overflow, 0, 1, s);
         if (T > 0) {
-            k_tet_candidates<TET_ONEPASS><<<nbT, BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i,
-                                                               tri_k, tri_e, T, pp, tgab, tsize, tet_cnt, qslab, qbtot,
-                                                               nullptr, nullptr, nullptr, cnt);
+            if (split)
+                k_tet_candidates<TET_ONEPASS, false><<<nbT, BLOCK, 0, s>>>(
+                    atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i, tri_k, tri_e, T, pp, tgab, tsize, tri_min,
+                    tet_cnt, qslab, qbtot, nullptr, nullptr, nullptr, cnt);
+            else
+                k_tet_candidates<TET_ONEPASS><<<nbT, BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up,
+                                                                   edge_i, tri_k, tri_e, T, pp, tgab, tsize, tri_min,
+                                                                   tet_cnt, qslab, qbtot, nullptr, nullptr, nullptr, cnt);
             LAUNCH_CHECK();
         }
         tm.mark(ST_TET_COUNT);
@@ -686,7 +750,6 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         const int Q = cq.Q;
         int *tet_t = sc.get<int>(Q > 0 ? Q : 1);
         int *tet_l = sc.get<int>(Q > 0 ? Q : 1);
-        unsigned char *qin = sc.get<unsigned char>(Q > 0 ? Q : 1);
         double *qsize = sc.get<double>(Q > 0 ? Q : 1);
         tm.mark(ST_TET_FILL);
         if (T > 0 && !tet_two_pass) {
@@ -695,19 +758,14 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         } else if (Q > 0) {
             k_tet_candidates<TET_FILL><<<nbT, BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i,
                                                             tri_k, tri_e, T, pp, nullptr, nullptr, nullptr, nullptr,
-                                                            nullptr, tet_start, tet_t, tet_l, cnt);
+                                                            nullptr, nullptr, tet_start, tet_t, tet_l, cnt);
             LAUNCH_CHECK();
         }
 
         // ---- pruning: tetrahedra, then triangles, edges, vertices ----
-        int *tri_att = sc.get<int>(T > 0 ? T : 1);
-        long long *tri_min = sc.get<long long>(T > 0 ? T : 1);
-        int *edge_att = sc.get<int>(E > 0 ? E : 1);
-        long long *edge_min = sc.get<long long>(E > 0 ? E : 1);
-        int *vert_att = sc.get<int>(n);
-        long long *vert_min = sc.get<long long>(n);
-        int *vin_in = sc.get<int>(n);
+        int *tri_att = nullptr, *edge_att = nullptr, *vert_att = nullptr;  // sweep only
         double *vsize_in = sc.get<double>(n);
+        int *vflag = sc.get<int>(n);
         int *vpos = sc.get<int>(n + 1);
         auto prune_init = [&]() {
             const long long mx = std::max<long long>(std::max<long long>(T, E), n);
@@ -717,15 +775,16 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         };
         // vertices of one alpha (Step 5), then their output in input order
         auto vert_final = [&](const PredParams &pa) {
-            k_vert_final<<<grid_for(n), BLOCK, 0, s>>>(atom, perm, n, pa, o.vertex_shortcut, vgab, vert_att, vert_min,
-                                                      vin_in, vsize_in);
+            k_vert_final<<<grid_for(n), BLOCK, 0, s>>>(atom, perm, n, pa, o.vertex_shortcut, vgab, vert_min, vsize_in);
             LAUNCH_CHECK();
         };
         auto vert_emit = [&](ac_complex *r, int *m_out) {
-            scan_i32(vin_in, vpos, n, s, sc, m_out);
+            k_vert_flags<<<grid_for(n), BLOCK, 0, s>>>(vsize_in, n, vflag);
+            LAUNCH_CHECK();
+            scan_i32(vflag, vpos, n, s, sc, m_out);
             r->d_simp[0] = static_cast<int32_t *>(dev_alloc((size_t)n * sizeof(int32_t)));
             r->d_size[0] = static_cast<double *>(dev_alloc((size_t)n * sizeof(double)));
-            k_vert_emit<<<grid_for(n), BLOCK, 0, s>>>(vin_in, vpos, vsize_in, n, r->d_simp[0], r->d_size[0]);
+            k_vert_emit<<<grid_for(n), BLOCK, 0, s>>>(vsize_in, vpos, n, r->d_simp[0], r->d_size[0]);
             LAUNCH_CHECK();
         };
         // rows of each molecule of a batch in the sorted outputs of r (device)
@@ -752,27 +811,30 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         long long *d_rows = n_mol > 1 ? sc.get<long long>((size_t)n_alpha * 4 * (n_mol + 1)) : nullptr;
 
         if (n_alpha == 1) {
-            unsigned char *tin = sc.get<unsigned char>(T > 0 ? T : 1);
-            unsigned char *ein = sc.get<unsigned char>(E > 0 ? E : 1);
-            double *esize = sc.get<double>(E > 0 ? E : 1);
-            prune_init();
+            // every candidate leaves its pruning kernel with its emit key
+            // (least input id, n if not kept) and payload
+            unsigned *qkey = sc.get<unsigned>(Q > 0 ? Q : 1), *tkey = sc.get<unsigned>(T > 0 ? T : 1);
+            unsigned *ekey = sc.get<unsigned>(E > 0 ? E : 1);
+            EmitPay<4>::type *qpay = sc.get<EmitPay<4>::type>(Q > 0 ? Q : 1);
+            EmitPay<3>::type *tpay = sc.get<EmitPay<3>::type>(T > 0 ? T : 1);
+            EmitPay<2>::type *epay = sc.get<EmitPay<2>::type>(E > 0 ? E : 1);
             tm.mark(ST_TETRA);
             if (Q > 0) {
                 k_tet_ac2<false><<<grid_for(Q), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i,
-                                                              tri_start, tri_k, tri_e, tet_t, tet_l, Q, pp, tgab, tri_att,
-                                                              tri_min, qin, qsize, nullptr, cnt);
+                                                              tri_start, tri_k, tri_e, tet_t, tet_l, Q, pp, tgab, tri_min,
+                                                              nullptr, qsize, nullptr, n, qkey, qpay, cnt);
                 LAUNCH_CHECK();
             }
             tm.mark(ST_TRI_FINAL);
             if (T > 0) {
-                k_tri_final<<<grid_for(T), BLOCK, 0, s>>>(up_start, up, edge_i, tri_k, tri_e, T, tgab, tsize, tri_att,
-                                                         tri_min, tin, egab, edge_att, edge_min, cnt);
+                k_tri_final<<<grid_for(T), BLOCK, 0, s>>>(up_start, up, edge_i, tri_k, tri_e, T, tgab, tsize, tri_min, egab,
+                                                         edge_min, perm, n, tkey, tpay, cnt);
                 LAUNCH_CHECK();
             }
             tm.mark(ST_EDGE_FINAL);
             if (E > 0) {
-                k_edge_final<<<grid_for(E), BLOCK, 0, s>>>(atom, up, edge_i, E, egab, edge_att, edge_min, ein, esize, vgab,
-                                                          vert_att, vert_min);
+                k_edge_final<<<grid_for(E), BLOCK, 0, s>>>(atom, up, edge_i, E, egab, edge_min, vgab, vert_min, perm, n,
+                                                          ekey, epay);
                 LAUNCH_CHECK();
             }
             tm.mark(ST_VERT_FINAL);
@@ -780,21 +842,24 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             // ---- emit ----
             tm.mark(ST_EMIT);
             vert_emit(res, &cnt->m0);
-            const Cands cd{up, edge_i, tri_k, tri_e, tet_t, tet_l, perm};
-            emit_dim<2>(ein, esize, E, cd, n, s, sc, res, 1, &cnt->m1);
-            emit_dim<3>(tin, tsize, T, cd, n, s, sc, res, 2, &cnt->m2);
-            emit_dim<4>(qin, qsize, Q, cd, n, s, sc, res, 3, &cnt->m3);
+            emit_dim<2>(ekey, epay, nullptr, E, n, s, sc, res, 1, &cnt->m1);
+            emit_dim<3>(tkey, tpay, nullptr, T, n, s, sc, res, 2, &cnt->m2);
+            emit_dim<4>(qkey, qpay, qsize, Q, n, s, sc, res, 3, &cnt->m3);
             if (n_mol > 1) mol_rows(res, cnt, d_rows, d_bound);
         } else {
             // ---- sweep: AC2 of the tetrahedra, the output order of every
             // candidate and each candidate's AC3 threshold once; then per
             // alpha, comparisons, pruning and compaction in output order ----
             tm.mark(ST_TETRA);
+            tri_att = sc.get<int>(T > 0 ? T : 1);
+            edge_att = sc.get<int>(E > 0 ? E : 1);
+            vert_att = sc.get<int>(n);
+            unsigned char *qin = sc.get<unsigned char>(Q > 0 ? Q : 1);
             int4 *tface = sc.get<int4>(Q > 0 ? Q : 1);
             if (Q > 0) {
                 k_tet_ac2<true><<<grid_for(Q), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i,
                                                              tri_start, tri_k, tri_e, tet_t, tet_l, Q, pp, tgab, nullptr,
-                                                             nullptr, qin, qsize, tface, cnt);
+                                                             qin, qsize, tface, n, nullptr, nullptr, cnt);
                 LAUNCH_CHECK();
             }
             int2 *tedge = sc.get<int2>(T > 0 ? T : 1);
@@ -948,46 +1013,65 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
 // 2 A, one pipeline run per slab, owned rows kept, then merged in output
 // order. Peak scratch memory is that of the largest slab's build.
 
-// Sorts the rows of dimension K - 1 gathered from all slabs into output
-// order and stores them in r (d_simp / d_size of dimension K - 1).
-template <int K>
-static void merge_rows(const int *rows, const double *size, int m, int n, hipStream_t s, Scope &sc, ac_complex *r) {
-    typedef typename OrderPay<K>::type P;
-    const int d = K - 1;
-    r->d_simp[d] = static_cast<int32_t *>(dev_alloc((size_t)(m > 0 ? m : 1) * K * sizeof(int32_t)));
-    r->d_size[d] = static_cast<double *>(dev_alloc((size_t)(m > 0 ? m : 1) * sizeof(double)));
-    if (m == 0) return;
-    unsigned *key = sc.get<unsigned>(m);
-    P *pay = sc.get<P>(m);
-    int *spos = sc.get<int>(m);
-    k_rows_keys<K><<<grid_for(m), BLOCK, 0, s>>>(rows, m, key, pay);
-    LAUNCH_CHECK();
-    radix_sort<P>(key, pay, m, bits_for((long long)n), s, sc);
-    k_order_rank<K><<<grid_for(m), BLOCK, 0, s>>>(key, pay, m, r->d_simp[d], spos);
-    k_place_sizes<<<grid_for(m), BLOCK, 0, s>>>(spos, size, m, r->d_size[d]);
-    LAUNCH_CHECK();
-}
+// Rows of dimension K - 1 that slab k owns, in emit form: flags, their scan
+// and count (read back: the slab's memory is freed next), then the packed
+// keys, payloads and (tetrahedra) Sizes, appended to the per-slab lists.
+struct OwnedRows {
+    std::vector<void *> key, pay, size;  // per slab with owned rows
+    std::vector<int> count;
+    long long total = 0;
+    ~OwnedRows() {
+        for (auto *v : {&key, &pay, &size})
+            for (void *p : *v) dev_free(p);
+    }
+};
 
 template <int K>
 static void own_rows(const ac_complex *ck, const int *sel, const int4 *q, int x0, int w, int parts, int k,
-                     hipStream_t s, Scope &sc, std::vector<int *> &rows, std::vector<double *> &sizes,
-                     std::vector<int *> &counts) {
+                     hipStream_t s, Scope &sc, OwnedRows &own) {
+    typedef typename EmitPay<K>::type P;
     const int d = K - 1;
     const int m = (int)ck->count[d];
     if (m == 0) return;
     int *flag = sc.get<int>(m);
     int *pos = sc.get<int>((size_t)m + 1);
     int *cnt = sc.get<int>(1);
-    int *out = sc.get<int>((size_t)m * K);
-    double *out_size = sc.get<double>(m);
     k_own_flags<K><<<grid_for(m), BLOCK, 0, s>>>(ck->d_simp[d], m, sel, q, x0, w, parts, k, flag);
     LAUNCH_CHECK();
     scan_i32(flag, pos, m, s, sc, cnt);
-    k_own_write<K><<<grid_for(m), BLOCK, 0, s>>>(ck->d_simp[d], ck->d_size[d], m, flag, pos, sel, out, out_size);
+    const int c = read_one(cnt, s);
+    if (c == 0) return;
+    check_total(own.total + c, "simplices of one dimension");
+    unsigned *key = static_cast<unsigned *>(dev_alloc((size_t)c * sizeof(unsigned)));
+    own.key.push_back(key);
+    P *pay = static_cast<P *>(dev_alloc((size_t)c * sizeof(P)));
+    own.pay.push_back(pay);
+    double *size = K == 4 ? static_cast<double *>(dev_alloc((size_t)c * sizeof(double))) : nullptr;
+    if (size) own.size.push_back(size);
+    k_own_emit<K><<<grid_for(m), BLOCK, 0, s>>>(ck->d_simp[d], ck->d_size[d], m, flag, pos, sel, (int)own.total, key,
+                                                pay, size);
     LAUNCH_CHECK();
-    rows.push_back(out);
-    sizes.push_back(out_size);
-    counts.push_back(cnt);
+    own.count.push_back(c);
+    own.total += c;
+}
+
+// All slabs' owned rows of dimension K - 1 in output order (into r).
+template <int K>
+static void merge_rows(OwnedRows &own, int n, hipStream_t s, Scope &sc, ac_complex *r, int *m_out) {
+    typedef typename EmitPay<K>::type P;
+    const int m = (int)own.total;
+    unsigned *key = sc.get<unsigned>(m > 0 ? m : 1);
+    P *pay = sc.get<P>(m > 0 ? m : 1);
+    double *size = K == 4 ? sc.get<double>(m > 0 ? m : 1) : nullptr;
+    long long off = 0;
+    for (size_t j = 0; j < own.count.size(); j++) {
+        const size_t c = (size_t)own.count[j];
+        HIP_TRY(hipMemcpyAsync(key + off, own.key[j], c * sizeof(unsigned), hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(pay + off, own.pay[j], c * sizeof(P), hipMemcpyDeviceToDevice, s));
+        if (size) HIP_TRY(hipMemcpyAsync(size + off, own.size[j], c * sizeof(double), hipMemcpyDeviceToDevice, s));
+        off += (long long)c;
+    }
+    emit_dim<K>(key, pay, size, m, n, s, sc, r, K - 1, m_out, false);
 }
 
 static ac_status run_partitioned(const double *d_xyz, const double *d_r, int64_t n64, double alpha, int parts,
@@ -1027,8 +1111,7 @@ static ac_status run_partitioned(const double *d_xyz, const double *d_r, int64_t
         const int x0 = h.minx;
         const int w = (int)(((long long)h.maxx - h.minx + parts) / parts);  // ceil((extent + 1) / parts)
 
-        std::vector<int *> rows[4], counts[4];
-        std::vector<double *> sizes[4];
+        OwnedRows own[4];
         int *kept = sc.get<int>(n);
         double *vsize = sc.get<double>(n);
         fill<int>(kept, 0, n, s);
@@ -1061,9 +1144,9 @@ static ac_status run_partitioned(const double *d_xyz, const double *d_r, int64_t
                                                                         kept, vsize);
                 LAUNCH_CHECK();
             }
-            own_rows<2>(ck, sel, q, x0, w, parts, k, s, sc, rows[1], sizes[1], counts[1]);
-            own_rows<3>(ck, sel, q, x0, w, parts, k, s, sc, rows[2], sizes[2], counts[2]);
-            own_rows<4>(ck, sel, q, x0, w, parts, k, s, sc, rows[3], sizes[3], counts[3]);
+            own_rows<2>(ck, sel, q, x0, w, parts, k, s, sc, own[1]);
+            own_rows<3>(ck, sel, q, x0, w, parts, k, s, sc, own[2]);
+            own_rows<4>(ck, sel, q, x0, w, parts, k, s, sc, own[3]);
             HIP_TRY(hipStreamSynchronize(s));  // the slab's result is consumed; free it
             free_complex(ck);
             ck = nullptr;
@@ -1080,32 +1163,12 @@ static ac_status run_partitioned(const double *d_xyz, const double *d_r, int64_t
         k_vertex_rows<<<grid_for(n), BLOCK, 0, s>>>(kept, pos, vsize, n, res->d_simp[0], res->d_size[0]);
         LAUNCH_CHECK();
         res->count[0] = read_one(m0, s);
-        // higher dimensions: gather every slab's owned rows, then one sort
-        for (int d = 1; d <= 3; d++) {
-            const int K = d + 1;
-            std::vector<int> c(counts[d].size());
-            long long total = 0;
-            for (size_t j = 0; j < counts[d].size(); j++) {
-                c[j] = read_one(counts[d][j], s);
-                total += c[j];
-            }
-            check_total(total, "simplices of one dimension");
-            int *all = sc.get<int>((size_t)(total > 0 ? total : 1) * K);
-            double *all_size = sc.get<double>(total > 0 ? total : 1);
-            long long off = 0;
-            for (size_t j = 0; j < c.size(); j++) {
-                if (!c[j]) continue;
-                HIP_TRY(hipMemcpyAsync(all + off * K, rows[d][j], (size_t)c[j] * K * sizeof(int), hipMemcpyDeviceToDevice,
-                                       s));
-                HIP_TRY(hipMemcpyAsync(all_size + off, sizes[d][j], (size_t)c[j] * sizeof(double),
-                                       hipMemcpyDeviceToDevice, s));
-                off += c[j];
-            }
-            if (d == 1) merge_rows<2>(all, all_size, (int)total, n, s, sc, res);
-            else if (d == 2) merge_rows<3>(all, all_size, (int)total, n, s, sc, res);
-            else merge_rows<4>(all, all_size, (int)total, n, s, sc, res);
-            res->count[d] = total;
-        }
+        // higher dimensions: every slab's owned rows merged into output order
+        int *mcount = sc.get<int>(4);
+        merge_rows<2>(own[1], n, s, sc, res, mcount + 1);
+        merge_rows<3>(own[2], n, s, sc, res, mcount + 2);
+        merge_rows<4>(own[3], n, s, sc, res, mcount + 3);
+        for (int d = 1; d <= 3; d++) res->count[d] = own[d].total;
         HIP_TRY(hipStreamSynchronize(s));
         res->n = n;
         res->n_mol = 1;
@@ -1121,6 +1184,272 @@ static ac_status run_partitioned(const double *d_xyz, const double *d_r, int64_t
         free_complex(ck);
         free_complex(res);
         return set_error(e.st, e.msg);
+    }
+    *out = res;
+    g_last_error.clear();
+    return AC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Host-streamed partitioned build: inputs and results stay in host memory.
+// One slab at a time (its core and halo) is copied to the device, built, and
+// the rows it owns are copied back in emit form; the slabs' lists, each
+// sorted already, are merged on the host. Device memory is that of one
+// slab's build.
+
+template <int K> struct HostPay { static constexpr int words = K == 2 ? 3 : 4; };
+
+// Owned rows of dimension K - 1 of all slabs, in host memory.
+struct HostRows {
+    std::vector<std::vector<uint32_t>> key, pay;  // per slab
+    std::vector<std::vector<double>> size;        // per slab (K = 4)
+};
+
+template <int K>
+static void own_rows_host(const ac_complex *ck, const int *sel, const int *qx, int x0, int w, int parts, int k,
+                          hipStream_t s, Scope &sc, HostRows &hr) {
+    typedef typename EmitPay<K>::type P;
+    const int d = K - 1;
+    const int m = (int)ck->count[d];
+    if (m == 0) return;
+    int *flag = sc.get<int>(m);
+    int *pos = sc.get<int>((size_t)m + 1);
+    int *cnt = sc.get<int>(1);
+    k_own_flags_local<K><<<grid_for(m), BLOCK, 0, s>>>(ck->d_simp[d], m, sel, qx, x0, w, parts, k, flag);
+    LAUNCH_CHECK();
+    scan_i32(flag, pos, m, s, sc, cnt);
+    const int c = read_one(cnt, s);
+    if (c == 0) return;
+    unsigned *key = sc.get<unsigned>(c);
+    P *pay = sc.get<P>(c);
+    double *size = K == 4 ? sc.get<double>(c) : nullptr;
+    k_own_emit<K><<<grid_for(m), BLOCK, 0, s>>>(ck->d_simp[d], ck->d_size[d], m, flag, pos, sel, 0, key, pay, size);
+    LAUNCH_CHECK();
+    static_assert(sizeof(P) == HostPay<K>::words * sizeof(uint32_t), "payload words");
+    hr.key.emplace_back((size_t)c);
+    hr.pay.emplace_back((size_t)c * HostPay<K>::words);
+    HIP_TRY(hipMemcpyAsync(hr.key.back().data(), key, (size_t)c * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hr.pay.back().data(), pay, (size_t)c * sizeof(P), hipMemcpyDeviceToHost, s));
+    if (size) {
+        hr.size.emplace_back((size_t)c);
+        HIP_TRY(hipMemcpyAsync(hr.size.back().data(), size, (size_t)c * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+}
+
+// K-way merge of the slabs' sorted lists into output order (rows of K input
+// ids, Sizes), in parallel over ranges of the least id.
+template <int K>
+static void merge_host(const HostRows &hr, int n, std::vector<int32_t> &rows, std::vector<double> &sizes) {
+    constexpr int W = HostPay<K>::words;
+    const size_t L = hr.key.size();
+    size_t M = 0;
+    for (const auto &k : hr.key) M += k.size();
+    rows.assign(M * K + 1, 0);
+    sizes.assign(M + 1, 0.0);
+    if (M == 0) return;
+    auto row_less = [&](size_t a, size_t ra, size_t b, size_t rb) {
+        if (hr.key[a][ra] != hr.key[b][rb]) return hr.key[a][ra] < hr.key[b][rb];
+        for (int u = 0; u < K - 1; u++) {
+            const uint32_t x = hr.pay[a][ra * W + u], y = hr.pay[b][rb * W + u];
+            if (x != y) return x < y;
+        }
+        return false;
+    };
+    const int T = (int)std::max<size_t>(1, std::min<size_t>(16, std::thread::hardware_concurrency()));
+    std::vector<std::vector<size_t>> lo(T + 1, std::vector<size_t>(L));
+    std::vector<size_t> start(T + 1, 0);
+    for (int t = 0; t <= T; t++) {
+        const uint32_t u = (uint32_t)((long long)n * t / T);
+        for (size_t j = 0; j < L; j++) {
+            lo[t][j] = t == T ? hr.key[j].size()
+                              : (size_t)(std::lower_bound(hr.key[j].begin(), hr.key[j].end(), u) - hr.key[j].begin());
+            start[t] += lo[t][j];
+        }
+    }
+    auto work = [&](int t) {
+        std::vector<size_t> at = lo[t];
+        auto greater = [&](size_t a, size_t b) { return row_less(b, at[b], a, at[a]); };
+        std::priority_queue<size_t, std::vector<size_t>, decltype(greater)> heap(greater);
+        for (size_t j = 0; j < L; j++)
+            if (at[j] < lo[t + 1][j]) heap.push(j);
+        size_t out = start[t];
+        while (!heap.empty()) {
+            const size_t j = heap.top();
+            heap.pop();
+            const size_t r = at[j];
+            rows[out * K] = (int32_t)hr.key[j][r];
+            for (int u = 1; u < K; u++) rows[out * K + u] = (int32_t)hr.pay[j][r * W + u - 1];
+            if constexpr (K == 4) {
+                sizes[out] = hr.size[j][r];
+            } else {
+                const uint64_t b = (uint64_t)hr.pay[j][r * W + K - 1] | ((uint64_t)hr.pay[j][r * W + K] << 32);
+                double z;
+                std::memcpy(&z, &b, sizeof z);
+                sizes[out] = z;
+            }
+            out++;
+            if (++at[j] < lo[t + 1][j]) heap.push(j);
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < T; t++) th.emplace_back(work, t);
+    work(0);
+    for (auto &x : th) x.join();
+}
+
+static ac_status run_streamed(const double *xyz, const double *r, int64_t n64, double alpha, int parts, const Options &o,
+                              ac_complex **out) {
+    *out = nullptr;
+    if (!xyz || !r) return set_error(AC_E_INVALID, "NULL input pointer");
+    if (n64 < 1 || n64 >= (1 << 26)) return set_error(AC_E_INVALID, "n must be in [1, 2^26)");
+    if (parts < 1 || parts > 1024) return set_error(AC_E_INVALID, "parts must be in [1, 1024]");
+    if (!std::isfinite(alpha)) return set_error(AC_E_INVALID, "alpha is not finite");
+    const double as = alpha * 1e6;
+    if (!(std::fabs(as) < 67108864.0)) return set_error(AC_E_RANGE, "|alpha| too large for the exact bit budget");
+    const long long aq = (long long)std::nearbyint(as);
+    const int n = (int)n64;
+    // the slabs' bounds need the quantised x of every ball and the largest
+    // weight: the same rounding (half to even) and checks as the device's
+    std::vector<int> qx((size_t)n);
+    long long wmax = 0;
+    for (int i = 0; i < n; i++) {
+        const double v = xyz[3 * (size_t)i];
+        if (!std::isfinite(v)) return set_error(AC_E_INVALID, "non-finite coordinate, or radius not positive");
+        const double sx = v * 1000.0;
+        if (!(std::fabs(sx) < 524288.0)) return set_error(AC_E_RANGE, "coordinate or radius outside the exact bit budget");
+        qx[i] = (int)std::nearbyint(sx);
+        if (qx[i] >= 524288 || qx[i] <= -524288)
+            return set_error(AC_E_RANGE, "coordinate or radius outside the exact bit budget");
+        const double rv = r[i];
+        if (!std::isfinite(rv) || !(rv > 0.0)) return set_error(AC_E_INVALID, "non-finite coordinate, or radius not positive");
+        if (!(rv * 1000.0 < 8192.0)) return set_error(AC_E_RANGE, "coordinate or radius outside the exact bit budget");
+        const long long R = (long long)std::nearbyint(rv * 1000.0);
+        wmax = std::max(wmax, R * R);
+    }
+    const long long sg2 = wmax + aq;
+    if (sg2 >= (1LL << 26)) return set_error(AC_E_RANGE, "r_max^2 + alpha too large for the exact bit budget");
+    const int halo = (int)(4 * isqrt_ceil(sg2 < 0 ? 0 : sg2) + 2000);
+    const int x0 = *std::min_element(qx.begin(), qx.end()), x1 = *std::max_element(qx.begin(), qx.end());
+    const int w = (int)(((long long)x1 - x0 + parts) / parts);  // ceil((extent + 1) / parts)
+    hipStream_t s = nullptr;
+    ac_complex *res = nullptr, *ck = nullptr;
+    void *pin = nullptr;
+    try {
+        // the slabs' balls (input order) and the largest slab
+        std::vector<std::vector<int>> slab((size_t)parts);
+        size_t big = 0;
+        for (int k = 0; k < parts; k++) {
+            const int lo = x0 + k * w, hi = k == parts - 1 ? INT_MAX - halo : lo + w;
+            for (int i = 0; i < n; i++)
+                if (qx[i] >= lo - halo && qx[i] < hi + halo) slab[k].push_back(i);
+            big = std::max(big, slab[k].size());
+        }
+        const size_t stage = big * (4 * sizeof(double) + 2 * sizeof(int));
+        HIP_TRY(hipHostMalloc(&pin, stage > 0 ? stage : 1, hipHostMallocDefault));
+        double *hx = static_cast<double *>(pin), *hrad = hx + 3 * big;
+        int *hsel = reinterpret_cast<int *>(hrad + big), *hqx = hsel + big;
+        std::vector<double> vsize((size_t)n, std::numeric_limits<double>::quiet_NaN());
+        HostRows rows[4];
+        long long fallbacks = 0;
+        for (int k = 0; k < parts; k++) {
+            const int ms = (int)slab[k].size();
+            if (ms == 0) continue;
+            for (int t = 0; t < ms; t++) {
+                const int i = slab[k][t];
+                hx[3 * t] = xyz[3 * (size_t)i];
+                hx[3 * t + 1] = xyz[3 * (size_t)i + 1];
+                hx[3 * t + 2] = xyz[3 * (size_t)i + 2];
+                hrad[t] = r[i];
+                hsel[t] = i;
+                hqx[t] = qx[i];
+            }
+            Scope sc;  // this slab's device memory, back to the pool after the slab
+            double *dx = sc.get<double>(3 * (size_t)ms), *dr = sc.get<double>(ms);
+            int *dsel = sc.get<int>(ms), *dqx = sc.get<int>(ms);
+            HIP_TRY(hipMemcpyAsync(dx, hx, 3 * (size_t)ms * sizeof(double), hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync(dr, hrad, (size_t)ms * sizeof(double), hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync(dsel, hsel, (size_t)ms * sizeof(int), hipMemcpyHostToDevice, s));
+            HIP_TRY(hipMemcpyAsync(dqx, hqx, (size_t)ms * sizeof(int), hipMemcpyHostToDevice, s));
+            Batch bt;
+            bt.off = {0, ms};
+            Options ok = o;
+            ok.profile = 0;
+            const ac_status stp = run_pipeline(dx, dr, ms, bt, alpha, ok, s, &ck);
+            if (stp != AC_OK) throw HipError{stp, g_last_error};
+            fallbacks += ck->fallbacks;
+            // vertices the slab owns: input id and Size
+            const int m0 = (int)ck->count[0];
+            if (m0 > 0) {
+                int *flag = sc.get<int>(m0), *pos = sc.get<int>((size_t)m0 + 1), *cnt = sc.get<int>(1);
+                k_own_flags_local<1><<<grid_for(m0), BLOCK, 0, s>>>(ck->d_simp[0], m0, dsel, dqx, x0, w, parts, k, flag);
+                LAUNCH_CHECK();
+                scan_i32(flag, pos, m0, s, sc, cnt);
+                const int c = read_one(cnt, s);
+                if (c > 0) {
+                    int *oid = sc.get<int>(c);
+                    double *osz = sc.get<double>(c);
+                    k_own_vertices_local<<<grid_for(m0), BLOCK, 0, s>>>(ck->d_simp[0], ck->d_size[0], m0, flag, pos, dsel,
+                                                                        oid, osz);
+                    LAUNCH_CHECK();
+                    std::vector<int> hid((size_t)c);
+                    std::vector<double> hsz((size_t)c);
+                    HIP_TRY(hipMemcpyAsync(hid.data(), oid, (size_t)c * sizeof(int), hipMemcpyDeviceToHost, s));
+                    HIP_TRY(hipMemcpyAsync(hsz.data(), osz, (size_t)c * sizeof(double), hipMemcpyDeviceToHost, s));
+                    HIP_TRY(hipStreamSynchronize(s));
+                    for (int t = 0; t < c; t++) vsize[hid[t]] = hsz[t];
+                }
+            }
+            own_rows_host<2>(ck, dsel, dqx, x0, w, parts, k, s, sc, rows[1]);
+            own_rows_host<3>(ck, dsel, dqx, x0, w, parts, k, s, sc, rows[2]);
+            own_rows_host<4>(ck, dsel, dqx, x0, w, parts, k, s, sc, rows[3]);
+            HIP_TRY(hipStreamSynchronize(s));
+            free_complex(ck);
+            ck = nullptr;
+        }
+        res = new ac_complex();
+        for (double &x : res->stage_ms) x = -1.0;
+        HIP_TRY(hipGetDevice(&res->device));
+        res->device_result = false;
+        // vertices in input order
+        std::vector<int32_t> &v0 = res->h_simp[0];
+        std::vector<double> &z0 = res->h_size[0];
+        for (int i = 0; i < n; i++)
+            if (vsize[i] == vsize[i]) {
+                v0.push_back(i);
+                z0.push_back(vsize[i]);
+            }
+        res->count[0] = (int64_t)v0.size();
+        v0.push_back(0);
+        z0.push_back(0.0);
+        merge_host<2>(rows[1], n, res->h_simp[1], res->h_size[1]);
+        merge_host<3>(rows[2], n, res->h_simp[2], res->h_size[2]);
+        merge_host<4>(rows[3], n, res->h_simp[3], res->h_size[3]);
+        for (int d = 1; d <= 3; d++) res->count[d] = (int64_t)res->h_size[d].size() - 1;
+        for (int d = 0; d < 4; d++) {
+            res->host_ready[d] = true;
+            res->cand[d] = -1;
+            res->mol_rows[d] = {0, res->count[d]};
+        }
+        res->n = n;
+        res->n_mol = 1;
+        res->alpha_q = aq;
+        res->fallbacks = fallbacks;
+        res->work[0] = res->work[1] = -1;
+        HIP_TRY(hipHostFree(pin));
+        pin = nullptr;
+    } catch (const HipError &e) {
+        (void)hipStreamSynchronize(s);
+        free_complex(ck);
+        free_complex(res);
+        if (pin) (void)hipHostFree(pin);
+        return set_error(e.st, e.msg);
+    } catch (const std::bad_alloc &) {
+        (void)hipStreamSynchronize(s);
+        free_complex(ck);
+        free_complex(res);
+        if (pin) (void)hipHostFree(pin);
+        return set_error(AC_E_NOMEM, "host allocation failed");
     }
     *out = res;
     g_last_error.clear();
@@ -1281,12 +1610,15 @@ static Options parse(const ac_options *opt) {
     if (opt->force_exact != 0 && opt->force_exact != 1) throw HipError{AC_E_INVALID, "ac_options.force_exact must be 0 or 1"};
     if (opt->vertex_shortcut != 0 && opt->vertex_shortcut != 1)
         throw HipError{AC_E_INVALID, "ac_options.vertex_shortcut must be 0 or 1"};
-    if (opt->profile < 0 || opt->profile > ST_COUNT + 1)
-        throw HipError{AC_E_INVALID, "ac_options.profile must be 0, 1 or 2 + a stage index"};
+    if (opt->profile < 0 || opt->profile > PROFILE_SPLIT)
+        throw HipError{AC_E_INVALID, "ac_options.profile must be 0, 1, 2 + a stage index or 2 + the stage count"};
+    if (opt->cell_order != ORDER_ROW && opt->cell_order != ORDER_MORTON)
+        throw HipError{AC_E_INVALID, "ac_options.cell_order must be 0 (row-major) or 1 (Morton)"};
     o.cell_mA = opt->cell_mA;
     o.force_exact = opt->force_exact;
     o.vertex_shortcut = opt->vertex_shortcut;
     o.profile = opt->profile;
+    o.cell_order = opt->cell_order;
     return o;
 }
 
@@ -1319,6 +1651,20 @@ ac_status ac_alpha_complex_partitioned(const double *d_xyz, const double *d_radi
         const Options o = parse(opt);
         if (!d_xyz || !d_radii) return set_error(AC_E_INVALID, "NULL input pointer");
         return run_partitioned(d_xyz, d_radii, n, alpha, parts, o, static_cast<hipStream_t>(stream), out);
+    } catch (const HipError &e) {
+        return set_error(e.st, e.msg);
+    } catch (...) {
+        return set_error(AC_E_DEVICE, "unexpected host exception");
+    }
+}
+
+ac_status ac_alpha_complex_partitioned_host(const double *xyz, const double *radii, int64_t n, double alpha,
+                                            int32_t parts, const ac_options *opt, ac_complex **out) {
+    if (!out) return set_error(AC_E_INVALID, "out is NULL");
+    *out = nullptr;
+    try {
+        const Options o = parse(opt);
+        return run_streamed(xyz, radii, n, alpha, parts, o, out);
     } catch (const HipError &e) {
         return set_error(e.st, e.msg);
     } catch (...) {

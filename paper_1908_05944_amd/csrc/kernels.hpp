@@ -21,6 +21,7 @@
 #include "common.hpp"
 #include "predicates.hpp"
 #include "radix.hpp"
+#include "emit.hpp"
 
 namespace acx {
 
@@ -29,10 +30,16 @@ struct Stats {
     int wmax, flags;  // flags: 1 invalid value, 2 out of range
 };
 
-// Uniform grid (Sec. 4.2), cells numbered in row-major order (x fastest), so
-// the cells of one grid row are contiguous in the sorted order. A batch of
-// molecules has one grid per molecule; their cells are numbered one after
-// the other in a single table, so no ball ever sees another molecule's balls.
+// Uniform grid (Sec. 4.2). Cells are numbered in row-major order (x fastest;
+// the cells of one grid row are then contiguous in the sorted order), or
+// along a Morton (Z-order) curve, the space-filling alternative Sec. 4.2
+// names: the bits of the three cell coordinates interleaved, over a cube of
+// 2^L cells a side. A batch of molecules has one grid per molecule; their
+// cells are numbered one after the other in a single table, so no ball ever
+// sees another molecule's balls.
+enum { ORDER_ROW = 0, ORDER_MORTON = 1 };
+constexpr int MORTON_MAX_BITS = 10;  // cell coordinates below 1024: 30-bit codes
+
 struct Grid {
     int ox, oy, oz;   // low corner (mA)
     int s;            // cell side (mA)
@@ -40,7 +47,18 @@ struct Grid {
     int reach;        // cells to scan on each side for neighbours
     long long base;   // first cell of this grid in the shared cell table
     int a0, a1;       // the molecule's balls: [a0, a1) in input and in sorted order
+    int order;        // ORDER_ROW or ORDER_MORTON
 };
+
+// v (< 2^10) with two zero bits after each of its bits
+__device__ __forceinline__ unsigned spread3(unsigned v) {
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
 
 // Molecule of ball i (input or sorted index): the last grid with a0 <= i.
 __device__ __forceinline__ int mol_of(const Grid *__restrict__ grids, int n_mol, int i) {
@@ -175,6 +193,8 @@ __global__ void __launch_bounds__(BLOCK) k_prune_init(long long T, long long E, 
 // Binning (Sec. 4.2): cell key per ball, a stable radix sort by key (inside a
 // cell the balls keep input order), then the dense cell table.
 __device__ __forceinline__ long long cell_id(const Grid &g, int cx, int cy, int cz) {
+    if (g.order == ORDER_MORTON)
+        return (long long)(spread3((unsigned)cx) | (spread3((unsigned)cy) << 1) | (spread3((unsigned)cz) << 2));
     return ((long long)cz * g.ny + cy) * g.nx + cx;
 }
 
@@ -262,7 +282,7 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
                                                        const int *__restrict__ nbr_start, const int *__restrict__ up_start,
                                                        int *__restrict__ nbr, int *__restrict__ up,
                                                        int *__restrict__ edge_i, unsigned char *__restrict__ vgab,
-                                                       Counters *cnt) {
+                                                       long long *__restrict__ vert_min, Counters *cnt) {
     static_assert(SLOT <= 32, "one mask bit per slot entry");
     constexpr int NB_SLAB = BLOCK * SLOT;
     constexpr bool ONE = MODE == NB_ONEPASS;
@@ -317,24 +337,30 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
                     const int ylo = g.oy + y * g.s, yhi = ylo + g.s - 1;
                     const int dym = a.y < ylo ? ylo - a.y : (a.y > yhi ? a.y - yhi : 0);
                     if (dym > reach1 || rz - dym * dym < 0) continue;
+                    // the row's balls: one range (row-major), or one per cell
+                    // (Morton; the row is sorted after the scan)
+                    const bool morton = g.order == ORDER_MORTON;
                     const long long rb = g.base + ((long long)z * g.ny + y) * g.nx;
-                    const int s = cell_start[rb + x0], e = cell_start[rb + x1 + 1];
-                    for (int j = s; j < e; j++) {
-                        const int4 bb = atom[j];
-                        // one combined test (a branch per condition costs more
-                        // exec-mask work than the arithmetic it would skip);
-                        // offsets clamped to reach1 + 1: d2 then fits int32, and
-                        // a clamped offset alone gives d2 > (2 ceil s_g)^2 >= lim
-                        const int dx = min(max(bb.x - a.x, -reach1 - 1), reach1 + 1);
-                        const int dy = min(max(bb.y - a.y, -reach1 - 1), reach1 + 1);
-                        const int dz = min(max(bb.z - a.z, -reach1 - 1), reach1 + 1);
-                        const int d2 = dx * dx + dy * dy + dz * dz;
-                        const int rb2 = bb.w + (int)pp.aq;
-                        const int L = d2 - ra - rb2;
-                        // grown balls meet: d <= rho_a + rho_b; equal centres are reported by k_dup_check
-                        const bool meet = (j != i) & (d2 <= lim) & (d2 != 0) & (rb2 >= 0) &
-                                          ((L <= 0) | ((i64)L * L <= 4 * (i64)ra * rb2));
-                        if (meet) on_meet(j, bb);
+                    for (int xc = x0; xc <= (morton ? x1 : x0); xc++) {
+                        const long long c0 = morton ? g.base + cell_id(g, xc, y, z) : rb + x0;
+                        const int s = cell_start[c0], e = cell_start[morton ? c0 + 1 : rb + x1 + 1];
+                        for (int j = s; j < e; j++) {
+                            const int4 bb = atom[j];
+                            // one combined test (a branch per condition costs more
+                            // exec-mask work than the arithmetic it would skip);
+                            // offsets clamped to reach1 + 1: d2 then fits int32, and
+                            // a clamped offset alone gives d2 > (2 ceil s_g)^2 >= lim
+                            const int dx = min(max(bb.x - a.x, -reach1 - 1), reach1 + 1);
+                            const int dy = min(max(bb.y - a.y, -reach1 - 1), reach1 + 1);
+                            const int dz = min(max(bb.z - a.z, -reach1 - 1), reach1 + 1);
+                            const int d2 = dx * dx + dy * dy + dz * dz;
+                            const int rb2 = bb.w + (int)pp.aq;
+                            const int L = d2 - ra - rb2;
+                            // grown balls meet: d <= rho_a + rho_b; equal centres are reported by k_dup_check
+                            const bool meet = (j != i) & (d2 <= lim) & (d2 != 0) & (rb2 >= 0) &
+                                              ((L <= 0) | ((i64)L * L <= 4 * (i64)ra * rb2));
+                            if (meet) on_meet(j, bb);
+                        }
                     }
                 }
             }
@@ -359,6 +385,16 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
             cn++;
         });
         const int kn = min(cn, capn);
+        if (g.order == ORDER_MORTON) {
+            // rows must ascend in sorted order (upper rows are merged and
+            // searched); a Morton scan visits the cells of a row out of order
+            for (int a = 1; a < kn; a++) {
+                const int v = rn[a * RS];
+                int b = a;
+                for (; b > 0 && rn[(b - 1) * RS] > v; b--) rn[b * RS] = rn[(b - 1) * RS];
+                rn[b * RS] = v;
+            }
+        }
         for (int k = 0; k < kn; k++) {
             const int j = rn[k * RS];
             tests(j, atom[j], k);
@@ -373,7 +409,12 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
             });
         }
     }
-    if (valid) vgab[i] = (unsigned char)(ra >= 0 && gab);
+    if (valid) {
+        vgab[i] = (unsigned char)(ra >= 0 && gab);
+        // start of the least Size of a kept incident edge (only read for a
+        // ball that fails AC2 at its own centre)
+        if (ONE && !(ra >= 0 && gab)) vert_min[i] = ORDERED_POS_INF;
+    }
     if (ONE) {
         if (valid) {
             deg_n[i] = cn;
@@ -516,13 +557,50 @@ constexpr int TRI_SLOT = 8;
 constexpr int AC2_GROUP = 4;  // neighbours loaded together in the edge AC2 loop
 constexpr int TRI_SLAB = 1024;
 
-template <int MODE>
+// AC2 of candidate edge e = (i, j) at its own ortho-centre (Step 4): every
+// violator meets the ortho-centre, so it is in i's neighbour row. Writes
+// egab[e], and starts edge_min[e] (the least Size of a kept coface) for an
+// edge that fails. Every neighbour is tested (no early exit: most edges pass,
+// and the loop stays convergent); only filter-undecided ones branch.
+// Neighbours go in groups of AC2_GROUP whose loads are all issued before the
+// first test, so a wave has several in flight.
+__device__ __forceinline__ void edge_ac2(const int4 *__restrict__ atom, const int *__restrict__ perm,
+                                         const int *__restrict__ nbr_start, const int *__restrict__ nbr_cnt,
+                                         const int *__restrict__ nbr, const PredParams &pp, int e, int i, int j,
+                                         int4 vi, int4 vj, unsigned char *__restrict__ egab,
+                                         long long *__restrict__ edge_min) {
+    const int ns = nbr_start[i], ne = ns + nbr_cnt[i];
+    const Edge ed = edge_setup(vi, vj);
+    bool viol = false;
+    for (int p0 = ns; p0 < ne; p0 += AC2_GROUP) {
+        int qs[AC2_GROUP];
+        int4 aqs[AC2_GROUP];
+#pragma unroll
+        for (int u = 0; u < AC2_GROUP; u++) qs[u] = p0 + u < ne ? nbr[p0 + u] : j;
+#pragma unroll
+        for (int u = 0; u < AC2_GROUP; u++) aqs[u] = atom[qs[u]];
+#pragma unroll
+        for (int u = 0; u < AC2_GROUP; u++) {
+            const int q = qs[u];  // padding entries repeat j, which is never tested
+            int sg = pp.force_exact ? 0 : edge_violation_filter(ed, aqs[u]);
+            if (sg == 0 && q != j) sg = edge_violation_sign(ed, i, j, aqs[u], q, perm, 1);
+            viol |= (sg < 0) & (q != j);
+        }
+    }
+    egab[e] = (unsigned char)!viol;
+    if (viol) edge_min[e] = ORDERED_POS_INF;
+}
+
+// AC2: whether the one-pass kernel also decides the edges' AC2 (the build
+// does; a profiled build run for a per-step breakdown times k_edge_ac2 apart).
+template <int MODE, bool AC2 = true>
 __global__ void __launch_bounds__(BLOCK) k_triangles(const int4 *__restrict__ atom, const int *__restrict__ perm,
                                                       const int *__restrict__ nbr_start, const int *__restrict__ nbr_cnt,
                                                       const int *__restrict__ nbr,
                                                       const int *__restrict__ up_start, const int *__restrict__ up,
                                                       const int *__restrict__ edge_i, int E, PredParams pp,
                                                       int *__restrict__ tri_cnt, unsigned char *__restrict__ egab,
+                                                      long long *__restrict__ edge_min,
                                                       int *__restrict__ slab, int *__restrict__ block_tot,
                                                       const int *__restrict__ tri_start, int *__restrict__ tri_k,
                                                       int *__restrict__ tri_e, Counters *cnt) {
@@ -535,31 +613,7 @@ __global__ void __launch_bounds__(BLOCK) k_triangles(const int4 *__restrict__ at
     if (e < E) {
         const int i = edge_i[e], j = up[e];
         const int4 vi = atom[i], vj = atom[j];
-        if (ONE) {
-            const int ns = nbr_start[i], ne = ns + nbr_cnt[i];
-            const Edge ed = edge_setup(vi, vj);
-            // every neighbour is tested (no early exit: most edges pass, and
-            // the loop stays convergent); only filter-undecided ones branch.
-            // Neighbours go in groups of AC2_GROUP whose loads are all issued
-            // before the first test, so a wave has several in flight.
-            bool viol = false;
-            for (int p0 = ns; p0 < ne; p0 += AC2_GROUP) {
-                int qs[AC2_GROUP];
-                int4 aqs[AC2_GROUP];
-#pragma unroll
-                for (int u = 0; u < AC2_GROUP; u++) qs[u] = p0 + u < ne ? nbr[p0 + u] : j;
-#pragma unroll
-                for (int u = 0; u < AC2_GROUP; u++) aqs[u] = atom[qs[u]];
-#pragma unroll
-                for (int u = 0; u < AC2_GROUP; u++) {
-                    const int q = qs[u];  // padding entries repeat j, which is never tested
-                    int sg = pp.force_exact ? 0 : edge_violation_filter(ed, aqs[u]);
-                    if (sg == 0 && q != j) sg = edge_violation_sign(ed, i, j, aqs[u], q, perm, 1);
-                    viol |= (sg < 0) & (q != j);
-                }
-            }
-            egab[e] = (unsigned char)!viol;
-        }
+        if (ONE && AC2) edge_ac2(atom, perm, nbr_start, nbr_cnt, nbr, pp, e, i, j, vi, vj, egab, edge_min);
         int pa = e + 1;
         const int ea = up_start[i + 1];
         int pb = up_start[j];
@@ -678,7 +732,39 @@ enum { TET_ONEPASS = 0, TET_FILL = 1 };
 constexpr int TET_SLOT = 4;
 constexpr int TET_SLAB = 256;
 
-template <int MODE>
+// AC2 of candidate triangle t = (i, j, k) at its own ortho-centre (Step 3;
+// violators are in i's neighbour row) and its OrthoSize. Writes tgab[t],
+// tsize[t], and starts tri_min[t] for a triangle that fails. Every neighbour
+// is tested (no early exit, convergent loop); only filter-undecided ones take
+// the exact branch.
+__device__ __forceinline__ void tri_ac2(const int4 *__restrict__ atom, const int *__restrict__ perm,
+                                        const int *__restrict__ nbr_start, const int *__restrict__ nbr_cnt,
+                                        const int *__restrict__ nbr, const PredParams &pp, int t, int i, int j, int k,
+                                        int4 vi, int4 vj, int4 vk, unsigned char *__restrict__ tgab,
+                                        double *__restrict__ tsize, long long *__restrict__ tri_min, Counters *cnt) {
+    const Tri tr = tri_setup(vi, vj, vk, pp);
+    bool viol = false;
+    const int ns = nbr_start[i], ne = ns + nbr_cnt[i];
+    for (int p = ns; p < ne; p++) {
+        const int q = nbr[p];
+        const int4 aq = atom[q];
+        const bool other = (q != j) & (q != k);
+        int sg = pp.force_exact ? 0 : tri_violation_filter(tr, aq);
+        if (sg == 0 && other) {
+            if (!pp.force_exact) note_fallback(cnt);
+            sg = tri_violation_exact(tr, i, j, k, aq, q, perm);
+        }
+        viol |= (sg < 0) & other;
+    }
+    tgab[t] = (unsigned char)!viol;
+    if (viol) tri_min[t] = ORDERED_POS_INF;
+    tsize[t] = tri_size_canon(vi, vj, vk, pp);
+}
+
+// AC2: whether the one-pass kernel also decides the triangles' AC2 and
+// OrthoSize (the build does; a profiled build for a per-step breakdown times
+// k_tri_ac2 apart).
+template <int MODE, bool AC2 = true>
 __global__ void __launch_bounds__(BLOCK, 4) k_tet_candidates(const int4 *__restrict__ atom, const int *__restrict__ perm,
                                                            const int *__restrict__ nbr_start,
                                                            const int *__restrict__ nbr_cnt, const int *__restrict__ nbr,
@@ -686,6 +772,7 @@ __global__ void __launch_bounds__(BLOCK, 4) k_tet_candidates(const int4 *__restr
                                                            const int *__restrict__ edge_i, const int *__restrict__ tri_k,
                                                            const int *__restrict__ tri_e, int T, PredParams pp,
                                                            unsigned char *__restrict__ tgab, double *__restrict__ tsize,
+                                                           long long *__restrict__ tri_min,
                                                            int *__restrict__ tet_cnt, int *__restrict__ slab,
                                                            int *__restrict__ block_tot,
                                                            const int *__restrict__ tet_start, int *__restrict__ tet_t,
@@ -700,26 +787,7 @@ __global__ void __launch_bounds__(BLOCK, 4) k_tet_candidates(const int4 *__restr
         const int e = tri_e[t];
         const int i = edge_i[e], j = up[e], k = tri_k[t];
         const int4 vi = atom[i], vj = atom[j], vk = atom[k];
-        if (ONE) {
-            const Tri tr = tri_setup(vi, vj, vk, pp);
-            // every neighbour is tested (no early exit, convergent loop);
-            // only filter-undecided ones take the exact branch
-            bool viol = false;
-            const int ns = nbr_start[i], ne = ns + nbr_cnt[i];
-            for (int p = ns; p < ne; p++) {
-                const int q = nbr[p];
-                const int4 aq = atom[q];
-                const bool other = (q != j) & (q != k);
-                int sg = pp.force_exact ? 0 : tri_violation_filter(tr, aq);
-                if (sg == 0 && other) {
-                    if (!pp.force_exact) note_fallback(cnt);
-                    sg = tri_violation_exact(tr, i, j, k, aq, q, perm);
-                }
-                viol |= (sg < 0) & other;
-            }
-            tgab[t] = (unsigned char)!viol;
-            tsize[t] = tri_size_canon(vi, vj, vk, pp);
-        }
+        if (ONE && AC2) tri_ac2(atom, perm, nbr_start, nbr_cnt, nbr, pp, t, i, j, k, vi, vj, vk, tgab, tsize, tri_min, cnt);
         int pa = e + 1;
         const int ea = up_start[i + 1];
         int pb = up_start[j];
@@ -788,18 +856,48 @@ __global__ void __launch_bounds__(BLOCK) k_tet_compact(const int *__restrict__ t
     for (int k = threadIdx.x; k < total; k += BLOCK) tet_l[g0 + k] = src[k];
 }
 
+// The AC2 tests of candidate edges and triangles as kernels of their own
+// (same results as inside the one-pass kernels), for a profiled per-step
+// breakdown.
+__global__ void __launch_bounds__(BLOCK) k_edge_ac2(const int4 *__restrict__ atom, const int *__restrict__ perm,
+                                                     const int *__restrict__ nbr_start, const int *__restrict__ nbr_cnt,
+                                                     const int *__restrict__ nbr, const int *__restrict__ up,
+                                                     const int *__restrict__ edge_i, int E, PredParams pp,
+                                                     unsigned char *__restrict__ egab, long long *__restrict__ edge_min) {
+    const int e = xcd_block() * BLOCK + threadIdx.x;
+    if (e >= E) return;
+    const int i = edge_i[e], j = up[e];
+    edge_ac2(atom, perm, nbr_start, nbr_cnt, nbr, pp, e, i, j, atom[i], atom[j], egab, edge_min);
+}
+
+__global__ void __launch_bounds__(BLOCK) k_tri_ac2(const int4 *__restrict__ atom, const int *__restrict__ perm,
+                                                    const int *__restrict__ nbr_start, const int *__restrict__ nbr_cnt,
+                                                    const int *__restrict__ nbr, const int *__restrict__ up,
+                                                    const int *__restrict__ edge_i, const int *__restrict__ tri_k,
+                                                    const int *__restrict__ tri_e, int T, PredParams pp,
+                                                    unsigned char *__restrict__ tgab, double *__restrict__ tsize,
+                                                    long long *__restrict__ tri_min, Counters *cnt) {
+    const int t = xcd_block() * BLOCK + threadIdx.x;
+    if (t >= T) return;
+    const int e = tri_e[t];
+    const int i = edge_i[e], j = up[e], k = tri_k[t];
+    tri_ac2(atom, perm, nbr_start, nbr_cnt, nbr, pp, t, i, j, k, atom[i], atom[j], atom[k], tgab, tsize, tri_min, cnt);
+}
+
 // A face that passes AC2 itself is in K with Size = OrthoSize whatever its
-// cofaces do, so only faces failing AC2 record the kept coface.
-__device__ __forceinline__ void mark_face(const unsigned char *gab, int *att, long long *mins, int f, long long key,
+// cofaces do, so only faces failing AC2 record the kept coface: the least
+// Size of their kept cofaces (order-preserving integer; +inf while none), so
+// such a face is kept iff that minimum is finite.
+__device__ __forceinline__ void mark_face(const unsigned char *gab, long long *mins, int f, long long key,
                                           Counters *cnt) {
     if (f < 0) { atomicOr(&cnt->lookup, 1); return; }
     if (gab[f]) return;
-    atomicOr(&att[f], 1);
     atomicMin(&mins[f], key);
 }
 
 // Tetrahedra (Step 2): kept iff no ball is strictly closer in power to the
-// ortho-centre; a kept tetrahedron records itself on its facets (Step 3).
+// ortho-centre; a kept tetrahedron records itself on its facets (Step 3) and
+// gets its emit key and payload (input ids; not kept: key n).
 // SWEEP (candidates of several alpha values): qin holds AC2 alone, and the
 // facet ids go to tface for the per-alpha passes instead of being marked.
 template <bool SWEEP>
@@ -811,9 +909,10 @@ __global__ void __launch_bounds__(BLOCK) k_tet_ac2(const int4 *__restrict__ atom
                                                     const int *__restrict__ tri_k, const int *__restrict__ tri_e,
                                                     const int *__restrict__ tet_t, const int *__restrict__ tet_l, int Q,
                                                     PredParams pp, const unsigned char *__restrict__ tgab,
-                                                    int *__restrict__ tri_att, long long *__restrict__ tri_min,
+                                                    long long *__restrict__ tri_min,
                                                     unsigned char *__restrict__ qin, double *__restrict__ qsize,
-                                                    int4 *__restrict__ tface, Counters *cnt) {
+                                                    int4 *__restrict__ tface, int n, unsigned *__restrict__ qkey,
+                                                    typename EmitPay<4>::type *__restrict__ qpay, Counters *cnt) {
     const int c = xcd_block() * BLOCK + threadIdx.x;
     if (c >= Q) return;
     const int t = tet_t[c], l = tet_l[c];
@@ -827,8 +926,14 @@ __global__ void __launch_bounds__(BLOCK) k_tet_ac2(const int4 *__restrict__ atom
         if (q == j || q == k || q == l) continue;
         if (tet_violation_sign(te, i, j, k, l, atom[q], q, perm, pp, cnt) < 0) { keep = false; break; }
     }
-    qin[c] = (unsigned char)keep;
-    if (!keep) return;
+    if (SWEEP) qin[c] = (unsigned char)keep;
+    if (!keep) {
+        if (!SWEEP) {
+            int v[4] = {0, 0, 0, 0};
+            emit_pack<4>(false, v, 0.0, c, n, qkey[c], qpay[c]);
+        }
+        return;
+    }
     const double sz = tet_size_canon(atom[i], atom[j], atom[k], atom[l], pp);
     qsize[c] = sz;
     const int f1 = find_tri(up_start, up, tri_start, tri_k, i, j, l);
@@ -838,42 +943,48 @@ __global__ void __launch_bounds__(BLOCK) k_tet_ac2(const int4 *__restrict__ atom
         tface[c] = make_int4(t, f1, f2, f3);
         return;
     }
+    int v[4] = {perm[i], perm[j], perm[k], perm[l]};
+    emit_pack<4>(true, v, sz, c, n, qkey[c], qpay[c]);
     const long long key = ordered_from_double(sz);
-    mark_face(tgab, tri_att, tri_min, t, key, cnt);
-    mark_face(tgab, tri_att, tri_min, f1, key, cnt);
-    mark_face(tgab, tri_att, tri_min, f2, key, cnt);
-    mark_face(tgab, tri_att, tri_min, f3, key, cnt);
+    mark_face(tgab, tri_min, t, key, cnt);
+    mark_face(tgab, tri_min, f1, key, cnt);
+    mark_face(tgab, tri_min, f2, key, cnt);
+    mark_face(tgab, tri_min, f3, key, cnt);
 }
 
 // Triangles (Step 3): kept iff AC2 holds at the ortho-centre or a kept
 // tetrahedron has it as a facet; Size is then the OrthoSize or the least Size
-// of a kept tetrahedron. Kept triangles record themselves on their edges.
+// of a kept tetrahedron. Kept triangles record themselves on their edges;
+// every triangle gets its emit key and payload (not kept: key n).
 __global__ void __launch_bounds__(BLOCK) k_tri_final(const int *__restrict__ up_start, const int *__restrict__ up,
                                                       const int *__restrict__ edge_i, const int *__restrict__ tri_k,
                                                       const int *__restrict__ tri_e, int T,
                                                       const unsigned char *__restrict__ tgab,
-                                                      double *__restrict__ tsize, const int *__restrict__ tri_att,
+                                                      const double *__restrict__ tsize,
                                                       const long long *__restrict__ tri_min,
-                                                      unsigned char *__restrict__ tin,
-                                                      const unsigned char *__restrict__ egab, int *__restrict__ edge_att,
-                                                      long long *__restrict__ edge_min, Counters *cnt) {
+                                                      const unsigned char *__restrict__ egab,
+                                                      long long *__restrict__ edge_min, const int *__restrict__ perm,
+                                                      int n, unsigned *__restrict__ tkey,
+                                                      typename EmitPay<3>::type *__restrict__ tpay, Counters *cnt) {
     const int t = xcd_block() * BLOCK + threadIdx.x;
     if (t >= T) return;
     const bool gab = tgab[t];
-    const bool in = gab || tri_att[t];
-    tin[t] = (unsigned char)in;
-    if (!in) return;
-    double sz = tsize[t];
-    if (!gab) {
-        sz = double_from_ordered(tri_min[t]);
-        tsize[t] = sz;
+    const long long mn = gab ? ORDERED_POS_INF : tri_min[t];
+    const bool in = gab || mn != ORDERED_POS_INF;
+    int v[4] = {0, 0, 0, 0};
+    if (!in) {
+        emit_pack<3>(false, v, 0.0, t, n, tkey[t], tpay[t]);
+        return;
     }
+    const double sz = gab ? tsize[t] : double_from_ordered(mn);
     const int e = tri_e[t];
     const int i = edge_i[e], j = up[e], k = tri_k[t];
+    v[0] = perm[i]; v[1] = perm[j]; v[2] = perm[k];
+    emit_pack<3>(true, v, sz, t, n, tkey[t], tpay[t]);
     const long long key = ordered_from_double(sz);
-    mark_face(egab, edge_att, edge_min, e, key, cnt);
-    mark_face(egab, edge_att, edge_min, find_edge(up_start, up, i, k), key, cnt);
-    mark_face(egab, edge_att, edge_min, find_edge(up_start, up, j, k), key, cnt);
+    mark_face(egab, edge_min, e, key, cnt);
+    mark_face(egab, edge_min, find_edge(up_start, up, i, k), key, cnt);
+    mark_face(egab, edge_min, find_edge(up_start, up, j, k), key, cnt);
 }
 
 // Edge ids (i, k) and (j, k) of every candidate triangle (i, j, k), once per
@@ -888,68 +999,62 @@ __global__ void __launch_bounds__(BLOCK) k_tri_edges(const int *__restrict__ up_
     tedge[t] = make_int2(find_edge(up_start, up, i, k), find_edge(up_start, up, j, k));
 }
 
-// Edges (Step 4).
+// Edges (Step 4), with their emit keys and payloads (not kept: key n).
 __global__ void __launch_bounds__(BLOCK) k_edge_final(const int4 *__restrict__ atom, const int *__restrict__ up,
                                                        const int *__restrict__ edge_i, int E,
                                                        const unsigned char *__restrict__ egab,
-                                                       const int *__restrict__ edge_att,
                                                        const long long *__restrict__ edge_min,
-                                                       unsigned char *__restrict__ ein, double *__restrict__ esize,
                                                        const unsigned char *__restrict__ vgab,
-                                                       int *__restrict__ vert_att, long long *__restrict__ vert_min) {
+                                                       long long *__restrict__ vert_min, const int *__restrict__ perm,
+                                                       int n, unsigned *__restrict__ ekey,
+                                                       typename EmitPay<2>::type *__restrict__ epay) {
     const int e = xcd_block() * BLOCK + threadIdx.x;
     if (e >= E) return;
     const bool gab = egab[e];
-    const bool in = gab || edge_att[e];
-    ein[e] = (unsigned char)in;
-    if (!in) return;
+    const long long mn = gab ? ORDERED_POS_INF : edge_min[e];
+    const bool in = gab || mn != ORDERED_POS_INF;
+    int v[4] = {0, 0, 0, 0};
+    if (!in) {
+        emit_pack<2>(false, v, 0.0, e, n, ekey[e], epay[e]);
+        return;
+    }
     const int i = edge_i[e], j = up[e];
-    const double sz = gab ? edge_size_canon(atom[i], atom[j]) : double_from_ordered(edge_min[e]);
-    esize[e] = sz;
+    const double sz = gab ? edge_size_canon(atom[i], atom[j]) : double_from_ordered(mn);
+    v[0] = perm[i]; v[1] = perm[j];
+    emit_pack<2>(true, v, sz, e, n, ekey[e], epay[e]);
     const long long key = ordered_from_double(sz);
-    if (!vgab[i]) { atomicOr(&vert_att[i], 1); atomicMin(&vert_min[i], key); }
-    if (!vgab[j]) { atomicOr(&vert_att[j], 1); atomicMin(&vert_min[j], key); }
+    if (!vgab[i]) atomicMin(&vert_min[i], key);
+    if (!vgab[j]) atomicMin(&vert_min[j], key);
 }
 
 // Vertices (Step 5): a ball with -W <= alpha is kept iff no ball is strictly
 // closer in power to its own centre (decided in k_neighbours), or it ends a
 // kept edge. With `shortcut`, every such ball is kept with Size -W (the
-// paper's implementation shortcut). Results are scattered to input order.
+// paper's implementation shortcut). One float64 per ball goes to its input
+// position: the Size in mA^2, NaN when not kept.
 __global__ void __launch_bounds__(BLOCK) k_vert_final(const int4 *__restrict__ atom, const int *__restrict__ perm, int n,
                                                        PredParams pp, int shortcut,
                                                        const unsigned char *__restrict__ vgab,
-                                                       const int *__restrict__ vert_att,
                                                        const long long *__restrict__ vert_min,
-                                                       int *__restrict__ vin_in, double *__restrict__ vsize_in) {
+                                                       double *__restrict__ vsize_in) {
     const int v = xcd_block() * BLOCK + threadIdx.x;
     if (v >= n) return;
     const int w = atom[v].w;
-    bool in = false;
-    double sz = 0.0;
+    double sz = __longlong_as_double(0x7ff8000000000000LL);  // NaN: not kept
     if ((i64)w + pp.aq >= 0) {
         const bool gab = shortcut || vgab[v];
-        in = gab || vert_att[v];
-        sz = gab ? -(double)w : double_from_ordered(vert_min[v]);
+        if (gab) {
+            sz = -(double)w;
+        } else {
+            const long long mn = vert_min[v];
+            if (mn != ORDERED_POS_INF) sz = double_from_ordered(mn);
+        }
     }
-    const int u = perm[v];
-    vin_in[u] = in ? 1 : 0;
-    vsize_in[u] = sz;
-}
-
-__global__ void __launch_bounds__(BLOCK) k_vert_emit(const int *__restrict__ vin_in, const int *__restrict__ vpos,
-                                                      const double *__restrict__ vsize_in, int n, int *__restrict__ out,
-                                                      double *__restrict__ out_size) {
-    const int u = blockIdx.x * BLOCK + threadIdx.x;
-    if (u >= n || !vin_in[u]) return;
-    const int p = vpos[u];
-    out[p] = u;
-    out_size[p] = vsize_in[u] / 1.0e6;  // mA^2 -> A^2
+    vsize_in[perm[v]] = sz;
 }
 
 // ---------------------------------------------------------------------------
-// Emit: rows of sorted-order indices -> rows of input ids sorted ascending,
-// rows in lexicographic order. Bucket by the first id (counting sort), then
-// insertion-sort each (short) bucket.
+// Output order of a sweep.
 // Row of candidate c (sorted-order indices) for d = 1, 2, 3.
 template <int K>
 __device__ __forceinline__ void candidate_row(int c, const int *__restrict__ up, const int *__restrict__ edge_i,
@@ -969,70 +1074,12 @@ __device__ __forceinline__ void candidate_row(int c, const int *__restrict__ up,
     }
 }
 
-// Sort payload of a row: the ids after the least, then the Size (edges,
-// triangles: read here in candidate order, so the final write needs no
-// gather) or the candidate index (tetrahedra, which are few).
-template <int K> struct EmitPay;
-template <> struct EmitPay<2> { typedef uint3 type; };  // v1, Size bits
-template <> struct EmitPay<3> { typedef uint4 type; };  // v1, v2, Size bits
-template <> struct EmitPay<4> { typedef uint4 type; };  // v1, v2, v3, candidate
-
 // Payload of the output-order sort of a sweep (every candidate, no Size):
 // the ids after the least, then the candidate index.
 template <int K> struct OrderPay;
 template <> struct OrderPay<2> { typedef uint2 type; };
 template <> struct OrderPay<3> { typedef uint3 type; };
 template <> struct OrderPay<4> { typedef uint4 type; };
-
-__device__ __forceinline__ uint2 bits_of(double x) {
-    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
-    return make_uint2((unsigned)b, (unsigned)(b >> 32));
-}
-__device__ __forceinline__ double double_of(unsigned lo, unsigned hi) {
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
-// Every candidate c -> key[c] = least input id of its row and pay[c] = (the
-// other ids, Size or c), or key[c] = n (after every id) when c is not kept,
-// so one sort by key puts the kept rows first, grouped by least id, with no
-// compaction pass.
-template <int K>
-__global__ void __launch_bounds__(BLOCK) k_emit_keys(const unsigned char *__restrict__ in, int M,
-                                                      const int *__restrict__ up, const int *__restrict__ edge_i,
-                                                      const int *__restrict__ tri_k, const int *__restrict__ tri_e,
-                                                      const int *__restrict__ tet_t, const int *__restrict__ tet_l,
-                                                      const int *__restrict__ perm, const double *__restrict__ size,
-                                                      int n, unsigned *__restrict__ key,
-                                                      typename EmitPay<K>::type *__restrict__ pay) {
-    const int c = xcd_block() * BLOCK + threadIdx.x;
-    if (c >= M) return;
-    typename EmitPay<K>::type q{};
-    if (!in[c]) {
-        key[c] = (unsigned)n;
-        pay[c] = q;
-        return;
-    }
-    int v[4];
-    candidate_row<K>(c, up, edge_i, tri_k, tri_e, tet_t, tet_l, v);
-#pragma unroll
-    for (int u = 0; u < K; u++) v[u] = perm[v[u]];
-#pragma unroll
-    for (int a = 1; a < K; a++)
-#pragma unroll
-        for (int b = a; b > 0; b--)
-            if (v[b - 1] > v[b]) { const int t = v[b]; v[b] = v[b - 1]; v[b - 1] = t; }
-    key[c] = (unsigned)v[0];
-    if constexpr (K == 2) {
-        const uint2 z = bits_of(size[c]);
-        q = make_uint3((unsigned)v[1], z.x, z.y);
-    } else if constexpr (K == 3) {
-        const uint2 z = bits_of(size[c]);
-        q = make_uint4((unsigned)v[1], (unsigned)v[2], z.x, z.y);
-    } else {
-        q = make_uint4((unsigned)v[1], (unsigned)v[2], (unsigned)v[3], (unsigned)c);
-    }
-    pay[c] = q;
-}
 
 // Output-order keys of a sweep: every candidate c, kept at some alpha or
 // not, keyed by the least input id of its row, payload (other ids, c).
@@ -1059,93 +1106,14 @@ __global__ void __launch_bounds__(BLOCK) k_order_keys(int M, const int *__restri
     else pay[c] = make_uint4((unsigned)v[1], (unsigned)v[2], (unsigned)v[3], (unsigned)c);
 }
 
-// Number of kept rows after the sort: the first position whose key is n.
-template <int K>
-__device__ __forceinline__ void pay_ids(const typename EmitPay<K>::type &q, unsigned (&r)[3]) {
-    if constexpr (K == 2) { r[0] = q.x; r[1] = 0; r[2] = 0; }
-    else if constexpr (K == 3) { r[0] = q.x; r[1] = q.y; r[2] = 0; }
-    else { r[0] = q.x; r[1] = q.y; r[2] = q.z; }
-}
-
-template <int K>
-__device__ __forceinline__ double pay_size(const typename EmitPay<K>::type &q, const double *__restrict__ size) {
-    if constexpr (K == 2) return double_of(q.y, q.z);
-    else if constexpr (K == 3) return double_of(q.z, q.w);
-    else return size[q.w];
-}
-
-// After the sort by least id, each row finds its bucket (equal keys are
-// adjacent; buckets are short) and its rank in the bucket by the remaining
-// ids, and writes itself to the final place. A block stages its 256 rows and
-// RANK_HALO rows on each side in LDS, so the bucket walks are LDS reads; a
-// bucket reaching past the halo is finished from global memory.
+// After the sort of a sweep's candidates by least id, each row finds its
+// bucket (equal keys are adjacent; buckets are short) and its rank in the
+// bucket by the remaining ids, and writes the sorted row to rows_s and each
+// candidate's place to spos. A block stages its 256 rows and RANK_HALO rows
+// on each side in LDS, so the bucket walks are LDS reads; a bucket reaching
+// past the halo is finished from global memory.
 constexpr int RANK_HALO = 64;
 
-template <int K>
-__global__ void __launch_bounds__(BLOCK) k_emit_rank(const unsigned *__restrict__ key,
-                                                      const typename EmitPay<K>::type *__restrict__ pay, int m, int n,
-                                                      const double *__restrict__ size_in, int *__restrict__ out,
-                                                      double *__restrict__ out_size, int *__restrict__ m_out) {
-    typedef typename EmitPay<K>::type P;
-    constexpr int SPAN = BLOCK + 2 * RANK_HALO;
-    __shared__ unsigned sk[SPAN];
-    __shared__ P sp[SPAN];
-    const int b0 = blockIdx.x * BLOCK;
-    const int lo = b0 - RANK_HALO;  // global position of sk[0]
-    for (int t = threadIdx.x; t < SPAN; t += BLOCK) {
-        const int g = lo + t;
-        if (g >= 0 && g < m) {
-            sk[t] = key[g];
-            sp[t] = pay[g];
-        } else {
-            sk[t] = 0xffffffffu;  // matches no id and not the sentinel n < 2^26
-        }
-    }
-    __syncthreads();
-    const int p = b0 + threadIdx.x;
-    if (p >= m) return;
-    const int lp = p - lo;
-    const unsigned u0 = sk[lp];
-    // the kept count: where the kept keys (< n) end; lp + 1 < SPAN
-    const bool kept = u0 < (unsigned)n;
-    if (kept ? (p + 1 == m || sk[lp + 1] >= (unsigned)n) : p == 0) *m_out = kept ? p + 1 : 0;
-    if (!kept) return;  // not kept (sorted after the kept rows)
-    const P me = sp[lp];
-    unsigned r[3];
-    pay_ids<K>(me, r);
-    auto before = [&](const P &x) -> int {
-        unsigned o[3];
-        pay_ids<K>(x, o);
-        return o[0] != r[0] ? o[0] < r[0] : (o[1] != r[1] ? o[1] < r[1] : o[2] < r[2]);
-    };
-    // the bucket inside the staged span (positions outside [0, m) hold a key
-    // no id has); a bucket reaching an end of the span is walked in global
-    // memory instead
-    int ls = lp;
-    while (ls > 0 && sk[ls - 1] == u0) ls--;
-    int le = lp + 1;
-    while (le < SPAN && sk[le] == u0) le++;
-    int s, rank = 0;
-    if ((ls > 0 || lo + ls == 0) && (le < SPAN || lo + le == m)) {
-        s = lo + ls;
-        for (int w = ls; w < le; w++) rank += (w != lp) && before(sp[w]);
-    } else {
-        s = p;
-        while (s > 0 && key[s - 1] == u0) s--;
-        int e = p + 1;
-        while (e < m && key[e] == u0) e++;
-        for (int w = s; w < e; w++) rank += (w != p) && before(pay[w]);
-    }
-    const long long q = (long long)(s + rank) * K;
-    out[q] = (int)u0;
-#pragma unroll
-    for (int u = 1; u < K; u++) out[q + u] = (int)r[u - 1];
-    out_size[s + rank] = pay_size<K>(me, size_in) / 1.0e6;  // mA^2 -> A^2
-}
-
-
-// Output order of a sweep: as k_emit_rank over every candidate, writing the
-// sorted rows to rows_s and each candidate's place to spos.
 template <int K>
 __global__ void __launch_bounds__(BLOCK) k_order_rank(const unsigned *__restrict__ key,
                                                        const typename OrderPay<K>::type *__restrict__ pay, int m,

@@ -65,20 +65,6 @@ __global__ void __launch_bounds__(BLOCK) k_own_flags(const int *__restrict__ row
     flag[s] = slab_of(best_x, x0, w, parts) == k;
 }
 
-// The owned rows, with input ids, packed in their order (pos: exclusive scan of flag).
-template <int K>
-__global__ void __launch_bounds__(BLOCK) k_own_write(const int *__restrict__ rows, const double *__restrict__ size, int m,
-                                                      const int *__restrict__ flag, const int *__restrict__ pos,
-                                                      const int *__restrict__ sel, int *__restrict__ out,
-                                                      double *__restrict__ out_size) {
-    const int s = blockIdx.x * BLOCK + threadIdx.x;
-    if (s >= m || !flag[s]) return;
-    const int p = pos[s];
-#pragma unroll
-    for (int u = 0; u < K; u++) out[(long long)p * K + u] = sel[rows[(long long)s * K + u]];
-    out_size[p] = size[s];
-}
-
 // Owned vertices of a slab's build, by input id (a vertex owns itself).
 __global__ void __launch_bounds__(BLOCK) k_own_vertices(const int *__restrict__ rows, const double *__restrict__ size,
                                                          int m, const int *__restrict__ sel, const int4 *__restrict__ q,
@@ -102,25 +88,62 @@ __global__ void __launch_bounds__(BLOCK) k_vertex_rows(const int *__restrict__ k
     out_size[pos[u]] = vsize[u];
 }
 
-// Merge of the slabs' rows: key = least id, payload = (other ids, row index),
-// for the sort by k_order_rank (rows_s, spos); Sizes follow by spos.
+// The owned rows of a slab in emit form, packed in their order (pos:
+// exclusive scan of flag): key = least input id (a row's ids ascend in the
+// slab's ids, and sel keeps their order), payload = the other input ids and
+// the Size bits (K = 2, 3), or the row's place idx_base + pos among the rows
+// of all slabs, whose Size goes to out_size[pos] (K = 4). Sizes stay in A^2.
+// k_emit_bucket then merges the rows of all slabs into output order.
 template <int K>
-__global__ void __launch_bounds__(BLOCK) k_rows_keys(const int *__restrict__ rows, int m, unsigned *__restrict__ key,
-                                                      typename OrderPay<K>::type *__restrict__ pay) {
+__global__ void __launch_bounds__(BLOCK) k_own_emit(const int *__restrict__ rows, const double *__restrict__ size, int m,
+                                                     const int *__restrict__ flag, const int *__restrict__ pos,
+                                                     const int *__restrict__ sel, int idx_base,
+                                                     unsigned *__restrict__ key,
+                                                     typename EmitPay<K>::type *__restrict__ pay,
+                                                     double *__restrict__ out_size) {
     const int s = blockIdx.x * BLOCK + threadIdx.x;
-    if (s >= m) return;
-    const int *r = rows + (long long)s * K;
-    key[s] = (unsigned)r[0];
-    if constexpr (K == 2) pay[s] = make_uint2((unsigned)r[1], (unsigned)s);
-    else if constexpr (K == 3) pay[s] = make_uint3((unsigned)r[1], (unsigned)r[2], (unsigned)s);
-    else pay[s] = make_uint4((unsigned)r[1], (unsigned)r[2], (unsigned)r[3], (unsigned)s);
+    if (s >= m || !flag[s]) return;
+    const int p = pos[s];
+    int v[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int u = 0; u < K; u++) v[u] = sel[rows[(long long)s * K + u]];
+    emit_pack<K>(true, v, size[s], idx_base + p, 0, key[p], pay[p]);
+    if (K == 4) out_size[p] = size[s];
 }
 
-__global__ void __launch_bounds__(BLOCK) k_place_sizes(const int *__restrict__ spos, const double *__restrict__ size,
-                                                        int m, double *__restrict__ out_size) {
+// Host-streamed slabs: the device holds only the slab (core and halo), so the
+// owner test reads the slab's own quantised x (qx, slab ids) and input ids
+// (sel, slab ids) instead of arrays over all balls.
+template <int K>
+__global__ void __launch_bounds__(BLOCK) k_own_flags_local(const int *__restrict__ rows, int m,
+                                                            const int *__restrict__ sel, const int *__restrict__ qx,
+                                                            int x0, int w, int parts, int k, int *__restrict__ flag) {
     const int s = blockIdx.x * BLOCK + threadIdx.x;
     if (s >= m) return;
-    out_size[spos[s]] = size[s];
+    int best_x = INT_MAX, best_id = INT_MAX;
+#pragma unroll
+    for (int u = 0; u < K; u++) {
+        const int l = rows[(long long)s * K + u];
+        const int x = qx[l], g = sel[l];
+        if (x < best_x || (x == best_x && g < best_id)) {
+            best_x = x;
+            best_id = g;
+        }
+    }
+    flag[s] = slab_of(best_x, x0, w, parts) == k;
+}
+
+// Owned vertices of a host-streamed slab, packed (pos: exclusive scan of
+// flag, set by k_own_flags_local<1>): input id and Size.
+__global__ void __launch_bounds__(BLOCK) k_own_vertices_local(const int *__restrict__ rows,
+                                                               const double *__restrict__ size, int m,
+                                                               const int *__restrict__ flag, const int *__restrict__ pos,
+                                                               const int *__restrict__ sel, int *__restrict__ out_id,
+                                                               double *__restrict__ out_size) {
+    const int s = blockIdx.x * BLOCK + threadIdx.x;
+    if (s >= m || !flag[s]) return;
+    out_id[pos[s]] = sel[rows[s]];
+    out_size[pos[s]] = size[s];
 }
 
 }  // namespace acx

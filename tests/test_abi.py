@@ -66,7 +66,7 @@ def _opt(acx, **kw):
 
 @pytest.mark.parametrize("field,value", [
     ("reserved", 1), ("wave_tile", 64), ("capacity_hint", 8), ("profile", -1), ("profile", 99),
-    ("cell_mA", -5), ("force_exact", 2), ("vertex_shortcut", -1),
+    ("cell_mA", -5), ("force_exact", 2), ("vertex_shortcut", -1), ("cell_order", 2),
 ])
 def test_options_out_of_range_are_rejected_before_device_work(field, value):
     """Every ac_options field outside its documented range is AC_E_INVALID,
@@ -87,6 +87,7 @@ def test_options_out_of_range_are_rejected_before_device_work(field, value):
         lambda: lib.ac_alpha_complex(xyz, rad, 1, 0.0, ctypes.byref(o), ctypes.byref(out)),
         lambda: lib.ac_alpha_complex_device(dummy, dummy, 1, 0.0, ctypes.byref(o), None, ctypes.byref(out)),
         lambda: lib.ac_alpha_complex_partitioned(dummy, dummy, 1, 0.0, 2, ctypes.byref(o), None, ctypes.byref(out)),
+        lambda: lib.ac_alpha_complex_partitioned_host(xyz, rad, 1, 0.0, 2, ctypes.byref(o), ctypes.byref(out)),
         lambda: lib.ac_alpha_sweep_device(dummy, dummy, 1, alphas, 1, ctypes.byref(o), None, outs),
         lambda: lib.ac_alpha_complex_batch(dummy, dummy, off, 1, 0.0, ctypes.byref(o), None, None, ctypes.byref(out)),
         lambda: lib.ac_tune_cells(dummy, dummy, off, 1, 0.0, ctypes.byref(o), None, cells, None),
@@ -94,6 +95,35 @@ def test_options_out_of_range_are_rejected_before_device_work(field, value):
     for k, call in enumerate(calls):
         assert call() == 1, (field, value, k)
         assert b"ac_options." + field.encode() in lib.ac_last_error(), (k, lib.ac_last_error())
+    assert not out.value
+
+
+def test_options_layout_matches_the_header():
+    """The binding's ac_options has the header's fields, in order."""
+    import paper_1908_05944_amd as acx
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = text[text.index("typedef struct {"):text.index("} ac_options;")]
+    fields = re.findall(r"\b(?:int32_t|int64_t)\s+([A-Za-z_]+)\s*;", body)
+    assert fields == [f for f, _ in acx.Options._fields_]
+
+
+def test_host_streamed_input_checks_without_device():
+    """The host-streamed build checks its x coordinates, radii, slab count and
+    alpha on the host before any device work."""
+    import paper_1908_05944_amd as acx
+    lib = acx.library()
+    out = ctypes.c_void_p()
+    xyz = (ctypes.c_double * 6)(0.0, 0.0, 0.0, float("nan"), 1.0, 1.0)
+    rad = (ctypes.c_double * 2)(1.5, 1.5)
+    assert lib.ac_alpha_complex_partitioned_host(xyz, rad, 2, 0.0, 2, None, ctypes.byref(out)) == 1
+    xyz[3] = 600.0
+    assert lib.ac_alpha_complex_partitioned_host(xyz, rad, 2, 0.0, 2, None, ctypes.byref(out)) == 3
+    xyz[3] = 2.0
+    for parts in (0, 1025):
+        assert lib.ac_alpha_complex_partitioned_host(xyz, rad, 2, 0.0, parts, None, ctypes.byref(out)) == 1
+    assert lib.ac_alpha_complex_partitioned_host(xyz, rad, 2, float("inf"), 2, None, ctypes.byref(out)) == 1
+    rad[1] = 0.0
+    assert lib.ac_alpha_complex_partitioned_host(xyz, rad, 2, 0.0, 2, None, ctypes.byref(out)) == 1
     assert not out.value
 
 

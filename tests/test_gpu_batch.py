@@ -57,10 +57,10 @@ class _Slice:
         return self._z[d]
 
 
-def _check_batch(acx, mols, alpha, cells=None, oracle_upto=0):
+def _check_batch(acx, mols, alpha, cells=None, oracle_upto=0, options=None):
     xyz, rad, off = _concat(mols)
-    print(f"[case] batch of {len(mols)} molecules, {len(rad)} balls, alpha={alpha}", flush=True)
-    c = acx.ac_alpha_complex_batch(_dev(xyz), _dev(rad), off, alpha, cell_mA=cells)
+    print(f"[case] batch of {len(mols)} molecules, {len(rad)} balls, alpha={alpha} {options}", flush=True)
+    c = acx.ac_alpha_complex_batch(_dev(xyz), _dev(rad), off, alpha, cell_mA=cells, options=options)
     assert c.molecule_count() == len(mols)
     for d in range(4):
         rows = c.molecule_rows(d)
@@ -140,6 +140,15 @@ def test_batch_union_measure(acx):
         As += a
     assert V == pytest.approx(Vs, rel=1e-12)
     assert A == pytest.approx(As, rel=1e-12)
+
+
+def test_morton_cells_in_a_batch(acx):
+    """Per-molecule Morton grids (each padded to a cube of 2^L cells, numbered
+    one after the other): molecule by molecule the single result and the oracle."""
+    sizes = [700, 30, 2200, 5, 1300]
+    mols = [synth.molecule(k, 300 + i) for i, k in enumerate(sizes)]
+    _check_batch(acx, mols, 0.0, oracle_upto=len(mols), options={"cell_order": 1})
+    _check_batch(acx, mols, 1.5, cells=np.array([900, 4000, 1800, 2500, 3100]), options={"cell_order": 1})
 
 
 def test_molecule_of_rows_only_for_batches(acx):

@@ -154,22 +154,39 @@ def test_options_do_not_change_result(acx):
     want = oracle.alpha_complex(m.xyz, m.radii, 1.0)
     base = _run(acx, m.xyz, m.radii, 1.0)
     assert_same_complex(base, want, "default")
-    for opt in ({"force_exact": 1}, {"cell_mA": 900}, {"cell_mA": 4000}, {"cell_mA": 2500, "force_exact": 1}):
+    for opt in ({"force_exact": 1}, {"cell_mA": 900}, {"cell_mA": 4000}, {"cell_mA": 2500, "force_exact": 1},
+                {"cell_order": 1}, {"cell_order": 1, "cell_mA": 900}, {"cell_order": 1, "cell_mA": 4000}):
         got = _run(acx, m.xyz, m.radii, 1.0, **opt)
         assert_same_complex(got, want, str(opt))
         for d in range(4):
             assert np.array_equal(got.sizes(d), base.sizes(d)), (opt, d)
 
 
+@pytest.mark.parametrize("sas", [False, True])
+def test_morton_order_100k(acx, sas):
+    """The 100k-atom molecule with cells on a Morton curve: the same complex as
+    with row-major cells, bit for bit (the solvent-accessible radii take the
+    counted-fill neighbour path)."""
+    m = synth.config_100k(sas=sas)
+    a = _run(acx, m.xyz, m.radii, 0.0)
+    b = _run(acx, m.xyz, m.radii, 0.0, cell_order=1)
+    for d in range(4):
+        assert np.array_equal(a.simplices(d), b.simplices(d)), d
+        assert np.array_equal(a.sizes(d), b.sizes(d)), d
+
+
 def test_stage_events(acx):
-    """profile=1 times every stage; profile=2+i only stage i (the others -1);
-    neither changes the result."""
+    """profile=1 times every stage of the build (the two AC2 stages of the
+    per-step arrangement are not run: -1); profile=2+i only stage i (the others
+    -1); profile=2+stage count runs the AC2 tests of edges and triangles as
+    kernels of their own and times every stage. None changes the result."""
     m = synth.molecule(2000, 13)
     base = _run(acx, m.xyz, m.radii, 0.0)
     names = acx.stage_names()
+    split_only = {"edges_ac2", "triangles_ac2"}
     full = _run(acx, m.xyz, m.radii, 0.0, profile=1)
-    assert all(v >= 0 for v in full.stage_ms().values())
-    for i in (0, names.index("triangles_count"), len(names) - 1):
+    assert all((v >= 0) != (k in split_only) for k, v in full.stage_ms().items()), full.stage_ms()
+    for i in (0, names.index("triangles_count"), names.index("emit")):
         one = _run(acx, m.xyz, m.radii, 0.0, profile=2 + i)
         ms = one.stage_ms()
         assert ms[names[i]] >= 0
@@ -177,6 +194,18 @@ def test_stage_events(acx):
         for d in range(4):
             assert np.array_equal(one.simplices(d), base.simplices(d))
             assert np.array_equal(one.sizes(d), base.sizes(d))
+    for alpha in (0.0, 1.5):
+        ref = _run(acx, m.xyz, m.radii, alpha)
+        split = _run(acx, m.xyz, m.radii, alpha, profile=2 + len(names))
+        assert all(v >= 0 for v in split.stage_ms().values()), split.stage_ms()
+        for d in range(4):
+            assert np.array_equal(split.simplices(d), ref.simplices(d))
+            assert np.array_equal(split.sizes(d), ref.sizes(d))
+    s = synth.config_100k(sas=True)  # counted-fill neighbour path, split arrangement
+    ref = _run(acx, s.xyz, s.radii, 0.0)
+    split = _run(acx, s.xyz, s.radii, 0.0, profile=2 + len(names))
+    for d in range(4):
+        assert np.array_equal(split.simplices(d), ref.simplices(d))
 
 
 def test_host_path_matches(acx):

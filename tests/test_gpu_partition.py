@@ -27,18 +27,22 @@ def _dev(a):
 
 
 def _check(acx, xyz, rad, alpha, parts, label, oracle_check=False):
+    """Both partitioned builds, device-resident and streamed from host memory,
+    against the single build bit for bit (and the oracle)."""
     print(f"[case] partitioned {label}: n={len(rad)} alpha={alpha} parts={parts}", flush=True)
     X, R = _dev(xyz), _dev(rad)
     single = acx.ac_alpha_complex_device(X, R, alpha)
+    want = oracle.alpha_complex(xyz, rad, alpha) if oracle_check else None
     for p in parts:
-        c = acx.ac_alpha_complex_partitioned(X, R, alpha, p)
-        assert c.counts() == single.counts(), (label, p)
-        for d in range(4):
-            assert np.array_equal(c.simplices(d), single.simplices(d)), (label, p, d)
-            assert np.array_equal(c.sizes(d), single.sizes(d)), (label, p, d)
-        if oracle_check:
-            assert_same_complex(c, oracle.alpha_complex(xyz, rad, alpha), f"{label} parts={p}")
-        c.close()
+        for how, c in (("device", acx.ac_alpha_complex_partitioned(X, R, alpha, p)),
+                       ("host", acx.ac_alpha_complex_partitioned_host(xyz, rad, alpha, p))):
+            assert c.counts() == single.counts(), (label, how, p)
+            for d in range(4):
+                assert np.array_equal(c.simplices(d), single.simplices(d)), (label, how, p, d)
+                assert np.array_equal(c.sizes(d), single.sizes(d)), (label, how, p, d)
+            if want is not None:
+                assert_same_complex(c, want, f"{label} {how} parts={p}")
+            c.close()
     single.close()
 
 
@@ -80,7 +84,34 @@ def test_errors(acx):
         with pytest.raises(acx.AlphaCxError) as e:
             acx.ac_alpha_complex_partitioned(X, R, 0.0, parts)
         assert e.value.status == 1
+    for parts in (0, 1025):
+        with pytest.raises(acx.AlphaCxError) as e:
+            acx.ac_alpha_complex_partitioned_host(m.xyz, m.radii, 0.0, parts)
+        assert e.value.status == 1
     dup = np.concatenate([m.xyz, m.xyz[:1]])
     with pytest.raises(acx.AlphaCxError) as e:
         acx.ac_alpha_complex_partitioned(_dev(dup), _dev(np.concatenate([m.radii, m.radii[:1]])), 0.0, 3)
     assert e.value.status == 2
+    with pytest.raises(acx.AlphaCxError) as e:
+        acx.ac_alpha_complex_partitioned_host(dup, np.concatenate([m.radii, m.radii[:1]]), 0.0, 3)
+    assert e.value.status == 2
+    bad = m.radii.copy()
+    bad[7] = -1.0  # found by the slab's own build on the device
+    with pytest.raises(acx.AlphaCxError) as e:
+        acx.ac_alpha_complex_partitioned_host(m.xyz, bad, 0.0, 2)
+    assert e.value.status == 1
+
+
+def test_host_streamed_many_slabs(acx):
+    """The 100k-atom molecule from host memory in 64 and 200 slabs (most balls
+    are halo in the thin ones), equal to the single build."""
+    m = synth.config_100k()
+    X, R = _dev(m.xyz), _dev(m.radii)
+    single = acx.ac_alpha_complex_device(X, R, 0.0)
+    for p in (64, 200):
+        print(f"[case] host-streamed 100k, {p} slabs", flush=True)
+        c = acx.ac_alpha_complex_partitioned_host(m.xyz, m.radii, 0.0, p)
+        for d in range(4):
+            assert np.array_equal(c.simplices(d), single.simplices(d)), (p, d)
+            assert np.array_equal(c.sizes(d), single.sizes(d)), (p, d)
+        assert acx.library().ac_simplices_device(c._h, 1) is None
