@@ -186,6 +186,48 @@ ac_status ac_alpha_complex_batch(const double *d_xyz, const double *d_radii, con
                                  double alpha, const ac_options *opt, const int32_t *cell_mA, void *stream,
                                  ac_complex **out);
 
+/* ---- Recorded batch builds (graph replay) ----
+ *
+ * A batch build whose every size is fixed in advance, captured once in a HIP
+ * graph and replayed: for a stream of inputs of one shape (the same molecules
+ * with new coordinates, e.g. the frames of a trajectory), each replay is one
+ * graph launch with no host synchronisation and no allocation.
+ *
+ * ac_plan_create runs one ordinary batch build of the given arrays to note
+ * the sizes (grid cells per molecule, candidate edges, triangles and
+ * tetrahedra), then fixes them with `headroom` (capacity = noted size x
+ * headroom + 256; every molecule's grid gets at least one cell per ball),
+ * takes the build's buffers and captures the whole pipeline on a stream of its
+ * own. Arguments as ac_alpha_complex_batch; opt->profile must be 0;
+ * 1 <= headroom <= 16. d_xyz / d_radii are recorded: every replay reads the
+ * coordinates and radii found at those addresses when it runs, so they must
+ * stay allocated until ac_plan_free. Synchronises `stream`. AC_E_CAPACITY if a
+ * stage of the input needs the counted fill (rows longer than the single-pass
+ * slots, e.g. solvent-accessible radii), which a recorded build does not have.
+ *
+ * ac_plan_launch enqueues one replay on `stream` (may be captured or ordered
+ * like any kernel launch). ac_plan_result then synchronises `stream` and
+ * returns the replay's complex as a new result (the same as
+ * ac_alpha_complex_batch on the arrays as they were at the replay, bit for
+ * bit, with ac_molecule_rows). If the input no longer fits what was recorded
+ * (a radius above the largest recorded one, a grid or a candidate total above
+ * its capacity, a row beyond its slot, duplicate or invalid values), the replay
+ * stops early and ac_plan_result runs an ordinary batch build of the same
+ * arrays instead (its errors are reported then); ac_plan_stopped gives the
+ * reason bits of the last result (0: the replay itself produced it; 1 input,
+ * 2 cells, 4 duplicates, 8 slot, 16 capacity) and ac_plan_ordinary_builds how
+ * often that happened. One replay of a plan at a time: call ac_plan_result
+ * before the next ac_plan_launch. The plan holds its buffers (about those of
+ * one ordinary build, with headroom) until ac_plan_free. */
+typedef struct ac_plan ac_plan;
+ac_status ac_plan_create(const double *d_xyz, const double *d_radii, const int64_t *offsets, int64_t n_mol, double alpha,
+                         const ac_options *opt, const int32_t *cell_mA, double headroom, void *stream, ac_plan **out);
+ac_status ac_plan_launch(ac_plan *p, void *stream);
+ac_status ac_plan_result(ac_plan *p, void *stream, ac_complex **out);
+int32_t ac_plan_stopped(const ac_plan *p);
+int64_t ac_plan_ordinary_builds(const ac_plan *p);
+void ac_plan_free(ac_plan *p);
+
 /* Molecules of the call that made c (1 for the single-molecule calls). */
 int64_t ac_molecule_count(const ac_complex *c);
 

@@ -87,6 +87,19 @@ def _load():
     lib.ac_alpha_complex.restype = ctypes.c_int
     lib.ac_alpha_complex_device.argtypes = [c_p, c_p, i64, dbl, ctypes.POINTER(Options), c_p, ctypes.POINTER(c_p)]
     lib.ac_alpha_complex_device.restype = ctypes.c_int
+    lib.ac_plan_create.argtypes = [c_p, c_p, c_p, i64, dbl, ctypes.POINTER(Options), c_p, dbl, c_p,
+                                   ctypes.POINTER(c_p)]
+    lib.ac_plan_create.restype = ctypes.c_int
+    lib.ac_plan_launch.argtypes = [c_p, c_p]
+    lib.ac_plan_launch.restype = ctypes.c_int
+    lib.ac_plan_result.argtypes = [c_p, c_p, ctypes.POINTER(c_p)]
+    lib.ac_plan_result.restype = ctypes.c_int
+    lib.ac_plan_stopped.argtypes = [c_p]
+    lib.ac_plan_stopped.restype = ctypes.c_int32
+    lib.ac_plan_ordinary_builds.argtypes = [c_p]
+    lib.ac_plan_ordinary_builds.restype = i64
+    lib.ac_plan_free.argtypes = [c_p]
+    lib.ac_plan_free.restype = None
     lib.ac_alpha_sweep_device.argtypes = [c_p, c_p, i64, ctypes.POINTER(dbl), i64, ctypes.POINTER(Options), c_p,
                                           ctypes.POINTER(c_p)]
     lib.ac_alpha_sweep_device.restype = ctypes.c_int
@@ -388,6 +401,64 @@ def ac_alpha_complex_batch(xyz, radii, offsets, alpha: float, options=None, cell
                                         _stream(xyz.device, stream), ctypes.byref(h))
     _check(st)
     return AlphaComplex(h)
+
+
+class Plan:
+    """A recorded batch build (ac_plan_create): the pipeline captured once in
+    a HIP graph on the given device tensors; launch() replays it on whatever
+    coordinates and radii those tensors hold then, result() returns the
+    complex (an ordinary batch build instead when the input no longer fits
+    what was recorded). Keep xyz and radii alive (and at the same storage)
+    for the plan's lifetime."""
+
+    def __init__(self, xyz, radii, offsets, alpha: float, options=None, cell_mA=None, headroom: float = 1.25,
+                 stream=None):
+        xyz_c, radii_c, off = _batch_args(xyz, radii, offsets)
+        if xyz_c.data_ptr() != xyz.data_ptr() or radii_c.data_ptr() != radii.data_ptr():
+            raise ValueError("contiguous tensors expected: the plan records their storage")
+        self._xyz, self._radii = xyz, radii
+        cells = None
+        if cell_mA is not None:
+            cells = np.ascontiguousarray(cell_mA, dtype=np.int32).reshape(-1)
+            if len(cells) != len(off) - 1:
+                raise ValueError("cell_mA needs one side per molecule")
+        self._device = xyz.device
+        h = ctypes.c_void_p()
+        st = _load().ac_plan_create(xyz.data_ptr(), radii.data_ptr(), off.ctypes.data, len(off) - 1, float(alpha),
+                                    _opts(options), None if cells is None else cells.ctypes.data, float(headroom),
+                                    _stream(xyz.device, stream), ctypes.byref(h))
+        _check(st)
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(_load().ac_plan_launch(self._h, _stream(self._device, stream)))
+
+    def result(self, stream=None) -> AlphaComplex:
+        h = ctypes.c_void_p()
+        _check(_load().ac_plan_result(self._h, _stream(self._device, stream), ctypes.byref(h)))
+        return AlphaComplex(h)
+
+    def stopped(self) -> int:
+        return int(_load().ac_plan_stopped(self._h))
+
+    def ordinary_builds(self) -> int:
+        return int(_load().ac_plan_ordinary_builds(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _load().ac_plan_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ac_plan_create(xyz, radii, offsets, alpha: float, options=None, cell_mA=None, headroom: float = 1.25,
+                   stream=None) -> Plan:
+    return Plan(xyz, radii, offsets, alpha, options=options, cell_mA=cell_mA, headroom=headroom, stream=stream)
 
 
 def ac_tune_cells(xyz, radii, offsets, alpha: float, options=None, stream=None):

@@ -24,6 +24,7 @@
 #include "measure.hpp"
 #include "sweep.hpp"
 #include "partition.hpp"
+#include "plan.hpp"
 
 using namespace acx;
 
@@ -73,7 +74,37 @@ size_t size_class(size_t n) {
 }
 }  // namespace
 
+// Allocations of a recorded build (ac_plan), kept for the plan's lifetime:
+// the first fixed run takes pool blocks and records them in order; the run
+// that is captured in a graph gets the same blocks back in the same order (its
+// requests are the same, since every size is fixed), so the graph's launches
+// address memory the plan owns.
+struct Recorder {
+    std::vector<std::pair<void *, size_t>> blocks;
+    size_t next = 0;
+    bool replay = false;
+};
+static thread_local Recorder *t_rec = nullptr;
+
 static void *dev_alloc(size_t n) {
+    if (Recorder *r = t_rec) {
+        if (r->replay) {
+            if (r->next >= r->blocks.size() || r->blocks[r->next].second < n)
+                throw HipError{AC_E_DEVICE, "internal error: a recorded build asked for other buffers than recorded"};
+            return r->blocks[r->next++].first;
+        }
+        t_rec = nullptr;  // a pool block, recorded
+        void *p = nullptr;
+        try {
+            p = dev_alloc(n);
+        } catch (...) {
+            t_rec = r;
+            throw;
+        }
+        t_rec = r;
+        r->blocks.emplace_back(p, n);
+        return p;
+    }
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     const size_t c = size_class(n ? n : 1);
@@ -108,6 +139,7 @@ static void *dev_alloc(size_t n) {
 
 static void dev_free(void *p) {
     if (!p) return;
+    if (t_rec) return;  // recorded blocks belong to the plan
     Pool &P = pool();
     std::lock_guard<std::mutex> g(P.mu);
     auto it = P.live.find(p);
@@ -286,7 +318,7 @@ struct Cands {
 // buffers of n entries.
 template <class P>
 static void radix_sort(unsigned *&key, P *&pay, int n, int lo, int hi, hipStream_t s, Scope &sc,
-                       unsigned **spare_key = nullptr, P **spare_pay = nullptr) {
+                       unsigned **spare_key = nullptr, P **spare_pay = nullptr, const int *live = nullptr) {
     unsigned *k2 = sc.get<unsigned>(n > 0 ? n : 1);
     P *p2 = sc.get<P>(n > 0 ? n : 1);
     unsigned *kin = key, *kout = k2;
@@ -296,9 +328,9 @@ static void radix_sort(unsigned *&key, P *&pay, int n, int lo, int hi, hipStream
         int *hist = sc.get<int>((size_t)RS_BINS * tiles);
         int *totals = sc.get<int>(RS_BINS);
         for (int shift = lo; shift < hi; shift += RS_BITS) {
-            k_rs_hist<<<tiles, RS_BLOCK, 0, s>>>(kin, n, shift, hist, tiles);
+            k_rs_hist<<<tiles, RS_BLOCK, 0, s>>>(kin, n, shift, hist, tiles, live);
             k_rs_digit_prefix<<<RS_BINS, RS_PREFIX_BLOCK, 0, s>>>(hist, tiles, totals);
-            k_rs_scatter<P><<<tiles, RS_BLOCK, 0, s>>>(kin, pin, kout, pout, n, shift, hist, totals, tiles);
+            k_rs_scatter<P><<<tiles, RS_BLOCK, 0, s>>>(kin, pin, kout, pout, n, shift, hist, totals, tiles, live);
             LAUNCH_CHECK();
             std::swap(kin, kout);
             std::swap(pin, pout);
@@ -326,23 +358,29 @@ static int bits_for(long long n) {
 // groups them into coarse buckets (one pass up to 2^22 balls, two above),
 // then k_emit_bucket finishes EB_KEYS keys per block and writes the sorted
 // rows. The output arrays have room for all M candidates; the kept count goes
-// to *m_out on the device.
+// to *m_out on the device. live: the count is read on the device (at most M).
 template <int K>
 static void emit_dim(unsigned *key, typename EmitPay<K>::type *pay, const double *size_in, int M, int n,
-                     hipStream_t s, Scope &sc, ac_complex *res, int d, int *m_out, bool to_A2 = true) {
+                     hipStream_t s, Scope &sc, ac_complex *res, int d, int *m_out, bool to_A2 = true,
+                     const int *live = nullptr) {
     typedef typename EmitPay<K>::type P;
     res->d_simp[d] = static_cast<int32_t *>(dev_alloc((size_t)(M > 0 ? M : 1) * K * sizeof(int32_t)));
     res->d_size[d] = static_cast<double *>(dev_alloc((size_t)(M > 0 ? M : 1) * sizeof(double)));
-    fill<int>(m_out, M, 1, s);
+    if (live) {
+        k_copy_int<<<1, WAVE, 0, s>>>(live, m_out);
+        LAUNCH_CHECK();
+    } else {
+        fill<int>(m_out, M, 1, s);
+    }
     if (M == 0) return;
     const int bits = bits_for((long long)n + 1);
     const int shift = std::min(std::max(bits - RS_BITS, 0), 14);
     unsigned *gkey = nullptr;
     P *gpay = nullptr;
-    radix_sort<P>(key, pay, M, shift, bits, s, sc, &gkey, &gpay);
+    radix_sort<P>(key, pay, M, shift, bits, s, sc, &gkey, &gpay, live);
     const unsigned blocks = (unsigned)(((long long)n + 1 + EB_KEYS - 1) / EB_KEYS);
     k_emit_bucket<K><<<blocks, EB_BLOCK, 0, s>>>(key, pay, M, n, shift, gkey, gpay, size_in, to_A2 ? 1 : 0,
-                                                 res->d_simp[d], res->d_size[d], m_out);
+                                                 res->d_simp[d], res->d_size[d], m_out, live);
     LAUNCH_CHECK();
 }
 
@@ -441,14 +479,58 @@ struct Batch {
 
 constexpr int QTILE = 1024;  // balls per block of the quantise kernel
 
+// Blocks of the quantise kernel: tiles of at most QTILE balls, each inside one
+// molecule; molecule m's tiles are [tile_first[m], tile_first[m+1]).
+static void quantise_tiles(const Batch &bt, std::vector<int2> &tiles, std::vector<int> &tile_first) {
+    const int n_mol = (int)bt.off.size() - 1;
+    tiles.clear();
+    tile_first.assign(n_mol + 1, 0);
+    for (int m = 0; m < n_mol; m++) {
+        tile_first[m] = (int)tiles.size();
+        for (int64_t a = bt.off[m]; a < bt.off[m + 1]; a += QTILE)
+            tiles.push_back(make_int2((int)a, (int)std::min<int64_t>(a + QTILE, bt.off[m + 1])));
+    }
+    tile_first[n_mol] = (int)tiles.size();
+}
+
+// Sizes of a recorded build (ac_plan). A learning run (learn = true) is an
+// ordinary build that notes them; a fixed run takes them, with the plan's
+// capacities, instead of reading any count back, so that it is a fixed
+// sequence of launches with no host synchronisation (see plan.hpp).
+struct Fixed {
+    bool learn = true;
+    // noted by the learning run
+    std::vector<Grid> grids;       // per molecule: cell side, reach, order, balls
+    std::vector<long long> cells;  // per molecule: grid cells
+    PredParams pp{};
+    int wmax = 0, slot = 0;
+    long long E = 0, T = 0, Q = 0;
+    bool two_pass = false;  // a stage needed the counted fill
+    // given to a fixed run (device arrays uploaded before it)
+    long long ncell = 0;  // cells of all molecules' capacities
+    int E_cap = 1, T_cap = 1, Q_cap = 1;
+    const int2 *d_tiles = nullptr;
+    const int *d_tile_first = nullptr;
+    const Grid *d_tmpl = nullptr;       // recorded grids with each molecule's first cell
+    const long long *d_cell_cap = nullptr;
+    const long long *d_bound = nullptr;  // first ball of each molecule, n_mol + 1
+    // left by a fixed run (device)
+    Counters *cnt = nullptr;
+    long long *d_rows = nullptr;
+};
+
 // The whole pipeline from device arrays, for n_alpha >= 1 alpha values: one
 // candidate search at the largest, then pruning and output per value (the
 // candidates of a smaller alpha are those of the larger that pass AC3 at the
 // smaller, and AC2 does not depend on alpha). Returns AC_OK and outs[k] for
 // alphas[k] on success; nothing is left allocated on failure.
 static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n64, const Batch &bt,
-                              const double *alphas, int n_alpha, const Options &o, hipStream_t s, ac_complex **outs) {
+                              const double *alphas, int n_alpha, const Options &o, hipStream_t s, ac_complex **outs,
+                              Fixed *fx = nullptr) {
     for (int k = 0; k < n_alpha; k++) outs[k] = nullptr;
+    // fixed: sizes from fx, nothing read back (only with one alpha)
+    const bool fixed = fx && !fx->learn;
+    if (fx && n_alpha != 1) return set_error(AC_E_INVALID, "a recorded build takes one alpha");
     if (n64 < 1 || n64 >= (1 << 26)) return set_error(AC_E_INVALID, "n must be in [1, 2^26)");
     if (n_alpha < 1 || n_alpha > AC_MAX_SWEEP) return set_error(AC_E_INVALID, "number of alpha values out of range");
     std::vector<long long> aqs(n_alpha);
@@ -481,34 +563,35 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         const int n_mol = (int)bt.off.size() - 1;
         int4 *q = sc.get<int4>(n);
         Counters *cnt = sc.get<Counters>(1);
-        HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(Counters), s));
+        static_assert(sizeof(Counters) % sizeof(int) == 0, "Counters cleared as ints");
+        fill<int>(reinterpret_cast<int *>(cnt), 0, sizeof(Counters) / sizeof(int), s);  // a kernel: graph-safe
         std::vector<int2> tiles;
-        std::vector<int> tile_first(n_mol + 1);
-        for (int m = 0; m < n_mol; m++) {
-            tile_first[m] = (int)tiles.size();
-            for (int64_t a = bt.off[m]; a < bt.off[m + 1]; a += QTILE)
-                tiles.push_back(make_int2((int)a, (int)std::min<int64_t>(a + QTILE, bt.off[m + 1])));
-        }
-        tile_first[n_mol] = (int)tiles.size();
+        std::vector<int> tile_first;
+        quantise_tiles(bt, tiles, tile_first);
         std::vector<Stats> hs(n_mol);
+        Stats *st = sc.get<Stats>(n_mol);
         {
-            int2 *d_tiles = sc.get<int2>(tiles.size());
-            int *d_tile_first = sc.get<int>(n_mol + 1);
+            const int2 *d_tiles = fixed ? fx->d_tiles : sc.get<int2>(tiles.size());
+            const int *d_tile_first = fixed ? fx->d_tile_first : sc.get<int>(n_mol + 1);
             Stats *part = sc.get<Stats>(tiles.size());
-            Stats *st = sc.get<Stats>(n_mol);
-            HIP_TRY(hipMemcpyAsync(d_tiles, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice, s));
-            HIP_TRY(hipMemcpyAsync(d_tile_first, tile_first.data(), (n_mol + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+            if (!fixed) {
+                HIP_TRY(hipMemcpyAsync(const_cast<int2 *>(d_tiles), tiles.data(), tiles.size() * sizeof(int2),
+                                       hipMemcpyHostToDevice, s));
+                HIP_TRY(hipMemcpyAsync(const_cast<int *>(d_tile_first), tile_first.data(), (n_mol + 1) * sizeof(int),
+                                       hipMemcpyHostToDevice, s));
+            }
             k_quantise<<<(unsigned)tiles.size(), BLOCK, 0, s>>>(d_xyz, d_r, d_tiles, q, part);
             LAUNCH_CHECK();
             k_stats_reduce<<<(unsigned)n_mol, BLOCK, 0, s>>>(part, d_tile_first, st);
             LAUNCH_CHECK();
-            read_back(hs.data(), st, (size_t)n_mol, s);
+            if (!fixed) read_back(hs.data(), st, (size_t)n_mol, s);
         }
         int flags = 0, wmax = 0;
         for (const Stats &x : hs) {
             flags |= x.flags;
             wmax = std::max(wmax, x.wmax);
         }
+        if (fixed) wmax = fx->wmax;  // the device checks that no radius exceeds it
         if (flags & 1) throw HipError{AC_E_INVALID, "non-finite coordinate, or radius not positive"};
         if (flags & 2) throw HipError{AC_E_RANGE, "coordinate or radius outside the exact bit budget"};
         const long long sg2 = (long long)wmax + aq;
@@ -521,11 +604,16 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         pp.bmax = 2.0 * (double)sgc;
         pp.gmax = 4.0 * (double)pp.sg2 + (double)wmax;
         pp.force_exact = o.force_exact;
+        if (fx && fx->learn) {
+            fx->pp = pp;
+            fx->wmax = wmax;
+        }
 
         // ---- grids: one per molecule, cells numbered consecutively ----
         std::vector<Grid> grids(n_mol);
         long long ncell = 0;
-        for (int m = 0; m < n_mol; m++) {
+        if (fx && fx->learn) fx->cells.assign(n_mol, 0);
+        for (int m = 0; m < n_mol && !fixed; m++) {
             const Stats &h = hs[m];
             const long long nm = bt.off[m + 1] - bt.off[m];
             Grid &g = grids[m];
@@ -552,11 +640,21 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             g.a0 = (int)bt.off[m];
             g.a1 = (int)bt.off[m + 1];
             g.order = o.cell_order;
+            if (fx && fx->learn) fx->cells[m] = ncell_of(side);
             ncell += ncell_of(side);
         }
+        if (fx && fx->learn) fx->grids = grids;
+        if (fixed) ncell = fx->ncell;
         if (ncell >= (long long)INT_MAX) throw HipError{AC_E_CAPACITY, "too many grid cells"};
         Grid *d_grids = sc.get<Grid>(n_mol);
-        HIP_TRY(hipMemcpyAsync(d_grids, grids.data(), n_mol * sizeof(Grid), hipMemcpyHostToDevice, s));
+        if (fixed) {
+            // this run's boxes, the recorded sides and capacities
+            k_plan_grids<<<grid_for(n_mol), BLOCK, 0, s>>>(st, n_mol, fx->d_tmpl, fx->d_cell_cap, fx->wmax, d_grids,
+                                                           cnt);
+            LAUNCH_CHECK();
+        } else {
+            HIP_TRY(hipMemcpyAsync(d_grids, grids.data(), n_mol * sizeof(Grid), hipMemcpyHostToDevice, s));
+        }
 
         // ---- binning ----
         tm.mark(ST_BIN);
@@ -588,17 +686,31 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         // with van der Waals radii), where rows outgrow 16 entries; beyond,
         // rows outgrow 32 too and the counted fill runs anyway
         const int slot = (pp.sgc > 1900 && pp.sgc <= 2600) ? NB_SLOT_WIDE : NB_SLOT;
+        if (fx && fx->learn) fx->slot = slot;
         const long long nb_slab = (long long)BLOCK * slot;
         int *nslab = sc.get<int>((size_t)nbN * nb_slab);
         unsigned *upmask = sc.get<unsigned>(n);
         int *nbtot = sc.get<int>(2 * (size_t)nbN);
         int *nboff = sc.get<int>(nbN + 1), *uboff = sc.get<int>(nbN + 1);
+        // the fast exact pair test applies when every scanned offset stays
+        // below 26 A per axis, s_g^2 < 2^25 and alpha >= 0 (see k_neighbours)
+        bool nb_fast = pp.aq >= 0 && pp.sg2 < (1LL << 25);
+        for (const Grid &g : (fixed ? fx->grids : grids))
+            nb_fast = nb_fast && (long long)(g.reach + 1) * g.s < 26000;
         tm.mark(ST_NBR_COUNT);
-        if (slot == NB_SLOT_WIDE)
+        if (slot == NB_SLOT_WIDE && nb_fast)
+            k_neighbours<NB_ONEPASS, NB_SLOT_WIDE, true><<<nbN, BLOCK, 0, s>>>(
+                atom, perm, n, d_grids, n_mol, cell_start, pp, deg_n, deg_up, upmask, nslab, nbtot, nullptr, nullptr,
+                nullptr, nullptr, nullptr, vgab, vert_min, cnt);
+        else if (slot == NB_SLOT_WIDE)
             k_neighbours<NB_ONEPASS, NB_SLOT_WIDE><<<nbN, BLOCK, 0, s>>>(atom, perm, n, d_grids, n_mol, cell_start, pp,
                                                                         deg_n, deg_up, upmask, nslab, nbtot, nullptr,
                                                                         nullptr, nullptr, nullptr, nullptr, vgab, vert_min,
                                                                         cnt);
+        else if (nb_fast)
+            k_neighbours<NB_ONEPASS, NB_SLOT, true><<<nbN, BLOCK, 0, s>>>(
+                atom, perm, n, d_grids, n_mol, cell_start, pp, deg_n, deg_up, upmask, nslab, nbtot, nullptr, nullptr,
+                nullptr, nullptr, nullptr, vgab, vert_min, cnt);
         else
             k_neighbours<NB_ONEPASS, NB_SLOT><<<nbN, BLOCK, 0, s>>>(atom, perm, n, d_grids, n_mol, cell_start, pp, deg_n,
                                                                    deg_up, upmask, nslab, nbtot, nullptr, nullptr,
@@ -608,10 +720,18 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         scan_i32(nbtot, nboff, nbN, s, sc, &cnt->Nn);
         scan_i32(nbtot + nbN, uboff, nbN, s, sc, &cnt->E);
         LAUNCH_CHECK();
-        Counters c0 = read_one(cnt, s);
+        Counters c0{};
+        if (fixed) {
+            k_plan_guard<<<1, WAVE, 0, s>>>(cnt, 0, fx->E_cap);
+            LAUNCH_CHECK();
+            c0.E = fx->E_cap;
+        } else {
+            c0 = read_one(cnt, s);
+        }
         if (c0.dup) throw HipError{AC_E_DUPLICATE, "two balls have equal quantised centres"};
         const bool nbr_two_pass = c0.overflow != 0;
-        if (nbr_two_pass || (long long)nbN * nb_slab >= (long long)INT_MAX) {
+        if (fx && fx->learn) fx->two_pass |= nbr_two_pass;
+        if (!fixed && (nbr_two_pass || (long long)nbN * nb_slab >= (long long)INT_MAX)) {
             // past this size the slab bound no longer keeps the total in 32 bits
             check_total(total_i64(deg_n, n, s, sc), "neighbour entries");
         }
@@ -622,6 +742,8 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             c0 = read_one(cnt, s);
         }
         const int E = c0.E, Nn = c0.Nn;
+        if (fx && fx->learn) fx->E = E;
+        const int *E_live = fixed ? &cnt->El : nullptr;  // fixed: the launches below read the count
         // neighbour rows: in the slabs after the one-pass search, else in CSR
         int *nbr = nbr_two_pass ? sc.get<int>(Nn > 0 ? Nn : 1) : nslab;
         int *up = sc.get<int>(E > 0 ? E : 1);
@@ -630,10 +752,15 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         if (!nbr_two_pass) {
             if (slot == NB_SLOT_WIDE)
                 k_nbr_compact<NB_SLOT_WIDE><<<nbN, BLOCK, 0, s>>>(deg_n, deg_up, upmask, n, nslab, uboff, nbr_start,
-                                                                 up_start, up, edge_i);
+                                                                 up_start, up, edge_i, fixed ? &cnt->stop : nullptr);
             else
                 k_nbr_compact<NB_SLOT><<<nbN, BLOCK, 0, s>>>(deg_n, deg_up, upmask, n, nslab, uboff, nbr_start, up_start,
-                                                            up, edge_i);
+                                                            up, edge_i, fixed ? &cnt->stop : nullptr);
+        } else if (nb_fast) {
+            k_neighbours<NB_FILL, NB_SLOT, true><<<nbN, BLOCK, 0, s>>>(atom, perm, n, d_grids, n_mol, cell_start, pp,
+                                                                      nullptr, nullptr, nullptr, nullptr, nullptr,
+                                                                      nbr_start, up_start, nbr, up, edge_i, vgab,
+                                                                      vert_min, cnt);
         } else {
             k_neighbours<NB_FILL, NB_SLOT><<<nbN, BLOCK, 0, s>>>(atom, perm, n, d_grids, n_mol, cell_start, pp, nullptr,
                                                                 nullptr, nullptr, nullptr, nullptr, nbr_start, up_start,
@@ -668,7 +795,7 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             else
                 k_triangles<TRI_ONEPASS><<<nbE, BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i,
                                                               E, pp, tri_cnt, egab, edge_min, tslab, tbtot, nullptr,
-                                                              nullptr, nullptr, cnt);
+                                                              nullptr, nullptr, cnt, E_live);
             LAUNCH_CHECK();
             tm.mark(ST_TRI_SCAN);
             scan_i32(tbtot, tboff, nbE, s, sc, &cnt->T);
@@ -677,9 +804,17 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             tm.mark(ST_TRI_SCAN);
             fill<int>(&cnt->T, 0, 1, s);
         }
-        Counters ct = read_one(cnt, s);
+        Counters ct{};
+        if (fixed) {
+            k_plan_guard<<<1, WAVE, 0, s>>>(cnt, 1, fx->T_cap);
+            LAUNCH_CHECK();
+            ct.T = fx->T_cap;
+        } else {
+            ct = read_one(cnt, s);
+        }
         const bool tri_two_pass = ct.overflow != 0;
-        if (tri_two_pass || (long long)nbE * TRI_SLAB >= (long long)INT_MAX) {
+        if (fx && fx->learn) fx->two_pass |= tri_two_pass;
+        if (!fixed && (tri_two_pass || (long long)nbE * TRI_SLAB >= (long long)INT_MAX)) {
             // past this size the slab bound no longer keeps the total in 32 bits
             check_total(total_i64(tri_cnt, E, s, sc), "candidate triangles");
         }
@@ -689,6 +824,8 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             ct = read_one(cnt, s);
         }
         const int T = ct.T;
+        if (fx && fx->learn) fx->T = T;
+        const int *T_live = fixed ? &cnt->Tl : nullptr;
         int *tri_k = sc.get<int>(T > 0 ? T : 1);
         int *tri_e = sc.get<int>(T > 0 ? T : 1);
         unsigned char *tgab = sc.get<unsigned char>(T > 0 ? T : 1);
@@ -697,8 +834,9 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         int *tet_cnt = sc.get<int>(T > 0 ? T : 1);
         int *tet_start = sc.get<int>(T + 1);
         tm.mark(ST_TRI_FILL);
+        if (fixed) fill<int>(tri_start, 0, 1, s);  // no edge at run time leaves tri_start[0] unwritten
         if (E > 0 && !tri_two_pass) {
-            k_tri_compact<<<nbE, BLOCK, 0, s>>>(tri_cnt, E, tslab, tboff, tri_start, tri_k, tri_e);
+            k_tri_compact<<<nbE, BLOCK, 0, s>>>(tri_cnt, E, tslab, tboff, tri_start, tri_k, tri_e, E_live);
             LAUNCH_CHECK();
         } else if (T > 0) {
             k_triangles<TRI_FILL><<<nbE, BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i, E, pp,
@@ -729,7 +867,8 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             else
                 k_tet_candidates<TET_ONEPASS><<<nbT, BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up,
                                                                    edge_i, tri_k, tri_e, T, pp, tgab, tsize, tri_min,
-                                                                   tet_cnt, qslab, qbtot, nullptr, nullptr, nullptr, cnt);
+                                                                   tet_cnt, qslab, qbtot, nullptr, nullptr, nullptr, cnt,
+                                                                   T_live);
             LAUNCH_CHECK();
         }
         tm.mark(ST_TET_COUNT);
@@ -739,8 +878,16 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         } else {
             fill<int>(&cnt->Q, 0, 1, s);
         }
-        Counters cq = read_one(cnt, s);
+        Counters cq{};
+        if (fixed) {
+            k_plan_guard<<<1, WAVE, 0, s>>>(cnt, 2, fx->Q_cap);
+            LAUNCH_CHECK();
+            cq.Q = fx->Q_cap;
+        } else {
+            cq = read_one(cnt, s);
+        }
         const bool tet_two_pass = cq.overflow != 0;
+        if (fx && fx->learn) fx->two_pass |= tet_two_pass;
         if (tet_two_pass) {
             check_total(total_i64(tet_cnt, T, s, sc), "candidate tetrahedra");
             scan_i32(tet_cnt, tet_start, T, s, sc, &cnt->Q);
@@ -748,12 +895,14 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             cq = read_one(cnt, s);
         }
         const int Q = cq.Q;
+        if (fx && fx->learn) fx->Q = Q;
+        const int *Q_live = fixed ? &cnt->Ql : nullptr;
         int *tet_t = sc.get<int>(Q > 0 ? Q : 1);
         int *tet_l = sc.get<int>(Q > 0 ? Q : 1);
         double *qsize = sc.get<double>(Q > 0 ? Q : 1);
         tm.mark(ST_TET_FILL);
         if (T > 0 && !tet_two_pass) {
-            k_tet_compact<<<nbT, BLOCK, 0, s>>>(tet_cnt, T, qslab, qboff, tet_t, tet_l);
+            k_tet_compact<<<nbT, BLOCK, 0, s>>>(tet_cnt, T, qslab, qboff, tet_t, tet_l, T_live);
             LAUNCH_CHECK();
         } else if (Q > 0) {
             k_tet_candidates<TET_FILL><<<nbT, BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i,
@@ -797,7 +946,9 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             LAUNCH_CHECK();
         };
         long long *d_bound = nullptr;
-        if (n_mol > 1) {
+        if (n_mol > 1 && fixed) {
+            d_bound = const_cast<long long *>(fx->d_bound);
+        } else if (n_mol > 1) {
             d_bound = sc.get<long long>(n_mol + 1);
             HIP_TRY(hipMemcpyAsync(d_bound, bt.off.data(), (n_mol + 1) * sizeof(long long), hipMemcpyHostToDevice, s));
         }
@@ -822,19 +973,19 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             if (Q > 0) {
                 k_tet_ac2<false><<<grid_for(Q), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i,
                                                               tri_start, tri_k, tri_e, tet_t, tet_l, Q, pp, tgab, tri_min,
-                                                              nullptr, qsize, nullptr, n, qkey, qpay, cnt);
+                                                              nullptr, qsize, nullptr, n, qkey, qpay, cnt, Q_live);
                 LAUNCH_CHECK();
             }
             tm.mark(ST_TRI_FINAL);
             if (T > 0) {
                 k_tri_final<<<grid_for(T), BLOCK, 0, s>>>(up_start, up, edge_i, tri_k, tri_e, T, tgab, tsize, tri_min, egab,
-                                                         edge_min, perm, n, tkey, tpay, cnt);
+                                                         edge_min, perm, n, tkey, tpay, cnt, T_live);
                 LAUNCH_CHECK();
             }
             tm.mark(ST_EDGE_FINAL);
             if (E > 0) {
                 k_edge_final<<<grid_for(E), BLOCK, 0, s>>>(atom, up, edge_i, E, egab, edge_min, vgab, vert_min, perm, n,
-                                                          ekey, epay);
+                                                          ekey, epay, E_live);
                 LAUNCH_CHECK();
             }
             tm.mark(ST_VERT_FINAL);
@@ -842,9 +993,9 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             // ---- emit ----
             tm.mark(ST_EMIT);
             vert_emit(res, &cnt->m0);
-            emit_dim<2>(ekey, epay, nullptr, E, n, s, sc, res, 1, &cnt->m1);
-            emit_dim<3>(tkey, tpay, nullptr, T, n, s, sc, res, 2, &cnt->m2);
-            emit_dim<4>(qkey, qpay, qsize, Q, n, s, sc, res, 3, &cnt->m3);
+            emit_dim<2>(ekey, epay, nullptr, E, n, s, sc, res, 1, &cnt->m1, true, E_live);
+            emit_dim<3>(tkey, tpay, nullptr, T, n, s, sc, res, 2, &cnt->m2, true, T_live);
+            emit_dim<4>(qkey, qpay, qsize, Q, n, s, sc, res, 3, &cnt->m3, true, Q_live);
             if (n_mol > 1) mol_rows(res, cnt, d_rows, d_bound);
         } else {
             // ---- sweep: AC2 of the tetrahedra, the output order of every
@@ -954,6 +1105,13 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             }
         }
         tm.mark(ST_COUNT);
+        if (fixed) {
+            // nothing is read back: the plan reads the counters after a replay
+            fx->cnt = cnt;
+            fx->d_rows = d_rows;
+            outs[0] = res;
+            return AC_OK;
+        }
 
         // ---- results ----
         std::vector<int64_t> rows;
@@ -1623,6 +1781,230 @@ static Options parse(const ac_options *opt) {
 }
 
 // ---------------------------------------------------------------------------
+// Recorded batch builds: one learning build notes the sizes, the fixed
+// pipeline is run once to take its buffers and once under stream capture,
+// and the captured graph is then replayed on new coordinates.
+struct ac_plan {
+    int device = 0;
+    hipStream_t cap_stream = nullptr;  // the stream the graph was captured on
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    Fixed fx;
+    Recorder rec;                 // the build's buffers, owned by the plan
+    std::vector<void *> consts;   // uploaded tiles, grid templates, capacities, molecule bounds
+    // what an ordinary build needs when a replay stops
+    const double *d_xyz = nullptr, *d_r = nullptr;
+    int64_t n = 0;
+    Batch bt;
+    double alpha = 0;
+    Options o;
+    int32_t *out_simp[4] = {};
+    double *out_size[4] = {};
+    int last_stop = 0;
+    int64_t ordinary_builds = 0;
+};
+
+static void free_plan(ac_plan *p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap_stream) {
+        (void)hipStreamSynchronize(p->cap_stream);
+        (void)hipStreamDestroy(p->cap_stream);
+    }
+    for (auto &b : p->rec.blocks) dev_free(b.first);
+    for (void *c : p->consts) dev_free(c);
+    delete p;
+}
+
+template <class T>
+static T *upload(ac_plan *p, const T *h, size_t n, hipStream_t s) {
+    T *d = static_cast<T *>(dev_alloc((n ? n : 1) * sizeof(T)));
+    p->consts.push_back(d);
+    if (n) HIP_TRY(hipMemcpyAsync(d, h, n * sizeof(T), hipMemcpyHostToDevice, s));
+    return d;
+}
+
+// Sets t_rec for the duration of a scope.
+struct RecordingOn {
+    explicit RecordingOn(Recorder *r) { t_rec = r; }
+    ~RecordingOn() { t_rec = nullptr; }
+};
+
+static ac_status plan_create(const double *d_xyz, const double *d_r, const Batch &bt, double alpha, const Options &o,
+                             double headroom, hipStream_t s, ac_plan **out) {
+    ac_plan *p = new ac_plan();
+    try {
+        HIP_TRY(hipGetDevice(&p->device));
+        p->d_xyz = d_xyz;
+        p->d_r = d_r;
+        p->n = bt.off.back();
+        p->bt = bt;
+        p->alpha = alpha;
+        p->o = o;
+        const int n_mol = (int)bt.off.size() - 1;
+        // 1. an ordinary build notes the sizes
+        Fixed &fx = p->fx;
+        fx.learn = true;
+        ac_complex *r0 = nullptr;
+        ac_status st = run_pipeline(d_xyz, d_r, p->n, bt, &alpha, 1, o, s, &r0, &fx);
+        if (st != AC_OK) {
+            free_plan(p);
+            return st;
+        }
+        free_complex(r0);
+        if (fx.two_pass)
+            throw HipError{AC_E_CAPACITY, "a stage of this input needs the counted fill (rows longer than the "
+                                          "single-pass slots); it has no recorded build"};
+        // 2. capacities: the learned sizes with headroom; every molecule's
+        // grid gets at least a cell per ball (a stopped molecule uses that)
+        auto grow = [&](long long v) {
+            const double c = std::ceil((double)v * headroom) + 256.0;
+            if (c >= (double)INT_MAX) throw HipError{AC_E_CAPACITY, "planned capacity beyond 2^31"};
+            return (int)c;
+        };
+        fx.E_cap = grow(fx.E);
+        fx.T_cap = grow(fx.T);
+        fx.Q_cap = grow(fx.Q);
+        std::vector<long long> cap(n_mol);
+        std::vector<Grid> tmpl = fx.grids;
+        long long base = 0;
+        for (int m = 0; m < n_mol; m++) {
+            cap[m] = std::max<long long>((long long)std::ceil((double)fx.cells[m] * headroom), bt.off[m + 1] - bt.off[m]);
+            tmpl[m].base = base;
+            base += cap[m];
+        }
+        if (base >= (long long)INT_MAX) throw HipError{AC_E_CAPACITY, "planned grid cells beyond 2^31"};
+        fx.ncell = base;
+        std::vector<int2> tiles;
+        std::vector<int> tile_first;
+        quantise_tiles(bt, tiles, tile_first);
+        std::vector<long long> bound(bt.off.begin(), bt.off.end());
+        fx.d_tiles = upload(p, tiles.data(), tiles.size(), s);
+        fx.d_tile_first = upload(p, tile_first.data(), tile_first.size(), s);
+        fx.d_tmpl = upload(p, tmpl.data(), tmpl.size(), s);
+        fx.d_cell_cap = upload(p, cap.data(), cap.size(), s);
+        fx.d_bound = upload(p, bound.data(), bound.size(), s);
+        HIP_TRY(hipStreamSynchronize(s));  // the host arrays above go out of scope
+        fx.learn = false;
+        // 3. the fixed pipeline once, taking (and recording) its buffers
+        HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+        ac_complex *r1 = nullptr;
+        {
+            const RecordingOn on(&p->rec);
+            st = run_pipeline(d_xyz, d_r, p->n, bt, &alpha, 1, o, p->cap_stream, &r1, &fx);
+            if (st != AC_OK) {
+                free_plan(p);
+                return st;
+            }
+            for (int d = 0; d < 4; d++) {
+                p->out_simp[d] = r1->d_simp[d];
+                p->out_size[d] = r1->d_size[d];
+            }
+            free_complex(r1);  // host object; its arrays are recorded blocks
+        }
+        Counters c{};
+        read_back(&c, fx.cnt, 1, p->cap_stream);
+        if (c.stop) throw HipError{AC_E_DEVICE, "internal error: the recorded build stopped on its own input"};
+        // 4. the same launches captured in a graph, on the recorded buffers
+        p->rec.replay = true;
+        p->rec.next = 0;
+        {
+            const RecordingOn on(&p->rec);
+            HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+            ac_complex *r2 = nullptr;
+            try {
+                st = run_pipeline(d_xyz, d_r, p->n, bt, &alpha, 1, o, p->cap_stream, &r2, &fx);
+            } catch (...) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(p->cap_stream, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            HIP_TRY(hipStreamEndCapture(p->cap_stream, &p->graph));
+            if (st != AC_OK) {
+                free_plan(p);
+                return st;
+            }
+            bool same = p->rec.next == p->rec.blocks.size();
+            for (int d = 0; d < 4; d++) same = same && r2->d_simp[d] == p->out_simp[d] && r2->d_size[d] == p->out_size[d];
+            free_complex(r2);
+            if (!same) throw HipError{AC_E_DEVICE, "internal error: the captured build used other buffers"};
+        }
+        HIP_TRY(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+        *out = p;
+        g_last_error.clear();
+        return AC_OK;
+    } catch (const HipError &e) {
+        t_rec = nullptr;
+        free_plan(p);
+        return set_error(e.st, e.msg);
+    }
+}
+
+static ac_status plan_result(ac_plan *p, hipStream_t s, ac_complex **out) {
+    const int n_mol = (int)p->bt.off.size() - 1;
+    Counters c{};
+    read_back(&c, p->fx.cnt, 1, s);
+    p->last_stop = c.stop;
+    if (c.stop) {
+        // the input did not fit the recording: an ordinary build of the same
+        // arguments (it also reports invalid input)
+        p->ordinary_builds++;
+        const ac_status st = run_pipeline(p->d_xyz, p->d_r, p->n, p->bt, &p->alpha, 1, p->o, s, out);
+        if (st == AC_OK) (*out)->batch = true;
+        return st;
+    }
+    if (c.lookup) throw HipError{AC_E_DEVICE, "internal error: a facet of a kept simplex is not a candidate"};
+    std::vector<int64_t> rows;
+    if (n_mol > 1) {
+        rows.resize(4 * (size_t)(n_mol + 1));
+        read_back(rows.data(), (const int64_t *)p->fx.d_rows, rows.size(), s);
+    }
+    ac_complex *r = new ac_complex();
+    try {
+        for (double &x : r->stage_ms) x = -1.0;
+        r->device = p->device;
+        r->device_result = true;
+        r->batch = true;
+        r->n_mol = n_mol;
+        r->n = p->n;
+        r->alpha_q = (int64_t)std::nearbyint(p->alpha * 1e6);
+        const int m[4] = {c.m0, c.m1, c.m2, c.m3};
+        r->cand[0] = p->n;
+        r->cand[1] = c.El;
+        r->cand[2] = c.Tl;
+        r->cand[3] = c.Ql;
+        r->fallbacks = (int64_t)c.exact_fallbacks;
+        r->work[0] = p->fx.ncell;
+        r->work[1] = c.Nn;
+        for (int d = 0; d < 4; d++) {
+            r->count[d] = m[d];
+            r->d_simp[d] = static_cast<int32_t *>(dev_alloc((size_t)(m[d] > 0 ? m[d] : 1) * (d + 1) * sizeof(int32_t)));
+            r->d_size[d] = static_cast<double *>(dev_alloc((size_t)(m[d] > 0 ? m[d] : 1) * sizeof(double)));
+            if (m[d] > 0) {
+                HIP_TRY(hipMemcpyAsync(r->d_simp[d], p->out_simp[d], (size_t)m[d] * (d + 1) * sizeof(int32_t),
+                                       hipMemcpyDeviceToDevice, s));
+                HIP_TRY(hipMemcpyAsync(r->d_size[d], p->out_size[d], (size_t)m[d] * sizeof(double),
+                                       hipMemcpyDeviceToDevice, s));
+            }
+            if (n_mol > 1) {
+                const int64_t *b0 = rows.data() + (size_t)d * (n_mol + 1);
+                r->mol_rows[d].assign(b0, b0 + (n_mol + 1));
+            } else {
+                r->mol_rows[d] = {0, r->count[d]};
+            }
+        }
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        free_complex(r);
+        throw;
+    }
+    *out = r;
+    return AC_OK;
+}
+
+// ---------------------------------------------------------------------------
 // C ABI
 extern "C" {
 
@@ -1748,6 +2130,64 @@ ac_status ac_alpha_complex_batch(const double *d_xyz, const double *d_radii, con
         return set_error(AC_E_DEVICE, "unexpected host exception");
     }
 }
+
+ac_status ac_plan_create(const double *d_xyz, const double *d_radii, const int64_t *offsets, int64_t n_mol, double alpha,
+                         const ac_options *opt, const int32_t *cell_mA, double headroom, void *stream, ac_plan **out) {
+    if (!out) return set_error(AC_E_INVALID, "out is NULL");
+    *out = nullptr;
+    try {
+        const Options o = parse(opt);
+        if (o.profile != 0) return set_error(AC_E_INVALID, "ac_options.profile must be 0 for a recorded build");
+        if (!d_xyz || !d_radii) return set_error(AC_E_INVALID, "NULL input pointer");
+        if (!std::isfinite(alpha)) return set_error(AC_E_INVALID, "alpha is not finite");
+        if (!(headroom >= 1.0 && headroom <= 16.0)) return set_error(AC_E_INVALID, "headroom must be in [1, 16]");
+        Batch bt;
+        const ac_status st = batch_from(offsets, n_mol, cell_mA, bt);
+        if (st != AC_OK) return st;
+        return plan_create(d_xyz, d_radii, bt, alpha, o, headroom, static_cast<hipStream_t>(stream), out);
+    } catch (const HipError &e) {
+        return set_error(e.st, e.msg);
+    } catch (...) {
+        return set_error(AC_E_DEVICE, "unexpected host exception");
+    }
+}
+
+ac_status ac_plan_launch(ac_plan *p, void *stream) {
+    if (!p) return set_error(AC_E_INVALID, "plan is NULL");
+    try {
+        int dev = -1;
+        HIP_TRY(hipGetDevice(&dev));
+        if (dev != p->device) return set_error(AC_E_INVALID, "the plan was made on another device");
+        HIP_TRY(hipGraphLaunch(p->exec, static_cast<hipStream_t>(stream)));
+        return AC_OK;
+    } catch (const HipError &e) {
+        return set_error(e.st, e.msg);
+    }
+}
+
+ac_status ac_plan_result(ac_plan *p, void *stream, ac_complex **out) {
+    if (!out) return set_error(AC_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!p) return set_error(AC_E_INVALID, "plan is NULL");
+    try {
+        int dev = -1;
+        HIP_TRY(hipGetDevice(&dev));
+        if (dev != p->device) return set_error(AC_E_INVALID, "the plan was made on another device");
+        const ac_status st = plan_result(p, static_cast<hipStream_t>(stream), out);
+        if (st == AC_OK) g_last_error.clear();
+        return st;
+    } catch (const HipError &e) {
+        return set_error(e.st, e.msg);
+    } catch (...) {
+        return set_error(AC_E_DEVICE, "unexpected host exception");
+    }
+}
+
+int32_t ac_plan_stopped(const ac_plan *p) { return p ? p->last_stop : -1; }
+
+int64_t ac_plan_ordinary_builds(const ac_plan *p) { return p ? p->ordinary_builds : -1; }
+
+void ac_plan_free(ac_plan *p) { free_plan(p); }
 
 int64_t ac_molecule_count(const ac_complex *c) { return c ? c->n_mol : -1; }
 

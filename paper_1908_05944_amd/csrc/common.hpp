@@ -34,6 +34,11 @@ __device__ __forceinline__ int xcd_block() {
     return x * q + min(x, r) + k;
 }
 
+// Item count of a launch: `cap`, the count it was sized for, or, when `live`
+// is given, the smaller count an earlier kernel on the stream wrote there
+// (launches recorded before their counts are known, as in a captured graph).
+__device__ __forceinline__ int live_count(int cap, const int *live) { return live ? min(cap, *live) : cap; }
+
 // Inclusive prefix sum over the 64 lanes of a wave.
 __device__ __forceinline__ int wave_inclusive_scan(int v) {
     const int lane = lane_id();

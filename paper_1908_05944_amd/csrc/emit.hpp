@@ -104,8 +104,9 @@ __global__ void __launch_bounds__(EB_BLOCK) k_emit_bucket(const unsigned *__rest
                                                            typename EmitPay<K>::type *__restrict__ gpay,
                                                            const double *__restrict__ size_in, int to_A2,
                                                            int *__restrict__ out, double *__restrict__ out_size,
-                                                           int *__restrict__ m_out) {
+                                                           int *__restrict__ m_out, const int *__restrict__ live = nullptr) {
     typedef typename EmitPay<K>::type P;
+    m = live_count(m, live);
     __shared__ int cnt[EB_KEYS];  // per-key counts, then each key's first place in the block's range
     __shared__ int cur[EB_KEYS];  // placement cursors
     __shared__ int wsum[EB_BLOCK / WAVE];

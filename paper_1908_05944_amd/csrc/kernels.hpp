@@ -37,7 +37,9 @@ struct Stats {
 // 2^L cells a side. A batch of molecules has one grid per molecule; their
 // cells are numbered one after the other in a single table, so no ball ever
 // sees another molecule's balls.
-enum { ORDER_ROW = 0, ORDER_MORTON = 1 };
+// ORDER_STOP: the grid of a molecule a recorded build could not take (ball k
+// of the molecule alone in its cell k, no neighbour scan); see plan.hpp.
+enum { ORDER_ROW = 0, ORDER_MORTON = 1, ORDER_STOP = 2 };
 constexpr int MORTON_MAX_BITS = 10;  // cell coordinates below 1024: 30-bit codes
 
 struct Grid {
@@ -208,7 +210,7 @@ __global__ void __launch_bounds__(BLOCK) k_cell_key(const int4 *__restrict__ q, 
     if (i >= n) return;
     const int4 a = q[i];
     const Grid &g = grids[mol_of(grids, n_mol, i)];
-    key[i] = (unsigned)(g.base + cell_of(g, a.x, a.y, a.z));
+    key[i] = (unsigned)(g.base + (g.order == ORDER_STOP ? i - g.a0 : cell_of(g, a.x, a.y, a.z)));
     idx[i] = (unsigned)i;
 }
 
@@ -272,7 +274,15 @@ enum { NB_ONEPASS = 0, NB_FILL = 1 };
 constexpr int NB_SLOT = 16;
 constexpr int NB_SLOT_WIDE = 32;
 
-template <int MODE, int SLOT>
+// FAST: the pair test without clamping and with full-rate arithmetic, for
+// grids where it is exact (the launch checks: every scanned offset below
+// 26 A per axis, s_g^2 < 2^25 mA^2, alpha >= 0): offsets of balls of cells
+// within `reach` are below (reach + 1) s, so d^2 < 2^31 and each square is a
+// 24-bit product; the grown balls meet iff L = d^2 - rho_a^2 - rho_b^2 <= 0
+// or L^2 <= 4 rho_a^2 rho_b^2, and in float64 4 rho_a^2 rho_b^2 < 2^52 is
+// exact while L^2 is exact below 2^53 and, above, rounds to at least 2^53:
+// the comparison is decided exactly either way.
+template <int MODE, int SLOT, bool FAST = false>
 __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ atom, const int *__restrict__ perm, int n,
                                                        const Grid *__restrict__ grids, int n_mol,
                                                        const int *__restrict__ cell_start, PredParams pp,
@@ -324,6 +334,7 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
         const int z0 = max(cz - g.reach, 0), z1 = min(cz + g.reach, g.nz - 1);
         const int lim = 4 * (int)pp.sg2;     // (2 s_g)^2 < 2^28
         const int reach1 = 2 * (int)pp.sgc;  // 2 ceil(s_g) <= 2^14
+        const double ra4 = 4.0 * (double)ra;
         // the balls whose grown balls meet this one's, in cell order
         auto scan = [&](auto &&on_meet) {
             for (int z = z0; z <= z1; z++) {
@@ -347,18 +358,29 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
                         for (int j = s; j < e; j++) {
                             const int4 bb = atom[j];
                             // one combined test (a branch per condition costs more
-                            // exec-mask work than the arithmetic it would skip);
-                            // offsets clamped to reach1 + 1: d2 then fits int32, and
-                            // a clamped offset alone gives d2 > (2 ceil s_g)^2 >= lim
-                            const int dx = min(max(bb.x - a.x, -reach1 - 1), reach1 + 1);
-                            const int dy = min(max(bb.y - a.y, -reach1 - 1), reach1 + 1);
-                            const int dz = min(max(bb.z - a.z, -reach1 - 1), reach1 + 1);
-                            const int d2 = dx * dx + dy * dy + dz * dz;
-                            const int rb2 = bb.w + (int)pp.aq;
-                            const int L = d2 - ra - rb2;
-                            // grown balls meet: d <= rho_a + rho_b; equal centres are reported by k_dup_check
-                            const bool meet = (j != i) & (d2 <= lim) & (d2 != 0) & (rb2 >= 0) &
-                                              ((L <= 0) | ((i64)L * L <= 4 * (i64)ra * rb2));
+                            // exec-mask work than the arithmetic it would skip)
+                            bool meet;
+                            if constexpr (FAST) {
+                                const int dx = bb.x - a.x, dy = bb.y - a.y, dz = bb.z - a.z;
+                                const int d2 = __mul24(dx, dx) + __mul24(dy, dy) + __mul24(dz, dz);
+                                const int rb2 = bb.w + (int)pp.aq;
+                                const int L = d2 - ra - rb2;
+                                // d2 == 0: the ball itself (equal centres are reported by k_dup_check)
+                                meet = (d2 <= lim) & (d2 != 0) &
+                                       ((L <= 0) | ((double)L * (double)L <= ra4 * (double)rb2));
+                            } else {
+                                // offsets clamped to reach1 + 1: d2 then fits int32, and
+                                // a clamped offset alone gives d2 > (2 ceil s_g)^2 >= lim
+                                const int dx = min(max(bb.x - a.x, -reach1 - 1), reach1 + 1);
+                                const int dy = min(max(bb.y - a.y, -reach1 - 1), reach1 + 1);
+                                const int dz = min(max(bb.z - a.z, -reach1 - 1), reach1 + 1);
+                                const int d2 = dx * dx + dy * dy + dz * dz;
+                                const int rb2 = bb.w + (int)pp.aq;
+                                const int L = d2 - ra - rb2;
+                                // grown balls meet: d <= rho_a + rho_b; equal centres are reported by k_dup_check
+                                meet = (j != i) & (d2 <= lim) & (d2 != 0) & (rb2 >= 0) &
+                                       ((L <= 0) | ((i64)L * L <= 4 * (i64)ra * rb2));
+                            }
                             if (meet) on_meet(j, bb);
                         }
                     }
@@ -466,7 +488,9 @@ __global__ void __launch_bounds__(BLOCK) k_nbr_compact(const int *__restrict__ d
                                                         const unsigned *__restrict__ upmask, int n,
                                                         const int *__restrict__ nslab, const int *__restrict__ uoff,
                                                         int *__restrict__ nbr_start, int *__restrict__ up_start,
-                                                        int *__restrict__ up, int *__restrict__ edge_i) {
+                                                        int *__restrict__ up, int *__restrict__ edge_i,
+                                                        const int *__restrict__ stop = nullptr) {
+    if (stop && *stop) return;  // a recorded build stopped: the upper rows may not fit
     const int b = blockIdx.x;
     const int i = b * BLOCK + threadIdx.x;
     const int cn = i < n ? deg_n[i] : 0, cu = i < n ? deg_up[i] : 0;
@@ -603,8 +627,10 @@ __global__ void __launch_bounds__(BLOCK) k_triangles(const int4 *__restrict__ at
                                                       long long *__restrict__ edge_min,
                                                       int *__restrict__ slab, int *__restrict__ block_tot,
                                                       const int *__restrict__ tri_start, int *__restrict__ tri_k,
-                                                      int *__restrict__ tri_e, Counters *cnt) {
+                                                      int *__restrict__ tri_e, Counters *cnt,
+                                                      const int *__restrict__ live = nullptr) {
     constexpr bool ONE = MODE == TRI_ONEPASS;
+    E = live_count(E, live);
     __shared__ int slot[ONE ? BLOCK * TRI_SLOT : 1];
     __shared__ int cand[BLOCK * TRI_SLOT];
     const int b = xcd_block();
@@ -666,7 +692,8 @@ __global__ void __launch_bounds__(BLOCK) k_triangles(const int4 *__restrict__ at
 __global__ void __launch_bounds__(BLOCK) k_tri_compact(const int *__restrict__ tri_cnt, int E,
                                                         const int *__restrict__ slab, const int *__restrict__ block_off,
                                                         int *__restrict__ tri_start, int *__restrict__ tri_k,
-                                                        int *__restrict__ tri_e) {
+                                                        int *__restrict__ tri_e, const int *__restrict__ live = nullptr) {
+    E = live_count(E, live);
     const int b = blockIdx.x;
     const int e = b * BLOCK + threadIdx.x;
     const int c = e < E ? tri_cnt[e] : 0;
@@ -776,8 +803,10 @@ __global__ void __launch_bounds__(BLOCK, 4) k_tet_candidates(const int4 *__restr
                                                            int *__restrict__ tet_cnt, int *__restrict__ slab,
                                                            int *__restrict__ block_tot,
                                                            const int *__restrict__ tet_start, int *__restrict__ tet_t,
-                                                           int *__restrict__ tet_l, Counters *cnt) {
+                                                           int *__restrict__ tet_l, Counters *cnt,
+                                                           const int *__restrict__ live = nullptr) {
     constexpr bool ONE = MODE == TET_ONEPASS;
+    T = live_count(T, live);
     __shared__ int slot[ONE ? BLOCK * TET_SLOT : 1];
     __shared__ int cand[BLOCK * TET_SLOT];
     const int b = xcd_block();
@@ -843,7 +872,9 @@ __global__ void __launch_bounds__(BLOCK, 4) k_tet_candidates(const int4 *__restr
 // Moves block b's slab of tetrahedron candidates to its final place.
 __global__ void __launch_bounds__(BLOCK) k_tet_compact(const int *__restrict__ tet_cnt, int T,
                                                         const int *__restrict__ slab, const int *__restrict__ block_off,
-                                                        int *__restrict__ tet_t, int *__restrict__ tet_l) {
+                                                        int *__restrict__ tet_t, int *__restrict__ tet_l,
+                                                        const int *__restrict__ live = nullptr) {
+    T = live_count(T, live);
     const int b = blockIdx.x;
     const int t = b * BLOCK + threadIdx.x;
     const int c = t < T ? tet_cnt[t] : 0;
@@ -912,9 +943,10 @@ __global__ void __launch_bounds__(BLOCK) k_tet_ac2(const int4 *__restrict__ atom
                                                     long long *__restrict__ tri_min,
                                                     unsigned char *__restrict__ qin, double *__restrict__ qsize,
                                                     int4 *__restrict__ tface, int n, unsigned *__restrict__ qkey,
-                                                    typename EmitPay<4>::type *__restrict__ qpay, Counters *cnt) {
+                                                    typename EmitPay<4>::type *__restrict__ qpay, Counters *cnt,
+                                                    const int *__restrict__ live = nullptr) {
     const int c = xcd_block() * BLOCK + threadIdx.x;
-    if (c >= Q) return;
+    if (c >= live_count(Q, live)) return;
     const int t = tet_t[c], l = tet_l[c];
     const int e = tri_e[t];
     const int i = edge_i[e], j = up[e], k = tri_k[t];
@@ -965,9 +997,10 @@ __global__ void __launch_bounds__(BLOCK) k_tri_final(const int *__restrict__ up_
                                                       const unsigned char *__restrict__ egab,
                                                       long long *__restrict__ edge_min, const int *__restrict__ perm,
                                                       int n, unsigned *__restrict__ tkey,
-                                                      typename EmitPay<3>::type *__restrict__ tpay, Counters *cnt) {
+                                                      typename EmitPay<3>::type *__restrict__ tpay, Counters *cnt,
+                                                      const int *__restrict__ live = nullptr) {
     const int t = xcd_block() * BLOCK + threadIdx.x;
-    if (t >= T) return;
+    if (t >= live_count(T, live)) return;
     const bool gab = tgab[t];
     const long long mn = gab ? ORDERED_POS_INF : tri_min[t];
     const bool in = gab || mn != ORDERED_POS_INF;
@@ -1007,9 +1040,10 @@ __global__ void __launch_bounds__(BLOCK) k_edge_final(const int4 *__restrict__ a
                                                        const unsigned char *__restrict__ vgab,
                                                        long long *__restrict__ vert_min, const int *__restrict__ perm,
                                                        int n, unsigned *__restrict__ ekey,
-                                                       typename EmitPay<2>::type *__restrict__ epay) {
+                                                       typename EmitPay<2>::type *__restrict__ epay,
+                                                       const int *__restrict__ live = nullptr) {
     const int e = xcd_block() * BLOCK + threadIdx.x;
-    if (e >= E) return;
+    if (e >= live_count(E, live)) return;
     const bool gab = egab[e];
     const long long mn = gab ? ORDERED_POS_INF : edge_min[e];
     const bool in = gab || mn != ORDERED_POS_INF;

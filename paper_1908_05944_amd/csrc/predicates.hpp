@@ -53,6 +53,10 @@ struct Counters {
     int Nn, E, T, Q;  // neighbour entries and candidate counts, copied from scan totals
     int m0, m1, m2, m3;
     int overflow;  // a single-pass stage ran out of its per-block room (then the two-pass path runs)
+    // recorded builds only (sizes fixed in advance): the live candidate
+    // counts the later launches read, and why the build stopped (0: it did not)
+    int El, Tl, Ql;
+    int stop;
 };
 
 __device__ __forceinline__ int sgn128(i128 v) { return (v > 0) - (v < 0); }

@@ -25,7 +25,9 @@ constexpr int RS_TILE = RS_BLOCK * RS_IPT;
 static_assert(RS_BINS == RS_BLOCK, "one histogram bin per thread");
 
 __global__ void __launch_bounds__(RS_BLOCK) k_rs_hist(const unsigned *__restrict__ keys, int n, int shift,
-                                                       int *__restrict__ hist, int tiles) {
+                                                       int *__restrict__ hist, int tiles,
+                                                       const int *__restrict__ live = nullptr) {
+    n = live_count(n, live);
     __shared__ int h[RS_BINS];
     h[threadIdx.x] = 0;
     __syncthreads();
@@ -83,7 +85,9 @@ template <class P>
 __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const unsigned *__restrict__ kin, const P *__restrict__ pin,
                                                           unsigned *__restrict__ kout, P *__restrict__ pout, int n,
                                                           int shift, const int *__restrict__ prefix,
-                                                          const int *__restrict__ totals, int tiles) {
+                                                          const int *__restrict__ totals, int tiles,
+                                                          const int *__restrict__ live = nullptr) {
+    n = live_count(n, live);
     constexpr int NW = RS_BLOCK / WAVE;
     constexpr int CHUNK = WAVE * RS_IPT;  // each wave owns a contiguous chunk of the tile
     __shared__ int gbase[RS_BINS];        // output start of each digit for this tile

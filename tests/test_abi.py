@@ -141,3 +141,29 @@ def test_measure_rejects_null_complex_without_device():
     V, A = ctypes.c_double(), ctypes.c_double()
     dummy = ctypes.c_void_p(16)
     assert lib.ac_union_measure(None, dummy, dummy, 1, ctypes.byref(V), ctypes.byref(A), None) == 1
+
+
+def test_plan_argument_checks_without_device():
+    """Argument errors of the recorded batch build are reported before any
+    device work; the plan accessors take NULL."""
+    import paper_1908_05944_amd as acx
+    lib = acx.library()
+    fake = ctypes.c_void_p(8)
+    off = (ctypes.c_int64 * 3)(0, 5, 10)
+    h = ctypes.c_void_p()
+    assert lib.ac_plan_create(fake, fake, off, 2, 0.0, None, None, 1.25, None, None) == 1
+    assert lib.ac_plan_create(None, None, off, 2, 0.0, None, None, 1.25, None, ctypes.byref(h)) == 1
+    assert lib.ac_plan_create(fake, fake, off, 2, 0.0, None, None, 0.5, None, ctypes.byref(h)) == 1
+    assert lib.ac_plan_create(fake, fake, off, 2, 0.0, None, None, 17.0, None, ctypes.byref(h)) == 1
+    assert lib.ac_plan_create(fake, fake, off, 2, float("inf"), None, None, 1.25, None, ctypes.byref(h)) == 1
+    bad = (ctypes.c_int64 * 3)(0, 5, 5)
+    assert lib.ac_plan_create(fake, fake, bad, 2, 0.0, None, None, 1.25, None, ctypes.byref(h)) == 1
+    o = acx.Options()
+    o.profile = 1
+    assert lib.ac_plan_create(fake, fake, off, 2, 0.0, ctypes.byref(o), None, 1.25, None, ctypes.byref(h)) == 1
+    assert not h
+    assert lib.ac_plan_launch(None, None) == 1
+    assert lib.ac_plan_result(None, None, ctypes.byref(h)) == 1
+    assert lib.ac_plan_stopped(None) == -1
+    assert lib.ac_plan_ordinary_builds(None) == -1
+    lib.ac_plan_free(None)
