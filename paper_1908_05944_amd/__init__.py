@@ -87,6 +87,8 @@ def _load():
     lib.ac_alpha_complex.restype = ctypes.c_int
     lib.ac_alpha_complex_device.argtypes = [c_p, c_p, i64, dbl, ctypes.POINTER(Options), c_p, ctypes.POINTER(c_p)]
     lib.ac_alpha_complex_device.restype = ctypes.c_int
+    lib.ac_alpha_complex_noalloc.argtypes = [c_p, c_p, i64, dbl, ctypes.POINTER(Options), c_p, c_p, c_p, c_p, c_p]
+    lib.ac_alpha_complex_noalloc.restype = ctypes.c_int
     lib.ac_plan_create.argtypes = [c_p, c_p, c_p, i64, dbl, ctypes.POINTER(Options), c_p, dbl, c_p,
                                    ctypes.POINTER(c_p)]
     lib.ac_plan_create.restype = ctypes.c_int
@@ -307,6 +309,56 @@ def ac_alpha_complex_device(xyz, radii, alpha: float, options=None, stream=None)
                                      ctypes.c_void_p(s.cuda_stream), ctypes.byref(h))
     _check(st)
     return AlphaComplex(h)
+
+
+class CapacityError(AlphaCxError):
+    """An output buffer of ac_alpha_complex_noalloc is smaller than the
+    result; `counts` holds the rows needed per dimension."""
+
+    def __init__(self, detail: str, counts):
+        super().__init__(6, detail)
+        self.counts = counts
+
+
+def ac_alpha_complex_noalloc(xyz, radii, alpha: float, simp_out, size_out, options=None, stream=None) -> list:
+    """As ac_alpha_complex_device, with no allocation by the library: its
+    buffers come from a fixed device scratch array, and the result goes into
+    the caller's tensors. simp_out[d]: contiguous int32 device tensor of shape
+    (capacity, d + 1); size_out[d]: contiguous float64 device tensor of
+    (capacity,) (d = 0..3). Returns the row counts [m0, m1, m2, m3]; rows
+    [:m_d] of the outputs hold the result. Nothing is copied or allocated
+    here: non-contiguous or mistyped tensors are refused. Raises
+    CapacityError (with .counts) when an output is too small."""
+    import torch
+    lib = _load()
+    for t in (xyz, radii, *simp_out, *size_out):
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("contiguous device tensors expected (no copy is made)")
+    if xyz.dtype != torch.float64 or radii.dtype != torch.float64:
+        raise ValueError("float64 inputs expected")
+    if xyz.dim() != 2 or xyz.shape[1] != 3 or radii.dim() != 1 or radii.shape[0] != xyz.shape[0]:
+        raise ValueError("xyz must be n x 3 and radii n")
+    if len(simp_out) != 4 or len(size_out) != 4:
+        raise ValueError("one output tensor per dimension 0..3")
+    cap = (ctypes.c_int64 * 4)()
+    sp = (ctypes.c_void_p * 4)()
+    zp = (ctypes.c_void_p * 4)()
+    for d in range(4):
+        a, z = simp_out[d], size_out[d]
+        if a.dtype != torch.int32 or a.dim() != 2 or a.shape[1] != d + 1:
+            raise ValueError(f"simp_out[{d}] must be int32 of shape (capacity, {d + 1})")
+        if z.dtype != torch.float64 or z.dim() != 1 or z.shape[0] != a.shape[0]:
+            raise ValueError(f"size_out[{d}] must be float64 of shape ({a.shape[0]},)")
+        cap[d] = a.shape[0]
+        sp[d] = a.data_ptr() if a.shape[0] else None
+        zp[d] = z.data_ptr() if a.shape[0] else None
+    counts = (ctypes.c_int64 * 4)()
+    st = lib.ac_alpha_complex_noalloc(xyz.data_ptr(), radii.data_ptr(), xyz.shape[0], float(alpha), _opts(options),
+                                      _stream(xyz.device, stream), sp, zp, cap, counts)
+    if st == 6 and min(counts) >= 0:
+        raise CapacityError(lib.ac_last_error().decode(errors="replace"), list(counts))
+    _check(st)
+    return list(counts)
 
 
 def ac_alpha_complex_partitioned(xyz, radii, alpha: float, parts: int, options=None, stream=None) -> AlphaComplex:

@@ -74,6 +74,17 @@ size_t size_class(size_t n) {
 }
 }  // namespace
 
+// Bump allocation from a caller-provided region instead of the pool, set for
+// the duration of one call on the calling thread (the no-allocation entry
+// point): every device buffer of the call, results included, then comes from
+// that region, and read-backs go to pageable memory, so the call makes no
+// allocation of its own.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0, peak = 0;
+};
+static thread_local Arena *t_arena = nullptr;
+
 // Allocations of a recorded build (ac_plan), kept for the plan's lifetime:
 // the first fixed run takes pool blocks and records them in order; the run
 // that is captured in a graph gets the same blocks back in the same order (its
@@ -87,6 +98,16 @@ struct Recorder {
 static thread_local Recorder *t_rec = nullptr;
 
 static void *dev_alloc(size_t n) {
+    if (Arena *a = t_arena) {
+        const size_t at = (a->used + 255) & ~(size_t)255;
+        if (n > a->cap || at > a->cap - n)
+            throw HipError{AC_E_CAPACITY, "the call needs more than the " + std::to_string(a->cap >> 20) +
+                                              " MiB of fixed scratch (" + std::to_string((at + n) >> 20) +
+                                              " MiB requested so far)"};
+        a->used = at + n;
+        a->peak = std::max(a->peak, a->used);
+        return a->base + at;
+    }
     if (Recorder *r = t_rec) {
         if (r->replay) {
             if (r->next >= r->blocks.size() || r->blocks[r->next].second < n)
@@ -139,6 +160,8 @@ static void *dev_alloc(size_t n) {
 
 static void dev_free(void *p) {
     if (!p) return;
+    if (const Arena *a = t_arena)
+        if (static_cast<char *>(p) >= a->base && static_cast<char *>(p) < a->base + a->cap) return;
     if (t_rec) return;  // recorded blocks belong to the plan
     Pool &P = pool();
     std::lock_guard<std::mutex> g(P.mu);
@@ -268,6 +291,12 @@ static void *pinned_block(size_t bytes) {
 template <class T>
 static void read_back(T *h, const T *d, size_t n, hipStream_t s) {
     if (n == 0) return;
+    if (t_arena) {
+        // no pinned block (that would be an allocation): pageable copy
+        HIP_TRY(hipMemcpyAsync(h, d, n * sizeof(T), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return;
+    }
     void *b = pinned_block(n * sizeof(T));
     HIP_TRY(hipMemcpyAsync(b, d, n * sizeof(T), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -2005,6 +2034,36 @@ static ac_status plan_result(ac_plan *p, hipStream_t s, ac_complex **out) {
 }
 
 // ---------------------------------------------------------------------------
+// Fixed device scratch of ac_alpha_complex_noalloc. Every device the library
+// runs on holds one copy of this array until the process ends. In host code
+// its name is only a stand-in: the device address of a device's copy comes
+// from hipGetSymbolAddress, taken once per device with that device current,
+// and only that address is handed to kernels and copies.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)AC_NOALLOC_SCRATCH_MIB << 20;
+// a ball needs more than this much scratch whatever the input (quantised and
+// sorted balls, sort keys, neighbour slots)
+constexpr size_t NOALLOC_MIN_BYTES_PER_BALL = 128;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu[NOALLOC_MAX_DEVICES];  // held for a whole call: one call per device at a time
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};  // device address of each device's copy, once known
+}  // namespace
+
+// Device address of the scratch array on device `dev` (the current device;
+// the caller holds g_scratch_mu[dev]).
+static char *scratch_on(int dev) {
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) throw HipError{AC_E_DEVICE, "hipGetSymbolAddress gave no address for the scratch array"};
+        g_scratch_ptr[dev] = p;
+    }
+    return static_cast<char *>(g_scratch_ptr[dev]);
+}
+
+// ---------------------------------------------------------------------------
 // C ABI
 extern "C" {
 
@@ -2021,6 +2080,80 @@ ac_status ac_alpha_complex_device(const double *d_xyz, const double *d_radii, in
     } catch (const HipError &e) {
         return set_error(e.st, e.msg);
     } catch (...) {
+        return set_error(AC_E_DEVICE, "unexpected host exception");
+    }
+}
+
+ac_status ac_alpha_complex_noalloc(const double *d_xyz, const double *d_radii, int64_t n, double alpha,
+                                   const ac_options *opt, void *stream, int32_t *const *d_simp,
+                                   double *const *d_size, const int64_t *capacity, int64_t *counts) {
+    if (!d_simp || !d_size || !capacity || !counts) return set_error(AC_E_INVALID, "NULL output argument");
+    for (int d = 0; d < 4; d++) counts[d] = -1;
+    ac_complex *c = nullptr;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int dev = -1;
+    try {
+        const Options o = parse(opt);
+        if (o.profile != 0) return set_error(AC_E_INVALID, "ac_options.profile must be 0 (profiling creates HIP events)");
+        if (!d_xyz || !d_radii) return set_error(AC_E_INVALID, "NULL input pointer");
+        if (n < 1 || n >= (1 << 26)) return set_error(AC_E_INVALID, "n must be in [1, 2^26)");
+        for (int d = 0; d < 4; d++) {
+            if (capacity[d] < 0) return set_error(AC_E_INVALID, "capacity must be >= 0");
+            if (capacity[d] > 0 && (!d_simp[d] || !d_size[d]))
+                return set_error(AC_E_INVALID, "NULL output buffer with a non-zero capacity");
+        }
+        if ((size_t)n > NOALLOC_SCRATCH_BYTES / NOALLOC_MIN_BYTES_PER_BALL)
+            return set_error(AC_E_CAPACITY, "n exceeds what the " + std::to_string(AC_NOALLOC_SCRATCH_MIB) +
+                                                " MiB of fixed scratch can hold");
+        HIP_TRY(hipGetDevice(&dev));
+        if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return set_error(AC_E_DEVICE, "device index out of range");
+    } catch (const HipError &e) {
+        return set_error(e.st, e.msg);
+    } catch (...) {
+        return set_error(AC_E_DEVICE, "unexpected host exception");
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu[dev]);
+    Arena ar;
+    struct ArenaOn {
+        explicit ArenaOn(Arena *a) { t_arena = a; }
+        ~ArenaOn() { t_arena = nullptr; }
+    };
+    try {
+        ar.base = scratch_on(dev);
+        ar.cap = NOALLOC_SCRATCH_BYTES;
+        const ArenaOn on(&ar);
+        Batch bt;
+        bt.off = {0, n};
+        const Options o = parse(opt);
+        const ac_status st = run_pipeline(d_xyz, d_radii, n, bt, alpha, o, s, &c);  // synchronises s on error
+        if (st != AC_OK) return st;
+        bool fits = true;
+        for (int d = 0; d < 4; d++) {
+            counts[d] = c->count[d];
+            fits = fits && c->count[d] <= capacity[d];
+        }
+        for (int d = 0; fits && d < 4; d++) {
+            const size_t m = (size_t)c->count[d];
+            if (m == 0) continue;
+            HIP_TRY(hipMemcpyAsync(d_simp[d], c->d_simp[d], m * (d + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(d_size[d], c->d_size[d], m * sizeof(double), hipMemcpyDeviceToDevice, s));
+        }
+        // the next call may reuse the scratch only once these copies are done
+        HIP_TRY(hipStreamSynchronize(s));
+        free_complex(c);  // host object only: its arrays lie in the scratch
+        c = nullptr;
+        if (!fits) return set_error(AC_E_CAPACITY, "an output buffer is smaller than the result (counts holds the sizes)");
+        g_last_error.clear();
+        return AC_OK;
+    } catch (const HipError &e) {
+        (void)hipStreamSynchronize(s);
+        if (c) {
+            const ArenaOn on(&ar);  // its arrays are scratch, not pool blocks
+            free_complex(c);
+        }
+        return set_error(e.st, e.msg);
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
         return set_error(AC_E_DEVICE, "unexpected host exception");
     }
 }

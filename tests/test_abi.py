@@ -143,6 +143,33 @@ def test_measure_rejects_null_complex_without_device():
     assert lib.ac_union_measure(None, dummy, dummy, 1, ctypes.byref(V), ctypes.byref(A), None) == 1
 
 
+def test_noalloc_argument_checks_without_device():
+    """Argument errors of the build without allocation are reported before
+    any device work (and before its scratch is touched)."""
+    import paper_1908_05944_amd as acx
+    lib = acx.library()
+    caps = (ctypes.c_int64 * 4)(10, 10, 10, 10)
+    ptrs = (ctypes.c_void_p * 4)(8, 8, 8, 8)  # never dereferenced: every call below fails its checks first
+    counts = (ctypes.c_int64 * 4)()
+    fake = ctypes.c_void_p(8)
+    assert lib.ac_alpha_complex_noalloc(fake, fake, 10, 0.0, None, None, None, ptrs, caps, counts) == 1
+    assert lib.ac_alpha_complex_noalloc(fake, fake, 10, 0.0, None, None, ptrs, ptrs, caps, None) == 1
+    assert lib.ac_alpha_complex_noalloc(None, None, 10, 0.0, None, None, ptrs, ptrs, caps, counts) == 1
+    assert list(counts) == [-1] * 4
+    o = acx.Options()
+    o.profile = 1
+    assert lib.ac_alpha_complex_noalloc(fake, fake, 10, 0.0, ctypes.byref(o), None, ptrs, ptrs, caps, counts) == 1
+    bad = (ctypes.c_int64 * 4)(10, -1, 10, 10)
+    assert lib.ac_alpha_complex_noalloc(fake, fake, 10, 0.0, None, None, ptrs, ptrs, bad, counts) == 1
+    nulls = (ctypes.c_void_p * 4)(8, None, 8, 8)
+    assert lib.ac_alpha_complex_noalloc(fake, fake, 10, 0.0, None, None, nulls, ptrs, caps, counts) == 1
+    assert lib.ac_alpha_complex_noalloc(fake, fake, 0, 0.0, None, None, ptrs, ptrs, caps, counts) == 1
+    # more balls than the fixed scratch can hold: refused up front
+    too_many = (256 << 20) // 128 + 1
+    assert lib.ac_alpha_complex_noalloc(fake, fake, too_many, 0.0, None, None, ptrs, ptrs, caps, counts) == 6
+    assert b"scratch" in lib.ac_last_error()
+
+
 def test_plan_argument_checks_without_device():
     """Argument errors of the recorded batch build are reported before any
     device work; the plan accessors take NULL."""
