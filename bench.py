@@ -27,11 +27,11 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 
 KERNEL_OF_STAGE = {
-    "neighbours_count": "k_neighbours<0, 16>",
+    "neighbours_count": "k_neighbours<0, 16, true>",
     "neighbours_fill": "k_nbr_compact<16>",
-    "triangles_count": "k_triangles<0>",
+    "triangles_count": "k_triangles<0, true>",
     "triangles_fill": "k_tri_compact",
-    "triangles_ac2_tetrahedra": "k_tet_candidates<0>",
+    "triangles_ac2_tetrahedra": "k_tet_candidates<0, true>",
     "tetrahedra_fill": "k_tet_compact",
     "tetrahedra_ac2": "k_tet_ac2",
     "triangles_final": "k_tri_final",
@@ -87,12 +87,12 @@ def measured_traffic_total():
     return sum(k["traffic_bytes"] * k["launches"] for k in rec["kernels"].values()) / rec["builds"]
 
 
-def measured_valu_issue(stage):
-    """Vector lane-operations per second of the stage's kernel over the issue
-    limit, from the SQ counters, or None."""
+def measured_valu_lane_ops(stage):
+    """Vector lane-operations per launch of the stage's kernel (VALU wave
+    instructions x 64, from the committed SQ counters), or None."""
     rec = _profile_record(VALU_FILE)
     k = None if rec is None else rec.get("kernels", {}).get(KERNEL_OF_STAGE.get(stage, stage))
-    return None if k is None else k.get("valu_tlane_ops_per_s") / VALU_ISSUE_PEAK_T
+    return None if k is None else k.get("valu_lane_ops_per_launch")
 
 
 def neighbour_pairs_tested(X, W, aq, cell_mA):
@@ -321,10 +321,23 @@ def bench_table2(acx, synth, torch, log, reps=5):
                 c.close()
             t_dev = _timed(torch, lambda: acx.ac_alpha_complex_device(X, R, alpha).close(), reps)
             t_host = _timed(torch, lambda: acx.ac_alpha_complex(m.xyz, m.radii, alpha).close(), reps)
+            # the same build recorded once and replayed as a HIP graph (no host
+            # synchronisation inside; the result stays in the plan's buffers)
+            try:
+                plan = acx.Plan(X, R, np.array([0, n]), alpha)
+            except acx.AlphaCxError:  # a stage needs the counted fill: no recorded build
+                plan = None
+            t_rec = None
+            if plan is not None:
+                plan.launch()
+                plan.result().close()
+                t_rec = _timed(torch, plan.launch, reps)
+                plan.close()
             med = {key: float(np.median([max(st[key], 0.0) for st in stages])) for key in stages[0]}
             cat = {name: sum(med[x] for x in parts) for name, parts in TABLE2_CATEGORIES.items()}
             cat["memory"] = max(t_host - t_dev, 0.0) * 1e3
             rows.append({"atoms": n, "alpha": alpha, "simplices": sum(counts), "device_ms": t_dev * 1e3,
+                         "recorded_replay_ms": None if t_rec is None else t_rec * 1e3,
                          "ms": {key: round(v, 4) for key, v in cat.items()}})
     est = ["potential_edges", "potential_triangles", "potential_tetrahedra"]
     pru = ["ac2_tetrahedra", "ac2_triangles", "ac2_edges_vertices"]  # Steps 2-5
@@ -333,7 +346,8 @@ def bench_table2(acx, synth, torch, log, reps=5):
                         ("ac2_tetrahedra", ["ac2_tetrahedra"]), ("output", ["output"])):
         share[name] = float(np.mean([sum(r["ms"][x] for x in parts) / sum(r["ms"].values()) for r in rows]))
     for r in rows:
-        log(f"[bench] table2: {r['atoms']:6d} atoms alpha {r['alpha']:.1f}: {r['device_ms']:.3f} ms device, "
+        log(f"[bench] table2: {r['atoms']:6d} atoms alpha {r['alpha']:.1f}: {r['device_ms']:.3f} ms device "
+            f"({r['recorded_replay_ms'] or float('nan'):.3f} ms as a graph replay), "
             + ", ".join(f"{key} {v:.3f}" for key, v in r["ms"].items()))
     log("[bench] table2 mean shares: " + ", ".join(f"{key} {v:.2f}" for key, v in share.items()))
     return {"rows": rows, "mean_share": share,
@@ -611,10 +625,11 @@ def main():
     t_dom = dom_ms * 1e-3
     b_dom, f_dom = alg_bytes[dom], alg_flops.get(dom, 0)
     traffic = measured_traffic(dom)
-    issue = measured_valu_issue(dom)
+    lane_ops = measured_valu_lane_ops(dom)
+    issue = None if lane_ops is None else lane_ops / t_dom / (VALU_ISSUE_PEAK_T * 1e12)
     hbm_meas = None if traffic is None else traffic / t_dom / (HBM_PEAK_GBS * 1e9)
     if issue is not None and hbm_meas is not None:
-        bound = "alu" if issue > hbm_meas and f_dom > 0 else "hbm"
+        bound = "alu" if issue > hbm_meas else "hbm"
         bound_from = f"counters: vector issue {issue:.2f} of its limit, HBM traffic {hbm_meas:.2f} of peak"
     else:
         bound = "alu" if f_dom / (FP64_VECTOR_PEAK_TFLOPS * 1e12) > b_dom / (HBM_PEAK_GBS * 1e9) else "hbm"
@@ -623,7 +638,11 @@ def main():
                 "frac": b_dom / t_dom / (HBM_PEAK_GBS * 1e9), "algorithmic_bytes": b_dom}
     fp64_view = {"achieved": f_dom / t_dom / 1e12, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                  "frac": f_dom / t_dom / (FP64_VECTOR_PEAK_TFLOPS * 1e12), "algorithmic_flops": f_dom}
-    main_view = fp64_view if bound == "alu" else hbm_view
+    # vector issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations/s
+    valu_view = None if lane_ops is None else {
+        "achieved": lane_ops / t_dom / 1e12, "peak": VALU_ISSUE_PEAK_T, "unit": "Tlane-op/s",
+        "frac": issue, "lane_ops_per_launch": lane_ops}
+    main_view = hbm_view if bound != "alu" else (valu_view if valu_view is not None else fp64_view)
     roofline = {
         "kernel": KERNEL_OF_STAGE.get(dom, dom),
         "bound": bound,
@@ -636,7 +655,7 @@ def main():
         "ms_per_launch": dom_ms,
         "hbm_view": hbm_view,
         "fp64_view": fp64_view,
-        "valu_issue_frac": issue,
+        "valu_view": valu_view,
     }
     # the whole build: max(B / HBM peak, F / float64 peak) over the step time
     t_step = ms_per_step * 1e-3

@@ -284,10 +284,11 @@ const int32_t *ac_molecule(ac_complex *c, int dim);
  * The molecules are put in size buckets ([0, 2k), [2k, 8k), [8k, 32k) and
  * [32k, inf) balls); for each bucket its molecules are copied into one
  * sub-batch and built with cell sides of 0.5, 0.7, 1, 1.4 and 2 times the
- * grown radius s_g (default 1 s_g), each timed twice by HIP events after a
- * warm-up run, and the fastest side is written to cell_mA_out[m] for every
- * molecule m of the bucket (and the bucket index to bucket_out[m] if not
- * NULL). Both are host arrays of n_mol. The cell side never changes the
+ * grown radius s_g (default 1 s_g); each side is timed by two HIP events
+ * around whole builds (the median of five, after a warm-up run), and the
+ * fastest side, if it beats the default by more than 3 % (else the default),
+ * is written to cell_mA_out[m] for every molecule m of the bucket (and the
+ * bucket index to bucket_out[m] if not NULL). Both are host arrays of n_mol. The cell side never changes the
  * result, only the time. Synchronises `stream`. */
 ac_status ac_tune_cells(const double *d_xyz, const double *d_radii, const int64_t *offsets, int64_t n_mol, double alpha,
                         const ac_options *opt, void *stream, int32_t *cell_mA_out, int32_t *bucket_out);

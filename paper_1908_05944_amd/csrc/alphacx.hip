@@ -344,10 +344,13 @@ struct Cands {
 // Stable LSD radix sort of (key, payload) on bits [lo, hi) of key, 8 bits per
 // pass. key / pay are set to the buffers that hold the result (the inputs' or
 // scratch of the scope); *spare_key / *spare_pay (if given) to two other
-// buffers of n entries.
+// buffers of n entries; *digit_tot (if given) to the per-digit counts of
+// the last pass (NULL if no pass ran).
 template <class P>
 static void radix_sort(unsigned *&key, P *&pay, int n, int lo, int hi, hipStream_t s, Scope &sc,
-                       unsigned **spare_key = nullptr, P **spare_pay = nullptr, const int *live = nullptr) {
+                       unsigned **spare_key = nullptr, P **spare_pay = nullptr, const int *live = nullptr,
+                       const int **digit_tot = nullptr) {
+    if (digit_tot) *digit_tot = nullptr;
     unsigned *k2 = sc.get<unsigned>(n > 0 ? n : 1);
     P *p2 = sc.get<P>(n > 0 ? n : 1);
     unsigned *kin = key, *kout = k2;
@@ -364,6 +367,7 @@ static void radix_sort(unsigned *&key, P *&pay, int n, int lo, int hi, hipStream
             std::swap(kin, kout);
             std::swap(pin, pout);
         }
+        if (digit_tot) *digit_tot = totals;
     }
     key = kin;
     pay = pin;
@@ -380,6 +384,22 @@ static int bits_for(long long n) {
     int b = 1;
     while ((1LL << b) < n) b++;
     return b;
+}
+
+// Emit keys for n balls: rows are keyed by their least input id (< n);
+// dropped candidates get `drop`, the first key of the coarse bucket (key >>
+// shift) after those of every id, which fits in `bits` key bits. The radix
+// pass sorts bits [shift, bits).
+struct EmitKeys {
+    int bits, shift;
+    unsigned drop;
+};
+static EmitKeys emit_keys(int n) {
+    EmitKeys k;
+    k.bits = bits_for((long long)n + 1 + (1 << 14));  // drop <= n + 2^shift < 2^bits
+    k.shift = std::min(std::max(k.bits - RS_BITS, 0), 14);
+    k.drop = (unsigned)((((long long)n >> k.shift) + 1) << k.shift);
+    return k;
 }
 
 // Emit dimension d = K - 1 from the candidates' keys (least input id; not
@@ -402,14 +422,16 @@ static void emit_dim(unsigned *key, typename EmitPay<K>::type *pay, const double
         fill<int>(m_out, M, 1, s);
     }
     if (M == 0) return;
-    const int bits = bits_for((long long)n + 1);
-    const int shift = std::min(std::max(bits - RS_BITS, 0), 14);
+    const EmitKeys ek = emit_keys(n);
     unsigned *gkey = nullptr;
     P *gpay = nullptr;
-    radix_sort<P>(key, pay, M, shift, bits, s, sc, &gkey, &gpay, live);
-    const unsigned blocks = (unsigned)(((long long)n + 1 + EB_KEYS - 1) / EB_KEYS);
-    k_emit_bucket<K><<<blocks, EB_BLOCK, 0, s>>>(key, pay, M, n, shift, gkey, gpay, size_in, to_A2 ? 1 : 0,
-                                                 res->d_simp[d], res->d_size[d], m_out, live);
+    const int *tot = nullptr;
+    radix_sort<P>(key, pay, M, ek.shift, ek.bits, s, sc, &gkey, &gpay, live, &tot);
+    // one pass: its digit is the coarse bucket, whose bounds its totals give
+    if (ek.bits - ek.shift > RS_BITS) tot = nullptr;
+    const unsigned blocks = (unsigned)std::max<long long>(((long long)n + EB_KEYS - 1) / EB_KEYS, 1);
+    k_emit_bucket<K><<<blocks, EB_BLOCK, 0, s>>>(key, pay, M, ek.drop, ek.shift, gkey, gpay, size_in, to_A2 ? 1 : 0,
+                                                 res->d_simp[d], res->d_size[d], m_out, tot, live);
     LAUNCH_CHECK();
 }
 
@@ -1002,19 +1024,20 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             if (Q > 0) {
                 k_tet_ac2<false><<<grid_for(Q), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i,
                                                               tri_start, tri_k, tri_e, tet_t, tet_l, Q, pp, tgab, tri_min,
-                                                              nullptr, qsize, nullptr, n, qkey, qpay, cnt, Q_live);
+                                                              nullptr, qsize, nullptr, emit_keys(n).drop, qkey, qpay, cnt,
+                                                              Q_live);
                 LAUNCH_CHECK();
             }
             tm.mark(ST_TRI_FINAL);
             if (T > 0) {
                 k_tri_final<<<grid_for(T), BLOCK, 0, s>>>(up_start, up, edge_i, tri_k, tri_e, T, tgab, tsize, tri_min, egab,
-                                                         edge_min, perm, n, tkey, tpay, cnt, T_live);
+                                                         edge_min, perm, emit_keys(n).drop, tkey, tpay, cnt, T_live);
                 LAUNCH_CHECK();
             }
             tm.mark(ST_EDGE_FINAL);
             if (E > 0) {
-                k_edge_final<<<grid_for(E), BLOCK, 0, s>>>(atom, up, edge_i, E, egab, edge_min, vgab, vert_min, perm, n,
-                                                          ekey, epay, E_live);
+                k_edge_final<<<grid_for(E), BLOCK, 0, s>>>(atom, up, edge_i, E, egab, edge_min, vgab, vert_min, perm,
+                                                          emit_keys(n).drop, ekey, epay, E_live);
                 LAUNCH_CHECK();
             }
             tm.mark(ST_VERT_FINAL);
@@ -1039,7 +1062,7 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             if (Q > 0) {
                 k_tet_ac2<true><<<grid_for(Q), BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i,
                                                              tri_start, tri_k, tri_e, tet_t, tet_l, Q, pp, tgab, nullptr,
-                                                             qin, qsize, tface, n, nullptr, nullptr, cnt);
+                                                             qin, qsize, tface, emit_keys(n).drop, nullptr, nullptr, cnt);
                 LAUNCH_CHECK();
             }
             int2 *tedge = sc.get<int2>(T > 0 ? T : 1);
@@ -1768,19 +1791,29 @@ static ac_status batch_from(const int64_t *offsets, int64_t n_mol, const int32_t
     return AC_OK;
 }
 
-// Device time of one pipeline run: the sum of its stage events (ms).
+// Time of one pipeline run on its stream (ms): two HIP events around the
+// whole run, so that the idle time of its host synchronisations counts and
+// no event between stages perturbs it.
 static ac_status timed_run(const double *x, const double *r, int64_t n, const Batch &bt, double alpha, Options o,
                            hipStream_t s, double *ms) {
-    o.profile = 1;
+    o.profile = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        throw HipError{AC_E_DEVICE, "hipEventCreate failed"};
+    }
     ac_complex *c = nullptr;
-    const ac_status st = run_pipeline(x, r, n, bt, alpha, o, s, &c);
-    if (st != AC_OK) return st;
-    double t = 0;
-    for (int i = 0; i < ST_COUNT; i++)
-        if (c->stage_ms[i] > 0) t += c->stage_ms[i];
+    ac_status st = hipEventRecord(e0, s) == hipSuccess ? run_pipeline(x, r, n, bt, alpha, o, s, &c) : AC_E_DEVICE;
+    float f = 0.f;
+    if (st == AC_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&f, e0, e1) != hipSuccess))
+        st = set_error(AC_E_DEVICE, "timing events failed");
     free_complex(c);
-    *ms = t;
-    return AC_OK;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = f;
+    return st;
 }
 
 // Options of a call, validated: every field has a documented range and a
@@ -2380,23 +2413,33 @@ ac_status ac_tune_cells(const double *d_xyz, const double *d_radii, const int64_
                                        hipMemcpyDeviceToDevice, s));
                 HIP_TRY(hipMemcpyAsync(r + sub.off[k], d_radii + all.off[m], nm * sizeof(double), hipMemcpyDeviceToDevice, s));
             }
-            double best_t = -1;
-            int32_t best = (int32_t)std::ceil(sg);
-            for (double f : kFactor) {
-                const int32_t side = std::max<int32_t>(1, (int32_t)std::lround(f * sg));
+            // each side: one warm-up run (fills the pool), then the median of
+            // kTuneReps timed runs; another side replaces the default s_g only
+            // when it is faster by more than kTuneMargin (run-to-run noise is a
+            // few per cent)
+            constexpr int kTuneReps = 5;
+            constexpr double kTuneMargin = 0.03;
+            std::vector<double> med(std::size(kFactor));
+            for (size_t fi = 0; fi < std::size(kFactor); fi++) {
+                const int32_t side = std::max<int32_t>(1, (int32_t)std::lround(kFactor[fi] * sg));
                 sub.cell_mA.assign(mols.size(), side);
-                double t = -1;
-                for (int rep = 0; rep < 3; rep++) {  // first run warms the pool
+                std::vector<double> ts;
+                for (int rep = 0; rep <= kTuneReps; rep++) {
                     double tr = 0;
                     st = timed_run(x, r, ns, sub, alpha, o, s, &tr);
                     if (st != AC_OK) return st;
-                    if (rep > 0 && (t < 0 || tr < t)) t = tr;
+                    if (rep > 0) ts.push_back(tr);
                 }
-                if (best_t < 0 || t < best_t) {
-                    best_t = t;
-                    best = side;
-                }
+                std::nth_element(ts.begin(), ts.begin() + ts.size() / 2, ts.end());
+                med[fi] = ts[ts.size() / 2];
             }
+            size_t def = 0;
+            while (kFactor[def] != 1.0) def++;
+            size_t bi = def;
+            for (size_t fi = 0; fi < med.size(); fi++)
+                if (med[fi] < med[bi]) bi = fi;
+            if (bi != def && med[bi] > (1.0 - kTuneMargin) * med[def]) bi = def;
+            const int32_t best = std::max<int32_t>(1, (int32_t)std::lround(kFactor[bi] * sg));
             for (int64_t m : mols) {
                 cell_mA_out[m] = best;
                 if (bucket_out) bucket_out[m] = b;

@@ -3,18 +3,22 @@
 // membership only).
 //
 // The pruning kernels key every candidate by the least input id of its row
-// (not kept: n, after every id) with the remaining ids and its Size (for a
-// tetrahedron: its candidate index) as payload. A stable LSD radix pass over
-// the high bits of the key (one 8-bit pass below 2^22 balls, two above)
-// groups the rows into coarse buckets; k_emit_bucket then finishes EB_KEYS
-// consecutive keys per block: the per-key counts by LDS atomics and their
-// scan give every key's place, each row is put in its key's group, and its
-// rank in the group by the remaining ids gives its final place. The rows of
-// one key are few (a ball's upper edges, triangles or tetrahedra), so the
-// rank is a short walk; no global atomics and no device-wide sort passes over
-// the low bits.
+// with the remaining ids and its Size (for a tetrahedron: its candidate
+// index) as payload; a candidate that is not kept gets the drop key, the
+// first key of the coarse bucket after every input id's. A stable LSD radix
+// pass over the high bits of the key (one 8-bit pass below 2^22 balls, two
+// above) groups the rows into coarse buckets, the dropped rows in one bucket
+// of their own at the end; k_emit_bucket then finishes EB_KEYS consecutive
+// keys per block: the per-key counts by LDS atomics and their scan give every
+// key's place, each row is put in its key's group, and its rank in the group
+// by the remaining ids gives its final place. The rows of one key are few (a
+// ball's upper edges, triangles or tetrahedra), so the rank is a short walk;
+// no global atomics, no device-wide sort passes over the low bits, and (above
+// 2^19 balls, where coarse buckets are whole multiples of a block's keys) no
+// block reads the dropped rows.
 #pragma once
 #include "common.hpp"
+#include "radix.hpp"
 
 namespace acx {
 
@@ -36,13 +40,13 @@ __device__ __forceinline__ double double_of(unsigned lo, unsigned hi) {
 
 // Key and payload of a candidate with input ids v[0..K) (any order): key =
 // least id, payload = the others ascending and `size` (K = 2, 3) or the
-// candidate index c (K = 4). Not kept: key n, empty payload.
+// candidate index c (K = 4). Not kept: the drop key, empty payload.
 template <int K>
-__device__ __forceinline__ void emit_pack(bool kept, int (&v)[4], double size, int c, int n, unsigned &key,
+__device__ __forceinline__ void emit_pack(bool kept, int (&v)[4], double size, int c, unsigned drop, unsigned &key,
                                           typename EmitPay<K>::type &pay) {
     pay = typename EmitPay<K>::type{};
     if (!kept) {
-        key = (unsigned)n;
+        key = drop;
         return;
     }
 #pragma unroll
@@ -62,15 +66,23 @@ __device__ __forceinline__ void emit_pack(bool kept, int (&v)[4], double size, i
     }
 }
 
+// Payloads held in registers as uint4 (a 12-byte uint3 in an array of a
+// batch ends up in scratch memory; uint4 stays in registers).
+__device__ __forceinline__ uint4 widen(const uint3 &q) { return make_uint4(q.x, q.y, q.z, 0u); }
+__device__ __forceinline__ uint4 widen(const uint4 &q) { return q; }
+template <class P> __device__ __forceinline__ P narrow(const uint4 &q);
+template <> __device__ __forceinline__ uint3 narrow<uint3>(const uint4 &q) { return make_uint3(q.x, q.y, q.z); }
+template <> __device__ __forceinline__ uint4 narrow<uint4>(const uint4 &q) { return q; }
+
 template <int K>
-__device__ __forceinline__ void pay_ids(const typename EmitPay<K>::type &q, unsigned (&r)[3]) {
+__device__ __forceinline__ void pay_ids(const uint4 &q, unsigned (&r)[3]) {
     if constexpr (K == 2) { r[0] = q.x; r[1] = 0; r[2] = 0; }
     else if constexpr (K == 3) { r[0] = q.x; r[1] = q.y; r[2] = 0; }
     else { r[0] = q.x; r[1] = q.y; r[2] = q.z; }
 }
 
 template <int K>
-__device__ __forceinline__ double pay_size(const typename EmitPay<K>::type &q, const double *__restrict__ size) {
+__device__ __forceinline__ double pay_size(const uint4 &q, const double *__restrict__ size) {
     if constexpr (K == 2) return double_of(q.y, q.z);
     else if constexpr (K == 3) return double_of(q.z, q.w);
     else return size[q.w];
@@ -89,43 +101,95 @@ __device__ __forceinline__ int coarse_lower_bound(const unsigned *__restrict__ k
 constexpr int EB_KEYS = 4096;   // keys finished by one block
 constexpr int EB_BLOCK = 512;
 constexpr int EB_PER_THREAD = EB_KEYS / EB_BLOCK;
+constexpr int EB_BATCH1 = 32;  // keys per thread loaded together in the counting sweep
+constexpr int EB_BATCH2 = 8;   // rows per thread loaded together in the placing sweep
+constexpr int EB_WIN = 2048;   // rows ranked together in LDS
 
 // Block b finishes the keys [b EB_KEYS, (b + 1) EB_KEYS) of key / pay (m rows
 // sorted by key >> shift), using gkey / gpay (m entries) as scratch, and
-// writes the kept rows (key < n) to out / out_size at their final places;
-// the block holding key n writes the kept count to *m_out (the host sets it
-// to m beforehand, for when every row is kept). Sizes are converted from
-// mA^2 to A^2 when to_A2 is set (emit of a build), else copied (merge of
-// rows that are already output).
+// writes the kept rows (key < drop) to out / out_size at their final places;
+// the last block writes the kept count to *m_out. The grid covers the input
+// ids, so every block's first key lies below the drop key, whose coarse
+// bucket follows all others. Sizes are converted from mA^2 to A^2 when to_A2
+// is set (emit of a build), else copied (merge of rows that are already
+// output).
 template <int K>
 __global__ void __launch_bounds__(EB_BLOCK) k_emit_bucket(const unsigned *__restrict__ key,
                                                            const typename EmitPay<K>::type *__restrict__ pay, int m,
-                                                           int n, int shift, unsigned *__restrict__ gkey,
+                                                           unsigned drop, int shift, unsigned *__restrict__ gkey,
                                                            typename EmitPay<K>::type *__restrict__ gpay,
                                                            const double *__restrict__ size_in, int to_A2,
                                                            int *__restrict__ out, double *__restrict__ out_size,
-                                                           int *__restrict__ m_out, const int *__restrict__ live = nullptr) {
+                                                           int *__restrict__ m_out, const int *__restrict__ digit_tot,
+                                                           const int *__restrict__ live = nullptr) {
     typedef typename EmitPay<K>::type P;
     m = live_count(m, live);
     __shared__ int cnt[EB_KEYS];  // per-key counts, then each key's first place in the block's range
-    __shared__ int cur[EB_KEYS];  // placement cursors
+    // placement cursors (int[EB_KEYS]) in sweeps 1-2, then the window of rows
+    // ranked in LDS in sweep 3
+    __shared__ uint4 sh[EB_WIN];
+    static_assert(sizeof(uint4) * EB_WIN >= sizeof(int) * EB_KEYS, "the cursors fit in the row window");
+    int *const cur = reinterpret_cast<int *>(sh);
     __shared__ int wsum[EB_BLOCK / WAVE];
     __shared__ int below_s;
     const long long k0 = (long long)blockIdx.x * EB_KEYS;
     const int t = threadIdx.x;
-    // the rows of the coarse buckets that hold this block's keys
-    const int bs = coarse_lower_bound(key, m, shift, k0 >> shift);
-    const int be = coarse_lower_bound(key, m, shift, ((k0 + EB_KEYS - 1) >> shift) + 1);
+    // the rows of the coarse buckets that hold this block's keys: from the
+    // digit totals of a single radix pass (the coarse bucket is the digit),
+    // else by binary search
+    const int c_lo = (int)(k0 >> shift), c_hi = (int)((k0 + EB_KEYS - 1) >> shift) + 1;
+    int bs, be;
+    if (digit_tot) {
+        __shared__ int part[2][EB_BLOCK / WAVE];
+        int a = 0, b = 0;
+        if (t < RS_BINS) {
+            const int v = digit_tot[t];
+            a = t < c_lo ? v : 0;
+            b = t < c_hi ? v : 0;
+        }
+        for (int off = WAVE / 2; off > 0; off >>= 1) {
+            a += __shfl_down(a, off, WAVE);
+            b += __shfl_down(b, off, WAVE);
+        }
+        if (lane_id() == 0) {
+            part[0][t / WAVE] = a;
+            part[1][t / WAVE] = b;
+        }
+        __syncthreads();
+        bs = 0;
+        be = 0;
+#pragma unroll
+        for (int w = 0; w < EB_BLOCK / WAVE; w++) {
+            bs += part[0][w];
+            be += part[1][w];
+        }
+    } else {
+        bs = coarse_lower_bound(key, m, shift, c_lo);
+        be = coarse_lower_bound(key, m, shift, c_hi);
+    }
 #pragma unroll
     for (int u = 0; u < EB_PER_THREAD; u++) cnt[u * EB_BLOCK + t] = 0;
     if (t == 0) below_s = 0;
     __syncthreads();
-    // sweep 1: counts per key; rows of the buckets with keys below this block's
+    // sweep 1: counts per key; rows of the buckets with keys below this block's.
+    // The sweeps load a batch of entries per thread before using any (one
+    // latency per batch, not per entry); keys are below 2^31, and a slot past
+    // the range holds 0xffffffff, which no test takes.
+    const unsigned ku0 = (unsigned)k0, ku1 = (unsigned)min(k0 + EB_KEYS, (long long)drop);
     int below = 0;
-    for (int e = bs + t; e < be; e += EB_BLOCK) {
-        const long long kk = key[e];
-        if (kk < k0) below++;
-        else if (kk < k0 + EB_KEYS) atomicAdd(&cnt[kk - k0], 1);
+    for (int e0 = bs + t; e0 < be; e0 += EB_BLOCK * EB_BATCH1) {
+        unsigned kb[EB_BATCH1];
+#pragma unroll
+        for (int u = 0; u < EB_BATCH1; u++) {
+            const int e = e0 + u * EB_BLOCK;
+            kb[u] = e < be ? key[e] : 0xffffffffu;
+        }
+#pragma unroll
+        for (int u = 0; u < EB_BATCH1; u++) {
+            const unsigned kk = kb[u];
+            if (kk < ku0) below++;  // kept: k0 < drop
+            else if (kk < ku1) atomicAdd(&cnt[kk - ku0], 1);
+        }
     }
     for (int off = WAVE / 2; off > 0; off >>= 1) below += __shfl_down(below, off, WAVE);
     if (lane_id() == 0 && below) atomicAdd(&below_s, below);
@@ -154,41 +218,70 @@ __global__ void __launch_bounds__(EB_BLOCK) k_emit_bucket(const unsigned *__rest
     }
     __syncthreads();
     const int gs = bs + below_s;  // global place of the block's first row
-    // the kept rows of the range end where key n starts (if n is in it)
-    const bool has_n = (long long)n >= k0 && (long long)n < k0 + EB_KEYS;
-    const int kept_end = has_n ? cnt[n - k0] : total;
-    if (has_n && t == 0) *m_out = gs + kept_end;
+    const int kept_end = total;
+    if (blockIdx.x == gridDim.x - 1 && t == 0) *m_out = coarse_lower_bound(key, m, shift, (long long)(drop >> shift));
     // sweep 2: every kept row into its key's group (order inside a group is
     // the atomics' order; the rank below fixes it)
-    for (int e = bs + t; e < be; e += EB_BLOCK) {
-        const long long kk = key[e];
-        if (kk < k0 || kk >= k0 + EB_KEYS || kk >= n) continue;
-        const int p = atomicAdd(&cur[kk - k0], 1);
-        gkey[gs + p] = (unsigned)kk;
-        gpay[gs + p] = pay[e];
+    for (int e0 = bs + t; e0 < be; e0 += EB_BLOCK * EB_BATCH2) {
+        unsigned kb[EB_BATCH2];
+        uint4 pb[EB_BATCH2];
+#pragma unroll
+        for (int u = 0; u < EB_BATCH2; u++) {
+            const int e = e0 + u * EB_BLOCK;
+            kb[u] = e < be ? key[e] : 0xffffffffu;
+        }
+#pragma unroll
+        for (int u = 0; u < EB_BATCH2; u++) {
+            const bool mine = kb[u] >= ku0 && kb[u] < ku1;
+            pb[u] = mine ? widen(pay[e0 + u * EB_BLOCK]) : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int u = 0; u < EB_BATCH2; u++) {
+            const unsigned kk = kb[u];
+            if (kk < ku0 || kk >= ku1) continue;
+            const int p = atomicAdd(&cur[kk - ku0], 1);
+            gkey[gs + p] = kk;
+            gpay[gs + p] = narrow<P>(pb[u]);
+        }
     }
     __syncthreads();
-    // sweep 3: rank inside the group by the remaining ids, then the final write
-    for (int p = t; p < kept_end; p += EB_BLOCK) {
-        const unsigned kk = gkey[gs + p];
-        const int loc = (int)(kk - k0);
-        const int g0 = cnt[loc], g1 = loc + 1 < EB_KEYS ? cnt[loc + 1] : total;
-        const P me = gpay[gs + p];
-        unsigned r[3];
-        pay_ids<K>(me, r);
-        int rank = 0;
-        for (int q = g0; q < g1; q++) {
-            if (q == p) continue;
-            unsigned o[3];
-            pay_ids<K>(gpay[gs + q], o);
-            rank += o[0] != r[0] ? o[0] < r[0] : (o[1] != r[1] ? o[1] < r[1] : o[2] < r[2]);
+    // sweep 3: rank inside the group by the remaining ids, then the final
+    // write. The placed rows go through LDS in windows of at most EB_WIN rows
+    // that end at a group boundary, so each rank walk reads its group from
+    // LDS (a group longer than a window, which the keys here never have, is
+    // cut and its rows beyond the window read from global memory).
+    for (int w0 = 0; w0 < kept_end;) {
+        int w1 = min(w0 + EB_WIN, kept_end);
+        if (w1 < kept_end) {
+            const int gb = cnt[gkey[gs + w1] - k0];  // start of the group holding row w1
+            if (gb > w0) w1 = gb;
         }
-        const long long pos = (long long)gs + g0 + rank;
-        out[pos * K] = (int)kk;
+        __syncthreads();  // the previous window is done with sh (and sweep 2 with the cursors)
+        for (int p = w0 + t; p < w1; p += EB_BLOCK) sh[p - w0] = widen(gpay[gs + p]);
+        __syncthreads();
+        for (int p = w0 + t; p < w1; p += EB_BLOCK) {
+            const unsigned kk = gkey[gs + p];
+            const int loc = (int)(kk - k0);
+            const int g0 = cnt[loc], g1 = loc + 1 < EB_KEYS ? cnt[loc + 1] : total;
+            const uint4 me = sh[p - w0];
+            unsigned r[3];
+            pay_ids<K>(me, r);
+            int rank = 0;
+            for (int q = g0; q < g1; q++) {
+                if (q == p) continue;
+                const uint4 o = q >= w0 && q < w1 ? sh[q - w0] : widen(gpay[gs + q]);
+                unsigned v[3];
+                pay_ids<K>(o, v);
+                rank += v[0] != r[0] ? v[0] < r[0] : (v[1] != r[1] ? v[1] < r[1] : v[2] < r[2]);
+            }
+            const long long pos = (long long)gs + g0 + rank;
+            out[pos * K] = (int)kk;
 #pragma unroll
-        for (int u = 1; u < K; u++) out[pos * K + u] = (int)r[u - 1];
-        const double z = pay_size<K>(me, size_in);
-        out_size[pos] = to_A2 ? z / 1.0e6 : z;
+            for (int c = 1; c < K; c++) out[pos * K + c] = (int)r[c - 1];
+            const double z = pay_size<K>(me, size_in);
+            out_size[pos] = to_A2 ? z / 1.0e6 : z;
+        }
+        w0 = w1;
     }
 }
 

@@ -928,7 +928,7 @@ __device__ __forceinline__ void mark_face(const unsigned char *gab, long long *m
 
 // Tetrahedra (Step 2): kept iff no ball is strictly closer in power to the
 // ortho-centre; a kept tetrahedron records itself on its facets (Step 3) and
-// gets its emit key and payload (input ids; not kept: key n).
+// gets its emit key and payload (input ids; not kept: the drop key).
 // SWEEP (candidates of several alpha values): qin holds AC2 alone, and the
 // facet ids go to tface for the per-alpha passes instead of being marked.
 template <bool SWEEP>
@@ -942,7 +942,7 @@ __global__ void __launch_bounds__(BLOCK) k_tet_ac2(const int4 *__restrict__ atom
                                                     PredParams pp, const unsigned char *__restrict__ tgab,
                                                     long long *__restrict__ tri_min,
                                                     unsigned char *__restrict__ qin, double *__restrict__ qsize,
-                                                    int4 *__restrict__ tface, int n, unsigned *__restrict__ qkey,
+                                                    int4 *__restrict__ tface, unsigned drop, unsigned *__restrict__ qkey,
                                                     typename EmitPay<4>::type *__restrict__ qpay, Counters *cnt,
                                                     const int *__restrict__ live = nullptr) {
     const int c = xcd_block() * BLOCK + threadIdx.x;
@@ -962,7 +962,7 @@ __global__ void __launch_bounds__(BLOCK) k_tet_ac2(const int4 *__restrict__ atom
     if (!keep) {
         if (!SWEEP) {
             int v[4] = {0, 0, 0, 0};
-            emit_pack<4>(false, v, 0.0, c, n, qkey[c], qpay[c]);
+            emit_pack<4>(false, v, 0.0, c, drop, qkey[c], qpay[c]);
         }
         return;
     }
@@ -976,7 +976,7 @@ __global__ void __launch_bounds__(BLOCK) k_tet_ac2(const int4 *__restrict__ atom
         return;
     }
     int v[4] = {perm[i], perm[j], perm[k], perm[l]};
-    emit_pack<4>(true, v, sz, c, n, qkey[c], qpay[c]);
+    emit_pack<4>(true, v, sz, c, drop, qkey[c], qpay[c]);
     const long long key = ordered_from_double(sz);
     mark_face(tgab, tri_min, t, key, cnt);
     mark_face(tgab, tri_min, f1, key, cnt);
@@ -987,7 +987,7 @@ __global__ void __launch_bounds__(BLOCK) k_tet_ac2(const int4 *__restrict__ atom
 // Triangles (Step 3): kept iff AC2 holds at the ortho-centre or a kept
 // tetrahedron has it as a facet; Size is then the OrthoSize or the least Size
 // of a kept tetrahedron. Kept triangles record themselves on their edges;
-// every triangle gets its emit key and payload (not kept: key n).
+// every triangle gets its emit key and payload (not kept: the drop key).
 __global__ void __launch_bounds__(BLOCK) k_tri_final(const int *__restrict__ up_start, const int *__restrict__ up,
                                                       const int *__restrict__ edge_i, const int *__restrict__ tri_k,
                                                       const int *__restrict__ tri_e, int T,
@@ -996,7 +996,7 @@ __global__ void __launch_bounds__(BLOCK) k_tri_final(const int *__restrict__ up_
                                                       const long long *__restrict__ tri_min,
                                                       const unsigned char *__restrict__ egab,
                                                       long long *__restrict__ edge_min, const int *__restrict__ perm,
-                                                      int n, unsigned *__restrict__ tkey,
+                                                      unsigned drop, unsigned *__restrict__ tkey,
                                                       typename EmitPay<3>::type *__restrict__ tpay, Counters *cnt,
                                                       const int *__restrict__ live = nullptr) {
     const int t = xcd_block() * BLOCK + threadIdx.x;
@@ -1006,14 +1006,14 @@ __global__ void __launch_bounds__(BLOCK) k_tri_final(const int *__restrict__ up_
     const bool in = gab || mn != ORDERED_POS_INF;
     int v[4] = {0, 0, 0, 0};
     if (!in) {
-        emit_pack<3>(false, v, 0.0, t, n, tkey[t], tpay[t]);
+        emit_pack<3>(false, v, 0.0, t, drop, tkey[t], tpay[t]);
         return;
     }
     const double sz = gab ? tsize[t] : double_from_ordered(mn);
     const int e = tri_e[t];
     const int i = edge_i[e], j = up[e], k = tri_k[t];
     v[0] = perm[i]; v[1] = perm[j]; v[2] = perm[k];
-    emit_pack<3>(true, v, sz, t, n, tkey[t], tpay[t]);
+    emit_pack<3>(true, v, sz, t, drop, tkey[t], tpay[t]);
     const long long key = ordered_from_double(sz);
     mark_face(egab, edge_min, e, key, cnt);
     mark_face(egab, edge_min, find_edge(up_start, up, i, k), key, cnt);
@@ -1032,14 +1032,14 @@ __global__ void __launch_bounds__(BLOCK) k_tri_edges(const int *__restrict__ up_
     tedge[t] = make_int2(find_edge(up_start, up, i, k), find_edge(up_start, up, j, k));
 }
 
-// Edges (Step 4), with their emit keys and payloads (not kept: key n).
+// Edges (Step 4), with their emit keys and payloads (not kept: the drop key).
 __global__ void __launch_bounds__(BLOCK) k_edge_final(const int4 *__restrict__ atom, const int *__restrict__ up,
                                                        const int *__restrict__ edge_i, int E,
                                                        const unsigned char *__restrict__ egab,
                                                        const long long *__restrict__ edge_min,
                                                        const unsigned char *__restrict__ vgab,
                                                        long long *__restrict__ vert_min, const int *__restrict__ perm,
-                                                       int n, unsigned *__restrict__ ekey,
+                                                       unsigned drop, unsigned *__restrict__ ekey,
                                                        typename EmitPay<2>::type *__restrict__ epay,
                                                        const int *__restrict__ live = nullptr) {
     const int e = xcd_block() * BLOCK + threadIdx.x;
@@ -1049,13 +1049,13 @@ __global__ void __launch_bounds__(BLOCK) k_edge_final(const int4 *__restrict__ a
     const bool in = gab || mn != ORDERED_POS_INF;
     int v[4] = {0, 0, 0, 0};
     if (!in) {
-        emit_pack<2>(false, v, 0.0, e, n, ekey[e], epay[e]);
+        emit_pack<2>(false, v, 0.0, e, drop, ekey[e], epay[e]);
         return;
     }
     const int i = edge_i[e], j = up[e];
     const double sz = gab ? edge_size_canon(atom[i], atom[j]) : double_from_ordered(mn);
     v[0] = perm[i]; v[1] = perm[j];
-    emit_pack<2>(true, v, sz, e, n, ekey[e], epay[e]);
+    emit_pack<2>(true, v, sz, e, drop, ekey[e], epay[e]);
     const long long key = ordered_from_double(sz);
     if (!vgab[i]) atomicMin(&vert_min[i], key);
     if (!vgab[j]) atomicMin(&vert_min[j], key);

@@ -25,6 +25,12 @@
 // exact int64 and d = 2, 3 use a floating-point filter with a static error
 // bound and an exact __int128 fallback. The bounds allow for fused
 // multiply-add contraction (a contracted a*b+c rounds once instead of twice).
+// The exact integers the filters start from are formed in the cheapest exact
+// way: products of two coordinate differences (below 2^28) as 24-bit
+// multiplies (full rate; a 32-bit multiply issues at a quarter of that), and
+// products of a difference with a cross-product component (below 2^43) as
+// float64 products, which are exact below 2^53; the values, and so every
+// filter decision, are those of the plain integer formulas.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -45,6 +51,9 @@ struct PredParams {
     i64 sgc;       // ceil(sqrt(sg2))
     int force_exact;
 };
+
+// a * b for |a|, |b| < 2^23 and |a b| < 2^31 (exact)
+__device__ __forceinline__ int m24(int a, int b) { return __mul24(a, b); }
 
 struct Counters {
     unsigned long long exact_fallbacks;
@@ -85,7 +94,7 @@ __device__ __forceinline__ void note_fallback(Counters *cnt) { atomicAdd(&cnt->e
 // from neighbour lists, so |b| <= 2 sqrt(sg2) < 2^14 and P fits in int32.
 __device__ __forceinline__ int vertex_violation_sign(int4 v, int sv, int4 q, int sq, const int *perm) {
     const int bx = q.x - v.x, by = q.y - v.y, bz = q.z - v.z;
-    const int P = bx * bx + by * by + bz * bz - q.w + v.w;
+    const int P = m24(bx, bx) + m24(by, by) + m24(bz, bz) - q.w + v.w;
     if (P) return P > 0 ? 1 : -1;
     // partials: W_q -> -1, W_v -> +1
     return perm[sq] < perm[sv] ? -1 : 1;
@@ -103,7 +112,7 @@ __device__ __forceinline__ Edge edge_setup(int4 v0, int4 v1) {
     Edge e;
     e.v0 = v0;
     e.ax = v1.x - v0.x; e.ay = v1.y - v0.y; e.az = v1.z - v0.z;
-    e.den = e.ax * e.ax + e.ay * e.ay + e.az * e.az;
+    e.den = m24(e.ax, e.ax) + m24(e.ay, e.ay) + m24(e.az, e.az);
     e.beta = e.den - v1.w + v0.w;
     return e;
 }
@@ -124,8 +133,8 @@ __device__ __forceinline__ double edge_orthosize(const Edge &e) {
 // rounding bound certifies it, 0 when the exact path has to decide.
 __device__ __forceinline__ int edge_violation_filter(const Edge &e, int4 q) {
     const int bx = q.x - e.v0.x, by = q.y - e.v0.y, bz = q.z - e.v0.z;
-    const int gam = bx * bx + by * by + bz * bz - q.w + e.v0.w;
-    const int t = e.ax * bx + e.ay * by + e.az * bz;
+    const int gam = m24(bx, bx) + m24(by, by) + m24(bz, bz) - q.w + e.v0.w;
+    const int t = m24(e.ax, bx) + m24(e.ay, by) + m24(e.az, bz);
     const double p1 = (double)e.den * (double)gam, p2 = (double)e.beta * (double)t;
     const double P = p1 - p2;
     const double eb = 4.0 * ACX_U * (fabs(p1) + fabs(p2));
@@ -136,8 +145,8 @@ __device__ __forceinline__ int edge_violation_filter(const Edge &e, int4 q) {
 __device__ __forceinline__ int edge_violation_sign(const Edge &e, int s0, int s1, int4 q, int sq, const int *perm,
                                                    int force_exact) {
     const int bx = q.x - e.v0.x, by = q.y - e.v0.y, bz = q.z - e.v0.z;
-    const int gam = bx * bx + by * by + bz * bz - q.w + e.v0.w;
-    const int t = e.ax * bx + e.ay * by + e.az * bz;
+    const int gam = m24(bx, bx) + m24(by, by) + m24(bz, bz) - q.w + e.v0.w;
+    const int t = m24(e.ax, bx) + m24(e.ay, by) + m24(e.az, bz);
     if (!force_exact) {
         const double p1 = (double)e.den * (double)gam, p2 = (double)e.beta * (double)t;
         const double P = p1 - p2;
@@ -156,81 +165,64 @@ __device__ __forceinline__ int edge_violation_sign(const Edge &e, int s0, int s1
 // Triangle (d = 2).
 struct Tri {
     int4 v0;
-    i64 a1x, a1y, a1z, a2x, a2y, a2z;
-    i64 nx, ny, nz;          // a1 x a2
-    i64 ux, uy, uz;          // a2 x n
-    i64 wx, wy, wz;          // n x a1
-    i64 b1, b2, den;         // beta1, beta2, |n|^2
+    int nx, ny, nz;          // n = a1 x a2 (components below 2^29)
+    double ux, uy, uz;       // a2 x n (exact integers below 2^44)
+    double wx, wy, wz;       // n x a1
+    int b1, b2;              // beta1, beta2
+    i64 den;                 // |n|^2
     double Mx, My, Mz;       // b1 u + b2 w (rounded)
     double eP;               // filter bound for AC2
 };
 
+// a * c - b * d for exact integer products below 2^53 (the result too): exact
+__device__ __forceinline__ double cross_d(int a, int c, int b, int d) {
+    return (double)a * (double)c - (double)b * (double)d;
+}
+
 __device__ __forceinline__ Tri tri_setup(int4 v0, int4 v1, int4 v2, const PredParams &pp) {
     Tri t;
     t.v0 = v0;
-    t.a1x = v1.x - v0.x; t.a1y = v1.y - v0.y; t.a1z = v1.z - v0.z;
-    t.a2x = v2.x - v0.x; t.a2y = v2.y - v0.y; t.a2z = v2.z - v0.z;
-    t.nx = t.a1y * t.a2z - t.a1z * t.a2y;
-    t.ny = t.a1z * t.a2x - t.a1x * t.a2z;
-    t.nz = t.a1x * t.a2y - t.a1y * t.a2x;
-    t.ux = t.a2y * t.nz - t.a2z * t.ny;
-    t.uy = t.a2z * t.nx - t.a2x * t.nz;
-    t.uz = t.a2x * t.ny - t.a2y * t.nx;
-    t.wx = t.ny * t.a1z - t.nz * t.a1y;
-    t.wy = t.nz * t.a1x - t.nx * t.a1z;
-    t.wz = t.nx * t.a1y - t.ny * t.a1x;
-    t.b1 = t.a1x * t.a1x + t.a1y * t.a1y + t.a1z * t.a1z - v1.w + v0.w;
-    t.b2 = t.a2x * t.a2x + t.a2y * t.a2y + t.a2z * t.a2z - v2.w + v0.w;
-    t.den = t.nx * t.nx + t.ny * t.ny + t.nz * t.nz;
+    const int a1x = v1.x - v0.x, a1y = v1.y - v0.y, a1z = v1.z - v0.z;
+    const int a2x = v2.x - v0.x, a2y = v2.y - v0.y, a2z = v2.z - v0.z;
+    t.nx = m24(a1y, a2z) - m24(a1z, a2y);
+    t.ny = m24(a1z, a2x) - m24(a1x, a2z);
+    t.nz = m24(a1x, a2y) - m24(a1y, a2x);
+    t.ux = cross_d(a2y, t.nz, a2z, t.ny);
+    t.uy = cross_d(a2z, t.nx, a2x, t.nz);
+    t.uz = cross_d(a2x, t.ny, a2y, t.nx);
+    t.wx = cross_d(t.ny, a1z, t.nz, a1y);
+    t.wy = cross_d(t.nz, a1x, t.nx, a1z);
+    t.wz = cross_d(t.nx, a1y, t.ny, a1x);
+    t.b1 = m24(a1x, a1x) + m24(a1y, a1y) + m24(a1z, a1z) - v1.w + v0.w;
+    t.b2 = m24(a2x, a2x) + m24(a2y, a2y) + m24(a2z, a2z) - v2.w + v0.w;
+    t.den = (i64)t.nx * t.nx + (i64)t.ny * t.ny + (i64)t.nz * t.nz;
     const double b1 = (double)t.b1, b2 = (double)t.b2;
-    t.Mx = b1 * (double)t.ux + b2 * (double)t.wx;
-    t.My = b1 * (double)t.uy + b2 * (double)t.wy;
-    t.Mz = b1 * (double)t.uz + b2 * (double)t.wz;
+    t.Mx = b1 * t.ux + b2 * t.wx;
+    t.My = b1 * t.uy + b2 * t.wy;
+    t.Mz = b1 * t.uz + b2 * t.wz;
     const double ab1 = fabs(b1), ab2 = fabs(b2);
-    const double Mabs = ab1 * (fabs((double)t.ux) + fabs((double)t.uy) + fabs((double)t.uz)) +
-                        ab2 * (fabs((double)t.wx) + fabs((double)t.wy) + fabs((double)t.wz));
+    const double Mabs = ab1 * (fabs(t.ux) + fabs(t.uy) + fabs(t.uz)) + ab2 * (fabs(t.wx) + fabs(t.wy) + fabs(t.wz));
     t.eP = 16.0 * ACX_U * ((double)t.den * pp.gmax + pp.bmax * Mabs);
     return t;
 }
 
 __device__ __forceinline__ bool tri_degenerate(const Tri &t) { return t.nx == 0 && t.ny == 0 && t.nz == 0; }
 
-// AC3 for a triangle in Gram form: beta^T adj(G) beta <= 4 det(G) (W0 + alpha),
-// G the Gram matrix of (a1, a2) and det(G) = |n|^2.
-__device__ __forceinline__ bool tri_ac3(const Tri &t, const PredParams &pp, Counters *cnt) {
-    const i64 g11 = t.a1x * t.a1x + t.a1y * t.a1y + t.a1z * t.a1z;
-    const i64 g12 = t.a1x * t.a2x + t.a1y * t.a2y + t.a1z * t.a2z;
-    const i64 g22 = t.a2x * t.a2x + t.a2y * t.a2y + t.a2z * t.a2z;
-    const i64 wa = t.v0.w + pp.aq;
-    if (!pp.force_exact) {
-        const double b1 = (double)t.b1, b2 = (double)t.b2;
-        const double q1 = (double)g22 * (b1 * b1), q2 = 2.0 * (double)g12 * (b1 * b2), q3 = (double)g11 * (b2 * b2);
-        const double Q = q1 - q2 + q3;
-        const double R = 4.0 * (double)t.den * (double)wa;
-        const double e = 16.0 * ACX_U * (fabs(q1) + fabs(q2) + fabs(q3) + fabs(R));
-        const double diff = Q - R;
-        if (diff < -e) return true;
-        if (diff > e) return false;
-        note_fallback(cnt);
-    }
-    const i128 Q = (i128)g22 * t.b1 * t.b1 - (i128)2 * g12 * t.b1 * t.b2 + (i128)g11 * t.b2 * t.b2;
-    const i128 R = (i128)4 * t.den * wa;
-    return Q <= R;
-}
-
-// Candidate test of a triangle (Step 1): not collinear, and AC3 in the Gram
-// form of tri_ac3, from the edge vectors only (the AC2 data of tri_setup is
-// not needed to decide candidacy).
+// Candidate test of a triangle (Step 1): not collinear, and AC3 in Gram form,
+// beta^T adj(G) beta <= 4 det(G) (W0 + alpha) with G the Gram matrix of
+// (a1, a2) and det(G) = |n|^2, from the edge vectors only (the AC2 data of
+// tri_setup is not needed to decide candidacy).
 __device__ __forceinline__ bool tri_candidate(int4 v0, int4 v1, int4 v2, const PredParams &pp, Counters *cnt) {
-    const i64 a1x = v1.x - v0.x, a1y = v1.y - v0.y, a1z = v1.z - v0.z;
-    const i64 a2x = v2.x - v0.x, a2y = v2.y - v0.y, a2z = v2.z - v0.z;
-    const i64 nx = a1y * a2z - a1z * a2y, ny = a1z * a2x - a1x * a2z, nz = a1x * a2y - a1y * a2x;
+    const int a1x = v1.x - v0.x, a1y = v1.y - v0.y, a1z = v1.z - v0.z;
+    const int a2x = v2.x - v0.x, a2y = v2.y - v0.y, a2z = v2.z - v0.z;
+    const int nx = m24(a1y, a2z) - m24(a1z, a2y), ny = m24(a1z, a2x) - m24(a1x, a2z),
+              nz = m24(a1x, a2y) - m24(a1y, a2x);
     if (nx == 0 && ny == 0 && nz == 0) return false;
-    const i64 den = nx * nx + ny * ny + nz * nz;
-    const i64 g11 = a1x * a1x + a1y * a1y + a1z * a1z;
-    const i64 g12 = a1x * a2x + a1y * a2y + a1z * a2z;
-    const i64 g22 = a2x * a2x + a2y * a2y + a2z * a2z;
-    const i64 b1 = g11 - v1.w + v0.w, b2 = g22 - v2.w + v0.w;
+    const i64 den = (i64)nx * nx + (i64)ny * ny + (i64)nz * nz;
+    const int g11 = m24(a1x, a1x) + m24(a1y, a1y) + m24(a1z, a1z);
+    const int g12 = m24(a1x, a2x) + m24(a1y, a2y) + m24(a1z, a2z);
+    const int g22 = m24(a2x, a2x) + m24(a2y, a2y) + m24(a2z, a2z);
+    const int b1 = g11 - v1.w + v0.w, b2 = g22 - v2.w + v0.w;
     const i64 wa = v0.w + pp.aq;
     if (!pp.force_exact) {
         const double db1 = (double)b1, db2 = (double)b2;
@@ -258,8 +250,8 @@ __device__ __forceinline__ double tri_orthosize(const Tri &t) {
 // Floating-point filter of tri_violation_sign: the sign of P when the
 // rounding bound certifies it, 0 when the exact path has to decide.
 __device__ __forceinline__ int tri_violation_filter(const Tri &t, int4 q) {
-    const i64 bx = q.x - t.v0.x, by = q.y - t.v0.y, bz = q.z - t.v0.z;
-    const i64 gam = bx * bx + by * by + bz * bz - q.w + t.v0.w;
+    const int bx = q.x - t.v0.x, by = q.y - t.v0.y, bz = q.z - t.v0.z;
+    const int gam = m24(bx, bx) + m24(by, by) + m24(bz, bz) - q.w + t.v0.w;
     const double P = (double)t.den * (double)gam - (t.Mx * (double)bx + t.My * (double)by + t.Mz * (double)bz);
     return (P > t.eP) - (P < -t.eP);
 }
@@ -283,13 +275,15 @@ __device__ __forceinline__ int tri_violation_exact(const Tri &t, int s0, int s1,
                                                    const int *perm) {
     const i64 bx = q.x - t.v0.x, by = q.y - t.v0.y, bz = q.z - t.v0.z;
     const i64 gam = bx * bx + by * by + bz * bz - q.w + t.v0.w;
-    const i128 Mx = (i128)t.b1 * t.ux + (i128)t.b2 * t.wx;
-    const i128 My = (i128)t.b1 * t.uy + (i128)t.b2 * t.wy;
-    const i128 Mz = (i128)t.b1 * t.uz + (i128)t.b2 * t.wz;
+    // u, w are exact integers below 2^44 held in float64
+    const i64 ux = (i64)t.ux, uy = (i64)t.uy, uz = (i64)t.uz, wx = (i64)t.wx, wy = (i64)t.wy, wz = (i64)t.wz;
+    const i128 Mx = (i128)t.b1 * ux + (i128)t.b2 * wx;
+    const i128 My = (i128)t.b1 * uy + (i128)t.b2 * wy;
+    const i128 Mz = (i128)t.b1 * uz + (i128)t.b2 * wz;
     const i128 P = (i128)t.den * gam - (Mx * bx + My * by + Mz * bz);
     if (P != 0) return sgn128(P);
-    const i64 ub = t.ux * bx + t.uy * by + t.uz * bz;
-    const i64 wb = t.wx * bx + t.wy * by + t.wz * bz;
+    const i64 ub = ux * bx + uy * by + uz * bz;
+    const i64 wb = wx * bx + wy * by + wz * bz;
     int ids[4] = {perm[sq], perm[s1], perm[s2], perm[s0]};
     i128 coef[4] = {-(i128)t.den, (i128)ub, (i128)wb, (i128)t.den - ub - wb};
     return sos_first<4>(ids, coef);
@@ -299,24 +293,26 @@ __device__ __forceinline__ int tri_violation_exact(const Tri &t, int s0, int s1,
 // Tetrahedron (d = 3).
 struct Tet {
     int4 v0;
-    i64 c1x, c1y, c1z, c2x, c2y, c2z, c3x, c3y, c3z; // a2xa3, a3xa1, a1xa2
-    i64 b1, b2, b3, D;
+    int c1x, c1y, c1z, c2x, c2y, c2z, c3x, c3y, c3z;  // a2xa3, a3xa1, a1xa2 (components below 2^29)
+    int b1, b2, b3;
+    i64 D;
     double Mx, My, Mz, Mabs2, eP;
 };
 
 __device__ __forceinline__ Tet tet_setup(int4 v0, int4 v1, int4 v2, int4 v3, const PredParams &pp) {
     Tet t;
     t.v0 = v0;
-    const i64 a1x = v1.x - v0.x, a1y = v1.y - v0.y, a1z = v1.z - v0.z;
-    const i64 a2x = v2.x - v0.x, a2y = v2.y - v0.y, a2z = v2.z - v0.z;
-    const i64 a3x = v3.x - v0.x, a3y = v3.y - v0.y, a3z = v3.z - v0.z;
-    t.c1x = a2y * a3z - a2z * a3y; t.c1y = a2z * a3x - a2x * a3z; t.c1z = a2x * a3y - a2y * a3x;
-    t.c2x = a3y * a1z - a3z * a1y; t.c2y = a3z * a1x - a3x * a1z; t.c2z = a3x * a1y - a3y * a1x;
-    t.c3x = a1y * a2z - a1z * a2y; t.c3y = a1z * a2x - a1x * a2z; t.c3z = a1x * a2y - a1y * a2x;
-    t.D = a1x * t.c1x + a1y * t.c1y + a1z * t.c1z;
-    t.b1 = a1x * a1x + a1y * a1y + a1z * a1z - v1.w + v0.w;
-    t.b2 = a2x * a2x + a2y * a2y + a2z * a2z - v2.w + v0.w;
-    t.b3 = a3x * a3x + a3y * a3y + a3z * a3z - v3.w + v0.w;
+    const int a1x = v1.x - v0.x, a1y = v1.y - v0.y, a1z = v1.z - v0.z;
+    const int a2x = v2.x - v0.x, a2y = v2.y - v0.y, a2z = v2.z - v0.z;
+    const int a3x = v3.x - v0.x, a3y = v3.y - v0.y, a3z = v3.z - v0.z;
+    t.c1x = m24(a2y, a3z) - m24(a2z, a3y); t.c1y = m24(a2z, a3x) - m24(a2x, a3z); t.c1z = m24(a2x, a3y) - m24(a2y, a3x);
+    t.c2x = m24(a3y, a1z) - m24(a3z, a1y); t.c2y = m24(a3z, a1x) - m24(a3x, a1z); t.c2z = m24(a3x, a1y) - m24(a3y, a1x);
+    t.c3x = m24(a1y, a2z) - m24(a1z, a2y); t.c3y = m24(a1z, a2x) - m24(a1x, a2z); t.c3z = m24(a1x, a2y) - m24(a1y, a2x);
+    // D = a1 . c1: products below 2^43, sum below 2^45, exact in float64
+    t.D = (i64)((double)a1x * (double)t.c1x + (double)a1y * (double)t.c1y + (double)a1z * (double)t.c1z);
+    t.b1 = m24(a1x, a1x) + m24(a1y, a1y) + m24(a1z, a1z) - v1.w + v0.w;
+    t.b2 = m24(a2x, a2x) + m24(a2y, a2y) + m24(a2z, a2z) - v2.w + v0.w;
+    t.b3 = m24(a3x, a3x) + m24(a3y, a3y) + m24(a3z, a3z) - v3.w + v0.w;
     const double b1 = (double)t.b1, b2 = (double)t.b2, b3 = (double)t.b3;
     t.Mx = b1 * (double)t.c1x + b2 * (double)t.c2x + b3 * (double)t.c3x;
     t.My = b1 * (double)t.c1y + b2 * (double)t.c2y + b3 * (double)t.c3y;
@@ -365,8 +361,8 @@ __device__ __forceinline__ double tet_orthosize(const Tet &t) {
 // P = sign(D) (D gamma - M.b)
 __device__ __forceinline__ int tet_violation_sign(const Tet &t, int s0, int s1, int s2, int s3, int4 q, int sq,
                                                   const int *perm, const PredParams &pp, Counters *cnt) {
-    const i64 bx = q.x - t.v0.x, by = q.y - t.v0.y, bz = q.z - t.v0.z;
-    const i64 gam = bx * bx + by * by + bz * bz - q.w + t.v0.w;
+    const int bx = q.x - t.v0.x, by = q.y - t.v0.y, bz = q.z - t.v0.z;
+    const int gam = m24(bx, bx) + m24(by, by) + m24(bz, bz) - q.w + t.v0.w;
     const int sD = t.D > 0 ? 1 : -1;
     if (!pp.force_exact) {
         const double P = (double)t.D * (double)gam - (t.Mx * (double)bx + t.My * (double)by + t.Mz * (double)bz);
@@ -378,9 +374,9 @@ __device__ __forceinline__ int tet_violation_sign(const Tet &t, int s0, int s1, 
     tet_exact_M(t, Mx, My, Mz);
     const i128 P = (i128)t.D * gam - (Mx * bx + My * by + Mz * bz);
     if (P != 0) return sD * sgn128(P);
-    const i64 k1 = t.c1x * bx + t.c1y * by + t.c1z * bz;
-    const i64 k2 = t.c2x * bx + t.c2y * by + t.c2z * bz;
-    const i64 k3 = t.c3x * bx + t.c3y * by + t.c3z * bz;
+    const i64 k1 = (i64)t.c1x * bx + (i64)t.c1y * by + (i64)t.c1z * bz;
+    const i64 k2 = (i64)t.c2x * bx + (i64)t.c2y * by + (i64)t.c2z * bz;
+    const i64 k3 = (i64)t.c3x * bx + (i64)t.c3y * by + (i64)t.c3z * bz;
     int ids[5] = {perm[sq], perm[s1], perm[s2], perm[s3], perm[s0]};
     i128 coef[5] = {-(i128)(t.D > 0 ? t.D : -t.D), (i128)sD * k1, (i128)sD * k2, (i128)sD * k3,
                     (i128)sD * (t.D - k1 - k2 - k3)};
