@@ -344,13 +344,10 @@ struct Cands {
 // Stable LSD radix sort of (key, payload) on bits [lo, hi) of key, 8 bits per
 // pass. key / pay are set to the buffers that hold the result (the inputs' or
 // scratch of the scope); *spare_key / *spare_pay (if given) to two other
-// buffers of n entries; *digit_tot (if given) to the per-digit counts of
-// the last pass (NULL if no pass ran).
+// buffers of n entries.
 template <class P>
 static void radix_sort(unsigned *&key, P *&pay, int n, int lo, int hi, hipStream_t s, Scope &sc,
-                       unsigned **spare_key = nullptr, P **spare_pay = nullptr, const int *live = nullptr,
-                       const int **digit_tot = nullptr) {
-    if (digit_tot) *digit_tot = nullptr;
+                       unsigned **spare_key = nullptr, P **spare_pay = nullptr, const int *live = nullptr) {
     unsigned *k2 = sc.get<unsigned>(n > 0 ? n : 1);
     P *p2 = sc.get<P>(n > 0 ? n : 1);
     unsigned *kin = key, *kout = k2;
@@ -367,7 +364,6 @@ static void radix_sort(unsigned *&key, P *&pay, int n, int lo, int hi, hipStream
             std::swap(kin, kout);
             std::swap(pin, pout);
         }
-        if (digit_tot) *digit_tot = totals;
     }
     key = kin;
     pay = pin;
@@ -386,28 +382,30 @@ static int bits_for(long long n) {
     return b;
 }
 
-// Emit keys for n balls: rows are keyed by their least input id (< n);
-// dropped candidates get `drop`, the first key of the coarse bucket (key >>
-// shift) after those of every id, which fits in `bits` key bits. The radix
-// pass sorts bits [shift, bits).
+// Emit keys for n balls: rows are keyed by their least input id (< n); a
+// bucket is 2^shift ids (at most EK_KEYS, and at least 256 buckets where n
+// allows, so that small inputs still spread over many blocks); dropped
+// candidates get `drop`, the first key of the bucket after those of every id,
+// which fits in `bits` key bits. The radix sort orders bits [shift, bits).
 struct EmitKeys {
     int bits, shift;
     unsigned drop;
 };
 static EmitKeys emit_keys(int n) {
     EmitKeys k;
-    k.bits = bits_for((long long)n + 1 + (1 << 14));  // drop <= n + 2^shift < 2^bits
-    k.shift = std::min(std::max(k.bits - RS_BITS, 0), 14);
+    k.shift = EK_SHIFT;
+    while (k.shift > 0 && (n >> k.shift) < 256) k.shift--;
     k.drop = (unsigned)((((long long)n >> k.shift) + 1) << k.shift);
+    k.bits = bits_for((long long)k.drop + 1);
     return k;
 }
 
 // Emit dimension d = K - 1 from the candidates' keys (least input id; not
-// kept: n) and payloads: an LSD radix pass over the key bits above `shift`
-// groups them into coarse buckets (one pass up to 2^22 balls, two above),
-// then k_emit_bucket finishes EB_KEYS keys per block and writes the sorted
-// rows. The output arrays have room for all M candidates; the kept count goes
-// to *m_out on the device. live: the count is read on the device (at most M).
+// kept: the drop key) and payloads: a radix sort over the key bits above the
+// bucket makes each bucket of EK_KEYS ids contiguous, k_emit_bounds finds the
+// buckets' starts and k_emit_block orders each bucket and writes its rows.
+// The output arrays have room for all M candidates; the kept count goes to
+// *m_out on the device. live: the count is read on the device (at most M).
 template <int K>
 static void emit_dim(unsigned *key, typename EmitPay<K>::type *pay, const double *size_in, int M, int n,
                      hipStream_t s, Scope &sc, ac_complex *res, int d, int *m_out, bool to_A2 = true,
@@ -415,23 +413,21 @@ static void emit_dim(unsigned *key, typename EmitPay<K>::type *pay, const double
     typedef typename EmitPay<K>::type P;
     res->d_simp[d] = static_cast<int32_t *>(dev_alloc((size_t)(M > 0 ? M : 1) * K * sizeof(int32_t)));
     res->d_size[d] = static_cast<double *>(dev_alloc((size_t)(M > 0 ? M : 1) * sizeof(double)));
-    if (live) {
-        k_copy_int<<<1, WAVE, 0, s>>>(live, m_out);
-        LAUNCH_CHECK();
-    } else {
-        fill<int>(m_out, M, 1, s);
+    if (M == 0) {
+        fill<int>(m_out, 0, 1, s);
+        return;
     }
-    if (M == 0) return;
     const EmitKeys ek = emit_keys(n);
     unsigned *gkey = nullptr;
     P *gpay = nullptr;
-    const int *tot = nullptr;
-    radix_sort<P>(key, pay, M, ek.shift, ek.bits, s, sc, &gkey, &gpay, live, &tot);
-    // one pass: its digit is the coarse bucket, whose bounds its totals give
-    if (ek.bits - ek.shift > RS_BITS) tot = nullptr;
-    const unsigned blocks = (unsigned)std::max<long long>(((long long)n + EB_KEYS - 1) / EB_KEYS, 1);
-    k_emit_bucket<K><<<blocks, EB_BLOCK, 0, s>>>(key, pay, M, ek.drop, ek.shift, gkey, gpay, size_in, to_A2 ? 1 : 0,
-                                                 res->d_simp[d], res->d_size[d], m_out, tot, live);
+    radix_sort<P>(key, pay, M, ek.shift, ek.bits, s, sc, &gkey, &gpay, live);
+    const int nb = (int)(ek.drop >> ek.shift);
+    int *start = sc.get<int>((size_t)nb + 1);
+    k_emit_bounds<<<(unsigned)((M + EK_BOUNDS_BLOCK) / EK_BOUNDS_BLOCK), EK_BOUNDS_BLOCK, 0, s>>>(key, M, ek.shift, nb,
+                                                                                                 start, live);
+    LAUNCH_CHECK();
+    k_emit_block<K><<<(unsigned)nb, EK_BLOCK, 0, s>>>(key, pay, start, ek.shift, nb, gkey, gpay, size_in,
+                                                     to_A2 ? 1 : 0, res->d_simp[d], res->d_size[d], m_out);
     LAUNCH_CHECK();
 }
 

@@ -5,17 +5,17 @@
 // The pruning kernels key every candidate by the least input id of its row
 // with the remaining ids and its Size (for a tetrahedron: its candidate
 // index) as payload; a candidate that is not kept gets the drop key, the
-// first key of the coarse bucket after every input id's. A stable LSD radix
-// pass over the high bits of the key (one 8-bit pass below 2^22 balls, two
-// above) groups the rows into coarse buckets, the dropped rows in one bucket
-// of their own at the end; k_emit_bucket then finishes EB_KEYS consecutive
-// keys per block: the per-key counts by LDS atomics and their scan give every
-// key's place, each row is put in its key's group, and its rank in the group
-// by the remaining ids gives its final place. The rows of one key are few (a
-// ball's upper edges, triangles or tetrahedra), so the rank is a short walk;
-// no global atomics, no device-wide sort passes over the low bits, and (above
-// 2^19 balls, where coarse buckets are whole multiples of a block's keys) no
-// block reads the dropped rows.
+// first key of the bucket after every input id's. A bucket is 2^shift
+// consecutive ids (at most EK_KEYS; smaller for small inputs, so that there
+// are some hundred buckets). A stable LSD radix sort over the key bits above
+// the bucket (8-bit passes) makes every bucket's rows contiguous, the dropped
+// rows last; k_emit_bounds finds where each
+// bucket starts, and k_emit_block finishes one bucket per block in LDS: it
+// loads the bucket's rows, counts the rows of each id with LDS atomics, scans
+// the counts, orders the rows by id, ranks each row in its id's group by the
+// remaining ids and writes it to its final place. Every global access is a
+// contiguous range; no global atomics, no scattered writes (a bucket with more
+// rows than LDS holds is finished through global scratch instead).
 #pragma once
 #include "common.hpp"
 #include "radix.hpp"
@@ -88,200 +88,181 @@ __device__ __forceinline__ double pay_size(const uint4 &q, const double *__restr
     else return size[q.w];
 }
 
-// First position p in [0, m) with (key[p] >> shift) >= b (key sorted by key >> shift).
-__device__ __forceinline__ int coarse_lower_bound(const unsigned *__restrict__ key, int m, int shift, long long b) {
-    int lo = 0, hi = m;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if ((long long)(key[mid] >> shift) < b) lo = mid + 1; else hi = mid;
-    }
-    return lo;
+constexpr int EK_SHIFT = 9;              // largest bucket: 2^EK_SHIFT ids
+constexpr int EK_KEYS = 1 << EK_SHIFT;
+constexpr int EK_BLOCK = 256;
+constexpr int EK_ROWS = 3072;            // rows a block orders in LDS
+constexpr int EK_BOUNDS_BLOCK = 256;
+
+// start[c] = the first row whose key >> shift is at least c, for c = 0..nb
+// (rows sorted by key >> shift; thread p, 0 <= p <= m, writes the starts of
+// the buckets in (bucket of row p - 1, bucket of row p]).
+__global__ void __launch_bounds__(EK_BOUNDS_BLOCK) k_emit_bounds(const unsigned *__restrict__ key, int m, int shift, int nb,
+                                                        int *__restrict__ start, const int *__restrict__ live = nullptr) {
+    m = live_count(m, live);
+    const int p = blockIdx.x * EK_BOUNDS_BLOCK + threadIdx.x;
+    if (p > m) return;
+    const int lo = p == 0 ? -1 : min((int)(key[p - 1] >> shift), nb);
+    const int hi = p == m ? nb : min((int)(key[p] >> shift), nb);
+    for (int c = lo + 1; c <= hi; c++) start[c] = p;
 }
 
-constexpr int EB_KEYS = 4096;   // keys finished by one block
-constexpr int EB_BLOCK = 512;
-constexpr int EB_PER_THREAD = EB_KEYS / EB_BLOCK;
-constexpr int EB_BATCH1 = 32;  // keys per thread loaded together in the counting sweep
-constexpr int EB_BATCH2 = 8;   // rows per thread loaded together in the placing sweep
-constexpr int EB_WIN = 2048;   // rows ranked together in LDS
-
-// Block b finishes the keys [b EB_KEYS, (b + 1) EB_KEYS) of key / pay (m rows
-// sorted by key >> shift), using gkey / gpay (m entries) as scratch, and
-// writes the kept rows (key < drop) to out / out_size at their final places;
-// the last block writes the kept count to *m_out. The grid covers the input
-// ids, so every block's first key lies below the drop key, whose coarse
-// bucket follows all others. Sizes are converted from mA^2 to A^2 when to_A2
-// is set (emit of a build), else copied (merge of rows that are already
-// output).
 template <int K>
-__global__ void __launch_bounds__(EB_BLOCK) k_emit_bucket(const unsigned *__restrict__ key,
-                                                           const typename EmitPay<K>::type *__restrict__ pay, int m,
-                                                           unsigned drop, int shift, unsigned *__restrict__ gkey,
-                                                           typename EmitPay<K>::type *__restrict__ gpay,
-                                                           const double *__restrict__ size_in, int to_A2,
-                                                           int *__restrict__ out, double *__restrict__ out_size,
-                                                           int *__restrict__ m_out, const int *__restrict__ digit_tot,
-                                                           const int *__restrict__ live = nullptr) {
-    typedef typename EmitPay<K>::type P;
-    m = live_count(m, live);
-    __shared__ int cnt[EB_KEYS];  // per-key counts, then each key's first place in the block's range
-    // placement cursors (int[EB_KEYS]) in sweeps 1-2, then the window of rows
-    // ranked in LDS in sweep 3
-    __shared__ uint4 sh[EB_WIN];
-    static_assert(sizeof(uint4) * EB_WIN >= sizeof(int) * EB_KEYS, "the cursors fit in the row window");
-    int *const cur = reinterpret_cast<int *>(sh);
-    __shared__ int wsum[EB_BLOCK / WAVE];
-    __shared__ int below_s;
-    const long long k0 = (long long)blockIdx.x * EB_KEYS;
-    const int t = threadIdx.x;
-    // the rows of the coarse buckets that hold this block's keys: from the
-    // digit totals of a single radix pass (the coarse bucket is the digit),
-    // else by binary search
-    const int c_lo = (int)(k0 >> shift), c_hi = (int)((k0 + EB_KEYS - 1) >> shift) + 1;
-    int bs, be;
-    if (digit_tot) {
-        __shared__ int part[2][EB_BLOCK / WAVE];
-        int a = 0, b = 0;
-        if (t < RS_BINS) {
-            const int v = digit_tot[t];
-            a = t < c_lo ? v : 0;
-            b = t < c_hi ? v : 0;
-        }
-        for (int off = WAVE / 2; off > 0; off >>= 1) {
-            a += __shfl_down(a, off, WAVE);
-            b += __shfl_down(b, off, WAVE);
-        }
-        if (lane_id() == 0) {
-            part[0][t / WAVE] = a;
-            part[1][t / WAVE] = b;
-        }
-        __syncthreads();
-        bs = 0;
-        be = 0;
-#pragma unroll
-        for (int w = 0; w < EB_BLOCK / WAVE; w++) {
-            bs += part[0][w];
-            be += part[1][w];
-        }
+__device__ __forceinline__ void write_row(int *__restrict__ out, long long pos, unsigned k, const unsigned (&r)[3]) {
+    if constexpr (K == 2) {
+        *reinterpret_cast<int2 *>(out + pos * 2) = make_int2((int)k, (int)r[0]);
+    } else if constexpr (K == 4) {
+        *reinterpret_cast<int4 *>(out + pos * 4) = make_int4((int)k, (int)r[0], (int)r[1], (int)r[2]);
     } else {
-        bs = coarse_lower_bound(key, m, shift, c_lo);
-        be = coarse_lower_bound(key, m, shift, c_hi);
+        out[pos * K] = (int)k;
+#pragma unroll
+        for (int c = 1; c < K; c++) out[pos * K + c] = (int)r[c - 1];
     }
-#pragma unroll
-    for (int u = 0; u < EB_PER_THREAD; u++) cnt[u * EB_BLOCK + t] = 0;
-    if (t == 0) below_s = 0;
+}
+
+__device__ __forceinline__ bool ids_less(const unsigned (&v)[3], const unsigned (&r)[3]) {
+    return v[0] != r[0] ? v[0] < r[0] : (v[1] != r[1] ? v[1] < r[1] : v[2] < r[2]);
+}
+
+// Block b finishes bucket b (b < nb, the drop key's bucket): its rows
+// [start[b], start[b + 1]) of key / pay are written, in order, to out /
+// out_size at the same places (every row before the bucket belongs to smaller
+// ids). Block 0 writes the kept count start[nb] to *m_out. gkey / gpay (m
+// entries) are scratch for a bucket with more than EK_ROWS rows. Sizes are
+// converted from mA^2 to A^2 when to_A2 is set (emit of a build), else copied
+// (merge of rows that are already output).
+template <int K>
+__global__ void __launch_bounds__(EK_BLOCK) k_emit_block(const unsigned *__restrict__ key,
+                                                          const typename EmitPay<K>::type *__restrict__ pay,
+                                                          const int *__restrict__ start, int shift, int nb,
+                                                          unsigned *__restrict__ gkey,
+                                                          typename EmitPay<K>::type *__restrict__ gpay,
+                                                          const double *__restrict__ size_in, int to_A2,
+                                                          int *__restrict__ out, double *__restrict__ out_size,
+                                                          int *__restrict__ m_out) {
+    typedef typename EmitPay<K>::type P;
+    constexpr int W = K == 2 ? 3 : 4;  // payload words
+    __shared__ unsigned sw[W][EK_ROWS];        // the bucket's payloads, in load order
+    __shared__ unsigned short skey[EK_ROWS];   // their ids less the bucket's first
+    __shared__ unsigned short sord[EK_ROWS];   // load positions in id order
+    __shared__ int cnt[EK_KEYS + 1];           // rows per id, then each id's first place
+    __shared__ int cur[EK_KEYS];
+    __shared__ int wsum[EK_BLOCK / WAVE];
+    const int b = blockIdx.x, t = threadIdx.x;
+    if (b == 0 && t == 0) *m_out = start[nb];
+    const int bs = start[b], rows = start[b + 1] - bs;
+    const unsigned k0 = (unsigned)b << shift;  // the bucket's ids: [k0, k0 + 2^shift), 2^shift <= EK_KEYS
+    for (int k = t; k <= EK_KEYS; k += EK_BLOCK) cnt[k] = 0;
     __syncthreads();
-    // sweep 1: counts per key; rows of the buckets with keys below this block's.
-    // The sweeps load a batch of entries per thread before using any (one
-    // latency per batch, not per entry); keys are below 2^31, and a slot past
-    // the range holds 0xffffffff, which no test takes.
-    const unsigned ku0 = (unsigned)k0, ku1 = (unsigned)min(k0 + EB_KEYS, (long long)drop);
-    int below = 0;
-    for (int e0 = bs + t; e0 < be; e0 += EB_BLOCK * EB_BATCH1) {
-        unsigned kb[EB_BATCH1];
+    const bool lds = rows <= EK_ROWS;
+    auto load = [&](int p) -> uint4 { return widen(pay[bs + p]); };
+    // counts per id (and, in LDS, the rows themselves); four rows per thread
+    // loaded together
+    for (int p0 = t; p0 < rows; p0 += 4 * EK_BLOCK) {
+        unsigned kk[4];
+        uint4 q[4];
 #pragma unroll
-        for (int u = 0; u < EB_BATCH1; u++) {
-            const int e = e0 + u * EB_BLOCK;
-            kb[u] = e < be ? key[e] : 0xffffffffu;
+        for (int u = 0; u < 4; u++) {
+            const int p = p0 + u * EK_BLOCK;
+            kk[u] = p < rows ? key[bs + p] - k0 : 0u;
+            q[u] = p < rows && lds ? load(p) : make_uint4(0u, 0u, 0u, 0u);
         }
 #pragma unroll
-        for (int u = 0; u < EB_BATCH1; u++) {
-            const unsigned kk = kb[u];
-            if (kk < ku0) below++;  // kept: k0 < drop
-            else if (kk < ku1) atomicAdd(&cnt[kk - ku0], 1);
-        }
-    }
-    for (int off = WAVE / 2; off > 0; off >>= 1) below += __shfl_down(below, off, WAVE);
-    if (lane_id() == 0 && below) atomicAdd(&below_s, below);
-    __syncthreads();
-    // exclusive scan of the counts: EB_PER_THREAD consecutive keys per thread
-    int c[EB_PER_THREAD], s = 0;
-#pragma unroll
-    for (int u = 0; u < EB_PER_THREAD; u++) {
-        c[u] = cnt[t * EB_PER_THREAD + u];
-        s += c[u];
-    }
-    const int incl = wave_inclusive_scan(s);
-    if (lane_id() == WAVE - 1) wsum[t / WAVE] = incl;
-    __syncthreads();
-    int run = incl - s, total = 0;
-#pragma unroll
-    for (int w = 0; w < EB_BLOCK / WAVE; w++) {
-        run += w < t / WAVE ? wsum[w] : 0;
-        total += wsum[w];
-    }
-#pragma unroll
-    for (int u = 0; u < EB_PER_THREAD; u++) {
-        cnt[t * EB_PER_THREAD + u] = run;
-        cur[t * EB_PER_THREAD + u] = run;
-        run += c[u];
-    }
-    __syncthreads();
-    const int gs = bs + below_s;  // global place of the block's first row
-    const int kept_end = total;
-    if (blockIdx.x == gridDim.x - 1 && t == 0) *m_out = coarse_lower_bound(key, m, shift, (long long)(drop >> shift));
-    // sweep 2: every kept row into its key's group (order inside a group is
-    // the atomics' order; the rank below fixes it)
-    for (int e0 = bs + t; e0 < be; e0 += EB_BLOCK * EB_BATCH2) {
-        unsigned kb[EB_BATCH2];
-        uint4 pb[EB_BATCH2];
-#pragma unroll
-        for (int u = 0; u < EB_BATCH2; u++) {
-            const int e = e0 + u * EB_BLOCK;
-            kb[u] = e < be ? key[e] : 0xffffffffu;
-        }
-#pragma unroll
-        for (int u = 0; u < EB_BATCH2; u++) {
-            const bool mine = kb[u] >= ku0 && kb[u] < ku1;
-            pb[u] = mine ? widen(pay[e0 + u * EB_BLOCK]) : make_uint4(0u, 0u, 0u, 0u);
-        }
-#pragma unroll
-        for (int u = 0; u < EB_BATCH2; u++) {
-            const unsigned kk = kb[u];
-            if (kk < ku0 || kk >= ku1) continue;
-            const int p = atomicAdd(&cur[kk - ku0], 1);
-            gkey[gs + p] = kk;
-            gpay[gs + p] = narrow<P>(pb[u]);
+        for (int u = 0; u < 4; u++) {
+            const int p = p0 + u * EK_BLOCK;
+            if (p >= rows) continue;
+            atomicAdd(&cnt[kk[u]], 1);
+            if (lds) {
+                skey[p] = (unsigned short)kk[u];
+                sw[0][p] = q[u].x;
+                sw[1][p] = q[u].y;
+                sw[2][p] = q[u].z;
+                if constexpr (W == 4) sw[W - 1][p] = q[u].w;
+            }
         }
     }
     __syncthreads();
-    // sweep 3: rank inside the group by the remaining ids, then the final
-    // write. The placed rows go through LDS in windows of at most EB_WIN rows
-    // that end at a group boundary, so each rank walk reads its group from
-    // LDS (a group longer than a window, which the keys here never have, is
-    // cut and its rows beyond the window read from global memory).
-    for (int w0 = 0; w0 < kept_end;) {
-        int w1 = min(w0 + EB_WIN, kept_end);
-        if (w1 < kept_end) {
-            const int gb = cnt[gkey[gs + w1] - k0];  // start of the group holding row w1
-            if (gb > w0) w1 = gb;
+    // exclusive scan of the counts (EK_KEYS / EK_BLOCK per thread)
+    {
+        constexpr int PT = EK_KEYS / EK_BLOCK;
+        int c[PT], s = 0;
+#pragma unroll
+        for (int u = 0; u < PT; u++) {
+            c[u] = cnt[t * PT + u];
+            s += c[u];
         }
-        __syncthreads();  // the previous window is done with sh (and sweep 2 with the cursors)
-        for (int p = w0 + t; p < w1; p += EB_BLOCK) sh[p - w0] = widen(gpay[gs + p]);
+        const int incl = wave_inclusive_scan(s);
+        if (lane_id() == WAVE - 1) wsum[t / WAVE] = incl;
         __syncthreads();
-        for (int p = w0 + t; p < w1; p += EB_BLOCK) {
-            const unsigned kk = gkey[gs + p];
-            const int loc = (int)(kk - k0);
-            const int g0 = cnt[loc], g1 = loc + 1 < EB_KEYS ? cnt[loc + 1] : total;
-            const uint4 me = sh[p - w0];
+        int run = incl - s;
+        for (int w = 0; w < t / WAVE; w++) run += wsum[w];
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PT; u++) {
+            cnt[t * PT + u] = run;
+            cur[t * PT + u] = run;
+            run += c[u];
+        }
+        if (t == EK_BLOCK - 1) cnt[EK_KEYS] = run;
+    }
+    __syncthreads();
+    if (lds) {
+        // order the rows by id (within an id in atomics' order), then rank
+        // each row in its id's group by the remaining ids
+        for (int p = t; p < rows; p += EK_BLOCK) sord[atomicAdd(&cur[skey[p]], 1)] = (unsigned short)p;
+        __syncthreads();
+        for (int s = t; s < rows; s += EK_BLOCK) {
+            const int p = sord[s];
+            const int k = skey[p];
+            const int g0 = cnt[k], g1 = cnt[k + 1];
             unsigned r[3];
-            pay_ids<K>(me, r);
+            r[0] = sw[0][p];
+            r[1] = K >= 3 ? sw[1][p] : 0u;
+            r[2] = K == 4 ? sw[2][p] : 0u;
             int rank = 0;
             for (int q = g0; q < g1; q++) {
-                if (q == p) continue;
-                const uint4 o = q >= w0 && q < w1 ? sh[q - w0] : widen(gpay[gs + q]);
-                unsigned v[3];
-                pay_ids<K>(o, v);
-                rank += v[0] != r[0] ? v[0] < r[0] : (v[1] != r[1] ? v[1] < r[1] : v[2] < r[2]);
+                const int o = sord[q];
+                const unsigned v[3] = {sw[0][o], K >= 3 ? sw[1][o] : 0u, K == 4 ? sw[2][o] : 0u};
+                rank += (q != s) && ids_less(v, r);
             }
-            const long long pos = (long long)gs + g0 + rank;
-            out[pos * K] = (int)kk;
-#pragma unroll
-            for (int c = 1; c < K; c++) out[pos * K + c] = (int)r[c - 1];
+            const long long pos = (long long)bs + g0 + rank;
+            write_row<K>(out, pos, k0 + k, r);
+            uint4 me;
+            me.x = sw[0][p];
+            me.y = sw[1][p];
+            me.z = sw[2][p];
+            me.w = W == 4 ? sw[W - 1][p] : 0u;
             const double z = pay_size<K>(me, size_in);
             out_size[pos] = to_A2 ? z / 1.0e6 : z;
         }
-        w0 = w1;
+        return;
+    }
+    // a bucket beyond LDS: rows placed in their id's group in global scratch
+    // (the bucket's own range of gkey / gpay), ranked from there
+    for (int p = t; p < rows; p += EK_BLOCK) {
+        const unsigned kk = key[bs + p] - k0;
+        const int slot = atomicAdd(&cur[kk], 1);
+        gkey[bs + slot] = kk;
+        gpay[bs + slot] = pay[bs + p];
+    }
+    __threadfence_block();
+    __syncthreads();
+    for (int s = t; s < rows; s += EK_BLOCK) {
+        const int k = (int)gkey[bs + s];
+        const int g0 = cnt[k], g1 = cnt[k + 1];
+        const uint4 me = widen(gpay[bs + s]);
+        unsigned r[3];
+        pay_ids<K>(me, r);
+        int rank = 0;
+        for (int q = g0; q < g1; q++) {
+            unsigned v[3];
+            pay_ids<K>(widen(gpay[bs + q]), v);
+            rank += (q != s) && ids_less(v, r);
+        }
+        const long long pos = (long long)bs + g0 + rank;
+        write_row<K>(out, pos, k0 + k, r);
+        const double z = pay_size<K>(me, size_in);
+        out_size[pos] = to_A2 ? z / 1.0e6 : z;
     }
 }
 

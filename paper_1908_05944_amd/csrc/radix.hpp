@@ -81,6 +81,15 @@ __global__ void __launch_bounds__(RS_PREFIX_BLOCK) k_rs_digit_prefix(int *__rest
     if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
+// Payload as held in registers: a 12-byte uint3 in an array ends up in
+// scratch memory, so it is widened to a uint4.
+template <class P> struct RsReg { typedef P type; };
+template <> struct RsReg<uint3> { typedef uint4 type; };
+template <class P> __device__ __forceinline__ P rs_to_reg(const P &p) { return p; }
+__device__ __forceinline__ uint4 rs_to_reg(const uint3 &p) { return make_uint4(p.x, p.y, p.z, 0u); }
+template <class P, class R> __device__ __forceinline__ P rs_from_reg(const R &r) { return r; }
+template <> __device__ __forceinline__ uint3 rs_from_reg<uint3, uint4>(const uint4 &r) { return make_uint3(r.x, r.y, r.z); }
+
 template <class P>
 __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const unsigned *__restrict__ kin, const P *__restrict__ pin,
                                                           unsigned *__restrict__ kout, P *__restrict__ pout, int n,
@@ -113,15 +122,22 @@ __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const unsigned *__restr
     // sweep: rank each element among the equal digits of its wave so far
     const unsigned long long lt = (1ull << lane) - 1ull;
     const long long base = (long long)blockIdx.x * RS_TILE + (long long)wave * CHUNK;
-    // keys and ranks stay in registers; payloads are read again (from L2)
-    // when placed, which keeps wide payloads from spilling
+    // keys, payloads and ranks stay in registers; every load of the tile is
+    // issued before the first ballot
+    typedef typename RsReg<P>::type R;
     unsigned key[RS_IPT];
+    R pv[RS_IPT];
     int rank[RS_IPT];
 #pragma unroll
     for (int r = 0; r < RS_IPT; r++) {
         const long long idx = base + (long long)r * WAVE + lane;
+        key[r] = idx < n ? kin[idx] : 0u;
+        pv[r] = idx < n ? rs_to_reg(pin[idx]) : R{};
+    }
+#pragma unroll
+    for (int r = 0; r < RS_IPT; r++) {
+        const long long idx = base + (long long)r * WAVE + lane;
         const bool valid = idx < n;
-        key[r] = valid ? kin[idx] : 0u;
         const unsigned d = (key[r] >> shift) & (RS_BINS - 1);
         unsigned long long peers = __ballot(valid);
 #pragma unroll
@@ -160,7 +176,7 @@ __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const unsigned *__restr
         const unsigned d = (key[r] >> shift) & (RS_BINS - 1);
         const int lpos = wcnt[wave][d] + rank[r];
         skey[lpos] = key[r];
-        spay[lpos] = pin[base + (long long)r * WAVE + lane];
+        spay[lpos] = rs_from_reg<P>(pv[r]);
     }
     __syncthreads();
     // the tile in digit order: each digit's run goes to consecutive addresses;
