@@ -162,6 +162,21 @@ def test_options_do_not_change_result(acx):
             assert np.array_equal(got.sizes(d), base.sizes(d)), (opt, d)
 
 
+@pytest.mark.parametrize("sas,alpha,cells", [(False, 0.0, (3600, 4000, 5000)), (False, 0.2, (3800,)),
+                                              (True, 0.0, (6400, 7000))])
+def test_one_cell_reach(acx, sas, alpha, cells):
+    """Cell sides of one-cell reach (the neighbour scan covers 3 x 3 x 3
+    cells), including solvent-accessible radii at 6.4 and 7 A cells, whose
+    rows outgrow the slot (counted fill). Every side gives the oracle's
+    complex."""
+    m = synth.molecule(6000, 17, sas=sas)
+    want = oracle.alpha_complex(m.xyz, m.radii, alpha)
+    for side in cells:
+        print(f"[case] one-cell reach sas={sas} alpha={alpha} cell_mA={side}", flush=True)
+        got = _run(acx, m.xyz, m.radii, alpha, cell_mA=side)
+        assert_same_complex(got, want, f"sas={sas} alpha={alpha} cell_mA={side}")
+
+
 @pytest.mark.parametrize("sas", [False, True])
 def test_morton_order_100k(acx, sas):
     """The 100k-atom molecule with cells on a Morton curve: the same complex as
