@@ -34,6 +34,22 @@ __device__ __forceinline__ int xcd_block() {
     return x * q + min(x, r) + k;
 }
 
+// The same for a launch sized for a capacity of which only the first `live`
+// blocks have work (counts known on the device only): those blocks are
+// spread evenly over the XCDs, each XCD taking one contiguous range of them,
+// and the idle blocks map onto [live, gridDim.x). Still a bijection on
+// [0, gridDim.x); with live = gridDim.x it is xcd_block().
+__device__ __forceinline__ int xcd_block(int live) {
+    const int nb = gridDim.x, b = blockIdx.x;
+    live = min(max(live, 0), nb);
+    const int x = b % NUM_XCD, k = b / NUM_XCD;
+    const int q = live / NUM_XCD, r = live % NUM_XCD;  // live blocks per XCD
+    const int len = q + (x < r);
+    if (k < len) return x * q + min(x, r) + k;
+    const int Q = nb / NUM_XCD, R = nb % NUM_XCD;  // blocks per XCD
+    return live + (x * Q + min(x, R)) - (x * q + min(x, r)) + (k - len);
+}
+
 // Item count of a launch: `cap`, the count it was sized for, or, when `live`
 // is given, the smaller count an earlier kernel on the stream wrote there
 // (launches recorded before their counts are known, as in a captured graph).

@@ -91,8 +91,14 @@ __device__ __forceinline__ double pay_size(const uint4 &q, const double *__restr
 constexpr int EK_SHIFT = 9;              // largest bucket: 2^EK_SHIFT ids
 constexpr int EK_KEYS = 1 << EK_SHIFT;
 constexpr int EK_BLOCK = 256;
-constexpr int EK_ROWS = 3072;            // rows a block orders in LDS
 constexpr int EK_BOUNDS_BLOCK = 256;
+// Rows a block orders in LDS, per dimension: its payload words, 16-bit ids and
+// order take 16 (edges), 20 (triangles, tetrahedra) bytes a row, so that an
+// edge block (about 35 KB) leaves room for four blocks per CU. The host picks
+// each dimension's bucket size so that its expected largest bucket fits (a
+// row is keyed by its least id, so the lowest ids of a randomly numbered
+// input key about K times the mean number of rows per id).
+template <int K> constexpr int ek_rows() { return K == 4 ? 512 : 2048; }
 
 // start[c] = the first row whose key >> shift is at least c, for c = 0..nb
 // (rows sorted by key >> shift; thread p, 0 <= p <= m, writes the starts of
@@ -128,7 +134,7 @@ __device__ __forceinline__ bool ids_less(const unsigned (&v)[3], const unsigned 
 // [start[b], start[b + 1]) of key / pay are written, in order, to out /
 // out_size at the same places (every row before the bucket belongs to smaller
 // ids). Block 0 writes the kept count start[nb] to *m_out. gkey / gpay (m
-// entries) are scratch for a bucket with more than EK_ROWS rows. Sizes are
+// entries) are scratch for a bucket with more than ek_rows<K>() rows. Sizes are
 // converted from mA^2 to A^2 when to_A2 is set (emit of a build), else copied
 // (merge of rows that are already output).
 template <int K>
@@ -142,9 +148,10 @@ __global__ void __launch_bounds__(EK_BLOCK) k_emit_block(const unsigned *__restr
                                                           int *__restrict__ m_out) {
     typedef typename EmitPay<K>::type P;
     constexpr int W = K == 2 ? 3 : 4;  // payload words
-    __shared__ unsigned sw[W][EK_ROWS];        // the bucket's payloads, in load order
-    __shared__ unsigned short skey[EK_ROWS];   // their ids less the bucket's first
-    __shared__ unsigned short sord[EK_ROWS];   // load positions in id order
+    constexpr int ROWS = ek_rows<K>();
+    __shared__ unsigned sw[W][ROWS];        // the bucket's payloads, in load order
+    __shared__ unsigned short skey[ROWS];   // their ids less the bucket's first
+    __shared__ unsigned short sord[ROWS];   // load positions in id order
     __shared__ int cnt[EK_KEYS + 1];           // rows per id, then each id's first place
     __shared__ int cur[EK_KEYS];
     __shared__ int wsum[EK_BLOCK / WAVE];
@@ -154,7 +161,7 @@ __global__ void __launch_bounds__(EK_BLOCK) k_emit_block(const unsigned *__restr
     const unsigned k0 = (unsigned)b << shift;  // the bucket's ids: [k0, k0 + 2^shift), 2^shift <= EK_KEYS
     for (int k = t; k <= EK_KEYS; k += EK_BLOCK) cnt[k] = 0;
     __syncthreads();
-    const bool lds = rows <= EK_ROWS;
+    const bool lds = rows <= ROWS;
     auto load = [&](int p) -> uint4 { return widen(pay[bs + p]); };
     // counts per id (and, in LDS, the rows themselves); four rows per thread
     // loaded together

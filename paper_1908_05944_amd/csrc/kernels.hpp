@@ -633,7 +633,7 @@ __global__ void __launch_bounds__(BLOCK) k_triangles(const int4 *__restrict__ at
     E = live_count(E, live);
     __shared__ int slot[ONE ? BLOCK * TRI_SLOT : 1];
     __shared__ int cand[BLOCK * TRI_SLOT];
-    const int b = xcd_block();
+    const int b = xcd_block(E / BLOCK + (E % BLOCK != 0));
     const int e = b * BLOCK + threadIdx.x;
     int c = 0;
     if (e < E) {
@@ -809,7 +809,7 @@ __global__ void __launch_bounds__(BLOCK, 4) k_tet_candidates(const int4 *__restr
     T = live_count(T, live);
     __shared__ int slot[ONE ? BLOCK * TET_SLOT : 1];
     __shared__ int cand[BLOCK * TET_SLOT];
-    const int b = xcd_block();
+    const int b = xcd_block(T / BLOCK + (T % BLOCK != 0));
     const int t = b * BLOCK + threadIdx.x;
     int c = 0;
     if (t < T) {
@@ -945,8 +945,9 @@ __global__ void __launch_bounds__(BLOCK) k_tet_ac2(const int4 *__restrict__ atom
                                                     int4 *__restrict__ tface, unsigned drop, unsigned *__restrict__ qkey,
                                                     typename EmitPay<4>::type *__restrict__ qpay, Counters *cnt,
                                                     const int *__restrict__ live = nullptr) {
-    const int c = xcd_block() * BLOCK + threadIdx.x;
-    if (c >= live_count(Q, live)) return;
+    const int Ql = live_count(Q, live);
+    const int c = xcd_block(Ql / BLOCK + (Ql % BLOCK != 0)) * BLOCK + threadIdx.x;
+    if (c >= Ql) return;
     const int t = tet_t[c], l = tet_l[c];
     const int e = tri_e[t];
     const int i = edge_i[e], j = up[e], k = tri_k[t];
@@ -999,8 +1000,9 @@ __global__ void __launch_bounds__(BLOCK) k_tri_final(const int *__restrict__ up_
                                                       unsigned drop, unsigned *__restrict__ tkey,
                                                       typename EmitPay<3>::type *__restrict__ tpay, Counters *cnt,
                                                       const int *__restrict__ live = nullptr) {
-    const int t = xcd_block() * BLOCK + threadIdx.x;
-    if (t >= live_count(T, live)) return;
+    const int Tl = live_count(T, live);
+    const int t = xcd_block(Tl / BLOCK + (Tl % BLOCK != 0)) * BLOCK + threadIdx.x;
+    if (t >= Tl) return;
     const bool gab = tgab[t];
     const long long mn = gab ? ORDERED_POS_INF : tri_min[t];
     const bool in = gab || mn != ORDERED_POS_INF;
@@ -1042,8 +1044,9 @@ __global__ void __launch_bounds__(BLOCK) k_edge_final(const int4 *__restrict__ a
                                                        unsigned drop, unsigned *__restrict__ ekey,
                                                        typename EmitPay<2>::type *__restrict__ epay,
                                                        const int *__restrict__ live = nullptr) {
-    const int e = xcd_block() * BLOCK + threadIdx.x;
-    if (e >= live_count(E, live)) return;
+    const int El = live_count(E, live);
+    const int e = xcd_block(El / BLOCK + (El % BLOCK != 0)) * BLOCK + threadIdx.x;
+    if (e >= El) return;
     const bool gab = egab[e];
     const long long mn = gab ? ORDERED_POS_INF : edge_min[e];
     const bool in = gab || mn != ORDERED_POS_INF;
