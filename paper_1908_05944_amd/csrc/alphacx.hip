@@ -429,8 +429,9 @@ static void emit_dim(unsigned *key, typename EmitPay<K>::type *pay, const double
     radix_sort<P>(key, pay, M, ek.shift, ek.bits, s, sc, &gkey, &gpay, live);
     const int nb = (int)(ek.drop >> ek.shift);
     int *start = sc.get<int>((size_t)nb + 1);
-    k_emit_bounds<<<(unsigned)((M + EK_BOUNDS_BLOCK) / EK_BOUNDS_BLOCK), EK_BOUNDS_BLOCK, 0, s>>>(key, M, ek.shift, nb,
-                                                                                                 start, live);
+    const long long bthreads = (long long)M / EK_BOUNDS_PT + 1;  // rows 0..M
+    k_emit_bounds<<<(unsigned)((bthreads + EK_BOUNDS_BLOCK - 1) / EK_BOUNDS_BLOCK), EK_BOUNDS_BLOCK, 0, s>>>(
+        key, M, ek.shift, nb, start, live);
     LAUNCH_CHECK();
     k_emit_block<K><<<(unsigned)nb, EK_BLOCK, 0, s>>>(key, pay, start, ek.shift, nb, gkey, gpay, size_in,
                                                      to_A2 ? 1 : 0, res->d_simp[d], res->d_size[d], m_out);
@@ -556,8 +557,6 @@ struct Batch {
     std::vector<int64_t> off;
     std::vector<int32_t> cell_mA;
 };
-
-constexpr int QTILE = 1024;  // balls per block of the quantise kernel
 
 // Blocks of the quantise kernel: tiles of at most QTILE balls, each inside one
 // molecule; molecule m's tiles are [tile_first[m], tile_first[m+1]).

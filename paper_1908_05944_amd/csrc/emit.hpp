@@ -101,16 +101,33 @@ constexpr int EK_BOUNDS_BLOCK = 256;
 template <int K> constexpr int ek_rows() { return K == 4 ? 512 : 2048; }
 
 // start[c] = the first row whose key >> shift is at least c, for c = 0..nb
-// (rows sorted by key >> shift; thread p, 0 <= p <= m, writes the starts of
-// the buckets in (bucket of row p - 1, bucket of row p]).
+// (rows sorted by key >> shift; row p, 0 <= p <= m, writes the starts of the
+// buckets in (bucket of row p - 1, bucket of row p], with row m in bucket nb).
+// A thread takes EK_BOUNDS_PT consecutive rows (one 16-byte load). `key` is
+// 16-byte aligned.
+constexpr int EK_BOUNDS_PT = 4;
 __global__ void __launch_bounds__(EK_BOUNDS_BLOCK) k_emit_bounds(const unsigned *__restrict__ key, int m, int shift, int nb,
                                                         int *__restrict__ start, const int *__restrict__ live = nullptr) {
     m = live_count(m, live);
-    const int p = blockIdx.x * EK_BOUNDS_BLOCK + threadIdx.x;
-    if (p > m) return;
-    const int lo = p == 0 ? -1 : min((int)(key[p - 1] >> shift), nb);
-    const int hi = p == m ? nb : min((int)(key[p] >> shift), nb);
-    for (int c = lo + 1; c <= hi; c++) start[c] = p;
+    const long long p0 = ((long long)blockIdx.x * EK_BOUNDS_BLOCK + threadIdx.x) * EK_BOUNDS_PT;
+    if (p0 > m) return;
+    unsigned k[EK_BOUNDS_PT];
+    if (p0 + EK_BOUNDS_PT <= m) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(key + p0);
+        k[0] = v.x; k[1] = v.y; k[2] = v.z; k[3] = v.w;
+    } else {
+#pragma unroll
+        for (int u = 0; u < EK_BOUNDS_PT; u++) k[u] = p0 + u < m ? key[p0 + u] : 0u;
+    }
+    int prev = p0 == 0 ? -1 : min((int)(key[p0 - 1] >> shift), nb);
+#pragma unroll
+    for (int u = 0; u < EK_BOUNDS_PT; u++) {
+        const long long p = p0 + u;
+        if (p > m) break;
+        const int cur = p == m ? nb : min((int)(k[u] >> shift), nb);
+        for (int c = prev + 1; c <= cur; c++) start[c] = (int)p;
+        prev = cur;
+    }
 }
 
 template <int K>

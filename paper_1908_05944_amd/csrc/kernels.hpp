@@ -76,18 +76,33 @@ constexpr int BLOCK = 256;
 
 // ---------------------------------------------------------------------------
 // Quantise: x -> rint(1000 x) (round half to even), W = R^2. Block b handles
-// the balls [tiles[b].x, tiles[b].y), all of one molecule, and writes their
-// bounding box and flags; k_stats_reduce folds each molecule's tiles.
+// the balls [tiles[b].x, tiles[b].y) (at most QTILE, all of one molecule) and
+// writes their bounding box and flags; k_stats_reduce folds each molecule's
+// tiles. Every load of a thread is issued before the first conversion.
+constexpr int QTILE = 1024;  // balls per block
 __global__ void __launch_bounds__(BLOCK) k_quantise(const double *__restrict__ xyz, const double *__restrict__ r,
                                                      const int2 *__restrict__ tiles, int4 *__restrict__ q,
                                                      Stats *__restrict__ part) {
+    constexpr int PT = QTILE / BLOCK;
     int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN}, wmax = 0, flags = 0;
     const int2 tile = tiles[blockIdx.x];
-    for (int i = tile.x + threadIdx.x; i < tile.y; i += BLOCK) {
+    double vx[PT][3], vr[PT];
+#pragma unroll
+    for (int u = 0; u < PT; u++) {
+        const int i = tile.x + (int)threadIdx.x + u * BLOCK;
+        const long long k = i < tile.y ? i : tile.x;  // past the tile: any ball of it, not used
+#pragma unroll
+        for (int a = 0; a < 3; a++) vx[u][a] = xyz[3 * k + a];
+        vr[u] = r[k];
+    }
+#pragma unroll
+    for (int u = 0; u < PT; u++) {
+        const int i = tile.x + (int)threadIdx.x + u * BLOCK;
+        if (i >= tile.y) break;
         int c[3];
 #pragma unroll
         for (int a = 0; a < 3; a++) {
-            const double v = xyz[3 * (long long)i + a];
+            const double v = vx[u][a];
             c[a] = 0;
             if (!isfinite(v)) { flags |= 1; continue; }
             const double s = v * 1000.0;
@@ -97,7 +112,7 @@ __global__ void __launch_bounds__(BLOCK) k_quantise(const double *__restrict__ x
             mn[a] = min(mn[a], c[a]);
             mx[a] = max(mx[a], c[a]);
         }
-        const double rv = r[i];
+        const double rv = vr[u];
         int W = 0;
         if (!isfinite(rv) || !(rv > 0.0)) {
             flags |= 1;
@@ -151,11 +166,22 @@ __global__ void __launch_bounds__(BLOCK) k_stats_reduce(const Stats *__restrict_
         b.maxx = max(b.maxx, o.maxx); b.maxy = max(b.maxy, o.maxy); b.maxz = max(b.maxz, o.maxz);
         b.wmax = max(b.wmax, o.wmax); b.flags |= o.flags;
     }
-    __shared__ Stats ws[BLOCK];
-    ws[threadIdx.x] = b;
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) {
+        b.minx = min(b.minx, __shfl_xor(b.minx, off, WAVE));
+        b.miny = min(b.miny, __shfl_xor(b.miny, off, WAVE));
+        b.minz = min(b.minz, __shfl_xor(b.minz, off, WAVE));
+        b.maxx = max(b.maxx, __shfl_xor(b.maxx, off, WAVE));
+        b.maxy = max(b.maxy, __shfl_xor(b.maxy, off, WAVE));
+        b.maxz = max(b.maxz, __shfl_xor(b.maxz, off, WAVE));
+        b.wmax = max(b.wmax, __shfl_xor(b.wmax, off, WAVE));
+        b.flags |= __shfl_xor(b.flags, off, WAVE);
+    }
+    __shared__ Stats ws[BLOCK / WAVE];
+    if (lane_id() == 0) ws[threadIdx.x / WAVE] = b;
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int k = 1; k < BLOCK; k++) {
+        for (int k = 1; k < BLOCK / WAVE; k++) {
             const Stats &o = ws[k];
             b.minx = min(b.minx, o.minx); b.miny = min(b.miny, o.miny); b.minz = min(b.minz, o.minz);
             b.maxx = max(b.maxx, o.maxx); b.maxy = max(b.maxy, o.maxy); b.maxz = max(b.maxz, o.maxz);
