@@ -517,6 +517,12 @@ __global__ void __launch_bounds__(BLOCK) k_nbr_compact(const int *__restrict__ d
                                                         int *__restrict__ up, int *__restrict__ edge_i,
                                                         const int *__restrict__ stop = nullptr) {
     if (stop && *stop) return;  // a recorded build stopped: the upper rows may not fit
+    // the block's upper entries are one contiguous range [gu, gu + totu):
+    // they and their owners are gathered in LDS and written with coalesced
+    // stores (each thread writing its own few entries would leave partial
+    // lines)
+    __shared__ int s_up[BLOCK * SLOT];
+    __shared__ unsigned char s_own[BLOCK * SLOT];
     const int b = blockIdx.x;
     const int i = b * BLOCK + threadIdx.x;
     const int cn = i < n ? deg_n[i] : 0, cu = i < n ? deg_up[i] : 0;
@@ -525,19 +531,25 @@ __global__ void __launch_bounds__(BLOCK) k_nbr_compact(const int *__restrict__ d
     const int offu = block_exclusive_scan<BLOCK>(cu, &totu);
     const int gu = uoff[b];
     const int base = b * (BLOCK * SLOT);  // the block's slab
-    if (i >= n) return;
-    nbr_start[i] = base + offn;
-    up_start[i] = gu + offu;
-    unsigned m = upmask[i];
-    int q = gu + offu;
-    while (m) {
-        const int k = __ffs((int)m) - 1;
-        m &= m - 1;
-        up[q] = nslab[base + offn + k];
-        edge_i[q] = i;
-        q++;
+    if (i < n) {
+        nbr_start[i] = base + offn;
+        up_start[i] = gu + offu;
+        if (i == n - 1) up_start[n] = gu + offu + cu;
+        unsigned m = upmask[i];
+        int q = offu;
+        while (m) {
+            const int k = __ffs((int)m) - 1;
+            m &= m - 1;
+            s_up[q] = nslab[base + offn + k];
+            s_own[q] = (unsigned char)threadIdx.x;
+            q++;
+        }
     }
-    if (i == n - 1) up_start[n] = gu + offu + cu;
+    __syncthreads();
+    for (int k = threadIdx.x; k < totu; k += BLOCK) {
+        up[gu + k] = s_up[k];
+        edge_i[gu + k] = b * BLOCK + s_own[k];
+    }
 }
 
 // 64-bit sum of n int32 counts: each block writes its partial to
@@ -726,13 +738,18 @@ __global__ void __launch_bounds__(BLOCK) k_tri_compact(const int *__restrict__ t
     int total;
     const int off = block_exclusive_scan<BLOCK>(c, &total);
     const int g0 = block_off[b];
+    __shared__ unsigned char s_own[TRI_SLAB];  // owner edge of each entry of the block (coalesced stores)
     if (e < E) {
         tri_start[e] = g0 + off;
-        for (int u = 0; u < c; u++) tri_e[g0 + off + u] = e;
+        for (int u = 0; u < c && off + u < TRI_SLAB; u++) s_own[off + u] = (unsigned char)threadIdx.x;
         if (e == E - 1) tri_start[E] = g0 + off + c;
     }
+    __syncthreads();
     const int *src = slab + (long long)b * TRI_SLAB;
-    for (int k = threadIdx.x; k < total; k += BLOCK) tri_k[g0 + k] = src[k];
+    for (int k = threadIdx.x; k < total; k += BLOCK) {
+        tri_k[g0 + k] = src[k];
+        tri_e[g0 + k] = b * BLOCK + s_own[k];
+    }
 }
 
 // OrthoSize evaluated with the vertices in lexicographic order of their
@@ -907,10 +924,15 @@ __global__ void __launch_bounds__(BLOCK) k_tet_compact(const int *__restrict__ t
     int total;
     const int off = block_exclusive_scan<BLOCK>(c, &total);
     const int g0 = block_off[b];
+    __shared__ unsigned char s_own[TET_SLAB];  // owner triangle of each entry of the block (coalesced stores)
     if (t < T)
-        for (int u = 0; u < c; u++) tet_t[g0 + off + u] = t;
+        for (int u = 0; u < c && off + u < TET_SLAB; u++) s_own[off + u] = (unsigned char)threadIdx.x;
+    __syncthreads();
     const int *src = slab + (long long)b * TET_SLAB;
-    for (int k = threadIdx.x; k < total; k += BLOCK) tet_l[g0 + k] = src[k];
+    for (int k = threadIdx.x; k < total; k += BLOCK) {
+        tet_l[g0 + k] = src[k];
+        tet_t[g0 + k] = b * BLOCK + s_own[k];
+    }
 }
 
 // The AC2 tests of candidate edges and triangles as kernels of their own
