@@ -916,7 +916,8 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         tm.mark(ST_TRI_FILL);
         if (fixed) fill<int>(tri_start, 0, 1, s);  // no edge at run time leaves tri_start[0] unwritten
         if (E > 0 && !tri_two_pass) {
-            k_tri_compact<<<nbE, BLOCK, 0, s>>>(tri_cnt, E, tslab, tboff, tri_start, tri_k, tri_e, E_live);
+            k_tri_compact<<<(nbE + TRI_CB - 1) / TRI_CB, BLOCK, 0, s>>>(tri_cnt, E, tslab, tboff, tri_start, tri_k,
+                                                                       tri_e, E_live);
             LAUNCH_CHECK();
         } else if (T > 0) {
             k_triangles<TRI_FILL><<<nbE, BLOCK, 0, s>>>(atom, perm, nbr_start, nbr_cnt, nbr, up_start, up, edge_i, E, pp,
@@ -1055,10 +1056,13 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
             // (the longest); the streams join before the counts are read.
             // Measured on the 3M-atom shell: 2.470 ms per build against 2.508
             // on one stream (a kernel on either stream mostly fills the GPU,
-            // so the other stream's kernels run in its gaps). A profile that
-            // times these stages keeps one stream, and so does a build on
-            // fixed scratch (which creates no stream or event).
-            const bool one_stream = (tm.on && (tm.only < 0 || tm.only >= ST_TETRA)) || t_arena;
+            // so the other stream's kernels run in its gaps). Small builds
+            // keep one stream (the waits between streams cost more than the
+            // overlap gains: 260 atoms, 0.36 ms against 0.31), and so do a
+            // profile that times these stages and a build on fixed scratch
+            // (which creates no stream or event).
+            const bool one_stream =
+                n < (1 << 20) || (tm.on && (tm.only < 0 || tm.only >= ST_TETRA)) || t_arena;
             AuxStream *ax = one_stream ? nullptr : &aux_stream();
             hipStream_t s2 = ax ? ax->s : s;
             s_aux = ax ? ax->s : nullptr;

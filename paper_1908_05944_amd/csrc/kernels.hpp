@@ -725,30 +725,61 @@ __global__ void __launch_bounds__(BLOCK) k_triangles(const int4 *__restrict__ at
     for (int u = 0; u < kept; u++) dst[u] = slot[u * BLOCK + threadIdx.x];
 }
 
-// Moves block b's slab to its final place (block_off = exclusive scan of the
-// block totals) and writes the row starts.
+// Moves the slabs of TRI_CB consecutive blocks of the triangle pass to their
+// final place (block_off = exclusive scan of the block totals: the slabs'
+// outputs are consecutive) and writes the row starts; a thread takes
+// TRI_CB consecutive edges (one 16-byte load of counts and one store of
+// starts), so that the block scan and its barriers serve 4 * BLOCK edges.
+constexpr int TRI_CB = 4;
 __global__ void __launch_bounds__(BLOCK) k_tri_compact(const int *__restrict__ tri_cnt, int E,
                                                         const int *__restrict__ slab, const int *__restrict__ block_off,
                                                         int *__restrict__ tri_start, int *__restrict__ tri_k,
                                                         int *__restrict__ tri_e, const int *__restrict__ live = nullptr) {
+    static_assert(TRI_CB == 4, "one int4 of counts per thread");
     E = live_count(E, live);
-    const int b = blockIdx.x;
-    const int e = b * BLOCK + threadIdx.x;
-    const int c = e < E ? tri_cnt[e] : 0;
-    int total;
-    const int off = block_exclusive_scan<BLOCK>(c, &total);
-    const int g0 = block_off[b];
-    __shared__ unsigned char s_own[TRI_SLAB];  // owner edge of each entry of the block (coalesced stores)
-    if (e < E) {
-        tri_start[e] = g0 + off;
-        for (int u = 0; u < c && off + u < TRI_SLAB; u++) s_own[off + u] = (unsigned char)threadIdx.x;
-        if (e == E - 1) tri_start[E] = g0 + off + c;
+    const int nb = E / BLOCK + (E % BLOCK != 0);  // blocks of the triangle pass
+    const int b0 = blockIdx.x * TRI_CB;            // its first block here
+    const long long e0 = (long long)blockIdx.x * (TRI_CB * BLOCK) + (long long)threadIdx.x * TRI_CB;
+    int c[TRI_CB];
+    if (e0 + TRI_CB <= E) {
+        const int4 v = *reinterpret_cast<const int4 *>(tri_cnt + e0);
+        c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
+    } else {
+#pragma unroll
+        for (int u = 0; u < TRI_CB; u++) c[u] = e0 + u < E ? tri_cnt[e0 + u] : 0;
     }
+    const int mine = c[0] + c[1] + c[2] + c[3];
+    int total;
+    const int off = block_exclusive_scan<BLOCK>(mine, &total);
+    const int g0 = b0 < nb ? block_off[b0] : 0;
+    // owner edge (index in this block's TRI_CB * BLOCK edges) of each entry
+    __shared__ unsigned short s_own[TRI_CB * TRI_SLAB];
+    __shared__ int sub[TRI_CB + 1];  // entries before each of the blocks' slabs
+    if (threadIdx.x <= TRI_CB) sub[threadIdx.x] = block_off[min(b0 + (int)threadIdx.x, nb)] - g0;
+    int st[TRI_CB], o = off;
+#pragma unroll
+    for (int u = 0; u < TRI_CB; u++) {
+        st[u] = g0 + o;
+        for (int w = 0; w < c[u] && o + w < TRI_CB * TRI_SLAB; w++)
+            s_own[o + w] = (unsigned short)(threadIdx.x * TRI_CB + u);
+        o += c[u];
+    }
+    if (e0 + TRI_CB <= E) {
+        *reinterpret_cast<int4 *>(tri_start + e0) = make_int4(st[0], st[1], st[2], st[3]);
+    } else {
+#pragma unroll
+        for (int u = 0; u < TRI_CB; u++)
+            if (e0 + u < E) tri_start[e0 + u] = st[u];
+    }
+    if (e0 <= E - 1 && E - 1 < e0 + TRI_CB) tri_start[E] = g0 + off + mine;
     __syncthreads();
-    const int *src = slab + (long long)b * TRI_SLAB;
+    const long long ebase = (long long)blockIdx.x * (TRI_CB * BLOCK);
     for (int k = threadIdx.x; k < total; k += BLOCK) {
-        tri_k[g0 + k] = src[k];
-        tri_e[g0 + k] = b * BLOCK + s_own[k];
+        int j = 0;
+#pragma unroll
+        for (int q = 1; q < TRI_CB; q++) j += k >= sub[q];
+        tri_k[g0 + k] = slab[(long long)(b0 + j) * TRI_SLAB + (k - sub[j])];
+        tri_e[g0 + k] = (int)(ebase + s_own[k]);
     }
 }
 
