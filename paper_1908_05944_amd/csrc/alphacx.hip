@@ -406,9 +406,18 @@ static EmitKeys emit_keys(int n, long long M) {
     return k;
 }
 
+// start[0..nb] of the ranges of key >> shift in m sorted keys (k_key_starts).
+static void key_starts(const unsigned *key, long long m, int shift, int nb, int *start, hipStream_t s,
+                       const int *live = nullptr) {
+    const long long threads = m / KS_PT + 1;  // rows 0..m
+    k_key_starts<<<(unsigned)((threads + KS_BLOCK - 1) / KS_BLOCK), KS_BLOCK, 0, s>>>(key, (int)m, shift, nb, start,
+                                                                                    live);
+    LAUNCH_CHECK();
+}
+
 // Emit dimension d = K - 1 from the candidates' keys (least input id; not
 // kept: the drop key) and payloads: a radix sort over the key bits above the
-// bucket makes each bucket of EK_KEYS ids contiguous, k_emit_bounds finds the
+// bucket makes each bucket of EK_KEYS ids contiguous, k_key_starts finds the
 // buckets' starts and k_emit_block orders each bucket and writes its rows.
 // The output arrays have room for all M candidates; the kept count goes to
 // *m_out on the device. live: the count is read on the device (at most M).
@@ -429,9 +438,7 @@ static void emit_dim(unsigned *key, typename EmitPay<K>::type *pay, const double
     radix_sort<P>(key, pay, M, ek.shift, ek.bits, s, sc, &gkey, &gpay, live);
     const int nb = (int)(ek.drop >> ek.shift);
     int *start = sc.get<int>((size_t)nb + 1);
-    const long long bthreads = (long long)M / EK_BOUNDS_PT + 1;  // rows 0..M
-    k_emit_bounds<<<(unsigned)((bthreads + EK_BOUNDS_BLOCK - 1) / EK_BOUNDS_BLOCK), EK_BOUNDS_BLOCK, 0, s>>>(
-        key, M, ek.shift, nb, start, live);
+    key_starts(key, M, ek.shift, nb, start, s, live);
     LAUNCH_CHECK();
     k_emit_block<K><<<(unsigned)nb, EK_BLOCK, 0, s>>>(key, pay, start, ek.shift, nb, gkey, gpay, size_in,
                                                      to_A2 ? 1 : 0, res->d_simp[d], res->d_size[d], m_out);
@@ -745,14 +752,16 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         k_cell_key<<<grid_for(n), BLOCK, 0, s>>>(q, n, d_grids, n_mol, ckey, cidx);
         LAUNCH_CHECK();
         radix_sort<unsigned>(ckey, cidx, n, bits_for(ncell), s, sc);
+        // the cell table from the populations (most cells are empty, so the
+        // starts are not taken from the sorted keys as the emit's buckets are:
+        // one thread would fill each run of empty cells)
         fill<int>(cell_count, 0, ncell, s);
         k_cell_runs<<<grid_for(n), BLOCK, 0, s>>>(ckey, n, cell_count);
         LAUNCH_CHECK();
         scan_i32(cell_count, cell_start, ncell, s, sc);
         int4 *atom = sc.get<int4>(n);
         int *perm = sc.get<int>(n);
-        k_gather_atoms<<<grid_for(n), BLOCK, 0, s>>>(q, cidx, n, atom, perm);
-        k_dup_check<<<grid_for(n), BLOCK, 0, s>>>(atom, ckey, n, cnt);
+        k_gather_atoms<<<grid_for(n), BLOCK, 0, s>>>(q, cidx, ckey, n, atom, perm, cnt);
         LAUNCH_CHECK();
 
         // ---- neighbours and candidate edges: one pass into per-block slabs,

@@ -9,7 +9,7 @@
 // consecutive ids (at most EK_KEYS; smaller for small inputs, so that there
 // are some hundred buckets). A stable LSD radix sort over the key bits above
 // the bucket (8-bit passes) makes every bucket's rows contiguous, the dropped
-// rows last; k_emit_bounds finds where each
+// rows last; k_key_starts finds where each
 // bucket starts, and k_emit_block finishes one bucket per block in LDS: it
 // loads the bucket's rows, counts the rows of each id with LDS atomics, scans
 // the counts, orders the rows by id, ranks each row in its id's group by the
@@ -91,7 +91,6 @@ __device__ __forceinline__ double pay_size(const uint4 &q, const double *__restr
 constexpr int EK_SHIFT = 9;              // largest bucket: 2^EK_SHIFT ids
 constexpr int EK_KEYS = 1 << EK_SHIFT;
 constexpr int EK_BLOCK = 256;
-constexpr int EK_BOUNDS_BLOCK = 256;
 // Rows a block orders in LDS, per dimension: its payload words, 16-bit ids and
 // order take 16 (edges), 20 (triangles, tetrahedra) bytes a row, so that an
 // edge block (about 35 KB) leaves room for four blocks per CU. The host picks
@@ -99,36 +98,6 @@ constexpr int EK_BOUNDS_BLOCK = 256;
 // row is keyed by its least id, so the lowest ids of a randomly numbered
 // input key about K times the mean number of rows per id).
 template <int K> constexpr int ek_rows() { return K == 4 ? 512 : 2048; }
-
-// start[c] = the first row whose key >> shift is at least c, for c = 0..nb
-// (rows sorted by key >> shift; row p, 0 <= p <= m, writes the starts of the
-// buckets in (bucket of row p - 1, bucket of row p], with row m in bucket nb).
-// A thread takes EK_BOUNDS_PT consecutive rows (one 16-byte load). `key` is
-// 16-byte aligned.
-constexpr int EK_BOUNDS_PT = 4;
-__global__ void __launch_bounds__(EK_BOUNDS_BLOCK) k_emit_bounds(const unsigned *__restrict__ key, int m, int shift, int nb,
-                                                        int *__restrict__ start, const int *__restrict__ live = nullptr) {
-    m = live_count(m, live);
-    const long long p0 = ((long long)blockIdx.x * EK_BOUNDS_BLOCK + threadIdx.x) * EK_BOUNDS_PT;
-    if (p0 > m) return;
-    unsigned k[EK_BOUNDS_PT];
-    if (p0 + EK_BOUNDS_PT <= m) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(key + p0);
-        k[0] = v.x; k[1] = v.y; k[2] = v.z; k[3] = v.w;
-    } else {
-#pragma unroll
-        for (int u = 0; u < EK_BOUNDS_PT; u++) k[u] = p0 + u < m ? key[p0 + u] : 0u;
-    }
-    int prev = p0 == 0 ? -1 : min((int)(key[p0 - 1] >> shift), nb);
-#pragma unroll
-    for (int u = 0; u < EK_BOUNDS_PT; u++) {
-        const long long p = p0 + u;
-        if (p > m) break;
-        const int cur = p == m ? nb : min((int)(k[u] >> shift), nb);
-        for (int c = prev + 1; c <= cur; c++) start[c] = (int)p;
-        prev = cur;
-    }
-}
 
 template <int K>
 __device__ __forceinline__ void write_row(int *__restrict__ out, long long pos, unsigned k, const unsigned (&r)[3]) {

@@ -253,28 +253,36 @@ __global__ void __launch_bounds__(BLOCK) k_cell_runs(const unsigned *__restrict_
     cell_count[c] = e - p;
 }
 
-// Sorted balls and their input indices (one gather per ball).
+// Sorted balls and their input indices (one gather per ball), and the check
+// for equal centres: they share a cell, so they are adjacent in the sorted
+// order; each ball compares itself with the following balls of its cell (of
+// this block from LDS, past its end from their inputs).
 __global__ void __launch_bounds__(BLOCK) k_gather_atoms(const int4 *__restrict__ q, const unsigned *__restrict__ idx,
-                                                         int n, int4 *__restrict__ atom, int *__restrict__ perm) {
-    const int p = blockIdx.x * BLOCK + threadIdx.x;
+                                                         const unsigned *__restrict__ key, int n,
+                                                         int4 *__restrict__ atom, int *__restrict__ perm, Counters *cnt) {
+    __shared__ int4 sa[BLOCK];
+    __shared__ unsigned sk[BLOCK];
+    const int b0 = blockIdx.x * BLOCK;
+    const int p = b0 + threadIdx.x;
+    int4 a = make_int4(0, 0, 0, 0);
+    unsigned c = 0;
+    if (p < n) {
+        const int me = (int)idx[p];
+        a = q[me];
+        c = key[p];
+        atom[p] = a;
+        perm[p] = me;
+    }
+    sa[threadIdx.x] = a;
+    sk[threadIdx.x] = c;
+    __syncthreads();
     if (p >= n) return;
-    const int me = (int)idx[p];
-    atom[p] = q[me];
-    perm[p] = me;
-}
-
-// Equal centres share a cell, so they are adjacent in the sorted order:
-// each ball compares itself with the following balls of its cell.
-__global__ void __launch_bounds__(BLOCK) k_dup_check(const int4 *__restrict__ atom, const unsigned *__restrict__ key,
-                                                      int n, Counters *cnt) {
-    const int p = blockIdx.x * BLOCK + threadIdx.x;
-    if (p >= n) return;
-    const int4 a = atom[p];
-    const unsigned c = key[p];
     bool dup = false;
-    for (int k = p + 1; k < n && key[k] == c; k++) {
-        const int4 b = atom[k];
-        dup |= b.x == a.x && b.y == a.y && b.z == a.z;
+    for (int k = p + 1; k < n; k++) {
+        const int t = k - b0;
+        if ((t < BLOCK ? sk[t] : key[k]) != c) break;
+        const int4 o = t < BLOCK ? sa[t] : q[idx[k]];
+        dup |= o.x == a.x && o.y == a.y && o.z == a.z;
     }
     if (dup) cnt->dup = 1;
 }
@@ -391,7 +399,7 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
                                 const int d2 = __mul24(dx, dx) + __mul24(dy, dy) + __mul24(dz, dz);
                                 const int rb2 = bb.w + (int)pp.aq;
                                 const int L = d2 - ra - rb2;
-                                // d2 == 0: the ball itself (equal centres are reported by k_dup_check)
+                                // d2 == 0: the ball itself (equal centres are reported by k_gather_atoms)
                                 meet = (d2 <= lim) & (d2 != 0) &
                                        ((L <= 0) | ((double)L * (double)L <= ra4 * (double)rb2));
                             } else {
@@ -403,7 +411,7 @@ __global__ void __launch_bounds__(BLOCK) k_neighbours(const int4 *__restrict__ a
                                 const int d2 = dx * dx + dy * dy + dz * dz;
                                 const int rb2 = bb.w + (int)pp.aq;
                                 const int L = d2 - ra - rb2;
-                                // grown balls meet: d <= rho_a + rho_b; equal centres are reported by k_dup_check
+                                // grown balls meet: d <= rho_a + rho_b; equal centres are reported by k_gather_atoms
                                 meet = (j != i) & (d2 <= lim) & (d2 != 0) & (rb2 >= 0) &
                                        ((L <= 0) | ((i64)L * L <= 4 * (i64)ra * rb2));
                             }

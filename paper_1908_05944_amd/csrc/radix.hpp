@@ -192,4 +192,37 @@ __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const unsigned *__restr
     }
 }
 
+// Starts of key ranges in sorted keys: start[c] = the first row whose
+// key >> shift is at least c, for c = 0..nb (rows sorted by key >> shift; row
+// p, 0 <= p <= m, writes the starts of the ranges in (range of row p - 1,
+// range of row p], with row m in range nb). The bucket starts of the emit
+// (every bucket holds rows, so each thread fills only a few starts). A thread
+// takes KS_PT consecutive rows (one 16-byte load); `key` is 16-byte aligned.
+// One pass over the keys: no count array, no scan.
+constexpr int KS_BLOCK = 256;
+constexpr int KS_PT = 4;
+__global__ void __launch_bounds__(KS_BLOCK) k_key_starts(const unsigned *__restrict__ key, int m, int shift, int nb,
+                                                        int *__restrict__ start, const int *__restrict__ live = nullptr) {
+    m = live_count(m, live);
+    const long long p0 = ((long long)blockIdx.x * KS_BLOCK + threadIdx.x) * KS_PT;
+    if (p0 > m) return;
+    unsigned k[KS_PT];
+    if (p0 + KS_PT <= m) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(key + p0);
+        k[0] = v.x; k[1] = v.y; k[2] = v.z; k[3] = v.w;
+    } else {
+#pragma unroll
+        for (int u = 0; u < KS_PT; u++) k[u] = p0 + u < m ? key[p0 + u] : 0u;
+    }
+    int prev = p0 == 0 ? -1 : min((int)(key[p0 - 1] >> shift), nb);
+#pragma unroll
+    for (int u = 0; u < KS_PT; u++) {
+        const long long p = p0 + u;
+        if (p > m) break;
+        const int cur = p == m ? nb : min((int)(k[u] >> shift), nb);
+        for (int c = prev + 1; c <= cur; c++) start[c] = (int)p;
+        prev = cur;
+    }
+}
+
 }  // namespace acx
