@@ -108,18 +108,46 @@ constexpr int SCAN_BLOCK = 256;
 constexpr int SCAN_IPT = 8;
 constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_IPT;
 
+// IPT consecutive ints at p[base..base + IPT), zero past n: 16-byte loads
+// when the run is whole and p is 16-byte aligned (a lane's run is one
+// 16-byte-multiple piece: 4 vector instead of 16 scalar loads per thread).
+template <int IPT>
+__device__ __forceinline__ void load_run(const int *__restrict__ p, long long base, long long n, int (&v)[IPT]) {
+    static_assert(IPT % 4 == 0, "whole int4 pieces");
+    if (base + IPT <= n && ((reinterpret_cast<uintptr_t>(p) & 15) == 0)) {
+        const int4 *q = reinterpret_cast<const int4 *>(p + base);
+#pragma unroll
+        for (int k = 0; k < IPT / 4; k++) {
+            const int4 x = q[k];
+            v[4 * k] = x.x; v[4 * k + 1] = x.y; v[4 * k + 2] = x.z; v[4 * k + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < IPT; k++) v[k] = base + k < n ? p[base + k] : 0;
+    }
+}
+template <int IPT>
+__device__ __forceinline__ void store_run(int *__restrict__ p, long long base, long long n, const int (&v)[IPT]) {
+    if (base + IPT <= n && ((reinterpret_cast<uintptr_t>(p) & 15) == 0)) {
+        int4 *q = reinterpret_cast<int4 *>(p + base);
+#pragma unroll
+        for (int k = 0; k < IPT / 4; k++) q[k] = make_int4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < IPT; k++)
+            if (base + k < n) p[base + k] = v[k];
+    }
+}
+
 __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_tiles(const int *__restrict__ in, int *__restrict__ out,
                                                             int *__restrict__ tile_sums, long long n) {
     __shared__ int wsum[SCAN_BLOCK / WAVE];
     const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_IPT;
     int v[SCAN_IPT];
+    load_run<SCAN_IPT>(in, base, n, v);
     int s = 0;
 #pragma unroll
-    for (int k = 0; k < SCAN_IPT; k++) {
-        const long long i = base + k;
-        v[k] = i < n ? in[i] : 0;
-        s += v[k];
-    }
+    for (int k = 0; k < SCAN_IPT; k++) s += v[k];
     const int incl = wave_inclusive_scan(s);
     const int w = threadIdx.x / WAVE, lane = lane_id();
     if (lane == WAVE - 1) wsum[w] = incl;
@@ -129,10 +157,11 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_tiles(const int *__restrict
     int run = woff + incl - s;
 #pragma unroll
     for (int k = 0; k < SCAN_IPT; k++) {
-        const long long i = base + k;
-        if (i < n) out[i] = run;
-        run += v[k];
+        const int x = v[k];
+        v[k] = run;
+        run += x;
     }
+    store_run<SCAN_IPT>(out, base, n, v);
     if (threadIdx.x == SCAN_BLOCK - 1) {
         int tot = 0;
         for (int k = 0; k < SCAN_BLOCK / WAVE; k++) tot += wsum[k];
@@ -152,13 +181,10 @@ __global__ void __launch_bounds__(SCAN_SMALL_BLOCK) k_scan_small(const int *__re
     __shared__ int wsum[SCAN_SMALL_BLOCK / WAVE];
     const int base = threadIdx.x * SCAN_SMALL_IPT;
     int v[SCAN_SMALL_IPT];
+    load_run<SCAN_SMALL_IPT>(in, base, n, v);
     int s = 0;
 #pragma unroll
-    for (int k = 0; k < SCAN_SMALL_IPT; k++) {
-        const int i = base + k;
-        v[k] = i < n ? in[i] : 0;
-        s += v[k];
-    }
+    for (int k = 0; k < SCAN_SMALL_IPT; k++) s += v[k];
     const int incl = wave_inclusive_scan(s);
     const int w = threadIdx.x / WAVE;
     if (lane_id() == WAVE - 1) wsum[w] = incl;
@@ -167,10 +193,11 @@ __global__ void __launch_bounds__(SCAN_SMALL_BLOCK) k_scan_small(const int *__re
     for (int k = 0; k < w; k++) run += wsum[k];
 #pragma unroll
     for (int k = 0; k < SCAN_SMALL_IPT; k++) {
-        const int i = base + k;
-        if (i < n) out[i] = run;
-        run += v[k];
+        const int x = v[k];
+        v[k] = run;
+        run += x;
     }
+    store_run<SCAN_SMALL_IPT>(out, base, n, v);
     if (threadIdx.x == SCAN_SMALL_BLOCK - 1) {
         out[n] = run;
         if (total_to) *total_to = run;
