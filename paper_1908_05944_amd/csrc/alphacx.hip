@@ -777,7 +777,7 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         const int slot = (pp.sgc > 1900 && pp.sgc <= 2600) ? NB_SLOT_WIDE : NB_SLOT;
         if (fx && fx->learn) fx->slot = slot;
         const long long nb_slab = (long long)BLOCK * slot;
-        int *nslab = sc.get<int>((size_t)nbN * nb_slab);
+        int *nslab = sc.get<int>((size_t)nbN * nb_slab + NBR_PAD);
         unsigned *upmask = sc.get<unsigned>(n);
         int *nbtot = sc.get<int>(2 * (size_t)nbN);
         int *nboff = sc.get<int>(nbN + 1), *uboff = sc.get<int>(nbN + 1);
@@ -834,7 +834,7 @@ static ac_status run_pipeline(const double *d_xyz, const double *d_r, int64_t n6
         if (fx && fx->learn) fx->E = E;
         const int *E_live = fixed ? &cnt->El : nullptr;  // fixed: the launches below read the count
         // neighbour rows: in the slabs after the one-pass search, else in CSR
-        int *nbr = nbr_two_pass ? sc.get<int>(Nn > 0 ? Nn : 1) : nslab;
+        int *nbr = nbr_two_pass ? sc.get<int>((size_t)(Nn > 0 ? Nn : 1) + NBR_PAD) : nslab;
         int *up = sc.get<int>(E > 0 ? E : 1);
         int *edge_i = sc.get<int>(E > 0 ? E : 1);
         tm.mark(ST_NBR_FILL);

@@ -625,6 +625,10 @@ __device__ __forceinline__ int find_tri(const int *__restrict__ up_start, const 
 enum { TRI_ONEPASS = 0, TRI_FILL = 1 };
 constexpr int TRI_SLOT = 8;
 constexpr int AC2_GROUP = 4;  // neighbours loaded together in the edge AC2 loop
+// Neighbour arrays are allocated AC2_GROUP - 1 entries longer, so that the
+// last group of a row can be loaded whole (entries past the row are
+// replaced, not used).
+constexpr int NBR_PAD = AC2_GROUP - 1;
 constexpr int TRI_SLAB = 1024;
 
 // AC2 of candidate edge e = (i, j) at its own ortho-centre (Step 4): every
@@ -646,7 +650,10 @@ __device__ __forceinline__ void edge_ac2(const int4 *__restrict__ atom, const in
         int qs[AC2_GROUP];
         int4 aqs[AC2_GROUP];
 #pragma unroll
-        for (int u = 0; u < AC2_GROUP; u++) qs[u] = p0 + u < ne ? nbr[p0 + u] : j;
+        for (int u = 0; u < AC2_GROUP; u++) {
+            const int r = nbr[p0 + u];  // in bounds: NBR_PAD
+            qs[u] = p0 + u < ne ? r : j;
+        }
 #pragma unroll
         for (int u = 0; u < AC2_GROUP; u++) aqs[u] = atom[qs[u]];
 #pragma unroll
