@@ -847,6 +847,7 @@ __device__ __forceinline__ double tet_size_canon(int4 a, int4 b, int4 c, int4 d,
 enum { TET_ONEPASS = 0, TET_FILL = 1 };
 constexpr int TET_SLOT = 4;
 constexpr int TET_SLAB = 256;
+constexpr int TRI_AC2_GROUP = 2;  // neighbours loaded together in the triangle AC2 loop (<= AC2_GROUP)
 
 // AC2 of candidate triangle t = (i, j, k) at its own ortho-centre (Step 3;
 // violators are in i's neighbour row) and its OrthoSize. Writes tgab[t],
@@ -861,16 +862,29 @@ __device__ __forceinline__ void tri_ac2(const int4 *__restrict__ atom, const int
     const Tri tr = tri_setup(vi, vj, vk, pp);
     bool viol = false;
     const int ns = nbr_start[i], ne = ns + nbr_cnt[i];
-    for (int p = ns; p < ne; p++) {
-        const int q = nbr[p];
-        const int4 aq = atom[q];
-        const bool other = (q != j) & (q != k);
-        int sg = pp.force_exact ? 0 : tri_violation_filter(tr, aq);
-        if (sg == 0 && other) {
-            if (!pp.force_exact) note_fallback(cnt);
-            sg = tri_violation_exact(tr, i, j, k, aq, q, perm);
+    // neighbours in pairs, both loads issued before the first test (the
+    // index pair is one load: the arrays are padded)
+    for (int p0 = ns; p0 < ne; p0 += TRI_AC2_GROUP) {
+        int qs[TRI_AC2_GROUP];
+        int4 aqs[TRI_AC2_GROUP];
+#pragma unroll
+        for (int u = 0; u < TRI_AC2_GROUP; u++) {
+            const int r = nbr[p0 + u];  // in bounds: NBR_PAD
+            qs[u] = p0 + u < ne ? r : j;  // padding repeats j, which is never tested
         }
-        viol |= (sg < 0) & other;
+#pragma unroll
+        for (int u = 0; u < TRI_AC2_GROUP; u++) aqs[u] = atom[qs[u]];
+#pragma unroll
+        for (int u = 0; u < TRI_AC2_GROUP; u++) {
+            const int q = qs[u];
+            const bool other = (q != j) & (q != k);
+            int sg = pp.force_exact ? 0 : tri_violation_filter(tr, aqs[u]);
+            if (sg == 0 && other) {
+                if (!pp.force_exact) note_fallback(cnt);
+                sg = tri_violation_exact(tr, i, j, k, aqs[u], q, perm);
+            }
+            viol |= (sg < 0) & other;
+        }
     }
     tgab[t] = (unsigned char)!viol;
     if (viol) tri_min[t] = ORDERED_POS_INF;
