@@ -1062,10 +1062,25 @@ __global__ void __launch_bounds__(BLOCK) k_tet_ac2(const int4 *__restrict__ atom
     const Tet te = tet_setup(atom[i], atom[j], atom[k], atom[l], pp);
     bool keep = true;
     const int ns = nbr_start[i], ne = ns + nbr_cnt[i];
-    for (int p = ns; p < ne; p++) {
-        const int q = nbr[p];
-        if (q == j || q == k || q == l) continue;
-        if (tet_violation_sign(te, i, j, k, l, atom[q], q, perm, pp, cnt) < 0) { keep = false; break; }
+    // neighbours in groups whose loads are all issued before the first test
+    // (few tetrahedra: a thread's chain of dependent loads is the kernel's
+    // time); the index group is one load (the arrays are padded)
+    for (int p0 = ns; p0 < ne && keep; p0 += AC2_GROUP) {
+        int qs[AC2_GROUP];
+        int4 aqs[AC2_GROUP];
+#pragma unroll
+        for (int u = 0; u < AC2_GROUP; u++) {
+            const int r = nbr[p0 + u];  // in bounds: NBR_PAD
+            qs[u] = p0 + u < ne ? r : j;  // padding repeats j, which is never tested
+        }
+#pragma unroll
+        for (int u = 0; u < AC2_GROUP; u++) aqs[u] = atom[qs[u]];
+#pragma unroll
+        for (int u = 0; u < AC2_GROUP; u++) {
+            const int q = qs[u];
+            if (!keep || q == j || q == k || q == l) continue;
+            if (tet_violation_sign(te, i, j, k, l, aqs[u], q, perm, pp, cnt) < 0) keep = false;
+        }
     }
     if (SWEEP) qin[c] = (unsigned char)keep;
     if (!keep) {
