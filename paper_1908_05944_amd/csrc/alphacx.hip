@@ -461,7 +461,9 @@ static AuxStream &aux_stream() {
     AuxStream &a = per_dev[dev];
     if (!a.s) {
         HIP_TRY(hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking));
-        for (hipEvent_t &e : a.ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        // order between two streams of one device: a device-scope release
+        // suffices (no system-scope fence, no timing)
+        for (hipEvent_t &e : a.ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventDisableSystemFence));
     }
     return a;
 }
@@ -515,7 +517,15 @@ constexpr int PROFILE_SPLIT = ST_COUNT + 2;
 
 // Events at stage boundaries. Each recorded event costs a few microseconds of
 // idle device time between two kernels, so a caller may ask for one stage
-// only (its two boundary events).
+// only (its two boundary events). The events come from a per-thread pool
+// (creating one in the middle of a build would hold up the host's launches),
+// one pool per device (an event belongs to the device it was created on).
+static std::vector<hipEvent_t> &event_pool() {
+    thread_local std::map<int, std::vector<hipEvent_t>> pools;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    return pools[dev];
+}
 struct StageTimer {
     bool on = false;
     int only = -1;  // >= 0: record the boundaries of this stage only
@@ -535,7 +545,15 @@ struct StageTimer {
         const bool need = only < 0 || i == only || cur == only;
         if (need) {
             hipEvent_t e;
-            HIP_TRY(hipEventCreate(&e));
+            std::vector<hipEvent_t> &pool = event_pool();
+            if (!pool.empty()) {
+                e = pool.back();
+                pool.pop_back();
+            } else {
+                // timing only: no system-scope fence (an L2 writeback and
+                // invalidate at every record, which stalls the next kernels)
+                HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+            }
             ev.push_back(e);
             HIP_TRY(hipEventRecord(e, s));
             const int k = (int)ev.size() - 1;
@@ -554,7 +572,15 @@ struct StageTimer {
         }
     }
     ~StageTimer() {
-        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        // back to the pool of this thread and device, for a later build (a
+        // re-record of an event still pending only moves it)
+        if (ev.empty()) return;
+        try {
+            std::vector<hipEvent_t> &pool = event_pool();
+            for (hipEvent_t e : ev) pool.push_back(e);
+        } catch (...) {
+            for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        }
     }
 };
 
