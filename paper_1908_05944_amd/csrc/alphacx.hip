@@ -432,6 +432,13 @@ static void emit_dim(unsigned *key, typename EmitPay<K>::type *pay, const double
         fill<int>(m_out, 0, 1, s);
         return;
     }
+    if (n <= EK_KEYS && M <= ek_rows<K>()) {
+        // a few hundred balls: one block orders every row, no radix sort
+        k_emit_block<K><<<1, EK_BLOCK, 0, s>>>(key, pay, nullptr, EK_SHIFT, 1, nullptr, nullptr, size_in, to_A2 ? 1 : 0,
+                                              res->d_simp[d], res->d_size[d], m_out, n, M, live);
+        LAUNCH_CHECK();
+        return;
+    }
     const EmitKeys ek = emit_keys<K>(n, M);
     unsigned *gkey = nullptr;
     P *gpay = nullptr;

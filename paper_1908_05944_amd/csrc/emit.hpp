@@ -123,6 +123,11 @@ __device__ __forceinline__ bool ids_less(const unsigned (&v)[3], const unsigned 
 // entries) are scratch for a bucket with more than ek_rows<K>() rows. Sizes are
 // converted from mA^2 to A^2 when to_A2 is set (emit of a build), else copied
 // (merge of rows that are already output).
+// single > 0: one block takes every row unsorted (at most ek_rows<K>(), ids
+// below single <= EK_KEYS, shift EK_SHIFT): the rows whose key is single or
+// more are dropped ones and skipped, and the block writes the kept count.
+// `start` is then unused and the row count is rows_cap, or *live if given.
+// A build of a few hundred balls then needs no radix sort.
 template <int K>
 __global__ void __launch_bounds__(EK_BLOCK) k_emit_block(const unsigned *__restrict__ key,
                                                           const typename EmitPay<K>::type *__restrict__ pay,
@@ -131,7 +136,8 @@ __global__ void __launch_bounds__(EK_BLOCK) k_emit_block(const unsigned *__restr
                                                           typename EmitPay<K>::type *__restrict__ gpay,
                                                           const double *__restrict__ size_in, int to_A2,
                                                           int *__restrict__ out, double *__restrict__ out_size,
-                                                          int *__restrict__ m_out) {
+                                                          int *__restrict__ m_out, int single = 0, int rows_cap = 0,
+                                                          const int *__restrict__ live = nullptr) {
     typedef typename EmitPay<K>::type P;
     constexpr int W = K == 2 ? 3 : 4;  // payload words
     constexpr int ROWS = ek_rows<K>();
@@ -141,9 +147,11 @@ __global__ void __launch_bounds__(EK_BLOCK) k_emit_block(const unsigned *__restr
     __shared__ int cnt[EK_KEYS + 1];           // rows per id, then each id's first place
     __shared__ int cur[EK_KEYS];
     __shared__ int wsum[EK_BLOCK / WAVE];
+    constexpr unsigned short DROPPED = 0xFFFF;  // skey of a skipped row (single block)
     const int b = blockIdx.x, t = threadIdx.x;
-    if (b == 0 && t == 0) *m_out = start[nb];
-    const int bs = start[b], rows = start[b + 1] - bs;
+    const bool one = single > 0;
+    if (!one && b == 0 && t == 0) *m_out = start[nb];
+    const int bs = one ? 0 : start[b], rows = one ? live_count(rows_cap, live) : start[b + 1] - bs;
     const unsigned k0 = (unsigned)b << shift;  // the bucket's ids: [k0, k0 + 2^shift), 2^shift <= EK_KEYS
     for (int k = t; k <= EK_KEYS; k += EK_BLOCK) cnt[k] = 0;
     __syncthreads();
@@ -164,9 +172,10 @@ __global__ void __launch_bounds__(EK_BLOCK) k_emit_block(const unsigned *__restr
         for (int u = 0; u < 4; u++) {
             const int p = p0 + u * EK_BLOCK;
             if (p >= rows) continue;
-            atomicAdd(&cnt[kk[u]], 1);
+            const bool drop = one && kk[u] >= (unsigned)single;  // k0 = 0 in a single block
+            if (!drop) atomicAdd(&cnt[kk[u]], 1);
             if (lds) {
-                skey[p] = (unsigned short)kk[u];
+                skey[p] = drop ? DROPPED : (unsigned short)kk[u];
                 sw[0][p] = q[u].x;
                 sw[1][p] = q[u].y;
                 sw[2][p] = q[u].z;
@@ -196,15 +205,20 @@ __global__ void __launch_bounds__(EK_BLOCK) k_emit_block(const unsigned *__restr
             cur[t * PT + u] = run;
             run += c[u];
         }
-        if (t == EK_BLOCK - 1) cnt[EK_KEYS] = run;
+        if (t == EK_BLOCK - 1) {
+            cnt[EK_KEYS] = run;
+            if (one) *m_out = run;  // the kept rows
+        }
     }
     __syncthreads();
     if (lds) {
         // order the rows by id (within an id in atomics' order), then rank
         // each row in its id's group by the remaining ids
-        for (int p = t; p < rows; p += EK_BLOCK) sord[atomicAdd(&cur[skey[p]], 1)] = (unsigned short)p;
+        for (int p = t; p < rows; p += EK_BLOCK)
+            if (skey[p] != DROPPED) sord[atomicAdd(&cur[skey[p]], 1)] = (unsigned short)p;
         __syncthreads();
-        for (int s = t; s < rows; s += EK_BLOCK) {
+        const int kept = one ? cnt[EK_KEYS] : rows;
+        for (int s = t; s < kept; s += EK_BLOCK) {
             const int p = sord[s];
             const int k = skey[p];
             const int g0 = cnt[k], g1 = cnt[k + 1];
