@@ -170,3 +170,26 @@ def test_counted_fill_inputs_have_no_plan(acx):
     with pytest.raises(acx.AlphaCxError) as ei:
         acx.Plan(X, R, np.array([0, m.n]), 0.0)
     assert ei.value.status == 6
+
+
+def test_large_plan_with_two_streams(acx):
+    """A recorded batch of more than 2^20 balls: its capture forks the emit
+    of tetrahedra, triangles and vertices onto a second stream and joins it
+    again; every replay must equal the ordinary batch build bit for bit."""
+    import torch
+    mols = [synth.molecule(20000, 4400 + i) for i in range(56)]
+    off = np.concatenate([[0], np.cumsum([m.n for m in mols])]).astype(np.int64)
+    assert off[-1] >= (1 << 20)
+    X = torch.from_numpy(np.concatenate([m.xyz for m in mols])).cuda()
+    R = torch.from_numpy(np.concatenate([m.radii for m in mols])).cuda()
+    print(f"[case] plan over {len(mols)} molecules, {int(off[-1])} balls", flush=True)
+    plan = acx.Plan(X, R, off, 0.0)
+    ref = acx.ac_alpha_complex_batch(X, R, off, 0.0)
+    for rep in range(2):
+        plan.launch()
+        got = plan.result()
+        assert plan.stopped() == 0
+        _same(got, ref, f"replay {rep}")
+        got.close()
+    ref.close()
+    plan.close()
