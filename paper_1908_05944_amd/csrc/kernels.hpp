@@ -625,10 +625,10 @@ __device__ __forceinline__ int find_tri(const int *__restrict__ up_start, const 
 enum { TRI_ONEPASS = 0, TRI_FILL = 1 };
 constexpr int TRI_SLOT = 8;
 constexpr int AC2_GROUP = 4;  // neighbours loaded together in the edge AC2 loop
-// Neighbour arrays are allocated AC2_GROUP - 1 entries longer, so that the
-// last group of a row can be loaded whole (entries past the row are
-// replaced, not used).
-constexpr int NBR_PAD = AC2_GROUP - 1;
+// Neighbour arrays are allocated AC2_GROUP entries longer, so that a group
+// that starts inside a row (or at its end) can be loaded whole (entries past
+// the row are replaced, not used).
+constexpr int NBR_PAD = AC2_GROUP;
 constexpr int TRI_SLAB = 1024;
 
 // AC2 of candidate edge e = (i, j) at its own ortho-centre (Step 4): every
@@ -646,14 +646,18 @@ __device__ __forceinline__ void edge_ac2(const int4 *__restrict__ atom, const in
     const int ns = nbr_start[i], ne = ns + nbr_cnt[i];
     const Edge ed = edge_setup(vi, vj);
     bool viol = false;
+    // the next group's indices are loaded while this group is tested
+    int nx[AC2_GROUP];
+#pragma unroll
+    for (int u = 0; u < AC2_GROUP; u++) nx[u] = nbr[ns + u];  // in bounds: NBR_PAD
     for (int p0 = ns; p0 < ne; p0 += AC2_GROUP) {
         int qs[AC2_GROUP];
         int4 aqs[AC2_GROUP];
 #pragma unroll
-        for (int u = 0; u < AC2_GROUP; u++) {
-            const int r = nbr[p0 + u];  // in bounds: NBR_PAD
-            qs[u] = p0 + u < ne ? r : j;
-        }
+        for (int u = 0; u < AC2_GROUP; u++) qs[u] = p0 + u < ne ? nx[u] : j;
+        const int pn = p0 + AC2_GROUP < ne ? p0 + AC2_GROUP : p0;  // the last group reloads itself
+#pragma unroll
+        for (int u = 0; u < AC2_GROUP; u++) nx[u] = nbr[pn + u];
 #pragma unroll
         for (int u = 0; u < AC2_GROUP; u++) aqs[u] = atom[qs[u]];
 #pragma unroll
@@ -863,15 +867,19 @@ __device__ __forceinline__ void tri_ac2(const int4 *__restrict__ atom, const int
     bool viol = false;
     const int ns = nbr_start[i], ne = ns + nbr_cnt[i];
     // neighbours in pairs, both loads issued before the first test (the
-    // index pair is one load: the arrays are padded)
+    // index pair is one load: the arrays are padded), the next pair's
+    // indices loaded while this pair is tested
+    int nx[TRI_AC2_GROUP];
+#pragma unroll
+    for (int u = 0; u < TRI_AC2_GROUP; u++) nx[u] = nbr[ns + u];  // in bounds: NBR_PAD
     for (int p0 = ns; p0 < ne; p0 += TRI_AC2_GROUP) {
         int qs[TRI_AC2_GROUP];
         int4 aqs[TRI_AC2_GROUP];
 #pragma unroll
-        for (int u = 0; u < TRI_AC2_GROUP; u++) {
-            const int r = nbr[p0 + u];  // in bounds: NBR_PAD
-            qs[u] = p0 + u < ne ? r : j;  // padding repeats j, which is never tested
-        }
+        for (int u = 0; u < TRI_AC2_GROUP; u++) qs[u] = p0 + u < ne ? nx[u] : j;  // padding repeats j, never tested
+        const int pn = p0 + TRI_AC2_GROUP < ne ? p0 + TRI_AC2_GROUP : p0;  // the last pair reloads itself
+#pragma unroll
+        for (int u = 0; u < TRI_AC2_GROUP; u++) nx[u] = nbr[pn + u];
 #pragma unroll
         for (int u = 0; u < TRI_AC2_GROUP; u++) aqs[u] = atom[qs[u]];
 #pragma unroll
