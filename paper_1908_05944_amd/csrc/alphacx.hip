@@ -417,9 +417,10 @@ static void key_starts(const unsigned *key, long long m, int shift, int nb, int 
 
 // Emit dimension d = K - 1 from the candidates' keys (least input id; not
 // kept: the drop key) and payloads: a radix sort over the key bits above the
-// bucket makes each bucket of EK_KEYS ids contiguous, k_key_starts finds the
-// buckets' starts and k_emit_block orders each bucket and writes its rows.
-// The output arrays have room for all M candidates; the kept count goes to
+// bucket (2^shift ids, emit_keys) makes each bucket contiguous, k_key_starts
+// finds the buckets' starts and k_emit_block orders each bucket and writes
+// its rows; up to EK_KEYS balls one block takes every row, unsorted. The
+// output arrays have room for all M candidates; the kept count goes to
 // *m_out on the device. live: the count is read on the device (at most M).
 template <int K>
 static void emit_dim(unsigned *key, typename EmitPay<K>::type *pay, const double *size_in, int M, int n,

@@ -93,7 +93,8 @@ __global__ void __launch_bounds__(BLOCK) k_vertex_rows(const int *__restrict__ k
 // slab's ids, and sel keeps their order), payload = the other input ids and
 // the Size bits (K = 2, 3), or the row's place idx_base + pos among the rows
 // of all slabs, whose Size goes to out_size[pos] (K = 4). Sizes stay in A^2.
-// k_emit_bucket then merges the rows of all slabs into output order.
+// The emit (radix sort by bucket, k_emit_block) then merges the rows of all
+// slabs into output order.
 template <int K>
 __global__ void __launch_bounds__(BLOCK) k_own_emit(const int *__restrict__ rows, const double *__restrict__ size, int m,
                                                      const int *__restrict__ flag, const int *__restrict__ pos,
