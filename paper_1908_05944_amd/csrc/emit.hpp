@@ -91,13 +91,22 @@ __device__ __forceinline__ double pay_size(const uint4 &q, const double *__restr
 constexpr int EK_SHIFT = 9;              // largest bucket: 2^EK_SHIFT ids
 constexpr int EK_KEYS = 1 << EK_SHIFT;
 constexpr int EK_BLOCK = 256;
-// Rows a block orders in LDS, per dimension: its payload words, 16-bit ids and
-// order take 16 (edges), 20 (triangles, tetrahedra) bytes a row, so that an
-// edge block (about 35 KB) leaves room for four blocks per CU. The host picks
-// each dimension's bucket size so that its expected largest bucket fits (a
-// row is keyed by its least id, so the lowest ids of a randomly numbered
-// input key about K times the mean number of rows per id).
+// Rows a block orders in LDS, per dimension. The host picks each dimension's
+// bucket size so that its expected largest bucket fits (a row is keyed by its
+// least id, so the lowest ids of a randomly numbered input key about K times
+// the mean number of rows per id).
 template <int K> constexpr int ek_rows() { return K == 4 ? 512 : 2048; }
+// What a row holds in LDS besides its 16-bit id in the bucket and its place
+// in the order. Edges: only the other id (8 bytes a row, about 18 KB a block,
+// eight blocks per CU); the Size bits are read again from the bucket's
+// payload when the row is written, from cache, as the block has just read
+// them. Triangles and tetrahedra: the whole payload (20 bytes a row; a
+// triangle block, about 42 KB, leaves room for three per CU). The edge emit
+// ends the build, so it gains from the occupancy; the triangle emit runs on
+// the second stream beside the edge path, and with the slim rows (six blocks
+// per CU) it took more of the GPU from that path than it saved: 2.26 ms per
+// build against 2.19 ms with edges alone slim and 2.22 ms with none.
+template <int K> constexpr bool ek_slim() { return K == 2; }
 
 template <int K>
 __device__ __forceinline__ void write_row(int *__restrict__ out, long long pos, unsigned k, const unsigned (&r)[3]) {
@@ -138,14 +147,16 @@ __global__ void __launch_bounds__(EK_BLOCK) k_emit_block(const unsigned *__restr
                                                           int *__restrict__ out, double *__restrict__ out_size,
                                                           int *__restrict__ m_out, int single = 0, int rows_cap = 0,
                                                           const int *__restrict__ live = nullptr) {
-    typedef typename EmitPay<K>::type P;
-    constexpr int W = K == 2 ? 3 : 4;  // payload words
+    constexpr int NI = K - 1;  // ids after the least
+    constexpr bool SLIM = ek_slim<K>();
+    constexpr int NW = SLIM ? NI : (K == 2 ? 3 : 4);  // payload words held in LDS
     constexpr int ROWS = ek_rows<K>();
-    __shared__ unsigned sw[W][ROWS];        // the bucket's payloads, in load order
+    __shared__ unsigned sid[NW][ROWS];      // the bucket's rows' other ids (payloads), in load order
     __shared__ unsigned short skey[ROWS];   // their ids less the bucket's first
     __shared__ unsigned short sord[ROWS];   // load positions in id order
-    __shared__ int cnt[EK_KEYS + 1];           // rows per id, then each id's first place
-    __shared__ int cur[EK_KEYS];
+    // rows per id; then each id's first place; after the ordering, where each
+    // id's group ends (= the next id's first place)
+    __shared__ int cnt[EK_KEYS + 1];
     __shared__ int wsum[EK_BLOCK / WAVE];
     constexpr unsigned short DROPPED = 0xFFFF;  // skey of a skipped row (single block)
     const int b = blockIdx.x, t = threadIdx.x;
@@ -156,9 +167,8 @@ __global__ void __launch_bounds__(EK_BLOCK) k_emit_block(const unsigned *__restr
     for (int k = t; k <= EK_KEYS; k += EK_BLOCK) cnt[k] = 0;
     __syncthreads();
     const bool lds = rows <= ROWS;
-    auto load = [&](int p) -> uint4 { return widen(pay[bs + p]); };
-    // counts per id (and, in LDS, the rows themselves); four rows per thread
-    // loaded together
+    // counts per id (and, in LDS, the rows' ids); four rows per thread loaded
+    // together
     for (int p0 = t; p0 < rows; p0 += 4 * EK_BLOCK) {
         unsigned kk[4];
         uint4 q[4];
@@ -166,7 +176,7 @@ __global__ void __launch_bounds__(EK_BLOCK) k_emit_block(const unsigned *__restr
         for (int u = 0; u < 4; u++) {
             const int p = p0 + u * EK_BLOCK;
             kk[u] = p < rows ? key[bs + p] - k0 : 0u;
-            q[u] = p < rows && lds ? load(p) : make_uint4(0u, 0u, 0u, 0u);
+            q[u] = p < rows && lds ? widen(pay[bs + p]) : make_uint4(0u, 0u, 0u, 0u);
         }
 #pragma unroll
         for (int u = 0; u < 4; u++) {
@@ -176,10 +186,10 @@ __global__ void __launch_bounds__(EK_BLOCK) k_emit_block(const unsigned *__restr
             if (!drop) atomicAdd(&cnt[kk[u]], 1);
             if (lds) {
                 skey[p] = drop ? DROPPED : (unsigned short)kk[u];
-                sw[0][p] = q[u].x;
-                sw[1][p] = q[u].y;
-                sw[2][p] = q[u].z;
-                if constexpr (W == 4) sw[W - 1][p] = q[u].w;
+                sid[0][p] = q[u].x;
+                if constexpr (NW >= 2) sid[1][p] = q[u].y;
+                if constexpr (NW >= 3) sid[2][p] = q[u].z;
+                if constexpr (NW >= 4) sid[3][p] = q[u].w;
             }
         }
     }
@@ -202,7 +212,6 @@ __global__ void __launch_bounds__(EK_BLOCK) k_emit_block(const unsigned *__restr
 #pragma unroll
         for (int u = 0; u < PT; u++) {
             cnt[t * PT + u] = run;
-            cur[t * PT + u] = run;
             run += c[u];
         }
         if (t == EK_BLOCK - 1) {
@@ -215,30 +224,35 @@ __global__ void __launch_bounds__(EK_BLOCK) k_emit_block(const unsigned *__restr
         // order the rows by id (within an id in atomics' order), then rank
         // each row in its id's group by the remaining ids
         for (int p = t; p < rows; p += EK_BLOCK)
-            if (skey[p] != DROPPED) sord[atomicAdd(&cur[skey[p]], 1)] = (unsigned short)p;
+            if (skey[p] != DROPPED) sord[atomicAdd(&cnt[skey[p]], 1)] = (unsigned short)p;
         __syncthreads();
         const int kept = one ? cnt[EK_KEYS] : rows;
         for (int s = t; s < kept; s += EK_BLOCK) {
             const int p = sord[s];
+            uint4 me;  // Size bits or candidate index
+            if constexpr (SLIM) {
+                me = widen(pay[bs + p]);
+            } else {
+                me.x = sid[0][p];
+                me.y = sid[NW >= 2 ? 1 : 0][p];
+                me.z = sid[NW >= 3 ? 2 : 0][p];
+                me.w = NW >= 4 ? sid[NW >= 4 ? 3 : 0][p] : 0u;
+            }
             const int k = skey[p];
-            const int g0 = cnt[k], g1 = cnt[k + 1];
+            const int g0 = k > 0 ? cnt[k - 1] : 0, g1 = cnt[k];
             unsigned r[3];
-            r[0] = sw[0][p];
-            r[1] = K >= 3 ? sw[1][p] : 0u;
-            r[2] = K == 4 ? sw[2][p] : 0u;
+            r[0] = sid[0][p];
+            r[1] = NI >= 2 ? sid[NI >= 2 ? 1 : 0][p] : 0u;
+            r[2] = NI >= 3 ? sid[NI >= 3 ? 2 : 0][p] : 0u;
             int rank = 0;
             for (int q = g0; q < g1; q++) {
                 const int o = sord[q];
-                const unsigned v[3] = {sw[0][o], K >= 3 ? sw[1][o] : 0u, K == 4 ? sw[2][o] : 0u};
+                const unsigned v[3] = {sid[0][o], NI >= 2 ? sid[NI >= 2 ? 1 : 0][o] : 0u,
+                                       NI >= 3 ? sid[NI >= 3 ? 2 : 0][o] : 0u};
                 rank += (q != s) && ids_less(v, r);
             }
             const long long pos = (long long)bs + g0 + rank;
             write_row<K>(out, pos, k0 + k, r);
-            uint4 me;
-            me.x = sw[0][p];
-            me.y = sw[1][p];
-            me.z = sw[2][p];
-            me.w = W == 4 ? sw[W - 1][p] : 0u;
             const double z = pay_size<K>(me, size_in);
             out_size[pos] = to_A2 ? z / 1.0e6 : z;
         }
@@ -248,7 +262,7 @@ __global__ void __launch_bounds__(EK_BLOCK) k_emit_block(const unsigned *__restr
     // (the bucket's own range of gkey / gpay), ranked from there
     for (int p = t; p < rows; p += EK_BLOCK) {
         const unsigned kk = key[bs + p] - k0;
-        const int slot = atomicAdd(&cur[kk], 1);
+        const int slot = atomicAdd(&cnt[kk], 1);
         gkey[bs + slot] = kk;
         gpay[bs + slot] = pay[bs + p];
     }
@@ -256,7 +270,7 @@ __global__ void __launch_bounds__(EK_BLOCK) k_emit_block(const unsigned *__restr
     __syncthreads();
     for (int s = t; s < rows; s += EK_BLOCK) {
         const int k = (int)gkey[bs + s];
-        const int g0 = cnt[k], g1 = cnt[k + 1];
+        const int g0 = k > 0 ? cnt[k - 1] : 0, g1 = cnt[k];
         const uint4 me = widen(gpay[bs + s]);
         unsigned r[3];
         pay_ids<K>(me, r);
