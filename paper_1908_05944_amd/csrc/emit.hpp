@@ -103,9 +103,9 @@ template <int K> constexpr int ek_rows() { return K == 4 ? 512 : 2048; }
 // them. Triangles and tetrahedra: the whole payload (20 bytes a row; a
 // triangle block, about 42 KB, leaves room for three per CU). The edge emit
 // ends the build, so it gains from the occupancy; the triangle emit runs on
-// the second stream beside the edge path, and with the slim rows (six blocks
-// per CU) it took more of the GPU from that path than it saved: 2.26 ms per
-// build against 2.19 ms with edges alone slim and 2.22 ms with none.
+// the second stream beside the edge path, and slim triangle rows (six blocks
+// per CU) did not shorten the build (2.185 against 2.190 ms), so they keep
+// the payload and do not read it twice.
 template <int K> constexpr bool ek_slim() { return K == 2; }
 
 template <int K>
