@@ -60,6 +60,25 @@ def test_dense_neighbourhoods(acx):
         assert_same_complex(_run(acx, m.xyz, m.radii, 0.0), want, "dense")
 
 
+def test_hub_ball_beyond_emit_lds(acx):
+    """A ball of radius 8 A at index 0 touched by 3,600 balls of radius
+    0.45 A spread over a sphere of radius 8.2 A around it: the hub is the least
+    id of more kept edges, triangles and tetrahedra than an emit block orders
+    in LDS (2,048 rows for edges and triangles, 512 for tetrahedra), so its
+    buckets are finished through global scratch."""
+    n = 3600
+    k = np.arange(n) + 0.5
+    phi, th = np.arccos(1 - 2 * k / n), np.pi * (1 + 5 ** 0.5) * k
+    shell = 8.2 * np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], 1)
+    xyz = np.vstack([[0.0, 0.0, 0.0], shell])
+    rad = np.concatenate([[8.0], np.full(n, 0.45)])
+    for alpha in (0.0, 1.0):
+        want = oracle.alpha_complex(xyz, rad, alpha)
+        hub_rows = [int((want.simplices[d][:, 0] == 0).sum()) for d in (1, 2, 3)]
+        assert hub_rows[0] > 2048 and hub_rows[1] > 2048 and hub_rows[2] > 512, hub_rows
+        assert_same_complex(_run(acx, xyz, rad, alpha), want, f"hub alpha={alpha}")
+
+
 def test_random_small(acx):
     rng = random.Random(42)
     for trial in range(40):
