@@ -317,23 +317,25 @@ constexpr int NB_SLOT_WIDE = 32;
 // exact while L^2 is exact below 2^53 and, above, rounds to at least 2^53:
 // the comparison is decided exactly either way.
 // The one-pass kernel with 16-entry slots runs eight waves per SIMD (64
-// registers, a few values spilled): the pass waits on its cell-row loads
-// more than on issue, and its LDS allows eight blocks per CU (0.259 ms
-// against 0.268 at the compiler's 66 registers, seven waves, on the 3M-atom
-// shell). The other forms are held to fewer waves by their LDS.
+// registers, a few values spilled; its LDS allows eight blocks per CU): the
+// eighth wave hides more of the latency of the cell-row loads than the
+// spills cost (0.259 ms against 0.268 at the compiler's 66 registers and
+// seven waves, on the 3M-atom shell). The other forms are held to fewer
+// waves by their LDS.
 template <int MODE, int SLOT>
 constexpr int nb_waves() { return MODE == NB_ONEPASS && SLOT == NB_SLOT ? 8 : 1; }
 template <int MODE, int SLOT, bool FAST = false>
-__global__ void __launch_bounds__(BLOCK, (nb_waves<MODE, SLOT>())) k_neighbours(const int4 *__restrict__ atom, const int *__restrict__ perm, int n,
-                                                       const Grid *__restrict__ grids, int n_mol,
-                                                       const int *__restrict__ cell_start, PredParams pp,
-                                                       int *__restrict__ deg_n, int *__restrict__ deg_up,
-                                                       unsigned *__restrict__ upmask, int *__restrict__ nslab,
-                                                       int *__restrict__ block_tot,
-                                                       const int *__restrict__ nbr_start, const int *__restrict__ up_start,
-                                                       int *__restrict__ nbr, int *__restrict__ up,
-                                                       int *__restrict__ edge_i, unsigned char *__restrict__ vgab,
-                                                       long long *__restrict__ vert_min, Counters *cnt) {
+__global__ void __launch_bounds__(BLOCK, (nb_waves<MODE, SLOT>()))
+k_neighbours(const int4 *__restrict__ atom, const int *__restrict__ perm, int n,
+             const Grid *__restrict__ grids, int n_mol,
+             const int *__restrict__ cell_start, PredParams pp,
+             int *__restrict__ deg_n, int *__restrict__ deg_up,
+             unsigned *__restrict__ upmask, int *__restrict__ nslab,
+             int *__restrict__ block_tot,
+             const int *__restrict__ nbr_start, const int *__restrict__ up_start,
+             int *__restrict__ nbr, int *__restrict__ up,
+             int *__restrict__ edge_i, unsigned char *__restrict__ vgab,
+             long long *__restrict__ vert_min, Counters *cnt) {
     static_assert(SLOT <= 32, "one mask bit per slot entry");
     constexpr int NB_SLAB = BLOCK * SLOT;
     constexpr bool ONE = MODE == NB_ONEPASS;
