@@ -97,6 +97,9 @@ __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const unsigned *__restr
                                                           const int *__restrict__ totals, int tiles,
                                                           const int *__restrict__ live = nullptr) {
     n = live_count(n, live);
+    // consecutive tiles on one XCD: their pieces of each digit run are
+    // adjacent, so the partial lines they write meet in that XCD's L2
+    const int tb = xcd_block(n / RS_TILE + (n % RS_TILE != 0));
     constexpr int NW = RS_BLOCK / WAVE;
     constexpr int CHUNK = WAVE * RS_IPT;  // each wave owns a contiguous chunk of the tile
     __shared__ int gbase[RS_BINS];        // output start of each digit for this tile
@@ -114,14 +117,14 @@ __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const unsigned *__restr
         __syncthreads();
         int below = incl - t;
         for (int w = 0; w < wave; w++) below += wsum[w];
-        gbase[threadIdx.x] = below + prefix[(long long)threadIdx.x * tiles + blockIdx.x];
+        gbase[threadIdx.x] = below + prefix[(long long)threadIdx.x * tiles + tb];
     }
 #pragma unroll
     for (int w = 0; w < NW; w++) wcnt[w][threadIdx.x] = 0;
     __syncthreads();
     // sweep: rank each element among the equal digits of its wave so far
     const unsigned long long lt = (1ull << lane) - 1ull;
-    const long long base = (long long)blockIdx.x * RS_TILE + (long long)wave * CHUNK;
+    const long long base = (long long)tb * RS_TILE + (long long)wave * CHUNK;
     // keys, payloads and ranks stay in registers; every load of the tile is
     // issued before the first ballot
     typedef typename RsReg<P>::type R;
@@ -181,7 +184,7 @@ __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const unsigned *__restr
     __syncthreads();
     // the tile in digit order: each digit's run goes to consecutive addresses;
     // a digit's tile-local start is the start of its first wave
-    const long long tbase = (long long)blockIdx.x * RS_TILE;
+    const long long tbase = (long long)tb * RS_TILE;
     const int cnt = (int)min((long long)RS_TILE, (long long)n - tbase);
     for (int p = threadIdx.x; p < cnt; p += RS_BLOCK) {
         const unsigned k = skey[p];
